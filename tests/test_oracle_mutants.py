@@ -1,0 +1,80 @@
+"""Planted mistakes: each mutant is a copy of the oracle with one plausible error (a
+dropped term, a flipped sign, a swapped index, a transposed operand). The pin suite must
+fail on every one of them; a mutant that survives means a part of the oracle is not
+pinned. Runs on the CPU only; mutants are built in a temporary directory."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "mgx_oracle.c")
+
+MUTANTS = {
+    "crb_sign": ("cross3(w, v, t3);", "cross3(v, w, t3);"),
+    "crb_rot_sign": ("cross3(w, Iw, t4);", "cross3(Iw, w, t4);"),
+    "ca_lin_sign": ("cross3(w, A1vr, c1);", "cross3(A1vr, w, c1);"),
+    "ca_ang_sign": ("cross3(vr, A1vr, c2);", "cross3(A1vr, vr, c2);"),
+    "ca_uses_v_not_vr": ("A1vr[j] = env->added[j] * vr[j];", "A1vr[j] = env->added[j] * v[j];"),
+    "damp_no_abs": ("fabs(nur[j])) * nur[j]", "nur[j]) * nur[j]"),
+    "restore_sign": ("out->restore[j] = -(W - env->buoy) * gb[j];", "out->restore[j] = (W - env->buoy) * gb[j];"),
+    "restore_moment_order": ("cross3(env->rb, gb, rbxg);\n    for (int j = 0; j < 3; ++j) {\n        out->restore",
+                             "cross3(gb, env->rb, rbxg);\n    for (int j = 0; j < 3; ++j) {\n        out->restore"),
+    "gravity_row": ("gb[j] = R[2][j];", "gb[j] = R[j][2];"),
+    "current_transposed": ("vc[j] = R[0][j] * env->current[0] + R[1][j] * env->current[1] + R[2][j] * env->current[2];",
+                           "vc[j] = R[j][0] * env->current[0] + R[j][1] * env->current[1] + R[j][2] * env->current[2];"),
+    "vr_sign": ("vr[j] = v[j] - vc[j];", "vr[j] = v[j] + vc[j];"),
+    "no_hadd": ("int amc = !(env->flags & ORC_FLAG_NO_AMC);", "int amc = 0;"),
+    "hadd_order": ("cross3(w, vc, wxvc);", "cross3(vc, w, wxvc);"),
+    "mass_no_added": ("return (j < 3 ? env->mass : env->inertia[j - 3]) + env->added[j];",
+                      "return (j < 3 ? env->mass : env->inertia[j - 3]);"),
+    "inertia_index": ("Iw[j] = env->inertia[j] * w[j];", "Iw[j] = env->inertia[(j + 1) % 3] * w[j];"),
+    "position_transposed": ("s->p[j] += env->dt * (R[j][0] * nun[0] + R[j][1] * nun[1] + R[j][2] * nun[2]);",
+                            "s->p[j] += env->dt * (R[0][j] * nun[0] + R[1][j] * nun[1] + R[2][j] * nun[2]);"),
+    "position_old_velocity": ("s->p[j] += env->dt * (R[j][0] * nun[0] + R[j][1] * nun[1] + R[j][2] * nun[2]);",
+                              "s->p[j] += env->dt * (R[j][0] * s->nu[0] + R[j][1] * s->nu[1] + R[j][2] * s->nu[2]);"),
+    "attitude_left_mult": ("orc_quat_mul(s->q, dq, qn);", "orc_quat_mul(dq, s->q, qn);"),
+    "attitude_full_angle": ("double half = 0.5 * wn * env->dt;", "double half = wn * env->dt;"),
+    "rotation_sign": ("R[0][1] = 2.0 * (x * y - w * z);", "R[0][1] = 2.0 * (x * y + w * z);"),
+    "thrust_moment_order": ("cross3(env->r[i], e, mom);", "cross3(e, env->r[i], mom);"),
+    "thrust_no_sign": ("double f = env->k[i] * s * fabs(s);", "double f = env->k[i] * s * s;"),
+    "lag_euler_always": ("return 1.0 - exp(-env->dt / env->tau[i]);", "return env->dt / env->tau[i];"),
+    "lag_before_clip": ("nl[i] = env->tau[i] > 0.0 ? s->n[i] + orc_lag_factor(env, i) * (c - s->n[i]) : c;",
+                        "nl[i] = env->tau[i] > 0.0 ? s->n[i] + orc_lag_factor(env, i) * (a[i] - s->n[i]) : c;"),
+    "thrust_from_old_rotor": ("orc_terms_eval(env, s->q, s->nu, nl, &t);", "orc_terms_eval(env, s->q, s->nu, s->n, &t);"),
+    "quat_product_sign": ("out[1 + j] = a[0] * bv[j] + b[0] * av[j] + c[j];", "out[1 + j] = a[0] * bv[j] + b[0] * av[j] - c[j];"),
+}
+
+
+def _build(tmp, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutant {name}: pattern not unique"
+    mdir = os.path.join(tmp, name)
+    os.makedirs(mdir)
+    path = os.path.join(mdir, "mgx_oracle.c")
+    open(path, "w").write(src.replace(old, new))
+    hdr = os.path.join(ROOT, "oracle", "mgx_oracle.h")
+    lib = os.path.join(mdir, "lib.so")
+    subprocess.check_call(["gcc", "-std=c11", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+                           "-fPIC", "-shared", "-D_GNU_SOURCE", "-I", os.path.dirname(hdr), path, "-o", lib,
+                           "-lm"])
+    return lib
+
+
+def test_every_planted_mistake_is_caught(tmp_path):
+    from concurrent.futures import ThreadPoolExecutor
+
+    def run(item):
+        name, (old, new) = item
+        lib = _build(str(tmp_path), name, old, new)
+        env = dict(os.environ, MGX_ORACLE_LIB=lib, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                            os.path.join(ROOT, "tests", "test_oracle_pins.py")], env=env, cwd=ROOT,
+                           capture_output=True, text=True)
+        return name, r.returncode
+
+    with ThreadPoolExecutor(max_workers=6) as ex:
+        results = list(ex.map(run, MUTANTS.items()))
+    survivors = [n for n, rc in results if rc == 0]
+    assert not survivors, f"pins did not catch: {survivors}"
