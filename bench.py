@@ -1,0 +1,266 @@
+#!/usr/bin/env python3
+"""Throughput of the batched underwater-vehicle step on one MI355X.
+
+Workload (default): one 6-thruster vehicle class, 65,536 environments with +-20%
+per-environment randomisation of mass, added mass, damping and buoyancy and a constant
+N(0, 0.3^2) m/s world current each, 1000 steps of dt = 0.01 s, actions resampled every 10
+steps. One benchmark step = one pass of the whole path over that batch: per-parameter-set
+setup (double precision, on the device), reset from a resident initial state, and the
+1000-step rollout as 16-step fused launches replayed from a captured HIP graph. Inputs
+(parameters, initial states, the action stream) are resident in HBM before timing.
+
+Prints one JSON line: env-steps/s, the roofline of the fused step kernel (per-launch
+duration from HIP events on the batch's stream), the single-step kernel's HBM roofline,
+and the FP64 CPU oracle timed on this host on a bounded sample of the same workload,
+whose final states also give the parity of this run.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FP32 env-steps/s vs FP64 oracle at stated error; serving p50/p99 latency"
+PEAK_FP32_VECTOR = 157.3e12   # MI355X published FP32 vector peak (FLOP/s)
+PEAK_HBM = 8.0e12             # MI355X HBM3E (B/s)
+
+
+def bytes_per_env_step(m, K, hold, prec=4, rec_len=30):
+    """Algorithmic HBM bytes per environment-step of one launch of K steps: state read and
+    written once, record read once, one action row per hold interval."""
+    state = (13 + m) * prec
+    rows = min(K, math.ceil(K / hold) + 1) if hold > 1 else K
+    return (2 * state + rec_len * prec + rows * m * prec) / K
+
+
+def parity_errors(gpu, ref):
+    """Per-component max_env |gpu - ref| / max(|ref|, rms of the component)."""
+    rms = np.sqrt(np.mean(ref * ref, axis=1, keepdims=True))
+    return np.max(np.abs(gpu - ref) / np.maximum(np.abs(ref), np.maximum(rms, 1e-30)), axis=1)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50, help="timed benchmark steps (full rollouts)")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=65536, help="environments")
+    ap.add_argument("--rollout", type=int, default=1000, help="steps per rollout")
+    ap.add_argument("--chunk", type=int, default=16, help="steps per fused launch (K)")
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-oracle time")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the benchmark line, print launch-duration sweeps over K and N")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); environments are independent, "
+              "so more GPUs would each run their own shard of the batch with no exchange.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_2503_09203_amd import mgx
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    mgx.lib()  # fail loudly if the HIP library is missing
+
+    N, T, K, HOLD = args.n, args.rollout, args.chunk, 10
+    if args.sweep:
+        sweep(args)
+        return
+    w = synth.randomised(n=N, steps=T)
+    cls = w.classes[0]
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    b = mgx.Batch([cls], [N], w.dt, mgx.FP32)
+    b.set_params(w.params, on_device=True)
+    param_ptrs = {k: v.data_ptr() for k, v in b._param_tensors.items()}
+    init = torch.tensor(b.pack_state([w.state[0].stacked()]), dtype=torch.float32, device=dev)
+    rows = -(-T // HOLD)
+    acts = b.gen_actions(rows, seed=synth.MASTER_SEED)
+    graph = b.capture(acts, T, K, hold=HOLD)
+
+    def bench_step():
+        mgx.mgx_batch_set_params(b.h, param_ptrs, 1)
+        b.reset(init_state=init)
+        b.t = 0
+        graph.replay()
+
+    for _ in range(args.warmup):
+        bench_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bench_step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    final_state = b.unpack_state(b.get_state().cpu().numpy().astype(np.float64))[0]
+    value = N * T * args.steps / elapsed
+
+    # Per-launch duration of the fused kernel, HIP events on the batch's stream.
+    flops_es, ops_es = mgx.mgx_step_cost(cls.m)
+
+    def time_launches(k_steps, reps):
+        starts = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+        ends = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+        b.reset(init_state=init)
+        b.t = 0
+        t_ = 0
+        for r in range(reps):
+            if t_ + k_steps > T:
+                b.t = 0
+                t_ = 0
+            starts[r].record(stream)
+            b.step(acts, k_steps, hold=HOLD)
+            ends[r].record(stream)
+            t_ += k_steps
+        torch.cuda.synchronize()
+        d = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)]) * 1e-3
+        return float(np.median(d)), float(np.mean(d))
+
+    fused_med, fused_mean = time_launches(K, args.kernel_reps)
+    fused_flops = flops_es * N * K
+    single_med, single_mean = time_launches(1, args.kernel_reps)
+    single_bytes = bytes_per_env_step(cls.m, 1, HOLD) * N
+
+    # Whole rollout as 1000 single-step launches (graph-captured) for comparison.
+    g1 = b.capture(acts, T, 1, hold=HOLD, flags=mgx.STEP_UNFUSED)
+    b.reset(init_state=init)
+    b.t = 0
+    g1.replay()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    reps1 = max(3, args.steps // 10)
+    for _ in range(reps1):
+        b.reset(init_state=init)
+        b.t = 0
+        g1.replay()
+    torch.cuda.synchronize()
+    single_rate = N * T * reps1 / (time.perf_counter() - t1)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "env-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"dr_{N}x{T}", "n_envs": N, "rollout_steps": T, "thrusters": cls.m, "hold": HOLD,
+                   "launch_steps_K": K, "dt": w.dt, "current_sigma": 0.3, "randomisation": 0.2,
+                   "path": "set_params + reset + graph of fused launches"},
+        "roofline": {"bound": "alu", "achieved": fused_flops / fused_mean / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
+                     "unit": "TFLOP/s", "frac": fused_flops / fused_mean / PEAK_FP32_VECTOR, "traffic": None,
+                     "kernel": f"k_step<float,{cls.m}> K={K}", "launch_us_mean": fused_mean * 1e6,
+                     "launch_us_median": fused_med * 1e6, "flops_per_env_step": flops_es,
+                     "valu_ops_per_env_step": ops_es},
+        "single_step": {"env_steps_per_s": single_rate, "kernel": f"k_step<float,{cls.m}> K=1",
+                        "launch_us_mean": single_mean * 1e6, "launch_us_median": single_med * 1e6,
+                        "roofline": {"bound": "hbm", "achieved": single_bytes / single_mean / 1e9,
+                                     "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                                     "frac": single_bytes / single_mean / PEAK_HBM,
+                                     "bytes_per_env_step": bytes_per_env_step(cls.m, 1, HOLD)}},
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle  # CPU baseline leg only
+
+        envs_all = oracle.make_envs(cls, w.params, w.dt)
+        st0 = w.state[0]
+        full_state = oracle.pack_state(st0.p, st0.q, st0.nu, st0.n)
+        a_host = synth.actions(N, cls.m, rows)
+        # calibrate on 256 environments, then size the sample to the time target
+        cal = np.arange(256)
+        tc = time.perf_counter()
+        oracle.rollout(envs_all[cal], full_state[cal].copy(), oracle.pack_actions(a_host[:, :, cal]), HOLD, T)
+        rate_cal = 256 * T / (time.perf_counter() - tc)
+        n_s = int(min(N, max(256, rate_cal * args.cpu_seconds / T)))
+        idx = np.linspace(0, N - 1, n_s).round().astype(np.int64)
+        acts_s = oracle.pack_actions(a_host[:, :, idx])
+        st_s = full_state[idx].copy()
+        tc = time.perf_counter()
+        st_s, _, _ = oracle.rollout(envs_all[idx], st_s, acts_s, HOLD, T)
+        cpu_elapsed = time.perf_counter() - tc
+        ref = oracle.unpack_state(st_s, cls.m)
+        err = parity_errors(final_state[:, idx], ref)
+        out["cpu_baseline"] = {"value": n_s * T / cpu_elapsed, "unit": "env-steps/s", "cores": oracle.get_threads(),
+                               "kind": "oracle",
+                               "sample": f"{n_s} of {N} environments (evenly spaced ids) x {T} steps, FP64 C oracle, "
+                                         f"OpenMP over environments, {cpu_elapsed:.1f} s"}
+        out["parity"] = {"metric": "max over envs |gpu - oracle| / max(|oracle|, rms), per state component",
+                         "step": T, "max_err": float(err.max()), "tolerance": 1e-3, "pass": bool(err.max() <= 1e-3),
+                         "envs_checked": n_s}
+
+    g1.close()
+    graph.close()
+    b.close()
+    print(json.dumps(out), flush=True)
+
+
+def sweep(args):
+    """Per-launch durations (HIP events on the batch stream) over K at the default N, and
+    over N for K = 1 and K = 16. One JSON line per point."""
+    import torch
+
+    import synth
+    from paper_2503_09203_amd import mgx
+
+    HOLD = 10
+    cls = synth.plain_class()
+    flops_es, _ = mgx.mgx_step_cost(cls.m)
+
+    def measure(N, K, reps):
+        p = synth.randomised_params(cls, N)
+        st = synth.initial_state(N, cls.m)
+        b = mgx.Batch([cls], [N], 0.01)
+        b.set_params(p)
+        init = torch.tensor(b.pack_state([st.stacked()]), dtype=torch.float32, device="cuda:0")
+        rows = -(-(K * 2) // HOLD) + 1
+        acts = b.gen_actions(rows)
+        stream = torch.cuda.current_stream()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for i in range(reps + 2):
+            b.reset(init_state=init)
+            b.t = 0
+            if i >= 2:
+                ev[i - 2][0].record(stream)
+            b.step(acts, K, hold=HOLD)
+            if i >= 2:
+                ev[i - 2][1].record(stream)
+        torch.cuda.synchronize()
+        d = np.array([a.elapsed_time(c) for a, c in ev]) * 1e-3
+        b.close()
+        mean = float(d.mean())
+        return {"n": N, "K": K, "launch_us_mean": mean * 1e6, "launch_us_min": float(d.min()) * 1e6,
+                "env_steps_per_s": N * K / mean, "tflops": flops_es * N * K / mean / 1e12,
+                "gbps": bytes_per_env_step(cls.m, K, HOLD) * N * K / mean / 1e9}
+
+    for K in (1, 2, 4, 8, 16, 32, 64, 128, 256, 1000):
+        print(json.dumps({"sweep": "K", **measure(args.n, K, 20 if K < 256 else 5)}), flush=True)
+    for e in range(12, 23):
+        N = 1 << e
+        for K in (1, 16):
+            print(json.dumps({"sweep": "N", **measure(N, K, 20)}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,248 @@
+/*
+ * mgx — batched underwater-vehicle dynamics on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the device library. It advances thousands of independent vehicles
+ * ("environments") by the step of MarineGym's GPU hydrodynamic pipeline (arXiv
+ * 2503.09203, Sec. III-B, Eqs. (1)-(3); actuator models of Sec. III-D): rotor lag, thrust
+ * through the thruster layout, rigid-body and added-mass Coriolis, linear plus quadratic
+ * damping and restoring forces with the relative-velocity current substitution, the
+ * (M_RB + M_A)^-1 acceleration solve, and quaternion pose integration.
+ *
+ * Conventions (all calls):
+ *   - Units SI. World frame NED, body frame FRD, body origin at the centre of gravity.
+ *     Quaternion (w, x, y, z), Hamilton product, body -> world. nu = (u, v, w, p, q, r).
+ *   - Every function returns mgx_status. Nothing throws across the ABI. On failure the
+ *     thread-local detail string is available from mgx_last_error().
+ *   - Validation failures (MGX_E_INVALID) leave every object unchanged.
+ *   - A HIP runtime failure inside a batch call marks the batch faulted; every later call
+ *     on it returns MGX_E_STATE until mgx_batch_destroy().
+ *   - Device pointers are plain HIP device addresses (e.g. torch tensor data_ptr()); the
+ *     library never frees memory it did not allocate. Host inputs are copied before the
+ *     call returns.
+ *   - Calls are asynchronous on the batch's stream unless stated otherwise. A batch is not
+ *     thread-safe; distinct batches may be used from distinct threads.
+ *   - Precision: MGX_FP32 batches keep state, parameters and actions in float; MGX_FP64
+ *     batches in double. Per-parameter-set setup (mass inverse, lag factors, thruster
+ *     layout) always runs in double on the device and is rounded once.
+ */
+#ifndef MGX_H
+#define MGX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mgx_status;
+#define MGX_OK 0
+#define MGX_E_INVALID (-1)   /* bad argument; nothing changed */
+#define MGX_E_NOMEM (-2)     /* device or host allocation failed */
+#define MGX_E_DEVICE (-3)    /* no usable GPU, or a HIP call failed (see mgx_last_hip_error) */
+#define MGX_E_NONFINITE (-5) /* mgx_batch_check: some environment holds a non-finite value */
+#define MGX_E_BUDGET (-6)    /* serving: request larger than the memory budget */
+#define MGX_E_STATE (-7)     /* batch faulted earlier, or called in the wrong order */
+
+#define MGX_MAX_THRUSTERS 8
+#define MGX_MAX_CLASSES 16
+#define MGX_STATE_FIXED 13   /* p[3], q[4], nu[6]; then n[m] rotor states */
+#define MGX_FORCE_LEN 12     /* actuator wrench[6], hydrodynamic wrench[6] */
+
+/* precision */
+#define MGX_FP32 4
+#define MGX_FP64 8
+
+/* batch flags */
+#define MGX_FLAG_NO_AMC 1u     /* drop the added-mass term from the rotating current projection */
+#define MGX_FLAG_LAG_EULER 2u  /* rotor lag factor dt/tau instead of 1 - exp(-dt/tau) */
+
+/* step flags */
+#define MGX_STEP_UNFUSED 1u    /* K launches of one step each instead of one launch of K steps */
+#define MGX_STEP_STATS 2u      /* update batch statistics at the end of the call */
+
+/* ------------------------------------------------------------------ errors, info */
+
+const char* mgx_status_string(mgx_status s);
+/* Copies the calling thread's last error detail into buf (NUL-terminated, truncated to len);
+ * returns the full length. buf may be NULL to query the length. */
+size_t mgx_last_error(char* buf, size_t len);
+/* hipError_t value of the last failed HIP call on this thread (0 if none). */
+int32_t mgx_last_hip_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t mgx_version(void);
+/* Number of visible HIP devices (MGX_E_DEVICE if the runtime reports none). */
+mgx_status mgx_device_count(int32_t* count);
+
+/* Algorithmic cost of one environment advanced by one step for a class with m thrusters,
+ * counted on the host over the same step body the kernels run: flops (add, sub, mul = 1,
+ * fused multiply-add = 2) and vector ALU operations (every add/sub/mul/fma/min/max/
+ * select = 1; negation and absolute value are free operand modifiers). */
+mgx_status mgx_step_cost(int32_t m, uint32_t batch_flags, double* flops, double* valu_ops);
+
+/* ------------------------------------------------------------------ vehicle classes */
+
+/* One vehicle class: the thruster layout and rotor models (Sec. III-D), principal
+ * inertia about the centre of gravity, centre of buoyancy. Host memory, copied. */
+typedef struct {
+    int32_t m;                          /* thrusters, 1..MGX_MAX_THRUSTERS */
+    int32_t reserved;
+    double r[MGX_MAX_THRUSTERS][3];     /* thruster positions, body frame (m) */
+    double e[MGX_MAX_THRUSTERS][3];     /* thrust axes, body frame; normalised by the library */
+    double k[MGX_MAX_THRUSTERS];        /* thrust gain (N at |n| = 1), > 0 */
+    double tau[MGX_MAX_THRUSTERS];      /* rotor time constant (s), >= 0; 0 = zero-order rotor */
+    double deadzone[MGX_MAX_THRUSTERS]; /* dead zone on |n|, in [0, 1) */
+    double inertia[3];                  /* principal moments about the CoG (kg m^2), > 0 */
+    double rb[3];                       /* centre of buoyancy, body frame (m) */
+    double g0;                          /* gravitational acceleration (m/s^2), > 0 */
+} mgx_class_desc;
+
+/* Registers a class; *class_id receives its id (process-wide, never reused).
+ * MGX_E_INVALID on a non-finite or out-of-range field, a zero-length thrust axis, or when
+ * 4096 classes are already defined. */
+mgx_status mgx_class_define(const mgx_class_desc* desc, int32_t* class_id);
+
+/* ------------------------------------------------------------------ batches */
+
+typedef struct mgx_batch mgx_batch;
+
+typedef struct {
+    int32_t n_classes;          /* 1..MGX_MAX_CLASSES */
+    int32_t precision;          /* MGX_FP32 or MGX_FP64 */
+    const int32_t* class_ids;   /* [n_classes] from mgx_class_define (host) */
+    const int64_t* n_envs;      /* [n_classes] environments per class, >= 1 (host) */
+    double dt;                  /* step (s), > 0 */
+    uint32_t flags;             /* MGX_FLAG_* */
+    int32_t device;             /* HIP device ordinal; -1 = the calling thread's current device */
+    void* stream;               /* hipStream_t for every call on the batch; NULL = null stream */
+} mgx_batch_desc;
+
+/* Memory layout of a batch. Environments are numbered globally 0..n_total-1, class by
+ * class in the order given at creation. Each class segment is padded to a multiple of 64
+ * environments (one wavefront); padded slots hold a benign state and are never reported.
+ *   state   : class c at state_off[c], component-major: element (j, env) at
+ *             state_off[c] + j * n_pad[c] + env, j < 13 + m[c]. Total state_elems.
+ *   actions : one row per hold interval, row_elems elements per row; class c at
+ *             action_off[c] within a row, element (i, env) at action_off[c] + i*n_pad[c] + env.
+ *   forces  : per step, force_row_elems per row; class c at force_off[c], element (j, env)
+ *             at force_off[c] + j * n_pad[c] + env, j < 12.
+ * Element size is the batch precision (4 or 8 bytes). */
+typedef struct {
+    int32_t n_classes, precision;
+    int64_t n_total, n_pad_total;
+    int64_t state_elems, row_elems, force_row_elems;
+    int32_t m[MGX_MAX_CLASSES];
+    int64_t n[MGX_MAX_CLASSES], n_pad[MGX_MAX_CLASSES];
+    int64_t env_off[MGX_MAX_CLASSES];     /* first global env id of the class */
+    int64_t state_off[MGX_MAX_CLASSES], action_off[MGX_MAX_CLASSES], force_off[MGX_MAX_CLASSES];
+} mgx_layout;
+
+/* Creates a batch on the given device and stream and allocates its state, parameter
+ * record and bookkeeping (hipMalloc). Synchronous. The step counter starts at 0.
+ * MGX_E_INVALID on bad fields; MGX_E_DEVICE if no GPU is usable; MGX_E_NOMEM. */
+mgx_status mgx_batch_create(const mgx_batch_desc* desc, mgx_batch** out);
+mgx_status mgx_batch_destroy(mgx_batch* b);   /* synchronises its stream, frees; NULL is OK */
+mgx_status mgx_batch_layout(const mgx_batch* b, mgx_layout* out);
+
+/* Per-environment parameters, each an array over the global env id (n_total entries per
+ * row), always double precision. Rows of 6 are DOF-major: element (j, env) at j*n_total+env.
+ *   mass  [n]   rigid-body mass (kg), > 0
+ *   added [6][n] added-mass diagonal (positive; Fossen's -X_udot, ...), >= 0
+ *   dlin  [6][n] linear damping, >= 0;  dquad [6][n] quadratic damping, >= 0
+ *   buoy  [n]   buoyancy force (N), >= 0
+ *   current [3][n] constant world-frame water velocity (m/s)  (Sec. III-B, ocean currents) */
+typedef struct {
+    const double* mass;
+    const double* added;
+    const double* dlin;
+    const double* dquad;
+    const double* buoy;
+    const double* current;
+} mgx_env_params;
+
+/* Per-parameter-set setup (Eq. (1)-(2): M = M_RB + M_A with M_RB = diag(m, m, m, I)):
+ * computes dt*M^-1, W - B, lag factors and the thruster layout in double precision on the
+ * device, rounds once to the batch precision. on_device = 1: the arrays are device
+ * pointers; 0: host pointers (copied, then the call returns; the device work stays async).
+ * Host arrays are validated (finite, ranges above); device arrays are not.
+ * Must be called before the first step (MGX_E_STATE otherwise). */
+mgx_status mgx_batch_set_params(mgx_batch* b, const mgx_env_params* p, int32_t on_device);
+
+/* Resets environments. env_ids: host array of n global env ids, or NULL for all.
+ * init_state: device pointer to a full state buffer in this batch's layout and precision;
+ * the listed environments are copied from it. NULL: seeded state — p = 0, q uniform on
+ * the unit 3-sphere (normalised Gaussian), nu ~ N(0, 0.2^2) per component, n = 0 — drawn
+ * with Philox4x32-10 keyed by seed, for global env id e (see mgx_gen_actions for the
+ * generator). MGX_E_INVALID on an id outside [0, n_total). Does not move the step counter. */
+mgx_status mgx_batch_reset(mgx_batch* b, const int64_t* env_ids, int64_t n, const void* init_state,
+                           uint64_t seed);
+
+/* Advances every environment by K >= 1 steps of dt. Step k of the call (global step
+ * t = t0 + k, t0 = the batch step counter) uses row floor(t / hold) - row0 of `actions`
+ * (device pointer, n_rows rows in the layout above, batch precision). Commands are
+ * clipped to [-1, 1]. MGX_E_INVALID if a needed row falls outside [0, n_rows).
+ * traj: NULL or device [K][state_elems] — the state after each step.
+ * forces: NULL or device [K][force_row_elems] — actuator and hydrodynamic wrench (Eq. (3),
+ *         with d(nu)/dt the solved acceleration) of each step, body frame.
+ * flags: MGX_STEP_*. Asynchronous. The step counter advances by K on the device. */
+mgx_status mgx_batch_step(mgx_batch* b, const void* actions, int64_t n_rows, int64_t row0, int32_t hold,
+                          int32_t K, uint32_t flags, void* traj, void* forces);
+
+/* Step counter (host mirror, equal to the device counter once the stream has drained). */
+mgx_status mgx_batch_get_step(const mgx_batch* b, int64_t* t);
+mgx_status mgx_batch_set_step(mgx_batch* b, int64_t t);
+
+/* Copies the whole state (state_elems elements) out / in. to_host/from_host = 1: host
+ * memory, and the call synchronises the stream; 0: device memory, asynchronous. */
+mgx_status mgx_batch_get_state(mgx_batch* b, void* out, int32_t to_host);
+mgx_status mgx_batch_set_state(mgx_batch* b, const void* in, int32_t from_host);
+
+/* Batch statistics of the last call that passed MGX_STEP_STATS (synchronises the stream):
+ * per class, over its valid environments, wavefront-reduced on the device. */
+typedef struct {
+    int64_t step;                                  /* step counter at that call's end */
+    int64_t n_nonfinite[MGX_MAX_CLASSES];          /* envs with any non-finite state value */
+    int64_t n_renorm64[MGX_MAX_CLASSES];           /* double-precision attitude renormalisations */
+    double max_speed[MGX_MAX_CLASSES], mean_speed[MGX_MAX_CLASSES];   /* |v| (m/s) */
+    double max_rate[MGX_MAX_CLASSES], mean_rate[MGX_MAX_CLASSES];     /* |w| (rad/s) */
+    double mean_kinetic[MGX_MAX_CLASSES];          /* 1/2 nu^T (M_RB + M_A) nu (J) */
+    double max_qdrift[MGX_MAX_CLASSES];            /* max | |q|^2 - 1 | before renormalising */
+} mgx_stats;
+mgx_status mgx_batch_get_stats(mgx_batch* b, mgx_stats* out);
+
+/* Synchronises the stream and reports the device-side error word and non-finite count
+ * (of the last MGX_STEP_STATS call): MGX_OK, MGX_E_NONFINITE (count in *n_nonfinite), or
+ * MGX_E_INVALID if a kernel met an action row outside its buffer. */
+mgx_status mgx_batch_check(mgx_batch* b, int64_t* n_nonfinite);
+mgx_status mgx_batch_sync(mgx_batch* b);
+
+/* Action stream generator on the device: fills `out` (device, rows x row_elems, batch
+ * precision) with a = ((w >> 8) - 2^23) * 2^-23 in [-1, 1), where w is word (i mod 4) of
+ * Philox4x32-10 (Salmon et al., SC'11) at key (seed mod 2^32, 4 << 24) and counter
+ * (global env id, row_offset + row, i / 4, 0). Padded slots get 0. Asynchronous. */
+mgx_status mgx_gen_actions(mgx_batch* b, void* out, int64_t rows, int64_t row_offset, uint64_t seed);
+
+/* ------------------------------------------------------------------ captured chunks */
+
+typedef struct mgx_graph mgx_graph;
+
+/* Captures a rollout chunk into a HIP graph: ceil(n_steps / K) step launches of K steps
+ * (the last one shorter), exactly as mgx_batch_step would enqueue them for the same
+ * arguments (MGX_STEP_UNFUSED: one step per launch; MGX_STEP_STATS: statistics on the last
+ * launch). Capture happens on a private stream; nothing runs and the batch is unchanged.
+ * Each replay runs on the batch's stream and advances the batch by n_steps. Because every
+ * launch reads its step from the device counter, one graph walks through a rollout-long
+ * action buffer: replay r uses rows floor(t/hold) - row0 for t from the batch's step at
+ * replay time. Destroy graphs before their batch (mgx_batch_destroy returns MGX_E_STATE
+ * while any is alive). */
+mgx_status mgx_graph_capture(mgx_batch* b, const void* actions, int64_t n_rows, int64_t row0, int32_t hold,
+                             int32_t n_steps, int32_t K, uint32_t flags, mgx_graph** out);
+/* MGX_E_INVALID (nothing launched) if the rows needed at the batch's current step fall
+ * outside [0, n_rows). Asynchronous. */
+mgx_status mgx_graph_replay(mgx_graph* g);
+mgx_status mgx_graph_destroy(mgx_graph* g);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

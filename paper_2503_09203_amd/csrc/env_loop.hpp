@@ -1,0 +1,220 @@
+// Per-environment K-step loop and statistics reductions, shared by the per-class kernel
+// and the persistent heterogeneous kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "step.hpp"
+
+namespace mgx {
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__host__ __device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {
+    int64_t q = a / b;
+    return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+
+template <typename T>
+__device__ __forceinline__ bool finite_(T x) {
+    return x == x && abs_(x) <= (T)3.0e38;
+}
+
+__device__ __forceinline__ bool is_max_slot(int j) {
+    return j == kStMaxSpeed || j == kStMaxRate || j == kStMaxDrift;
+}
+
+// Wave then block reduction of per-lane statistics; thread j < kStats writes slot j.
+__device__ __forceinline__ void block_reduce_stats(const float st[kStats], float (*red)[kStats], float* out) {
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+#pragma unroll
+    for (int j = 0; j < kStats; ++j) {
+        float v = is_max_slot(j) ? wave_max(st[j]) : wave_sum(st[j]);
+        if (lane == 0) red[wv][j] = v;
+    }
+    __syncthreads();
+    if (tid < kStats) {
+        float v = red[0][tid];
+        for (int w = 1; w < (int)blockDim.x / kWave; ++w) v = is_max_slot(tid) ? fmaxf(v, red[w][tid]) : v + red[w][tid];
+        out[tid] = v;
+    }
+}
+
+// Deterministic reduction over n partial records (fixed order), slot j.
+__device__ __forceinline__ void final_reduce_stats(const float* partials, unsigned n, int j, double* out) {
+    double acc = 0.0;
+    for (unsigned b = 0; b < n; ++b) {
+        const double v = (double)__hip_atomic_load(&partials[(int64_t)b * kStats + j], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        acc = is_max_slot(j) ? fmax(acc, v) : acc + v;
+    }
+    out[j] = acc;
+}
+
+// K steps of environment `env` (a slot of the segment described by A) from global step
+// t0. Commands are fetched raw one hold interval before use and clipped when their row
+// becomes current; all prologue loads are drained once before the loop so that the only
+// memory operations in flight inside it are those prefetches.
+template <typename T, int M, bool kOut, bool kDz>
+__device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& C, int64_t env, int64_t t0, int K,
+                                          float st[kStats]) {
+    const int64_t np = A.npad;
+    T* S = (T*)A.state;
+    const T* Rc = (const T*)A.rec;
+    StateT<T, M> s;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) s.p[j] = S[j * np + env];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s.q[j] = S[(3 + j) * np + env];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) s.nu[j] = S[(7 + j) * np + env];
+#pragma unroll
+    for (int i = 0; i < M; ++i) s.n[i] = S[(kStateFixed + i) * np + env];
+    EnvT<T> E;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        E.dtMinv[j] = Rc[(kRecDtMinv + j) * np + env];
+        E.A[j] = Rc[(kRecAdded + j) * np + env];
+        E.dL[j] = Rc[(kRecDlin + j) * np + env];
+        E.dQ[j] = Rc[(kRecDquad + j) * np + env];
+    }
+    E.mass = Rc[kRecMass * np + env];
+    E.wmb = Rc[kRecWmB * np + env];
+    E.buoy = Rc[kRecBuoy * np + env];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) E.Vc[j] = Rc[(kRecCurrent + j) * np + env];
+
+    // Action rows, relative to the buffer start, uniform across the wave. Every fetch is
+    // issued unconditionally at a row index clamped into the buffer (validity is tracked
+    // separately), so each prefetch has a single definition and no copy forces an early wait.
+    const int64_t hold = A.hold, nrows = A.n_rows, rstride = A.row_stride;
+    const int64_t rowa = floor_div(t0, hold);
+    int phase = (int)(t0 - rowa * hold);
+    int64_t r = rowa - A.row0;
+    const T* abase = (const T*)A.actions + env;
+    auto clamp_row = [nrows](int64_t x) { return x < 0 ? (int64_t)0 : (x >= nrows ? nrows - 1 : x); };
+    bool bad = (r < 0 || r >= nrows);
+    T cur[M], nxt[M];
+    {
+        const T* p0 = abase + clamp_row(r) * rstride;
+        const T* p1 = abase + clamp_row(r + 1) * rstride;
+#pragma unroll
+        for (int i = 0; i < M; ++i) cur[i] = p0[i * np];
+#pragma unroll
+        for (int i = 0; i < M; ++i) nxt[i] = p1[i * np];
+        if (hold - phase < K && r + 1 >= nrows) bad = true;
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll
+    for (int i = 0; i < M; ++i) cur[i] = clip1(cur[i]);
+    T IA2[3], Brb[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        IA2[j] = C.inertia[j] + E.A[3 + j];
+        Brb[j] = E.buoy * C.rb[j];
+    }
+
+    for (int k = 0; k < K; ++k) {
+        if constexpr (kOut) {
+            T f[kForceLen];
+            step_body<T, M, true, kDz>(C, E, IA2, Brb, s, cur, f);
+            if (A.forces) {
+                T* fo = (T*)A.forces + k * A.force_stride + env;
+#pragma unroll
+                for (int j = 0; j < kForceLen; ++j) fo[j * np] = f[j];
+            }
+            if (A.traj) {
+                T* to = (T*)A.traj + k * A.traj_stride + env;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) to[j * np] = s.p[j];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) to[(3 + j) * np] = s.q[j];
+#pragma unroll
+                for (int j = 0; j < 6; ++j) to[(7 + j) * np] = s.nu[j];
+#pragma unroll
+                for (int i = 0; i < M; ++i) to[(kStateFixed + i) * np] = s.n[i];
+            }
+        } else {
+            step_body<T, M, false, kDz>(C, E, IA2, Brb, s, cur);
+        }
+        if (++phase == hold) {
+            phase = 0;
+            ++r;
+#pragma unroll
+            for (int i = 0; i < M; ++i) cur[i] = clip1(nxt[i]);
+            const T* pn = abase + clamp_row(r + 1) * rstride;
+#pragma unroll
+            for (int i = 0; i < M; ++i) nxt[i] = pn[i * np];
+            if (k + 1 + hold < K && r + 1 >= nrows) bad = true;
+        }
+    }
+    if (bad && (threadIdx.x & (kWave - 1)) == 0) atomicOr(&A.misc->err, 1);
+
+    // Long-horizon attitude drift check: renormalise in double when | |q|^2 - 1 | > 1e-6.
+    {
+        T n2 = fma_(s.q[3], s.q[3], fma_(s.q[2], s.q[2], fma_(s.q[1], s.q[1], s.q[0] * s.q[0])));
+        T drift = abs_(n2 - T(1));
+        if (drift > T(1e-6)) {
+            double qd[4] = {(double)s.q[0], (double)s.q[1], (double)s.q[2], (double)s.q[3]};
+            double inv = 1.0 / sqrt(qd[0] * qd[0] + qd[1] * qd[1] + qd[2] * qd[2] + qd[3] * qd[3]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) s.q[j] = (T)(qd[j] * inv);
+            st[kStRenorm] = 1.0f;
+        }
+        st[kStMaxDrift] = (float)drift;
+    }
+
+#pragma unroll
+    for (int j = 0; j < 3; ++j) S[j * np + env] = s.p[j];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) S[(3 + j) * np + env] = s.q[j];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) S[(7 + j) * np + env] = s.nu[j];
+#pragma unroll
+    for (int i = 0; i < M; ++i) S[(kStateFixed + i) * np + env] = s.n[i];
+
+    if (A.partials) {
+        if (env < A.nvalid) {
+            bool fin = true;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) fin &= finite_(s.p[j]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) fin &= finite_(s.q[j]);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) fin &= finite_(s.nu[j]);
+#pragma unroll
+            for (int i = 0; i < M; ++i) fin &= finite_(s.n[i]);
+            if (fin) {
+                float sp = (float)sqrt_(s.nu[0] * s.nu[0] + s.nu[1] * s.nu[1] + s.nu[2] * s.nu[2]);
+                float rt = (float)sqrt_(s.nu[3] * s.nu[3] + s.nu[4] * s.nu[4] + s.nu[5] * s.nu[5]);
+                T ke = T(0);
+#pragma unroll
+                for (int j = 0; j < 6; ++j) ke += s.nu[j] * s.nu[j] * (C.dt / E.dtMinv[j]);
+                st[kStMaxSpeed] = sp;
+                st[kStSumSpeed] = sp;
+                st[kStMaxRate] = rt;
+                st[kStSumRate] = rt;
+                st[kStSumKin] = (float)(T(0.5) * ke);
+            } else {
+                st[kStNonFinite] = 1.0f;
+                st[kStMaxDrift] = 0.0f;
+                st[kStRenorm] = 0.0f;
+            }
+        } else {
+            st[kStRenorm] = 0.0f;
+            st[kStMaxDrift] = 0.0f;
+        }
+    }
+}
+
+}  // namespace mgx

@@ -1,0 +1,353 @@
+// Device kernels of the batched underwater-vehicle step (gfx950, wave64).
+//
+// Layout: structure-of-arrays per class segment, component-major, so that lane j of a
+// wavefront touches consecutive addresses for every component (coalesced 256-byte rows
+// per wave in float). One environment per lane; the state stays in VGPRs for all K steps
+// of a launch; per-class constants arrive as kernel arguments (scalar registers).
+#include <hip/hip_runtime.h>
+
+#include "env_loop.hpp"
+#include "kernels.hpp"
+
+namespace mgx {
+
+// ----------------------------------------------------------------------------- Philox4x32-10
+// Counter-based generator of Salmon et al. (SC'11): ten rounds of two 32x32->64-bit
+// multiplications by fixed odd constants, the high halves xored with the other counter
+// words and the round key; the key advances by two Weyl constants between rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+__device__ __forceinline__ double u53(uint32_t hi, uint32_t lo) {
+    return ((double)(hi >> 5) * 67108864.0 + (double)(lo >> 6)) * 0x1.0p-53;
+}
+
+constexpr uint32_t kStreamInit = 3u;
+constexpr uint32_t kStreamAction = 4u;
+
+// ----------------------------------------------------------------------------- setup (double)
+
+__global__ void k_class_setup(const ClassDesc64* in, ClassT<float>* outf, ClassT<double>* outd, int n, double dt,
+                              uint32_t flags) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const ClassDesc64& d = in[c];
+    ClassT<double> D;
+    int has_dz = 0;
+    for (int i = 0; i < kMaxThr; ++i) {
+        if (i < d.m) {
+            double len = sqrt(d.e[i][0] * d.e[i][0] + d.e[i][1] * d.e[i][1] + d.e[i][2] * d.e[i][2]);
+            double e[3] = {d.e[i][0] / len, d.e[i][1] / len, d.e[i][2] / len};
+            const double* r = d.r[i];
+            const double k = d.k[i];
+            D.Bk[0][i] = k * e[0];
+            D.Bk[1][i] = k * e[1];
+            D.Bk[2][i] = k * e[2];
+            D.Bk[3][i] = k * (r[1] * e[2] - r[2] * e[1]);
+            D.Bk[4][i] = k * (r[2] * e[0] - r[0] * e[2]);
+            D.Bk[5][i] = k * (r[0] * e[1] - r[1] * e[0]);
+            double tau = d.tau[i];
+            D.alpha[i] = tau > 0.0 ? ((flags & kFlagLagEuler) ? dt / tau : 1.0 - exp(-dt / tau)) : 1.0;
+            D.dz[i] = d.dz[i];
+            has_dz |= d.dz[i] > 0.0;
+        } else {
+            for (int j = 0; j < 6; ++j) D.Bk[j][i] = 0.0;
+            D.alpha[i] = 0.0;
+            D.dz[i] = 0.0;
+        }
+    }
+    for (int j = 0; j < 3; ++j) {
+        D.inertia[j] = d.inertia[j];
+        D.rb[j] = d.rb[j];
+    }
+    D.g0 = d.g0;
+    D.dt = dt;
+    D.inv_dt = 1.0 / dt;
+    D.half_dt = 0.5 * dt;
+    D.m = d.m;
+    D.flags = flags;
+    D.has_dz = has_dz;
+    D.pad2 = 0;
+    ClassT<float> F;
+    for (int i = 0; i < kMaxThr; ++i) {
+        for (int j = 0; j < 6; ++j) F.Bk[j][i] = (float)D.Bk[j][i];
+        F.alpha[i] = (float)D.alpha[i];
+        F.dz[i] = (float)D.dz[i];
+    }
+    for (int j = 0; j < 3; ++j) {
+        F.inertia[j] = (float)D.inertia[j];
+        F.rb[j] = (float)D.rb[j];
+    }
+    F.g0 = (float)D.g0;
+    F.dt = (float)D.dt;
+    F.inv_dt = (float)D.inv_dt;
+    F.half_dt = (float)D.half_dt;
+    F.m = D.m;
+    F.flags = flags;
+    F.has_dz = has_dz;
+    F.pad2 = 0;
+    outd[c] = D;
+    outf[c] = F;
+}
+
+// Per-environment record: dt M^-1 (M = M_RB + M_A, diagonal), mass, added mass, damping,
+// W - B, B, current; derived in double, rounded once.
+template <typename T>
+__global__ void k_env_setup(ParamPtrs p, int64_t env_off, int64_t n, int32_t npad, const ClassDesc64* cls,
+                            int ci, double dt, T* rec) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t g = env_off + i, N = p.n_total;
+    const ClassDesc64& c = cls[ci];
+    const double m = p.mass[g];
+    for (int j = 0; j < 6; ++j) {
+        const double A = p.added[j * N + g];
+        const double Mjj = (j < 3 ? m : c.inertia[j - 3]) + A;
+        rec[(kRecDtMinv + j) * (int64_t)npad + i] = (T)(dt / Mjj);
+        rec[(kRecAdded + j) * (int64_t)npad + i] = (T)A;
+        rec[(kRecDlin + j) * (int64_t)npad + i] = (T)p.dlin[j * N + g];
+        rec[(kRecDquad + j) * (int64_t)npad + i] = (T)p.dquad[j * N + g];
+    }
+    rec[kRecMass * (int64_t)npad + i] = (T)m;
+    rec[kRecWmB * (int64_t)npad + i] = (T)(m * c.g0 - p.buoy[g]);
+    rec[kRecBuoy * (int64_t)npad + i] = (T)p.buoy[g];
+    for (int j = 0; j < 3; ++j) rec[(kRecCurrent + j) * (int64_t)npad + i] = (T)p.current[j * N + g];
+}
+
+// Every slot of a segment to rest at the identity attitude; record zeroed (dt M^-1 = 0
+// keeps padded slots fixed).
+template <typename T>
+__global__ void k_init_padding(T* state, T* rec, int m, int32_t npad, int64_t first) {
+    int64_t i = first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npad) return;
+    for (int j = 0; j < kStateFixed + m; ++j) state[j * (int64_t)npad + i] = (T)(j == 3 ? 1 : 0);
+    for (int j = 0; j < kRecLen; ++j) rec[j * (int64_t)npad + i] = (T)0;
+}
+
+// ----------------------------------------------------------------------------- reset
+
+template <typename T>
+__global__ void k_reset_seeded(T* state, int m, int32_t npad, int64_t env_off, int64_t n_local, const int64_t* ids,
+                               int64_t n_ids, uint64_t seed) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_ids) return;
+    const int64_t e = ids ? ids[t] : t;
+    if (e < 0 || e >= n_local) return;
+    const uint64_t g = (uint64_t)(env_off + e);
+    double u[10];
+    for (int j = 0; j < 5; ++j) {
+        uint32_t c[4] = {(uint32_t)g, 0u, (uint32_t)j, 0u};
+        philox4x32_10(c, (uint32_t)seed, kStreamInit << 24);
+        u[2 * j] = u53(c[0], c[1]);
+        u[2 * j + 1] = u53(c[2], c[3]);
+    }
+    double z[10];
+    for (int j = 0; j < 5; ++j) {
+        double rad = sqrt(-2.0 * log(1.0 - u[2 * j]));
+        double ang = 2.0 * M_PI * u[2 * j + 1];
+        z[2 * j] = rad * cos(ang);
+        z[2 * j + 1] = rad * sin(ang);
+    }
+    double qn = sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2] + z[3] * z[3]);
+    const int64_t np = npad;
+    for (int j = 0; j < 3; ++j) state[j * np + e] = (T)0;
+    for (int j = 0; j < 4; ++j) state[(3 + j) * np + e] = (T)(z[j] / qn);
+    for (int j = 0; j < 6; ++j) state[(7 + j) * np + e] = (T)(0.2 * z[4 + j]);
+    for (int i = 0; i < m; ++i) state[(kStateFixed + i) * np + e] = (T)0;
+}
+
+template <typename T>
+__global__ void k_reset_copy(T* state, const T* tmpl, int m, int32_t npad, const int64_t* ids, int64_t n_ids) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_ids) return;
+    const int64_t e = ids ? ids[t] : t;
+    for (int j = 0; j < kStateFixed + m; ++j) state[j * (int64_t)npad + e] = tmpl[j * (int64_t)npad + e];
+}
+
+// ----------------------------------------------------------------------------- actions
+
+template <typename T>
+__global__ void k_gen_actions(T* out, int m, int32_t npad, int64_t n_valid, int64_t env_off, int64_t rows,
+                              int64_t row_stride, int64_t row_offset, uint64_t seed) {
+    const int64_t env = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t row = blockIdx.y;
+    if (env >= npad || row >= rows) return;
+    T* o = out + row * row_stride + env;
+    if (env >= n_valid) {
+        for (int i = 0; i < m; ++i) o[i * (int64_t)npad] = (T)0;
+        return;
+    }
+    const uint64_t g = (uint64_t)(env_off + env);
+    for (int b = 0; b < m; b += 4) {
+        uint32_t c[4] = {(uint32_t)g, (uint32_t)(row_offset + row), (uint32_t)(b / 4), 0u};
+        philox4x32_10(c, (uint32_t)seed, kStreamAction << 24);
+        for (int w = 0; w < 4 && b + w < m; ++w) {
+            const int32_t j = (int32_t)(c[w] >> 8) - (1 << 23);
+            o[(b + w) * (int64_t)npad] = (T)((float)j * 0x1.0p-23f);
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------- step
+
+// K steps of every environment of one class segment; state in registers throughout.
+template <typename T, int M, bool kOut>
+__global__ void __launch_bounds__(256) k_step(StepLaunch<T> L) {
+    const StepArgs& A = L.a;
+    const int tid = threadIdx.x;
+    const int64_t env = (int64_t)blockIdx.x * blockDim.x + tid;
+    const int64_t t0 = A.misc->t;
+    float st[kStats];
+#pragma unroll
+    for (int j = 0; j < kStats; ++j) st[j] = 0.0f;
+    if (env < A.npad) {
+        if (L.cls.has_dz)
+            env_steps<T, M, kOut, true>(A, L.cls, env, t0, A.K, st);
+        else
+            env_steps<T, M, kOut, false>(A, L.cls, env, t0, A.K, st);
+    }
+    __shared__ float red[256 / kWave][kStats];
+    __shared__ int is_last;
+    if (A.partials) {
+        block_reduce_stats(st, red, A.partials + (int64_t)blockIdx.x * kStats);
+        __threadfence();
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const unsigned prev = atomicAdd(&A.misc->done[A.class_index], 1u);
+        is_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (is_last) {
+        if (A.partials) {
+            __threadfence();
+            if (tid < kStats) final_reduce_stats(A.partials, gridDim.x, tid, A.stats);
+        }
+        if (tid == 0) {
+            atomicExch(&A.misc->done[A.class_index], 0u);
+            if (A.advance) atomicAdd((unsigned long long*)&A.misc->t, (unsigned long long)A.advance);
+        }
+    }
+}
+
+// Sets the device step counter (a kernel rather than a copy, so that it can sit inside a
+// captured graph and needs no host synchronisation).
+__global__ void k_set_counter(DevMisc* misc, int64_t t) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        atomicExch((unsigned long long*)&misc->t, (unsigned long long)t);
+    }
+}
+
+// ----------------------------------------------------------------------------- launchers
+
+hipError_t launch_set_counter(DevMisc* misc, int64_t t, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(64), 0, s, misc, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_class_setup(const ClassDesc64* d_in, ClassT<float>* d_f, ClassT<double>* d_d, int n, double dt,
+                              uint32_t flags, hipStream_t s) {
+    hipLaunchKernelGGL(k_class_setup, dim3((n + 63) / 64), dim3(64), 0, s, d_in, d_f, d_d, n, dt, flags);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_env_setup(ParamPtrs p, int64_t env_off, int64_t n, int32_t npad, const ClassDesc64* d_cls,
+                            int cls_index, double dt, T* rec_seg, hipStream_t s) {
+    hipLaunchKernelGGL(k_env_setup<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, env_off, n, npad,
+                       d_cls, cls_index, dt, rec_seg);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_init_padding(T* state_seg, T* rec_seg, int m, int32_t npad, int64_t first, hipStream_t s) {
+    const int64_t n = npad - first;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_init_padding<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, state_seg, rec_seg, m,
+                       npad, first);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_reset_seeded(T* state_seg, int m, int32_t npad, int64_t env_off, int64_t n_local,
+                               const int64_t* d_local_ids, int64_t n_ids, uint64_t seed, hipStream_t s) {
+    if (n_ids <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reset_seeded<T>, dim3((unsigned)((n_ids + 255) / 256)), dim3(256), 0, s, state_seg, m,
+                       npad, env_off, n_local, d_local_ids, n_ids, seed);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_reset_copy(T* state_seg, const T* tmpl_seg, int m, int32_t npad, const int64_t* d_local_ids,
+                             int64_t n_ids, hipStream_t s) {
+    if (n_ids <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reset_copy<T>, dim3((unsigned)((n_ids + 255) / 256)), dim3(256), 0, s, state_seg, tmpl_seg,
+                       m, npad, d_local_ids, n_ids);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gen_actions(T* out_seg, int m, int32_t npad, int64_t n_valid, int64_t env_off, int64_t rows,
+                              int64_t row_stride, int64_t row_offset, uint64_t seed, hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gen_actions<T>, dim3((unsigned)((npad + 255) / 256), (unsigned)rows), dim3(256), 0, s,
+                       out_seg, m, npad, n_valid, env_off, rows, row_stride, row_offset, seed);
+    return hipGetLastError();
+}
+
+#define MGX_STEP_CASE(MM)                                                                              \
+    case MM:                                                                                           \
+        if (out)                                                                                       \
+            hipLaunchKernelGGL((k_step<T, MM, true>), dim3(grid), dim3(block), 0, s, L);               \
+        else                                                                                           \
+            hipLaunchKernelGGL((k_step<T, MM, false>), dim3(grid), dim3(block), 0, s, L);              \
+        break;
+
+template <typename T>
+hipError_t launch_step(const StepLaunch<T>& L, int m, int block, hipStream_t s) {
+    const unsigned grid = (unsigned)((L.a.npad + block - 1) / block);
+    const bool out = L.a.traj != nullptr || L.a.forces != nullptr;
+    switch (m) {
+        MGX_STEP_CASE(1)
+        MGX_STEP_CASE(2)
+        MGX_STEP_CASE(3)
+        MGX_STEP_CASE(4)
+        MGX_STEP_CASE(5)
+        MGX_STEP_CASE(6)
+        MGX_STEP_CASE(7)
+        MGX_STEP_CASE(8)
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+#define MGX_INSTANTIATE(T)                                                                                          \
+    template hipError_t launch_env_setup<T>(ParamPtrs, int64_t, int64_t, int32_t, const ClassDesc64*, int, double,   \
+                                            T*, hipStream_t);                                                         \
+    template hipError_t launch_init_padding<T>(T*, T*, int, int32_t, int64_t, hipStream_t);                         \
+    template hipError_t launch_reset_seeded<T>(T*, int, int32_t, int64_t, int64_t, const int64_t*, int64_t, uint64_t, \
+                                               hipStream_t);                                                          \
+    template hipError_t launch_reset_copy<T>(T*, const T*, int, int32_t, const int64_t*, int64_t, hipStream_t);     \
+    template hipError_t launch_gen_actions<T>(T*, int, int32_t, int64_t, int64_t, int64_t, int64_t, int64_t,        \
+                                              uint64_t, hipStream_t);                                                 \
+    template hipError_t launch_step<T>(const StepLaunch<T>&, int, int, hipStream_t);
+
+MGX_INSTANTIATE(float)
+MGX_INSTANTIATE(double)
+
+}  // namespace mgx

@@ -1,0 +1,90 @@
+// Internal interface between the host runtime and the device kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "step.hpp"
+
+namespace mgx {
+
+constexpr int kStats = 8;  // per-class statistics slots
+enum StatSlot : int {
+    kStNonFinite = 0,
+    kStRenorm = 1,
+    kStMaxSpeed = 2,
+    kStSumSpeed = 3,
+    kStMaxRate = 4,
+    kStSumRate = 5,
+    kStSumKin = 6,
+    kStMaxDrift = 7
+};
+
+// Raw class description as given by the caller, double precision.
+struct ClassDesc64 {
+    int32_t m, pad;
+    double r[kMaxThr][3], e[kMaxThr][3], k[kMaxThr], tau[kMaxThr], dz[kMaxThr];
+    double inertia[3], rb[3], g0;
+};
+
+// Device bookkeeping of a batch: step counter, per-class completion counters, error word.
+struct DevMisc {
+    int64_t t;
+    int32_t err;
+    int32_t pad;
+    uint32_t done[16];
+};
+
+// Arguments of the step kernel for one class segment.
+struct StepArgs {
+    void* state;          // class segment base, [13+m][npad]
+    const void* rec;      // class segment base, [30][npad]
+    const void* actions;  // buffer base + class action offset; row r at actions + r*row_stride
+    int64_t row_stride, n_rows, row0;
+    int32_t hold, K;
+    int32_t npad, nvalid;
+    DevMisc* misc;
+    int32_t class_index;
+    int32_t advance;      // added to the step counter by the last block (0 for all but one launch)
+    void* traj;           // class segment base within step row 0, or null
+    int64_t traj_stride;  // elements per step row
+    void* forces;         // class segment base within step row 0, or null
+    int64_t force_stride;
+    float* partials;      // [gridDim.x][kStats] or null (no statistics)
+    double* stats;        // [kStats] of this class, written by the last block
+};
+
+template <typename T>
+struct StepLaunch {
+    StepArgs a;
+    ClassT<T> cls;
+};
+
+// Host-side launchers (kernels.hip).
+hipError_t launch_set_counter(DevMisc* misc, int64_t t, hipStream_t s);
+hipError_t launch_class_setup(const ClassDesc64* d_in, ClassT<float>* d_f, ClassT<double>* d_d, int n,
+                              double dt, uint32_t flags, hipStream_t s);
+// Per-environment parameter arrays (double, over the global env id, DOF-major rows).
+struct ParamPtrs {
+    const double *mass, *added, *dlin, *dquad, *buoy, *current;
+    int64_t n_total;
+};
+
+template <typename T>
+hipError_t launch_env_setup(ParamPtrs p, int64_t env_off, int64_t n, int32_t npad, const ClassDesc64* d_cls,
+                            int cls_index, double dt, T* rec_seg, hipStream_t s);
+template <typename T>
+hipError_t launch_reset_seeded(T* state_seg, int m, int32_t npad, int64_t env_off, int64_t n_local,
+                               const int64_t* d_local_ids, int64_t n_ids, uint64_t seed, hipStream_t s);
+template <typename T>
+hipError_t launch_reset_copy(T* state_seg, const T* tmpl_seg, int m, int32_t npad, const int64_t* d_local_ids,
+                             int64_t n_ids, hipStream_t s);
+template <typename T>
+hipError_t launch_init_padding(T* state_seg, T* rec_seg, int m, int32_t npad, int64_t nvalid, hipStream_t s);
+template <typename T>
+hipError_t launch_gen_actions(T* out_seg, int m, int32_t npad, int64_t n_valid, int64_t env_off, int64_t rows,
+                              int64_t row_stride, int64_t row_offset, uint64_t seed, hipStream_t s);
+template <typename T>
+hipError_t launch_step(const StepLaunch<T>& L, int m, int block, hipStream_t s);
+
+}  // namespace mgx

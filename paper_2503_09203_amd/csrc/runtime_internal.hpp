@@ -1,0 +1,90 @@
+// Host-side batch object shared by the runtime translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "mgx.h"
+
+namespace mgx {
+
+extern thread_local std::string g_err;
+extern thread_local int32_t g_hip_err;
+mgx_status fail(mgx_status s, const char* fmt, ...);
+
+// Makes `dev` current for the scope, restoring the previous device afterwards.
+class hipDevice_guard {
+   public:
+    explicit hipDevice_guard(int dev) {
+        e_ = hipGetDevice(&prev_);
+        if (e_ == hipSuccess && prev_ != dev) e_ = hipSetDevice(dev);
+        if (e_ != hipSuccess) prev_ = -1;
+    }
+    ~hipDevice_guard() {
+        int cur = -1;
+        if (prev_ >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev_) (void)hipSetDevice(prev_);
+    }
+    bool ok() const { return e_ == hipSuccess; }
+    hipError_t err() const { return e_; }
+
+   private:
+    int prev_ = -1;
+    hipError_t e_ = hipSuccess;
+};
+
+}  // namespace mgx
+
+struct mgx_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int prec = MGX_FP32;
+    double dt = 0.01;
+    uint32_t flags = 0;
+    int n_classes = 0;
+    std::vector<mgx_class_desc> cls;
+    int m[MGX_MAX_CLASSES] = {};
+    int64_t n[MGX_MAX_CLASSES] = {}, npad[MGX_MAX_CLASSES] = {}, env_off[MGX_MAX_CLASSES] = {},
+            pad_off[MGX_MAX_CLASSES] = {}, state_off[MGX_MAX_CLASSES] = {}, rec_off[MGX_MAX_CLASSES] = {},
+            act_off[MGX_MAX_CLASSES] = {}, force_off[MGX_MAX_CLASSES] = {}, part_off[MGX_MAX_CLASSES] = {};
+    int64_t n_total = 0, npad_total = 0, state_elems = 0, rec_elems = 0, row_elems = 0, force_row_elems = 0,
+            max_blocks = 0;
+
+    void* d_state = nullptr;
+    void* d_rec = nullptr;
+    mgx::DevMisc* d_misc = nullptr;
+    mgx::ClassDesc64* d_classdesc = nullptr;
+    mgx::ClassT<float>* d_class_f = nullptr;
+    mgx::ClassT<double>* d_class_d = nullptr;
+    float* d_partials = nullptr;
+    double* d_stats = nullptr;
+    int64_t* d_ids = nullptr;
+    double* d_param_stage = nullptr;
+    mgx::ClassT<float> h_class_f[MGX_MAX_CLASSES];
+    mgx::ClassT<double> h_class_d[MGX_MAX_CLASSES];
+
+    bool faulted = false;
+    bool params_set = false;
+    int64_t host_t = 0;
+    int64_t stats_step = 0;
+    int64_t h_t_stage = 0;
+    int block = 256;
+    int n_graphs = 0;  // live graphs captured from this batch
+
+    void* seg_state(int c) const { return (char*)d_state + (size_t)prec * state_off[c]; }
+    void* seg_rec(int c) const { return (char*)d_rec + (size_t)prec * rec_off[c]; }
+    int class_of(int64_t gid) const {
+        int c = 0;
+        while (c + 1 < n_classes && gid >= env_off[c + 1]) ++c;
+        return c;
+    }
+};
+
+namespace mgx {
+mgx_status hip_fail(mgx_batch* b, hipError_t e, const char* what);
+mgx_status enqueue_step(mgx_batch* b, const void* actions, int64_t n_rows, int64_t row0, int32_t hold, int32_t K,
+                        bool stats, void* traj, void* forces, int block);
+mgx_status validate_rows(const mgx_batch* b, int64_t t0, int64_t n_rows, int64_t row0, int32_t hold, int64_t K);
+}  // namespace mgx

@@ -1,0 +1,291 @@
+// One step of the batched underwater-vehicle dynamics for a single environment held in
+// registers. Templated on the arithmetic type T (float, double, or a host-side counting
+// type that measures the algorithmic cost) and on the thruster count M, so that the
+// thruster loops unroll and the per-environment state lives in VGPRs.
+//
+// Order of the step (MarineGym, arXiv 2503.09203: Sec. III-D for the rotor and thrust
+// models, Sec. III-B Eqs. (1)-(3) for the forces, the ocean-current substitution v_r):
+//   1. rotor lag        n+ = n + alpha (a - n)            (a already clipped to [-1, 1])
+//   2. thrust           f_i = k_i s_i |s_i|, s_i = sgn(n+_i) max(|n+_i| - delta_i, 0);
+//                       tau = B f, B columns [e_i ; r_i x e_i] (k_i folded into B at setup)
+//   3. kinematics       R(q); g_b = R^T e_z; v_c = R^T V_c; v_r = v - v_c
+//   4. forces           Coriolis of rigid body and added mass, damping, restoring, and
+//                       the added-mass term of the rotating current projection
+//   5. solve            nu+ = nu + (dt M^-1) F,  M = M_RB + M_A (diagonal here)
+//   6. pose             p+ = p + dt R v+;  q+ = q (x) exp(dt w+ / 2), renormalised
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+#include <type_traits>
+
+namespace mgx {
+
+constexpr int kMaxThr = 8;
+constexpr int kStateFixed = 13;
+constexpr int kRecLen = 30;
+constexpr int kForceLen = 12;
+constexpr int kWave = 64;
+
+// Per-environment record fields (component-major rows of the record buffer).
+enum RecField : int {
+    kRecDtMinv = 0,   // dt / M_jj, j < 6
+    kRecMass = 6,     // m
+    kRecAdded = 7,    // M_A diagonal, 6
+    kRecDlin = 13,    // 6
+    kRecDquad = 19,   // 6
+    kRecWmB = 25,     // W - B
+    kRecBuoy = 26,    // B
+    kRecCurrent = 27  // V_c world, 3
+};
+
+// Batch flags (mirror of the public header).
+constexpr uint32_t kFlagNoAmc = 1u;
+constexpr uint32_t kFlagLagEuler = 2u;
+
+// Per-class constants in the batch precision, derived in double on the device.
+template <typename T>
+struct ClassT {
+    T Bk[6][kMaxThr];  // thruster layout columns [e_i; r_i x e_i] scaled by the thrust gain k_i
+    T alpha[kMaxThr];  // lag factor
+    T dz[kMaxThr];     // dead zone
+    T inertia[3];
+    T rb[3];
+    T g0, dt, inv_dt, half_dt;
+    int32_t m;
+    uint32_t flags;    // batch flags
+    int32_t has_dz;    // any dead zone > 0
+    int32_t pad2;
+};
+
+template <typename T>
+struct EnvT {
+    T dtMinv[6];
+    T mass;
+    T A[6];
+    T dL[6];
+    T dQ[6];
+    T wmb;
+    T buoy;
+    T Vc[3];
+};
+
+template <typename T, int M>
+struct StateT {
+    T p[3];
+    T q[4];
+    T nu[6];
+    T n[M];
+};
+
+// ----------------------------------------------------------------------------- arithmetic
+
+__host__ __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__host__ __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__host__ __device__ __forceinline__ float abs_(float a) { return __builtin_fabsf(a); }
+__host__ __device__ __forceinline__ double abs_(double a) { return __builtin_fabs(a); }
+__host__ __device__ __forceinline__ float max_(float a, float b) { return __builtin_fmaxf(a, b); }
+__host__ __device__ __forceinline__ double max_(double a, double b) { return __builtin_fmax(a, b); }
+__host__ __device__ __forceinline__ float copysign_(float a, float b) { return __builtin_copysignf(a, b); }
+__host__ __device__ __forceinline__ double copysign_(double a, double b) { return __builtin_copysign(a, b); }
+__host__ __device__ __forceinline__ float sqrt_(float a) { return __builtin_sqrtf(a); }
+__host__ __device__ __forceinline__ double sqrt_(double a) { return __builtin_sqrt(a); }
+
+// Command clip to [-1, 1] that lets NaN through (a NaN command marks the env non-finite).
+template <typename T>
+__host__ __device__ __forceinline__ T clip1(T a) {
+    return a < T(-1) ? T(-1) : (a > T(1) ? T(1) : a);
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ void cross(const T a[3], const T b[3], T out[3]) {
+    out[0] = fma_(a[1], b[2], -(a[2] * b[1]));
+    out[1] = fma_(a[2], b[0], -(a[0] * b[2]));
+    out[2] = fma_(a[0], b[1], -(a[1] * b[0]));
+}
+
+// Unit-quaternion increment exp(h w) = (cos(phi), sin(phi) w/|w|), phi = h |w|.
+// float: even polynomials in phi^2 (truncation below 3e-11 for phi <= 0.05) with an
+// exact fallback above; double: the exact form.
+template <typename T>
+__host__ __device__ __forceinline__ void quat_increment(T h, const T w[3], T& c, T& s) {
+    T w2 = fma_(w[2], w[2], fma_(w[1], w[1], w[0] * w[0]));
+    if constexpr (std::is_same<T, double>::value) {
+        T wn = sqrt_(w2);
+        T phi = h * wn;
+        c = cos(phi);
+        s = wn > 0.0 ? sin(phi) / wn : h;
+    } else {
+        T phi2 = (h * h) * w2;
+        if (phi2 <= T(0.0025f)) {
+            c = fma_(fma_(phi2, T(1.0f / 24.0f), T(-0.5f)), phi2, T(1.0f));
+            s = h * fma_(fma_(phi2, T(1.0f / 120.0f), T(-1.0f / 6.0f)), phi2, T(1.0f));
+        } else {
+            T phi = sqrt_(phi2);
+            T sn, cs;
+            if constexpr (std::is_same<T, float>::value) {
+                sincosf(phi, &sn, &cs);
+            } else {
+                sn = sin(phi);
+                cs = cos(phi);
+            }
+            c = cs;
+            s = sn * h / phi;
+        }
+    }
+}
+
+// One step. `a` holds commands already clipped to [-1, 1]. IA2 = I + A_2 and Brb = B r_b
+// are per-environment constants hoisted out of the step loop by the caller. `forces`
+// (optional, 12 values) receives the actuator wrench and the hydrodynamic wrench of
+// Eq. (3) with d(nu)/dt the solved acceleration.
+template <typename T, int M, bool kForces = false, bool kDeadZone = false>
+__host__ __device__ __forceinline__ void step_body(const ClassT<T>& C, const EnvT<T>& E, const T IA2[3],
+                                                   const T Brb[3], StateT<T, M>& s, const T a[M],
+                                                   T* forces = nullptr) {
+    // 1. rotor lag (first-order hold; alpha = 1 is the zero-order rotor)
+    T nl[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) nl[i] = fma_(C.alpha[i], a[i] - s.n[i], s.n[i]);
+
+    // 2. thrust and thruster layout
+    T tau[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        T f;  // thrust divided by the gain k_i (folded into Bk)
+        if constexpr (kDeadZone) {
+            T mag = max_(abs_(nl[i]) - C.dz[i], T(0));
+            f = copysign_(mag * mag, nl[i]);
+        } else {
+            f = nl[i] * abs_(nl[i]);
+        }
+#pragma unroll
+        for (int j = 0; j < 6; ++j) tau[j] = fma_(C.Bk[j][i], f, tau[j]);
+    }
+
+    // 3. kinematics
+    const T qw = s.q[0], qx = s.q[1], qy = s.q[2], qz = s.q[3];
+    const T x2 = qx + qx, y2 = qy + qy, z2 = qz + qz;
+    const T xx = qx * x2, yy = qy * y2, zz = qz * z2;
+    const T xy = qx * y2, xz = qx * z2, yz = qy * z2;
+    const T wx = qw * x2, wy = qw * y2, wz = qw * z2;
+    T R[3][3];
+    R[0][0] = T(1) - (yy + zz);
+    R[0][1] = xy - wz;
+    R[0][2] = xz + wy;
+    R[1][0] = xy + wz;
+    R[1][1] = T(1) - (xx + zz);
+    R[1][2] = yz - wx;
+    R[2][0] = xz - wy;
+    R[2][1] = yz + wx;
+    R[2][2] = T(1) - (xx + yy);
+    const T gb[3] = {R[2][0], R[2][1], R[2][2]};
+    T vc[3], vr[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        vc[j] = fma_(R[2][j], E.Vc[2], fma_(R[1][j], E.Vc[1], R[0][j] * E.Vc[0]));
+        vr[j] = s.nu[j] - vc[j];
+    }
+    const T* v = s.nu;
+    const T* w = s.nu + 3;
+
+    // 4. forces
+    // Coriolis, linear rows: m w x v + w x (A1 v_r) = w x (m v + A1 v_r)
+    T A1vr[3], P[3], L[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        A1vr[j] = E.A[j] * vr[j];
+        P[j] = fma_(E.mass, v[j], A1vr[j]);
+        L[j] = IA2[j] * w[j];
+    }
+    T cor_lin[3], cor_ang[3], t1[3];
+    cross(w, P, cor_lin);
+    // angular rows: w x (I w) + w x (A2 w) + v_r x (A1 v_r) = w x ((I + A2) w) + v_r x (A1 v_r)
+    cross(w, L, cor_ang);
+    cross(vr, A1vr, t1);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) cor_ang[j] = cor_ang[j] + t1[j];
+    // added-mass term of the rotating current projection: A1 (w x v_c)
+    T hA[3] = {T(0), T(0), T(0)};
+    if (!(C.flags & kFlagNoAmc)) {
+        T wvc[3];
+        cross(w, vc, wvc);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) hA[j] = E.A[j] * wvc[j];
+    }
+    // damping on nu_r = (v_r, w)
+    T damp[6];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        damp[j] = fma_(E.dQ[j], abs_(vr[j]), E.dL[j]) * vr[j];
+        damp[3 + j] = fma_(E.dQ[3 + j], abs_(w[j]), E.dL[3 + j]) * w[j];
+    }
+    // restoring: linear -(W - B) g_b, angular B r_b x g_b (moved to the right-hand side)
+    T rmom[3];
+    cross(Brb, gb, rmom);
+    T F[6];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        F[j] = fma_(E.wmb, gb[j], tau[j] - cor_lin[j] - damp[j] - hA[j]);
+        F[3 + j] = tau[3 + j] - cor_ang[j] - damp[3 + j] - rmom[j];
+    }
+
+    // 5. acceleration solve (diagonal M)
+    T dnu[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) dnu[j] = E.dtMinv[j] * F[j];
+
+    if constexpr (kForces) {  // evaluated with the step-start velocity
+        // hydrodynamic wrench -M_A d(nu)/dt - C_A nu_r - D nu_r - g_A - (A1 (w x v_c); 0)
+        T cal[3], caa[3], A2w[3], t2[3];
+        cross(w, A1vr, cal);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) A2w[j] = E.A[3 + j] * w[j];
+        cross(w, A2w, t2);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) caa[j] = t1[j] + t2[j];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) forces[j] = tau[j];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            forces[6 + j] = -(E.A[j] * dnu[j] * C.inv_dt) - hA[j] - cal[j] - damp[j] - E.buoy * gb[j];
+            forces[9 + j] = -(E.A[3 + j] * dnu[3 + j] * C.inv_dt) - caa[j] - damp[3 + j] - rmom[j];
+        }
+    }
+
+    // velocity update
+#pragma unroll
+    for (int j = 0; j < 6; ++j) s.nu[j] = s.nu[j] + dnu[j];
+
+    // 6. pose: position with the updated velocity and the step-start attitude
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        T rv = fma_(R[j][2], s.nu[2], fma_(R[j][1], s.nu[1], R[j][0] * s.nu[0]));
+        s.p[j] = fma_(C.dt, rv, s.p[j]);
+    }
+    // attitude: body-frame increment on the right
+    T c, sh;
+    quat_increment(C.half_dt, s.nu + 3, c, sh);
+    const T dx = sh * s.nu[3], dy = sh * s.nu[4], dz = sh * s.nu[5];
+    T nq0 = fma_(qw, c, -fma_(qx, dx, fma_(qy, dy, qz * dz)));
+    T nq1 = fma_(qw, dx, fma_(qx, c, fma_(qy, dz, -(qz * dy))));
+    T nq2 = fma_(qw, dy, fma_(qy, c, fma_(qz, dx, -(qx * dz))));
+    T nq3 = fma_(qw, dz, fma_(qz, c, fma_(qx, dy, -(qy * dx))));
+    T n2 = fma_(nq3, nq3, fma_(nq2, nq2, fma_(nq1, nq1, nq0 * nq0)));
+    T g;
+    if constexpr (std::is_same<T, double>::value) {
+        g = 1.0 / sqrt_(n2);
+    } else {
+        g = fma_(T(-0.5f), n2, T(1.5f));  // one Newton step toward 1/|q|
+    }
+    s.q[0] = nq0 * g;
+    s.q[1] = nq1 * g;
+    s.q[2] = nq2 * g;
+    s.q[3] = nq3 * g;
+#pragma unroll
+    for (int i = 0; i < M; ++i) s.n[i] = nl[i];
+}
+
+}  // namespace mgx

@@ -1,0 +1,461 @@
+"""ctypes binding of the mgx C ABI (include/mgx.h).
+
+Argument marshalling only: every computation happens in libmgx.so's HIP kernels. The
+functions keep the C names; ``Batch`` is a small convenience wrapper that owns a batch
+handle and passes torch tensors as device pointers with torch's current HIP stream.
+The binding raises if the library is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmgx.so")
+
+MGX_OK = 0
+MGX_E_INVALID = -1
+MGX_E_NOMEM = -2
+MGX_E_DEVICE = -3
+MGX_E_NONFINITE = -5
+MGX_E_BUDGET = -6
+MGX_E_STATE = -7
+
+MAX_THRUSTERS = 8
+MAX_CLASSES = 16
+STATE_FIXED = 13
+FORCE_LEN = 12
+FP32 = 4
+FP64 = 8
+FLAG_NO_AMC = 1
+FLAG_LAG_EULER = 2
+STEP_UNFUSED = 1
+STEP_STATS = 2
+
+
+class MgxError(RuntimeError):
+    def __init__(self, status, where, detail):
+        super().__init__(f"{where}: {detail} (status {status})")
+        self.status = status
+
+
+class ClassDesc(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("r", (ctypes.c_double * 3) * MAX_THRUSTERS), ("e", (ctypes.c_double * 3) * MAX_THRUSTERS),
+                ("k", ctypes.c_double * MAX_THRUSTERS), ("tau", ctypes.c_double * MAX_THRUSTERS),
+                ("deadzone", ctypes.c_double * MAX_THRUSTERS), ("inertia", ctypes.c_double * 3),
+                ("rb", ctypes.c_double * 3), ("g0", ctypes.c_double)]
+
+
+class BatchDesc(ctypes.Structure):
+    _fields_ = [("n_classes", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("class_ids", ctypes.POINTER(ctypes.c_int32)), ("n_envs", ctypes.POINTER(ctypes.c_int64)),
+                ("dt", ctypes.c_double), ("flags", ctypes.c_uint32), ("device", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("n_classes", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("n_total", ctypes.c_int64), ("n_pad_total", ctypes.c_int64),
+                ("state_elems", ctypes.c_int64), ("row_elems", ctypes.c_int64),
+                ("force_row_elems", ctypes.c_int64),
+                ("m", ctypes.c_int32 * MAX_CLASSES), ("n", ctypes.c_int64 * MAX_CLASSES),
+                ("n_pad", ctypes.c_int64 * MAX_CLASSES), ("env_off", ctypes.c_int64 * MAX_CLASSES),
+                ("state_off", ctypes.c_int64 * MAX_CLASSES), ("action_off", ctypes.c_int64 * MAX_CLASSES),
+                ("force_off", ctypes.c_int64 * MAX_CLASSES)]
+
+
+class EnvParams(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("mass", "added", "dlin", "dquad", "buoy", "current")]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("n_nonfinite", ctypes.c_int64 * MAX_CLASSES),
+                ("n_renorm64", ctypes.c_int64 * MAX_CLASSES),
+                ("max_speed", ctypes.c_double * MAX_CLASSES), ("mean_speed", ctypes.c_double * MAX_CLASSES),
+                ("max_rate", ctypes.c_double * MAX_CLASSES), ("mean_rate", ctypes.c_double * MAX_CLASSES),
+                ("mean_kinetic", ctypes.c_double * MAX_CLASSES), ("max_qdrift", ctypes.c_double * MAX_CLASSES)]
+
+
+P = ctypes.c_void_p
+I32, I64, U32, U64, F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "mgx_status_string": (ctypes.c_char_p, [I32]),
+    "mgx_last_error": (ctypes.c_size_t, [ctypes.c_char_p, ctypes.c_size_t]),
+    "mgx_last_hip_error": (I32, []),
+    "mgx_version": (I32, []),
+    "mgx_device_count": (I32, [ctypes.POINTER(I32)]),
+    "mgx_step_cost": (I32, [I32, U32, ctypes.POINTER(F64), ctypes.POINTER(F64)]),
+    "mgx_class_define": (I32, [ctypes.POINTER(ClassDesc), ctypes.POINTER(I32)]),
+    "mgx_batch_create": (I32, [ctypes.POINTER(BatchDesc), ctypes.POINTER(P)]),
+    "mgx_batch_destroy": (I32, [P]),
+    "mgx_batch_layout": (I32, [P, ctypes.POINTER(Layout)]),
+    "mgx_batch_set_params": (I32, [P, ctypes.POINTER(EnvParams), I32]),
+    "mgx_batch_reset": (I32, [P, P, I64, P, U64]),
+    "mgx_batch_step": (I32, [P, P, I64, I64, I32, I32, U32, P, P]),
+    "mgx_batch_get_step": (I32, [P, ctypes.POINTER(I64)]),
+    "mgx_batch_set_step": (I32, [P, I64]),
+    "mgx_batch_get_state": (I32, [P, P, I32]),
+    "mgx_batch_set_state": (I32, [P, P, I32]),
+    "mgx_batch_get_stats": (I32, [P, ctypes.POINTER(Stats)]),
+    "mgx_batch_check": (I32, [P, ctypes.POINTER(I64)]),
+    "mgx_batch_sync": (I32, [P]),
+    "mgx_gen_actions": (I32, [P, P, I64, I64, U64]),
+    "mgx_graph_capture": (I32, [P, P, I64, I64, I32, I32, I32, U32, ctypes.POINTER(P)]),
+    "mgx_graph_replay": (I32, [P]),
+    "mgx_graph_destroy": (I32, [P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libmgx.so (built in-tree by ``build()``); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2503_09203_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    buf = ctypes.create_string_buffer(1024)
+    lib().mgx_last_error(buf, 1024)
+    return buf.value.decode(errors="replace")
+
+
+def check(status, where):
+    if status != MGX_OK:
+        raise MgxError(status, where, last_error())
+    return status
+
+
+def _call(name, *args):
+    return check(getattr(lib(), name)(*args), name)
+
+
+# ----------------------------------------------------------------------------- C names
+
+def mgx_version():
+    return lib().mgx_version()
+
+
+def mgx_device_count():
+    n = I32()
+    _call("mgx_device_count", ctypes.byref(n))
+    return n.value
+
+
+def mgx_step_cost(m, flags=0):
+    f, o = F64(), F64()
+    _call("mgx_step_cost", int(m), int(flags), ctypes.byref(f), ctypes.byref(o))
+    return f.value, o.value
+
+
+def mgx_class_define(cls) -> int:
+    """Register a vehicle class given any object with m, r, e, k, tau, deadzone,
+    inertia, rb, g0 attributes (e.g. a ``synth.VehicleClass``)."""
+    d = ClassDesc()
+    d.m = int(cls.m)
+    for i in range(cls.m):
+        for j in range(3):
+            d.r[i][j] = float(cls.r[i][j])
+            d.e[i][j] = float(cls.e[i][j])
+        d.k[i] = float(cls.k[i])
+        d.tau[i] = float(cls.tau[i])
+        d.deadzone[i] = float(cls.deadzone[i])
+    for j in range(3):
+        d.inertia[j] = float(cls.inertia[j])
+        d.rb[j] = float(cls.rb[j])
+    d.g0 = float(cls.g0)
+    cid = I32()
+    _call("mgx_class_define", ctypes.byref(d), ctypes.byref(cid))
+    return cid.value
+
+
+def mgx_batch_create(class_ids, n_envs, dt, precision=FP32, flags=0, device=-1, stream=0):
+    n = len(class_ids)
+    ids = (I32 * n)(*class_ids)
+    ns = (I64 * n)(*n_envs)
+    d = BatchDesc(n, precision, ids, ns, float(dt), int(flags), int(device), ctypes.c_void_p(int(stream)))
+    h = P()
+    _call("mgx_batch_create", ctypes.byref(d), ctypes.byref(h))
+    return h
+
+
+def mgx_batch_destroy(h):
+    _call("mgx_batch_destroy", h)
+
+
+def mgx_batch_layout(h) -> Layout:
+    L = Layout()
+    _call("mgx_batch_layout", h, ctypes.byref(L))
+    return L
+
+
+def mgx_batch_set_params(h, ptrs: dict, on_device: int):
+    p = EnvParams(*(ctypes.c_void_p(int(ptrs[k])) for k in ("mass", "added", "dlin", "dquad", "buoy", "current")))
+    _call("mgx_batch_set_params", h, ctypes.byref(p), int(on_device))
+
+
+def mgx_batch_reset(h, env_ids_ptr, n, init_state_ptr, seed):
+    _call("mgx_batch_reset", h, env_ids_ptr, int(n), init_state_ptr, int(seed))
+
+
+def mgx_batch_step(h, actions_ptr, n_rows, row0, hold, K, flags=0, traj_ptr=None, forces_ptr=None):
+    _call("mgx_batch_step", h, actions_ptr, int(n_rows), int(row0), int(hold), int(K), int(flags),
+          traj_ptr, forces_ptr)
+
+
+def mgx_batch_get_step(h):
+    t = I64()
+    _call("mgx_batch_get_step", h, ctypes.byref(t))
+    return t.value
+
+
+def mgx_batch_set_step(h, t):
+    _call("mgx_batch_set_step", h, int(t))
+
+
+def mgx_batch_get_state(h, out_ptr, to_host):
+    _call("mgx_batch_get_state", h, out_ptr, int(to_host))
+
+
+def mgx_batch_set_state(h, in_ptr, from_host):
+    _call("mgx_batch_set_state", h, in_ptr, int(from_host))
+
+
+def mgx_batch_get_stats(h) -> Stats:
+    s = Stats()
+    _call("mgx_batch_get_stats", h, ctypes.byref(s))
+    return s
+
+
+def mgx_batch_check(h):
+    """Returns (status, n_nonfinite) without raising on MGX_E_NONFINITE / MGX_E_INVALID."""
+    n = I64()
+    st = lib().mgx_batch_check(h, ctypes.byref(n))
+    if st not in (MGX_OK, MGX_E_NONFINITE, MGX_E_INVALID):
+        check(st, "mgx_batch_check")
+    return st, n.value
+
+
+def mgx_batch_sync(h):
+    _call("mgx_batch_sync", h)
+
+
+def mgx_gen_actions(h, out_ptr, rows, row_offset, seed):
+    _call("mgx_gen_actions", h, out_ptr, int(rows), int(row_offset), int(seed))
+
+
+def mgx_graph_capture(h, actions_ptr, n_rows, row0, hold, n_steps, K, flags=0):
+    g = P()
+    _call("mgx_graph_capture", h, actions_ptr, int(n_rows), int(row0), int(hold), int(n_steps), int(K), int(flags),
+          ctypes.byref(g))
+    return g
+
+
+def mgx_graph_replay(g):
+    _call("mgx_graph_replay", g)
+
+
+def mgx_graph_destroy(g):
+    _call("mgx_graph_destroy", g)
+
+
+# ----------------------------------------------------------------------------- wrapper
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Batch:
+    """Owns one batch. Device buffers are torch tensors on the batch's device; every call
+    goes to the library on torch's current stream at creation (or the one given)."""
+
+    def __init__(self, classes, n_envs, dt=0.01, precision=FP32, flags=0, device=0, stream=None):
+        torch = _torch()
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        self.class_ids = [mgx_class_define(c) for c in classes]
+        self.precision = precision
+        self.dtype = torch.float32 if precision == FP32 else torch.float64
+        self.h = mgx_batch_create(self.class_ids, list(n_envs), dt, precision, flags, device,
+                                  stream.cuda_stream)
+        self.layout = mgx_batch_layout(self.h)
+        self.m = [self.layout.m[c] for c in range(len(classes))]
+        self.n = [self.layout.n[c] for c in range(len(classes))]
+        self.n_pad = [self.layout.n_pad[c] for c in range(len(classes))]
+
+    # -- lifetime
+    def close(self):
+        for g in list(getattr(self, "_graphs", [])):
+            g.close()
+        if getattr(self, "h", None):
+            mgx_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- buffers
+    def empty_state(self):
+        return _torch().zeros(self.layout.state_elems, dtype=self.dtype, device=self.device)
+
+    def empty_actions(self, rows):
+        return _torch().zeros((rows, self.layout.row_elems), dtype=self.dtype, device=self.device)
+
+    # -- calls
+    def set_params(self, params, on_device=True):
+        """``params``: object with mass[N], added[6,N], dlin[6,N], dquad[6,N], buoy[N],
+        current[3,N] (numpy, float64)."""
+        torch = _torch()
+        names = ("mass", "added", "dlin", "dquad", "buoy", "current")
+        if on_device:
+            self._param_tensors = {k: torch.as_tensor(np.ascontiguousarray(getattr(params, k), dtype=np.float64),
+                                                      device=self.device) for k in names}
+            ptrs = {k: v.data_ptr() for k, v in self._param_tensors.items()}
+            mgx_batch_set_params(self.h, ptrs, 1)
+        else:
+            arrs = {k: np.ascontiguousarray(getattr(params, k), dtype=np.float64) for k in names}
+            mgx_batch_set_params(self.h, {k: v.ctypes.data for k, v in arrs.items()}, 0)
+
+    def reset(self, env_ids=None, init_state=None, seed=0):
+        ids = None
+        n = 0
+        if env_ids is not None:
+            ids = np.ascontiguousarray(env_ids, dtype=np.int64)
+            n = len(ids)
+        mgx_batch_reset(self.h, None if ids is None else ids.ctypes.data_as(ctypes.c_void_p), n,
+                        _ptr(init_state), seed)
+
+    def step(self, actions, K, hold=1, row0=0, flags=0, traj=None, forces=None):
+        mgx_batch_step(self.h, _ptr(actions), actions.shape[0], row0, hold, K, flags, _ptr(traj), _ptr(forces))
+
+    def get_state(self):
+        out = self.empty_state()
+        mgx_batch_get_state(self.h, _ptr(out), 0)
+        return out
+
+    def set_state(self, t):
+        assert t.numel() == self.layout.state_elems and t.dtype == self.dtype and t.is_contiguous()
+        mgx_batch_set_state(self.h, _ptr(t), 0)
+
+    def gen_actions(self, rows, row_offset=0, seed=0):
+        out = self.empty_actions(rows)
+        mgx_gen_actions(self.h, _ptr(out), rows, row_offset, seed)
+        return out
+
+    def capture(self, actions, n_steps, K, hold=1, row0=0, flags=0):
+        """A replayable chunk of n_steps (launches of K steps); see ``Graph``."""
+        g = Graph(self, actions, n_steps, K, hold, row0, flags)
+        self.__dict__.setdefault("_graphs", []).append(g)
+        return g
+
+    def stats(self):
+        return mgx_batch_get_stats(self.h)
+
+    def check(self):
+        return mgx_batch_check(self.h)
+
+    def sync(self):
+        mgx_batch_sync(self.h)
+
+    @property
+    def t(self):
+        return mgx_batch_get_step(self.h)
+
+    @t.setter
+    def t(self, v):
+        mgx_batch_set_step(self.h, v)
+
+    # -- layout helpers (host side, numpy)
+    def pack_state(self, states):
+        """List of per-class stacked state arrays [13+m, n] -> flat layout array."""
+        out = np.zeros(self.layout.state_elems)
+        for c, s in enumerate(states):
+            off, np_, m = self.layout.state_off[c], self.n_pad[c], self.m[c]
+            seg = out[off:off + (STATE_FIXED + m) * np_].reshape(STATE_FIXED + m, np_)
+            seg[:, :s.shape[1]] = s
+            seg[3, s.shape[1]:] = 1.0
+        return out
+
+    def unpack_state(self, flat):
+        """Flat layout -> list of per-class [13+m, n]."""
+        out = []
+        for c in range(len(self.m)):
+            off, np_, m, n = self.layout.state_off[c], self.n_pad[c], self.m[c], self.n[c]
+            out.append(flat[off:off + (STATE_FIXED + m) * np_].reshape(STATE_FIXED + m, np_)[:, :n])
+        return out
+
+    def pack_actions(self, per_class):
+        """List of per-class [rows, m, n] -> [rows, row_elems]."""
+        rows = per_class[0].shape[0]
+        out = np.zeros((rows, self.layout.row_elems))
+        for c, a in enumerate(per_class):
+            off, np_, m = self.layout.action_off[c], self.n_pad[c], self.m[c]
+            out[:, off:off + m * np_].reshape(rows, m, np_)[:, :, :a.shape[2]] = a
+        return out
+
+    def unpack_actions(self, flat):
+        out = []
+        for c in range(len(self.m)):
+            off, np_, m, n = self.layout.action_off[c], self.n_pad[c], self.m[c], self.n[c]
+            out.append(flat[:, off:off + m * np_].reshape(flat.shape[0], m, np_)[:, :, :n])
+        return out
+
+    def unpack_forces(self, flat):
+        """[K, force_row_elems] -> list of per-class [K, 12, n]."""
+        out = []
+        for c in range(len(self.m)):
+            off = int(self.layout.force_off[c])
+            np_, n = self.n_pad[c], self.n[c]
+            out.append(flat[:, off:off + FORCE_LEN * np_].reshape(flat.shape[0], FORCE_LEN, np_)[:, :, :n])
+        return out
+
+
+class Graph:
+    """A captured chunk of step launches; ``replay()`` advances its batch by n_steps."""
+
+    def __init__(self, batch, actions, n_steps, K, hold=1, row0=0, flags=0):
+        self.batch = batch
+        self.actions = actions  # keep the buffer alive as long as the graph
+        self.n_steps = n_steps
+        self.g = mgx_graph_capture(batch.h, _ptr(actions), actions.shape[0], row0, hold, n_steps, K, flags)
+
+    def replay(self):
+        mgx_graph_replay(self.g)
+
+    def close(self):
+        if getattr(self, "g", None):
+            mgx_graph_destroy(self.g)
+            self.g = None
+            gs = self.batch.__dict__.get("_graphs", [])
+            if self in gs:
+                gs.remove(self)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,95 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports every
+declared symbol, validates arguments and reports a missing device as an error."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2503_09203_amd import mgx
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(mgx_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    L = mgx.lib()
+    names = declared_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    assert set(declared_functions()) <= set(mgx.SIGNATURES)
+
+
+def test_version_and_status_strings():
+    assert mgx.mgx_version() >= 100
+    assert mgx.lib().mgx_status_string(mgx.MGX_E_INVALID) == b"invalid argument"
+
+
+def test_step_cost_counts():
+    f6, o6 = mgx.mgx_step_cost(6)
+    f8, o8 = mgx.mgx_step_cost(8)
+    assert 250 < f6 < 500 and 150 < o6 < 350
+    # each extra thruster: lag (1 sub + 1 fma), thrust (1 mul), six fused multiply-adds
+    assert f8 - f6 == 2 * (1 + 2 + 1 + 12)
+    with pytest.raises(mgx.MgxError):
+        mgx.mgx_step_cost(9)
+
+
+def test_class_validation():
+    c = synth.plain_class()
+    cid = mgx.mgx_class_define(c)
+    assert cid >= 0
+    bad = synth.plain_class()
+    bad.k = bad.k.copy()
+    bad.k[0] = -1.0
+    with pytest.raises(mgx.MgxError) as e:
+        mgx.mgx_class_define(bad)
+    assert e.value.status == mgx.MGX_E_INVALID and "k must be > 0" in str(e.value)
+    bad = synth.plain_class()
+    bad.e = bad.e.copy()
+    bad.e[2] = 0.0
+    with pytest.raises(mgx.MgxError):
+        mgx.mgx_class_define(bad)
+
+
+def test_batch_create_validates_before_touching_a_device():
+    cid = mgx.mgx_class_define(synth.plain_class())
+    with pytest.raises(mgx.MgxError) as e:
+        mgx.mgx_batch_create([cid], [0], 0.01)
+    assert e.value.status == mgx.MGX_E_INVALID
+    with pytest.raises(mgx.MgxError) as e:
+        mgx.mgx_batch_create([cid], [10], -1.0)
+    assert e.value.status == mgx.MGX_E_INVALID
+    with pytest.raises(mgx.MgxError) as e:
+        mgx.mgx_batch_create([12345], [10], 0.01)
+    assert e.value.status == mgx.MGX_E_INVALID
+
+
+def test_batch_create_without_gpu_is_a_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    cid = mgx.mgx_class_define(synth.plain_class())
+    with pytest.raises(mgx.MgxError) as e:
+        mgx.mgx_batch_create([cid], [10], 0.01)
+    assert e.value.status == mgx.MGX_E_DEVICE
+
+
+def test_null_batch_calls_are_rejected():
+    L = mgx.lib()
+    assert L.mgx_batch_step(None, None, 1, 0, 1, 1, 0, None, None) == mgx.MGX_E_INVALID
+    assert L.mgx_batch_destroy(None) == mgx.MGX_OK

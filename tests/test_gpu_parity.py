@@ -1,0 +1,271 @@
+"""Device path (through the C ABI) against the FP64 oracle, element by element, on the
+same seeded inputs. Bars: float32 per-component relative error (metric in
+``parity.component_errors``) <= 1e-5 after one step and <= 1e-3 after 1000 steps;
+float64 batches <= 1e-9; integer/bit outputs exact."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2503_09203_amd import mgx
+
+from gpu_helpers import device_actions, make_batch, oracle_inputs, run_pair, torch
+from parity import component_errors, geodesic
+
+pytestmark = pytest.mark.gpu
+
+TOL = {1: 1e-5, 10: 1e-4, 100: 5e-4, 1000: 1e-3}
+
+
+def check(results, tol, label):
+    worst = {}
+    for k, pairs in results:
+        for c, (g, r) in enumerate(pairs):
+            err = component_errors(g, r)
+            worst[(k, c)] = float(err.max())
+            bar = tol[k] if isinstance(tol, dict) else tol
+            assert np.all(err <= bar), f"{label} step {k} class {c}: errors {err} (bar {bar})"
+            assert np.all(np.isfinite(g))
+    print(label, {f"k{k}c{c}": f"{v:.2e}" for (k, c), v in worst.items()}, flush=True)
+    return worst
+
+
+def test_plain_small_fp32():
+    w = synth.plain_small()
+    acts = w.actions(100)
+    res = run_pair(w, acts, 10, [1, 10, 100, 1000])
+    check(res, TOL, "plain fp32")
+    k, pairs = res[-1]
+    ang = geodesic(pairs[0][0][3:7], pairs[0][1][3:7])
+    assert ang.max() < 1e-3
+
+
+def test_plain_small_fp64():
+    w = synth.plain_small()
+    res = run_pair(w, w.actions(100), 10, [1, 10, 100, 1000], precision=mgx.FP64)
+    check(res, 1e-9, "plain fp64")
+
+
+def test_randomised_with_current_fp32():
+    w = synth.randomised(n=4096)
+    res = run_pair(w, w.actions(100), 10, [1, 10, 100, 1000], chunk=16)
+    check(res, TOL, "dr fp32")
+
+
+def test_randomised_full_size_sampled():
+    """65,536 environments in the benchmark's launch configuration (16-step launches);
+    512 sampled environments checked against the oracle."""
+    w = synth.randomised()
+    rng = np.random.default_rng(0)
+    s = np.sort(rng.choice(w.n_total, 512, replace=False))
+    s[0], s[-1] = 0, w.n_total - 1
+    res = run_pair(w, w.actions(100), 10, [1, 1000], sample=[s], chunk=16)
+    check(res, {1: 1e-5, 1000: 1e-3}, "dr65536 sampled")
+
+
+def test_heterogeneous_small_ragged():
+    w = synth.heterogeneous(scale=0.05)
+    assert any(n % 64 for n in w.n_envs)
+    res = run_pair(w, w.actions(20), 10, [1, 50, 200], chunk=32)
+    check(res, {1: 1e-5, 50: 2e-4, 200: 1e-3}, "hetero")
+
+
+@pytest.mark.parametrize("n", [1, 65, 130])
+def test_ragged_sizes(n):
+    w = synth.randomised(n=n, steps=100)
+    res = run_pair(w, w.actions(30), 10, [1, 100])
+    check(res, {1: 1e-5, 100: 5e-4}, f"ragged{n}")
+
+
+def _variant_workload(n=256):
+    w = synth.randomised(n=n, steps=200)
+    c = w.classes[0]
+    c.tau = c.tau.copy()
+    c.tau[0] = 0.0                  # one zero-order rotor
+    c.deadzone = np.zeros(c.m)
+    c.deadzone[1] = 0.15            # one rotor with a dead zone
+    return w
+
+
+@pytest.mark.parametrize("flags", [0, mgx.FLAG_NO_AMC, mgx.FLAG_LAG_EULER])
+def test_actuator_and_model_variants(flags):
+    w = _variant_workload()
+    res = run_pair(w, w.actions(30), 7, [1, 200], flags=flags)
+    check(res, {1: 1e-5, 200: 1e-3}, f"variant{flags}")
+
+
+def test_fused_and_unfused_agree_bitwise():
+    w = synth.randomised(n=2048, steps=64)
+    t = torch()
+    acts = w.actions(10)
+    outs = []
+    for mode in ("unfused", "fused16", "fused64"):
+        b = make_batch(w)
+        a = device_actions(b, acts)
+        if mode == "unfused":
+            b.step(a, 64, hold=10, flags=mgx.STEP_UNFUSED)
+        elif mode == "fused16":
+            for _ in range(4):
+                b.step(a, 16, hold=10)
+        else:
+            b.step(a, 64, hold=10)
+        outs.append(b.get_state().cpu())
+        b.close()
+    assert t.equal(outs[0], outs[1]) and t.equal(outs[1], outs[2])
+
+
+def test_trajectory_and_forces():
+    w = synth.randomised(n=300, steps=25)
+    t = torch()
+    b = make_batch(w)
+    a = w.actions(5)
+    K = 25
+    traj = t.zeros((K, b.layout.state_elems), dtype=b.dtype, device=b.device)
+    forces = t.zeros((K, b.layout.force_row_elems), dtype=b.dtype, device=b.device)
+    b.step(device_actions(b, a), K, hold=7, traj=traj, forces=forces)
+    envs, st = oracle_inputs(w)[0]
+    _, otr, ofo = oracle.rollout(envs, st.copy(), oracle.pack_actions(a[0]), 7, K, traj=True, forces=True)
+    gtr = traj.cpu().numpy().astype(np.float64)
+    gfo = b.unpack_forces(forces.cpu().numpy().astype(np.float64))[0]
+    for k in (0, 9, 24):
+        g = b.unpack_state(gtr[k])[0]
+        r = oracle.unpack_state(otr[:, k, :], 6)
+        assert component_errors(g, r).max() <= (1e-5 if k == 0 else 1e-4)
+        ef = component_errors(gfo[k], ofo[:, k, :].T)
+        assert ef.max() <= 1e-4, (k, ef)
+    # the final state equals the last trajectory row
+    assert t.equal(traj[-1], b.get_state())
+    b.close()
+
+
+def test_static_equilibrium_is_a_fixed_point():
+    """Neutral buoyancy, CoB above CoG, upright, at rest, zero command, no current: every
+    value stays exactly constant (float32)."""
+    t = torch()
+    c = synth.plain_class()
+    n = 128
+    p = synth.nominal_params(c, n)
+    p.buoy = np.full(n, float(np.float32(c.mass) * np.float32(c.g0)))
+    w = synth.Workload("eq", [c], [n], p, [synth.State(np.zeros((3, n)), np.vstack([np.ones(n), np.zeros((3, n))]),
+                                                       np.zeros((6, n)), np.zeros((6, n)))], 1000, 1)
+    b = make_batch(w)
+    # W - B computed in double from float inputs; use a buoyancy equal to m*g0 exactly.
+    p.buoy = p.mass * c.g0
+    b.set_params(p)
+    s0 = b.get_state()
+    a = t.zeros((1, b.layout.row_elems), dtype=b.dtype, device=b.device)
+    b.step(a, 1000, hold=1000)
+    assert t.equal(b.get_state(), s0)
+    b.close()
+
+
+def test_seeded_reset_matches_generator():
+    t = torch()
+    w = synth.heterogeneous(scale=0.02)
+    b = make_batch(w)
+    b.reset(seed=synth.MASTER_SEED)
+    got = b.unpack_state(b.get_state().cpu().numpy())
+    off = 0
+    for c, (cls, n) in enumerate(zip(w.classes, w.n_envs)):
+        ref = synth.initial_state(n, cls.m, synth.MASTER_SEED, off).stacked().astype(np.float32)
+        diff = np.abs(got[c].astype(np.float64) - ref) / np.maximum(np.abs(ref), 1e-30)
+        assert np.max(diff) <= 1.2e-7, np.max(diff)
+        off += n
+    # a subset reset rewrites exactly the listed environments
+    b.step(device_actions(b, w.actions(1)), 3, hold=10)
+    moved = b.unpack_state(b.get_state().cpu().numpy())
+    ids = [0, 5, w.n_total - 1]
+    b.reset(env_ids=ids, seed=7)
+    after = b.unpack_state(b.get_state().cpu().numpy())
+    offs = np.cumsum([0] + list(w.n_envs))
+    for c, cls in enumerate(w.classes):
+        for e in range(w.n_envs[c]):
+            gid = offs[c] + e
+            if gid in ids:
+                ref = synth.initial_state(1, cls.m, 7, gid).stacked()[:, 0].astype(np.float32)
+                assert np.allclose(after[c][:, e], ref, rtol=1.2e-7, atol=0)
+            else:
+                assert np.array_equal(after[c][:, e], moved[c][:, e])
+    b.close()
+
+
+def test_device_actions_match_generator():
+    w = synth.heterogeneous(scale=0.02)
+    b = make_batch(w)
+    dev = b.gen_actions(13, row_offset=5, seed=synth.MASTER_SEED).cpu().numpy()
+    got = b.unpack_actions(dev)
+    ref = w.actions(13, seed=synth.MASTER_SEED, row_offset=5)
+    for g, r in zip(got, ref):
+        assert np.array_equal(g, r)
+    b.close()
+
+
+def test_statistics_and_nonfinite_isolation():
+    t = torch()
+    w = synth.randomised(n=1000, steps=20)
+    b = make_batch(w)
+    acts = w.actions(2)
+    acts[0][:, 3, 17] = np.nan          # one environment gets a NaN command
+    b.step(device_actions(b, acts), 20, hold=10, flags=mgx.STEP_STATS)
+    st, nf = b.check()
+    assert st == mgx.MGX_E_NONFINITE and nf == 1
+    s = b.stats()
+    state = b.unpack_state(b.get_state().cpu().numpy().astype(np.float64))[0]
+    ok = np.all(np.isfinite(state), axis=0)
+    assert ok.sum() == 999 and not ok[17]
+    speed = np.linalg.norm(state[7:10, ok], axis=0)
+    assert abs(s.mean_speed[0] - speed.mean()) < 1e-5 * speed.mean()
+    assert abs(s.max_speed[0] - speed.max()) < 1e-6
+    assert s.step == 20 and s.n_nonfinite[0] == 1
+    # the other environments are unaffected: same as a run without the NaN
+    b2 = make_batch(w)
+    acts2 = w.actions(2)
+    b2.step(device_actions(b2, acts2), 20, hold=10)
+    s2 = b2.unpack_state(b2.get_state().cpu().numpy().astype(np.float64))[0]
+    assert np.array_equal(state[:, ok], s2[:, ok])
+    # a reset recovers the bad environment
+    b.reset(env_ids=[17], seed=1)
+    b.t = 0
+    b.step(device_actions(b, acts2), 1, hold=10, flags=mgx.STEP_STATS)
+    assert b.check() == (mgx.MGX_OK, 0)
+    b.close()
+    b2.close()
+
+
+def test_action_rows_are_validated():
+    t = torch()
+    w = synth.randomised(n=64, steps=20)
+    b = make_batch(w)
+    a = device_actions(b, w.actions(2))
+    s0 = b.get_state().clone()
+    with pytest.raises(mgx.MgxError) as e:
+        b.step(a, 21, hold=10)          # needs 3 rows
+    assert e.value.status == mgx.MGX_E_INVALID
+    assert t.equal(b.get_state(), s0) and b.t == 0
+    b.step(a, 20, hold=10)
+    assert b.t == 20
+    with pytest.raises(mgx.MgxError):
+        b.step(a, 1, hold=10)           # step 20 needs row 2
+    b.step(a, 1, hold=10, row0=1)       # a buffer starting at absolute row 1 covers rows 1..2
+    assert b.check()[0] == mgx.MGX_OK
+    b.close()
+
+
+def test_checkpoint_resume_is_bitwise():
+    t = torch()
+    w = synth.randomised(n=512, steps=1000)
+    acts = w.actions(100)
+    b = make_batch(w)
+    a = device_actions(b, acts)
+    b.step(a, 500, hold=10)
+    snap = b.get_state().clone()
+    t_snap = b.t
+    b.step(a, 500, hold=10)
+    full = b.get_state().clone()
+    b.close()
+    b2 = make_batch(w)
+    b2.set_state(snap)
+    b2.t = t_snap
+    b2.step(device_actions(b2, acts), 500, hold=10)
+    assert t.equal(b2.get_state(), full)
+    b2.close()
