@@ -58,7 +58,6 @@ def main():
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark line, print launch-duration sweeps over K and N")
     args = ap.parse_args()
@@ -94,63 +93,57 @@ def main():
     acts = b.gen_actions(rows, seed=synth.MASTER_SEED)
     graph = b.capture(acts, T, K, hold=HOLD)
 
-    def bench_step():
+    n_launch = -(-T // K)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+
+    def bench_step(i=None):
         mgx.mgx_batch_set_params(b.h, param_ptrs, 1)
         b.reset(init_state=init)
         b.t = 0
+        if i is not None:
+            ev[i][0].record(stream)
         graph.replay()
+        if i is not None:
+            ev[i][1].record(stream)
 
     for _ in range(args.warmup):
         bench_step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        bench_step()
+    for i in range(args.steps):
+        bench_step(i)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     final_state = b.unpack_state(b.get_state().cpu().numpy().astype(np.float64))[0]
     value = N * T * args.steps / elapsed
 
-    # Per-launch duration of the fused kernel, HIP events on the batch's stream.
+    # Fused kernel: HIP events on the batch's stream around every graph replay (the
+    # rollout's n_launch kernel launches back to back); average launch duration =
+    # elapsed / n_launch, so inter-kernel gaps count against the kernel.
     flops_es, ops_es = mgx.mgx_step_cost(cls.m)
+    graph_s = np.array([a.elapsed_time(c) for a, c in ev]) * 1e-3
+    fused_launch = float(graph_s.mean()) / n_launch
+    fused_flops_per_launch = flops_es * N * T / n_launch
 
-    def time_launches(k_steps, reps):
-        starts = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
-        ends = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
-        b.reset(init_state=init)
-        b.t = 0
-        t_ = 0
-        for r in range(reps):
-            if t_ + k_steps > T:
-                b.t = 0
-                t_ = 0
-            starts[r].record(stream)
-            b.step(acts, k_steps, hold=HOLD)
-            ends[r].record(stream)
-            t_ += k_steps
-        torch.cuda.synchronize()
-        d = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)]) * 1e-3
-        return float(np.median(d)), float(np.mean(d))
-
-    fused_med, fused_mean = time_launches(K, args.kernel_reps)
-    fused_flops = flops_es * N * K
-    single_med, single_mean = time_launches(1, args.kernel_reps)
-    single_bytes = bytes_per_env_step(cls.m, 1, HOLD) * N
-
-    # Whole rollout as 1000 single-step launches (graph-captured) for comparison.
+    # The same rollout as T single-step launches (graph-captured), timed the same way.
     g1 = b.capture(acts, T, 1, hold=HOLD, flags=mgx.STEP_UNFUSED)
-    b.reset(init_state=init)
-    b.t = 0
-    g1.replay()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
     reps1 = max(3, args.steps // 10)
-    for _ in range(reps1):
+    ev1 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps1 + 1)]
+    t1 = None
+    for i in range(reps1 + 1):
+        if i == 1:
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
         b.reset(init_state=init)
         b.t = 0
+        ev1[i][0].record(stream)
         g1.replay()
+        ev1[i][1].record(stream)
     torch.cuda.synchronize()
     single_rate = N * T * reps1 / (time.perf_counter() - t1)
+    single_launch = float(np.mean([a.elapsed_time(c) for a, c in ev1[1:]])) * 1e-3 / T
+    single_bytes = bytes_per_env_step(cls.m, 1, HOLD) * N
 
     out = {
         "metric": METRIC,
@@ -168,16 +161,17 @@ def main():
         "config": {"workload": f"dr_{N}x{T}", "n_envs": N, "rollout_steps": T, "thrusters": cls.m, "hold": HOLD,
                    "launch_steps_K": K, "dt": w.dt, "current_sigma": 0.3, "randomisation": 0.2,
                    "path": "set_params + reset + graph of fused launches"},
-        "roofline": {"bound": "alu", "achieved": fused_flops / fused_mean / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
-                     "unit": "TFLOP/s", "frac": fused_flops / fused_mean / PEAK_FP32_VECTOR, "traffic": None,
-                     "kernel": f"k_step<float,{cls.m}> K={K}", "launch_us_mean": fused_mean * 1e6,
-                     "launch_us_median": fused_med * 1e6, "flops_per_env_step": flops_es,
+        "roofline": {"bound": "alu", "achieved": fused_flops_per_launch / fused_launch / 1e12,
+                     "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
+                     "frac": fused_flops_per_launch / fused_launch / PEAK_FP32_VECTOR, "traffic": None,
+                     "kernel": f"k_step<float,{cls.m},false> K={K}", "launches_per_step": n_launch,
+                     "launch_us_mean": fused_launch * 1e6, "flops_per_env_step": flops_es,
                      "valu_ops_per_env_step": ops_es},
-        "single_step": {"env_steps_per_s": single_rate, "kernel": f"k_step<float,{cls.m}> K=1",
-                        "launch_us_mean": single_mean * 1e6, "launch_us_median": single_med * 1e6,
-                        "roofline": {"bound": "hbm", "achieved": single_bytes / single_mean / 1e9,
+        "single_step": {"env_steps_per_s": single_rate, "kernel": f"k_step<float,{cls.m},false> K=1",
+                        "launch_us_mean": single_launch * 1e6,
+                        "roofline": {"bound": "hbm", "achieved": single_bytes / single_launch / 1e9,
                                      "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                                     "frac": single_bytes / single_mean / PEAK_HBM,
+                                     "frac": single_bytes / single_launch / PEAK_HBM,
                                      "bytes_per_env_step": bytes_per_env_step(cls.m, 1, HOLD)}},
     }
 

@@ -1,6 +1,7 @@
 // Captured rollout chunks: the step launches of a chunk recorded once into a HIP graph and
 // replayed with one launch call. The step counter lives on the device, so replays need no
-// parameter updates.
+// parameter updates. Because the counter is double-buffered, the chunk is captured twice,
+// once per starting slot, and each replay picks the copy for the batch's current slot.
 #include <hip/hip_runtime.h>
 
 #include <new>
@@ -12,12 +13,22 @@ using namespace mgx;
 
 struct mgx_graph {
     mgx_batch* batch = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
     int64_t n_rows = 0, row0 = 0;
     int32_t hold = 1, n_steps = 0;
+    int32_t n_launches = 0;
     bool stats = false;
 };
+
+static void release(mgx_graph* g) {
+    for (int p = 0; p < 2; ++p) {
+        if (g->exec[p]) (void)hipGraphExecDestroy(g->exec[p]);
+        if (g->graph[p]) (void)hipGraphDestroy(g->graph[p]);
+        g->exec[p] = nullptr;
+        g->graph[p] = nullptr;
+    }
+}
 
 extern "C" mgx_status mgx_graph_capture(mgx_batch* b, const void* actions, int64_t n_rows, int64_t row0, int32_t hold,
                                         int32_t n_steps, int32_t K, uint32_t flags, mgx_graph** out) {
@@ -38,38 +49,45 @@ extern "C" mgx_status mgx_graph_capture(mgx_batch* b, const void* actions, int64
         delete g;
         return hip_fail(nullptr, e, "hipStreamCreateWithFlags");
     }
-    hipStream_t saved = b->stream;
-    b->stream = cap;
+    hipStream_t saved_stream = b->stream;
+    const int saved_slot = b->slot;
+    const int32_t per = (flags & MGX_STEP_UNFUSED) ? 1 : K;
+    const bool stats = (flags & MGX_STEP_STATS) != 0;
     mgx_status st = MGX_OK;
-    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        const int32_t per = (flags & MGX_STEP_UNFUSED) ? 1 : K;
-        const bool stats = (flags & MGX_STEP_STATS) != 0;
+    b->stream = cap;
+    for (int p = 0; p < 2 && st == MGX_OK; ++p) {
+        b->slot = p;
+        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            st = hip_fail(nullptr, e, "hipStreamBeginCapture");
+            break;
+        }
+        int32_t launches = 0;
         for (int32_t done = 0; done < n_steps && st == MGX_OK;) {
             const int32_t k = (n_steps - done) < per ? (n_steps - done) : per;
             st = enqueue_step(b, actions, n_rows, row0, hold, k, stats && done + k == n_steps, nullptr, nullptr,
                               b->block);
             done += k;
+            ++launches;
         }
+        g->n_launches = launches;
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(cap, &graph);
         if (st == MGX_OK && e2 != hipSuccess) st = hip_fail(nullptr, e2, "hipStreamEndCapture");
         if (st == MGX_OK) {
-            g->graph = graph;
-            e2 = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+            g->graph[p] = graph;
+            e2 = hipGraphInstantiate(&g->exec[p], graph, nullptr, nullptr, 0);
             if (e2 != hipSuccess) st = hip_fail(nullptr, e2, "hipGraphInstantiate");
         } else if (graph) {
             (void)hipGraphDestroy(graph);
         }
-    } else {
-        st = hip_fail(nullptr, e, "hipStreamBeginCapture");
     }
-    b->stream = saved;
+    b->stream = saved_stream;
+    b->slot = saved_slot;
     b->faulted = false;  // capture records launches only; the batch itself is untouched
     (void)hipStreamDestroy(cap);
     if (st != MGX_OK) {
-        if (g->exec) (void)hipGraphExecDestroy(g->exec);
-        if (g->graph) (void)hipGraphDestroy(g->graph);
+        release(g);
         delete g;
         return st;
     }
@@ -91,9 +109,10 @@ extern "C" mgx_status mgx_graph_replay(mgx_graph* g) {
     mgx_status v = validate_rows(b, b->host_t, g->n_rows, g->row0, g->hold, g->n_steps);
     if (v != MGX_OK) return v;
     hipDevice_guard guard(b->device);
-    hipError_t e = hipGraphLaunch(g->exec, b->stream);
+    hipError_t e = hipGraphLaunch(g->exec[b->slot], b->stream);
     if (e != hipSuccess) return hip_fail(b, e, "hipGraphLaunch");
     b->host_t += g->n_steps;
+    if (g->n_launches & 1) b->slot = 1 - b->slot;
     if (g->stats) b->stats_step = b->host_t;
     return MGX_OK;
 }
@@ -105,8 +124,7 @@ extern "C" mgx_status mgx_graph_destroy(mgx_graph* g) {
         (void)hipStreamSynchronize(g->batch->stream);
         g->batch->n_graphs -= 1;
     }
-    if (g->exec) (void)hipGraphExecDestroy(g->exec);
-    if (g->graph) (void)hipGraphDestroy(g->graph);
+    release(g);
     delete g;
     return MGX_OK;
 }

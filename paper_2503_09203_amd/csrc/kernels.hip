@@ -210,7 +210,8 @@ __global__ void __launch_bounds__(256) k_step(StepLaunch<T> L) {
     const StepArgs& A = L.a;
     const int tid = threadIdx.x;
     const int64_t env = (int64_t)blockIdx.x * blockDim.x + tid;
-    const int64_t t0 = A.misc->t;
+    const int64_t t0 = A.misc->t[A.rd];
+    if (A.advance && blockIdx.x == 0 && tid == 0) A.misc->t[A.wr] = t0 + A.advance;
     float st[kStats];
 #pragma unroll
     for (int j = 0; j < kStats; ++j) st[j] = 0.0f;
@@ -220,12 +221,12 @@ __global__ void __launch_bounds__(256) k_step(StepLaunch<T> L) {
         else
             env_steps<T, M, kOut, false>(A, L.cls, env, t0, A.K, st);
     }
+    if (!A.partials) return;
+    // Statistics: block partials, then the last block to finish reduces them in order.
     __shared__ float red[256 / kWave][kStats];
     __shared__ int is_last;
-    if (A.partials) {
-        block_reduce_stats(st, red, A.partials + (int64_t)blockIdx.x * kStats);
-        __threadfence();
-    }
+    block_reduce_stats(st, red, A.partials + (int64_t)blockIdx.x * kStats);
+    __threadfence();
     __syncthreads();
     if (tid == 0) {
         const unsigned prev = atomicAdd(&A.misc->done[A.class_index], 1u);
@@ -233,29 +234,22 @@ __global__ void __launch_bounds__(256) k_step(StepLaunch<T> L) {
     }
     __syncthreads();
     if (is_last) {
-        if (A.partials) {
-            __threadfence();
-            if (tid < kStats) final_reduce_stats(A.partials, gridDim.x, tid, A.stats);
-        }
-        if (tid == 0) {
-            atomicExch(&A.misc->done[A.class_index], 0u);
-            if (A.advance) atomicAdd((unsigned long long*)&A.misc->t, (unsigned long long)A.advance);
-        }
+        __threadfence();
+        if (tid < kStats) final_reduce_stats(A.partials, gridDim.x, tid, A.stats);
+        if (tid == 0) atomicExch(&A.misc->done[A.class_index], 0u);
     }
 }
 
 // Sets the device step counter (a kernel rather than a copy, so that it can sit inside a
 // captured graph and needs no host synchronisation).
-__global__ void k_set_counter(DevMisc* misc, int64_t t) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        atomicExch((unsigned long long*)&misc->t, (unsigned long long)t);
-    }
+__global__ void k_set_counter(DevMisc* misc, int slot, int64_t t) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) misc->t[slot] = t;
 }
 
 // ----------------------------------------------------------------------------- launchers
 
-hipError_t launch_set_counter(DevMisc* misc, int64_t t, hipStream_t s) {
-    hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(64), 0, s, misc, t);
+hipError_t launch_set_counter(DevMisc* misc, int slot, int64_t t, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(64), 0, s, misc, slot, t);
     return hipGetLastError();
 }
 

@@ -27,9 +27,12 @@ struct ClassDesc64 {
     double inertia[3], rb[3], g0;
 };
 
-// Device bookkeeping of a batch: step counter, per-class completion counters, error word.
+// Device bookkeeping of a batch. The step counter is double-buffered: a launch reads
+// slot rd and (if it moves the counter) its first block writes slot wr = 1 - rd, so the
+// counter advances with one plain store and no completion handshake. `done` counts
+// finished blocks per class for the statistics reduction only.
 struct DevMisc {
-    int64_t t;
+    int64_t t[2];
     int32_t err;
     int32_t pad;
     uint32_t done[16];
@@ -45,7 +48,8 @@ struct StepArgs {
     int32_t npad, nvalid;
     DevMisc* misc;
     int32_t class_index;
-    int32_t advance;      // added to the step counter by the last block (0 for all but one launch)
+    int32_t advance;      // 0, or K: block 0 writes t[wr] = t[rd] + K
+    int32_t rd, wr;       // step-counter slots
     void* traj;           // class segment base within step row 0, or null
     int64_t traj_stride;  // elements per step row
     void* forces;         // class segment base within step row 0, or null
@@ -61,7 +65,7 @@ struct StepLaunch {
 };
 
 // Host-side launchers (kernels.hip).
-hipError_t launch_set_counter(DevMisc* misc, int64_t t, hipStream_t s);
+hipError_t launch_set_counter(DevMisc* misc, int slot, int64_t t, hipStream_t s);
 hipError_t launch_class_setup(const ClassDesc64* d_in, ClassT<float>* d_f, ClassT<double>* d_d, int n,
                               double dt, uint32_t flags, hipStream_t s);
 // Per-environment parameter arrays (double, over the global env id, DOF-major rows).

@@ -455,6 +455,8 @@ mgx_status enqueue_step(mgx_batch* b, const void* actions, int64_t n_rows, int64
         a.misc = b->d_misc;
         a.class_index = c;
         a.advance = (c == b->n_classes - 1) ? K : 0;
+        a.rd = b->slot;
+        a.wr = 1 - b->slot;
         a.traj = traj ? (char*)traj + P * b->state_off[c] : nullptr;
         a.traj_stride = b->state_elems;
         a.forces = forces ? (char*)forces + P * b->force_off[c] : nullptr;
@@ -471,6 +473,7 @@ mgx_status enqueue_step(mgx_batch* b, const void* actions, int64_t n_rows, int64
         }
         if (e != hipSuccess) return hip_fail(b, e, "step launch");
     }
+    b->slot = 1 - b->slot;
     return MGX_OK;
 }
 
@@ -523,7 +526,7 @@ extern "C" mgx_status mgx_batch_set_step(mgx_batch* b, int64_t t) {
     CHECK_BATCH(b);
     if (t < 0) return fail(MGX_E_INVALID, "t must be >= 0");
     hipDevice_guard g(b->device);
-    HIP_TRY(b, launch_set_counter(b->d_misc, t, b->stream));
+    HIP_TRY(b, launch_set_counter(b->d_misc, b->slot, t, b->stream));
     b->host_t = t;
     return MGX_OK;
 }

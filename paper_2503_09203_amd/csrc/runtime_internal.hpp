@@ -68,6 +68,7 @@ struct mgx_batch {
     bool faulted = false;
     bool params_set = false;
     int64_t host_t = 0;
+    int slot = 0;  // step-counter slot the next launch reads
     int64_t stats_step = 0;
     int64_t h_t_stage = 0;
     int block = 256;
@@ -84,6 +85,7 @@ struct mgx_batch {
 
 namespace mgx {
 mgx_status hip_fail(mgx_batch* b, hipError_t e, const char* what);
+// Enqueues K steps of every class and flips the counter slot.
 mgx_status enqueue_step(mgx_batch* b, const void* actions, int64_t n_rows, int64_t row0, int32_t hold, int32_t K,
                         bool stats, void* traj, void* forces, int block);
 mgx_status validate_rows(const mgx_batch* b, int64_t t0, int64_t n_rows, int64_t row0, int32_t hold, int64_t K);

@@ -269,3 +269,37 @@ def test_checkpoint_resume_is_bitwise():
     b2.step(device_actions(b2, acts), 500, hold=10)
     assert t.equal(b2.get_state(), full)
     b2.close()
+
+
+@pytest.mark.parametrize("n_steps,K", [(48, 16), (40, 16), (7, 3)])
+def test_graph_replays_equal_eager_steps(n_steps, K):
+    """A captured chunk replayed across a rollout-long action buffer gives the same state,
+    bit for bit, as eager calls; odd and even launch counts exercise both counter slots."""
+    t = torch()
+    w = synth.randomised(n=700, steps=4 * n_steps)
+    acts = w.actions(-(-4 * n_steps // 10) + 1)
+    be = make_batch(w)
+    a_e = device_actions(be, acts)
+    for _ in range(4):
+        done = 0
+        while done < n_steps:
+            k = min(K, n_steps - done)
+            be.step(a_e, k, hold=10)
+            done += k
+    bg = make_batch(w)
+    a_g = device_actions(bg, acts)
+    g = bg.capture(a_g, n_steps, K, hold=10)
+    for _ in range(4):
+        g.replay()
+    assert bg.t == be.t == 4 * n_steps
+    assert t.equal(bg.get_state(), be.get_state())
+    # the step counter on the device agrees with the host: one more eager step matches
+    be.step(a_e, 1, hold=10)
+    bg.step(a_g, 1, hold=10)
+    assert t.equal(bg.get_state(), be.get_state())
+    g.close()
+    with pytest.raises(mgx.MgxError):
+        g2 = bg.capture(a_g, 8 * n_steps, K, hold=10)
+        g2.replay()          # needs rows beyond the buffer at the current step
+    bg.close()
+    be.close()
