@@ -58,6 +58,8 @@ def main():
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="dr", choices=["dr", "hetero"],
+                    help="dr: the default benchmark line; hetero: five classes in one persistent launch")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark line, print launch-duration sweeps over K and N")
     args = ap.parse_args()
@@ -80,6 +82,9 @@ def main():
     N, T, K, HOLD = args.n, args.rollout, args.chunk, 10
     if args.sweep:
         sweep(args)
+        return
+    if args.workload == "hetero":
+        hetero(args)
         return
     w = synth.randomised(n=N, steps=T)
     cls = w.classes[0]
@@ -206,6 +211,60 @@ def main():
 
     g1.close()
     graph.close()
+    b.close()
+    print(json.dumps(out), flush=True)
+
+
+def hetero(args):
+    """Five vehicle classes (4, 5, 6, 8, 8 thrusters; 512 / 3000 / 20000 / 40000 / 7000
+    envs) advanced 1024 steps as 32 captured 32-step chunks, launch shape from the
+    autotuner, against the same chunks as one launch per class (K = 16)."""
+    import torch
+
+    import synth
+    from paper_2503_09203_amd import mgx
+
+    T, CHUNK, HOLD = 1024, 32, 10
+    w = synth.heterogeneous(steps=T)
+    b = mgx.Batch(w.classes, w.n_envs, w.dt)
+    b.set_params(w.params)
+    init = torch.tensor(b.pack_state([s.stacked() for s in w.state]), dtype=torch.float32, device="cuda:0")
+    b.set_state(init)
+    acts = b.gen_actions(-(-T // HOLD) + 1, seed=synth.MASTER_SEED)
+    stream = torch.cuda.current_stream()
+    n = w.n_total
+    flops = sum(mgx.mgx_step_cost(c.m)[0] * k for c, k in zip(w.classes, w.n_envs))
+
+    def run(label):
+        g = b.capture(acts, CHUNK, 0, hold=HOLD)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        for i in range(args.warmup + args.steps):
+            b.reset(init_state=init)
+            b.t = 0
+            if i >= args.warmup:
+                ev[i - args.warmup][0].record(stream)
+            for _ in range(T // CHUNK):
+                g.replay()
+            if i >= args.warmup:
+                ev[i - args.warmup][1].record(stream)
+        torch.cuda.synchronize()
+        sec = float(np.mean([a.elapsed_time(c) for a, c in ev])) * 1e-3
+        g.close()
+        sh = b.shape()
+        return {"label": label, "mode": "persistent" if sh.mode == mgx.LAUNCH_PERSISTENT else "per_class",
+                "K": sh.K, "block": sh.block, "grid_per_cu": sh.grid_per_cu, "ms_per_rollout": sec * 1e3,
+                "env_steps_per_s": n * T / sec, "tflops": flops * T / sec / 1e12}
+
+    b.set_shape(mgx.LAUNCH_PER_CLASS, 16)
+    base = run("per-class launches, K=16")
+    b.reset(init_state=init)
+    b.t = 0
+    tuned = b.autotune(acts, CHUNK, hold=HOLD)
+    best = run("autotuned")
+    out = {"metric": METRIC, "workload": f"hetero_{n}x{T}", "value": best["env_steps_per_s"], "unit": "env-steps/s",
+           "n_envs": n, "classes": [c.m for c in w.classes], "n_per_class": w.n_envs, "chunk_steps": CHUNK,
+           "autotune": {"candidates": tuned.candidates, "us_per_chunk": tuned.us_per_chunk}, "tuned": best,
+           "baseline": base, "speedup_vs_per_class": best["env_steps_per_s"] / base["env_steps_per_s"]}
     b.close()
     print(json.dumps(out), flush=True)
 

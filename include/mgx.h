@@ -177,7 +177,8 @@ mgx_status mgx_batch_set_params(mgx_batch* b, const mgx_env_params* p, int32_t o
 mgx_status mgx_batch_reset(mgx_batch* b, const int64_t* env_ids, int64_t n, const void* init_state,
                            uint64_t seed);
 
-/* Advances every environment by K >= 1 steps of dt. Step k of the call (global step
+/* Advances every environment by K >= 1 steps of dt (K = 0: the launch-shape K), fused in
+ * one launch (MGX_STEP_UNFUSED: K launches of one step). Step k of the call (global step
  * t = t0 + k, t0 = the batch step counter) uses row floor(t / hold) - row0 of `actions`
  * (device pointer, n_rows rows in the layout above, batch precision). Commands are
  * clipped to [-1, 1]. MGX_E_INVALID if a needed row falls outside [0, n_rows).
@@ -221,6 +222,41 @@ mgx_status mgx_batch_sync(mgx_batch* b);
  * Philox4x32-10 (Salmon et al., SC'11) at key (seed mod 2^32, 4 << 24) and counter
  * (global env id, row_offset + row, i / 4, 0). Padded slots get 0. Asynchronous. */
 mgx_status mgx_gen_actions(mgx_batch* b, void* out, int64_t rows, int64_t row_offset, uint64_t seed);
+
+/* ------------------------------------------------------------------ launch shape, autotuner */
+
+#define MGX_LAUNCH_PER_CLASS 0   /* one launch per class segment */
+#define MGX_LAUNCH_PERSISTENT 1  /* one launch for all classes: per-class constants staged in
+                                    LDS, waves pull 64-environment tiles from a device work
+                                    counter (FP32 batches; steps without traj/forces) */
+
+typedef struct {
+    int32_t mode;         /* MGX_LAUNCH_* */
+    int32_t K;            /* steps per launch used when a call passes K = 0 */
+    int32_t block;        /* threads per block (64, 128 or 256) */
+    int32_t grid_per_cu;  /* persistent mode: blocks per compute unit */
+    double us_per_chunk;  /* autotuner: measured time of one chunk with this shape */
+    int32_t candidates;   /* autotuner: shapes measured */
+    int32_t from_cache;   /* autotuner: 1 if taken from the cache without measuring */
+} mgx_launch_shape;
+
+/* Reads / sets the launch shape of a batch (validated; MGX_LAUNCH_PERSISTENT on a double
+ * batch is MGX_E_INVALID). Default: per-class launches, K = 16, block 256. */
+mgx_status mgx_batch_get_shape(const mgx_batch* b, mgx_launch_shape* out);
+mgx_status mgx_batch_set_shape(mgx_batch* b, const mgx_launch_shape* in);
+
+/* Autotuner: times one chunk of chunk_steps steps (from the batch's current step, action
+ * rows as in mgx_batch_step) for every candidate shape — launch mode, steps per launch K
+ * dividing chunk_steps, block size, persistent grid — with HIP events on the batch stream,
+ * keeps the fastest, and records it in a process-wide cache keyed by (GPU architecture,
+ * precision, per-class thruster counts and padded sizes, hold, chunk_steps). A cache hit
+ * applies the stored shape without measuring. The batch's state and step counter are
+ * restored afterwards (synchronous). */
+mgx_status mgx_autotune(mgx_batch* b, const void* actions, int64_t n_rows, int64_t row0, int32_t hold,
+                        int32_t chunk_steps, mgx_launch_shape* out);
+/* Cache persistence as plain text, one shape per line. */
+mgx_status mgx_autotune_save(const char* path);
+mgx_status mgx_autotune_load(const char* path);
 
 /* ------------------------------------------------------------------ captured chunks */
 

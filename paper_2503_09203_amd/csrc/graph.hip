@@ -37,6 +37,7 @@ extern "C" mgx_status mgx_graph_capture(mgx_batch* b, const void* actions, int64
     if (b->faulted) return fail(MGX_E_STATE, "batch faulted by an earlier device error");
     if (!b->params_set) return fail(MGX_E_STATE, "mgx_batch_set_params has not been called");
     if (!actions) return fail(MGX_E_INVALID, "actions is NULL");
+    if (K == 0) K = b->shape_K;
     if (n_steps < 1 || K < 1 || hold < 1 || n_rows < 1) return fail(MGX_E_INVALID, "n_steps, K, hold, n_rows must be >= 1");
     if (flags & ~(MGX_STEP_UNFUSED | MGX_STEP_STATS)) return fail(MGX_E_INVALID, "unknown step flag");
     if (n_steps > (1 << 20)) return fail(MGX_E_INVALID, "n_steps too large for one graph");

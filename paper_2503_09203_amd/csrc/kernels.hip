@@ -211,7 +211,11 @@ __global__ void __launch_bounds__(256) k_step(StepLaunch<T> L) {
     const int tid = threadIdx.x;
     const int64_t env = (int64_t)blockIdx.x * blockDim.x + tid;
     const int64_t t0 = A.misc->t[A.rd];
-    if (A.advance && blockIdx.x == 0 && tid == 0) A.misc->t[A.wr] = t0 + A.advance;
+    if (blockIdx.x == 0 && tid == 0) {
+        if (A.advance) A.misc->t[A.wr] = t0 + A.advance;
+        A.misc->work[A.wr] = 0u;  // the next launch may be a persistent one
+        A.misc->exits[A.wr] = 0u;
+    }
     float st[kStats];
 #pragma unroll
     for (int j = 0; j < kStats; ++j) st[j] = 0.0f;
@@ -243,7 +247,11 @@ __global__ void __launch_bounds__(256) k_step(StepLaunch<T> L) {
 // Sets the device step counter (a kernel rather than a copy, so that it can sit inside a
 // captured graph and needs no host synchronisation).
 __global__ void k_set_counter(DevMisc* misc, int slot, int64_t t) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) misc->t[slot] = t;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        misc->t[slot] = t;
+        misc->work[slot] = 0u;
+        misc->exits[slot] = 0u;
+    }
 }
 
 // ----------------------------------------------------------------------------- launchers

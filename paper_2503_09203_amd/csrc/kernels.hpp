@@ -36,6 +36,31 @@ struct DevMisc {
     int32_t err;
     int32_t pad;
     uint32_t done[16];
+    uint32_t work[2];   // persistent launch: next tile (slot rd), reset for the next launch (slot wr)
+    uint32_t exits[2];  // persistent launch with statistics: waves finished
+};
+
+// One class segment as the persistent kernel sees it.
+struct SegDesc {
+    void* state;
+    const void* rec;
+    int64_t act_off;   // elements from the start of an action row
+    int32_t npad, nvalid, m, has_dz;
+};
+
+// Arguments of the persistent heterogeneous kernel (all classes, one launch).
+struct PersistArgs {
+    const SegDesc* segs;
+    const void* cls;       // ClassT<T>[n_classes], staged into LDS by every block
+    const int32_t* tiles;  // (class, first env) pairs, heaviest class first
+    int32_t n_classes, n_tiles;
+    const void* actions;
+    int64_t row_stride, n_rows, row0;
+    int32_t hold, K;
+    DevMisc* misc;
+    int32_t rd, wr, advance, pad;
+    float* tile_partials;  // [n_tiles][kStats] or null
+    double* stats;         // [16][kStats]
 };
 
 // Arguments of the step kernel for one class segment.
@@ -90,5 +115,7 @@ hipError_t launch_gen_actions(T* out_seg, int m, int32_t npad, int64_t n_valid, 
                               int64_t row_stride, int64_t row_offset, uint64_t seed, hipStream_t s);
 template <typename T>
 hipError_t launch_step(const StepLaunch<T>& L, int m, int block, hipStream_t s);
+template <typename T>
+hipError_t launch_persistent(const PersistArgs& P, int grid, int block, hipStream_t s);
 
 }  // namespace mgx

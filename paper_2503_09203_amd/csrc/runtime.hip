@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -155,7 +156,7 @@ static void* dalloc(size_t bytes, hipError_t* e) {
 
 static void free_batch_mem(mgx_batch* b) {
     void* ptrs[] = {b->d_state, b->d_rec, b->d_misc, b->d_classdesc, b->d_class_f, b->d_class_d, b->d_partials,
-                    b->d_stats, b->d_ids, b->d_param_stage};
+                    b->d_stats, b->d_ids, b->d_param_stage, b->d_tiles, b->d_segs, b->d_tile_partials};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -242,6 +243,10 @@ extern "C" mgx_status mgx_batch_create(const mgx_batch_desc* d, mgx_batch** out)
     if (e == hipSuccess) b->d_partials = (float*)dalloc(sizeof(float) * kStats * max_blocks, &e);
     if (e == hipSuccess) b->d_stats = (double*)dalloc(sizeof(double) * kStats * MGX_MAX_CLASSES, &e);
     if (e == hipSuccess) b->d_ids = (int64_t*)dalloc(sizeof(int64_t) * b->n_total, &e);
+    b->n_tiles = (int32_t)(b->npad_total / kWave);
+    if (e == hipSuccess) b->d_tiles = (int32_t*)dalloc(sizeof(int32_t) * 2 * b->n_tiles, &e);
+    if (e == hipSuccess) b->d_segs = (SegDesc*)dalloc(sizeof(SegDesc) * MGX_MAX_CLASSES, &e);
+    if (e == hipSuccess) b->d_tile_partials = (float*)dalloc(sizeof(float) * kStats * b->n_tiles, &e);
     if (e != hipSuccess) {
         free_batch_mem(b);
         delete b;
@@ -253,6 +258,35 @@ extern "C" mgx_status mgx_batch_create(const mgx_batch_desc* d, mgx_batch** out)
     // kernels as kernel arguments (scalar registers).
     std::vector<ClassDesc64> d64(MGX_MAX_CLASSES);
     for (int c = 0; c < b->n_classes; ++c) d64[c] = to_desc64(cls[c]);
+    // Persistent launch: tiles of 64 environments, heaviest class (most thrusters) first.
+    std::vector<int32_t> tiles;
+    std::vector<int> order(b->n_classes);
+    for (int c = 0; c < b->n_classes; ++c) order[c] = c;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->m[x] > b->m[y]; });
+    for (int c : order)
+        for (int64_t e0 = 0; e0 < b->npad[c]; e0 += kWave) {
+            tiles.push_back(c);
+            tiles.push_back((int32_t)e0);
+        }
+    std::vector<SegDesc> segs(MGX_MAX_CLASSES);
+    for (int c = 0; c < b->n_classes; ++c) {
+        segs[c].state = b->seg_state(c);
+        segs[c].rec = b->seg_rec(c);
+        segs[c].act_off = b->act_off[c];
+        segs[c].npad = (int32_t)b->npad[c];
+        segs[c].nvalid = (int32_t)b->n[c];
+        segs[c].m = b->m[c];
+        bool dz = false;
+        for (int i = 0; i < b->m[c]; ++i) dz |= cls[c].deadzone[i] > 0.0;
+        segs[c].has_dz = dz ? 1 : 0;
+    }
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            b->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+            b->arch = prop.gcnArchName;
+        }
+    }
     mgx_status st = MGX_OK;
     auto run = [&]() -> mgx_status {
         HIP_TRY(b, hipMemcpyAsync(b->d_classdesc, d64.data(), sizeof(ClassDesc64) * MGX_MAX_CLASSES,
@@ -264,6 +298,10 @@ extern "C" mgx_status mgx_batch_create(const mgx_batch_desc* d, mgx_batch** out)
         HIP_TRY(b, hipMemcpyAsync(b->h_class_d, b->d_class_d, sizeof(ClassT<double>) * MGX_MAX_CLASSES,
                                   hipMemcpyDeviceToHost, b->stream));
         HIP_TRY(b, hipMemsetAsync(b->d_misc, 0, sizeof(DevMisc), b->stream));
+        HIP_TRY(b, hipMemcpyAsync(b->d_tiles, tiles.data(), sizeof(int32_t) * tiles.size(), hipMemcpyHostToDevice,
+                                  b->stream));
+        HIP_TRY(b, hipMemcpyAsync(b->d_segs, segs.data(), sizeof(SegDesc) * MGX_MAX_CLASSES, hipMemcpyHostToDevice,
+                                  b->stream));
         HIP_TRY(b, hipMemsetAsync(b->d_stats, 0, sizeof(double) * kStats * MGX_MAX_CLASSES, b->stream));
         for (int c = 0; c < b->n_classes; ++c) {
             if (b->prec == MGX_FP32) {
@@ -439,6 +477,36 @@ namespace mgx {
 mgx_status enqueue_step(mgx_batch* b, const void* actions, int64_t n_rows, int64_t row0, int32_t hold, int32_t K,
                         bool stats, void* traj, void* forces, int block) {
     const size_t P = (size_t)b->prec;
+    if (b->mode == MGX_LAUNCH_PERSISTENT && !traj && !forces && b->prec == MGX_FP32) {
+        PersistArgs pa;
+        std::memset(&pa, 0, sizeof pa);
+        pa.segs = b->d_segs;
+        pa.cls = b->d_class_f;
+        pa.tiles = b->d_tiles;
+        pa.n_classes = b->n_classes;
+        pa.n_tiles = b->n_tiles;
+        pa.actions = actions;
+        pa.row_stride = b->row_elems;
+        pa.n_rows = n_rows;
+        pa.row0 = row0;
+        pa.hold = hold;
+        pa.K = K;
+        pa.misc = b->d_misc;
+        pa.rd = b->slot;
+        pa.wr = 1 - b->slot;
+        pa.advance = K;
+        pa.tile_partials = stats ? b->d_tile_partials : nullptr;
+        pa.stats = b->d_stats;
+        const int waves_per_block = block / kWave;
+        int grid = b->n_cu * b->grid_per_cu;
+        const int needed = (b->n_tiles + waves_per_block - 1) / waves_per_block;
+        if (grid > needed) grid = needed;
+        if (grid < 1) grid = 1;
+        hipError_t e = launch_persistent<float>(pa, grid, block, b->stream);
+        if (e != hipSuccess) return hip_fail(b, e, "persistent launch");
+        b->slot = 1 - b->slot;
+        return MGX_OK;
+    }
     for (int c = 0; c < b->n_classes; ++c) {
         StepArgs a;
         std::memset(&a, 0, sizeof a);
@@ -491,7 +559,8 @@ extern "C" mgx_status mgx_batch_step(mgx_batch* b, const void* actions, int64_t 
     CHECK_BATCH(b);
     if (!b->params_set) return fail(MGX_E_STATE, "mgx_batch_set_params has not been called");
     if (!actions) return fail(MGX_E_INVALID, "actions is NULL");
-    if (K < 1) return fail(MGX_E_INVALID, "K=%d must be >= 1", K);
+    if (K == 0) K = b->shape_K;
+    if (K < 1) return fail(MGX_E_INVALID, "K=%d must be >= 1 (or 0)", K);
     if (hold < 1) return fail(MGX_E_INVALID, "hold=%d must be >= 1", hold);
     if (n_rows < 1) return fail(MGX_E_INVALID, "n_rows must be >= 1");
     if (flags & ~(MGX_STEP_UNFUSED | MGX_STEP_STATS)) return fail(MGX_E_INVALID, "unknown step flag");
@@ -620,5 +689,31 @@ extern "C" mgx_status mgx_gen_actions(mgx_batch* b, void* out, int64_t rows, int
                                            b->n[c], b->env_off[c], rows, b->row_elems, row_offset, seed, b->stream);
         if (e != hipSuccess) return hip_fail(b, e, "gen_actions launch");
     }
+    return MGX_OK;
+}
+
+extern "C" mgx_status mgx_batch_get_shape(const mgx_batch* b, mgx_launch_shape* out) {
+    if (!b || !out) return fail(MGX_E_INVALID, "NULL argument");
+    std::memset(out, 0, sizeof *out);
+    out->mode = b->mode;
+    out->K = b->shape_K;
+    out->block = b->block;
+    out->grid_per_cu = b->grid_per_cu;
+    return MGX_OK;
+}
+
+extern "C" mgx_status mgx_batch_set_shape(mgx_batch* b, const mgx_launch_shape* in) {
+    CHECK_BATCH(b);
+    if (!in) return fail(MGX_E_INVALID, "NULL argument");
+    if (in->mode != MGX_LAUNCH_PER_CLASS && in->mode != MGX_LAUNCH_PERSISTENT) return fail(MGX_E_INVALID, "unknown mode");
+    if (in->mode == MGX_LAUNCH_PERSISTENT && b->prec != MGX_FP32)
+        return fail(MGX_E_INVALID, "the persistent launch is for float batches");
+    if (in->K < 1 || in->K > 65536) return fail(MGX_E_INVALID, "K=%d outside [1, 65536]", in->K);
+    if (in->block != 64 && in->block != 128 && in->block != 256) return fail(MGX_E_INVALID, "block must be 64, 128 or 256");
+    if (in->grid_per_cu < 1 || in->grid_per_cu > 8) return fail(MGX_E_INVALID, "grid_per_cu outside [1, 8]");
+    b->mode = in->mode;
+    b->shape_K = in->K;
+    b->block = in->block;
+    b->grid_per_cu = in->grid_per_cu;
     return MGX_OK;
 }

@@ -73,6 +73,17 @@ struct mgx_batch {
     int64_t h_t_stage = 0;
     int block = 256;
     int n_graphs = 0;  // live graphs captured from this batch
+    // launch shape
+    int mode = MGX_LAUNCH_PER_CLASS;
+    int shape_K = 16;
+    int grid_per_cu = 2;
+    int n_cu = 256;
+    std::string arch;
+    // persistent launch: tile table (class, first env), heaviest class first
+    int32_t n_tiles = 0;
+    int32_t* d_tiles = nullptr;
+    mgx::SegDesc* d_segs = nullptr;
+    float* d_tile_partials = nullptr;
 
     void* seg_state(int c) const { return (char*)d_state + (size_t)prec * state_off[c]; }
     void* seg_rec(int c) const { return (char*)d_rec + (size_t)prec * rec_off[c]; }

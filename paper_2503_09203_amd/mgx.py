@@ -33,6 +33,8 @@ FLAG_NO_AMC = 1
 FLAG_LAG_EULER = 2
 STEP_UNFUSED = 1
 STEP_STATS = 2
+LAUNCH_PER_CLASS = 0
+LAUNCH_PERSISTENT = 1
 
 
 class MgxError(RuntimeError):
@@ -65,6 +67,12 @@ class Layout(ctypes.Structure):
                 ("n_pad", ctypes.c_int64 * MAX_CLASSES), ("env_off", ctypes.c_int64 * MAX_CLASSES),
                 ("state_off", ctypes.c_int64 * MAX_CLASSES), ("action_off", ctypes.c_int64 * MAX_CLASSES),
                 ("force_off", ctypes.c_int64 * MAX_CLASSES)]
+
+
+class LaunchShape(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("K", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("grid_per_cu", ctypes.c_int32), ("us_per_chunk", ctypes.c_double),
+                ("candidates", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
 
 
 class EnvParams(ctypes.Structure):
@@ -105,6 +113,11 @@ SIGNATURES = {
     "mgx_batch_check": (I32, [P, ctypes.POINTER(I64)]),
     "mgx_batch_sync": (I32, [P]),
     "mgx_gen_actions": (I32, [P, P, I64, I64, U64]),
+    "mgx_batch_get_shape": (I32, [P, ctypes.POINTER(LaunchShape)]),
+    "mgx_batch_set_shape": (I32, [P, ctypes.POINTER(LaunchShape)]),
+    "mgx_autotune": (I32, [P, P, I64, I64, I32, I32, ctypes.POINTER(LaunchShape)]),
+    "mgx_autotune_save": (I32, [ctypes.c_char_p]),
+    "mgx_autotune_load": (I32, [ctypes.c_char_p]),
     "mgx_graph_capture": (I32, [P, P, I64, I64, I32, I32, I32, U32, ctypes.POINTER(P)]),
     "mgx_graph_replay": (I32, [P]),
     "mgx_graph_destroy": (I32, [P]),
@@ -258,6 +271,31 @@ def mgx_gen_actions(h, out_ptr, rows, row_offset, seed):
     _call("mgx_gen_actions", h, out_ptr, int(rows), int(row_offset), int(seed))
 
 
+def mgx_batch_get_shape(h) -> LaunchShape:
+    s = LaunchShape()
+    _call("mgx_batch_get_shape", h, ctypes.byref(s))
+    return s
+
+
+def mgx_batch_set_shape(h, mode, K, block=256, grid_per_cu=2):
+    s = LaunchShape(int(mode), int(K), int(block), int(grid_per_cu), 0.0, 0, 0)
+    _call("mgx_batch_set_shape", h, ctypes.byref(s))
+
+
+def mgx_autotune(h, actions_ptr, n_rows, row0, hold, chunk) -> LaunchShape:
+    s = LaunchShape()
+    _call("mgx_autotune", h, actions_ptr, int(n_rows), int(row0), int(hold), int(chunk), ctypes.byref(s))
+    return s
+
+
+def mgx_autotune_save(path):
+    _call("mgx_autotune_save", str(path).encode())
+
+
+def mgx_autotune_load(path):
+    _call("mgx_autotune_load", str(path).encode())
+
+
 def mgx_graph_capture(h, actions_ptr, n_rows, row0, hold, n_steps, K, flags=0):
     g = P()
     _call("mgx_graph_capture", h, actions_ptr, int(n_rows), int(row0), int(hold), int(n_steps), int(K), int(flags),
@@ -374,6 +412,15 @@ class Batch:
 
     def stats(self):
         return mgx_batch_get_stats(self.h)
+
+    def shape(self):
+        return mgx_batch_get_shape(self.h)
+
+    def set_shape(self, mode, K, block=256, grid_per_cu=2):
+        mgx_batch_set_shape(self.h, mode, K, block, grid_per_cu)
+
+    def autotune(self, actions, chunk, hold=1, row0=0):
+        return mgx_autotune(self.h, _ptr(actions), actions.shape[0], row0, hold, chunk)
 
     def check(self):
         return mgx_batch_check(self.h)
