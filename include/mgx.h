@@ -258,6 +258,42 @@ mgx_status mgx_autotune(mgx_batch* b, const void* actions, int64_t n_rows, int64
 mgx_status mgx_autotune_save(const char* path);
 mgx_status mgx_autotune_load(const char* path);
 
+/* ------------------------------------------------------------------ differentiable rollout */
+
+/* Forward pass of a differentiable rollout: H steps exactly as mgx_batch_step (same action
+ * indexing, clip, launch per class), additionally writing the position after every step
+ * and the full state every ckpt_every steps into library-owned scratch (allocated on first
+ * use, kept until destroy). pos_out: device [H][3 * n_pad_total], class c at
+ * 3 * (sum of n_pad of the classes before c), element (j, env) at that offset + j * n_pad[c]
+ * + env. The batch advances by H. The actions buffer must stay valid until the matching
+ * mgx_rollout_backward. */
+mgx_status mgx_rollout_forward(mgx_batch* b, const void* actions, int64_t n_rows, int64_t row0, int32_t hold,
+                               int32_t H, int32_t ckpt_every, void* pos_out);
+
+/* Reverse-mode sweep of the last forward pass (vector-Jacobian product of the step map,
+ * written out by hand): each environment recomputes every ckpt_every-step segment from its
+ * checkpoint into scratch, then runs the adjoint backwards through it. Given
+ * dpos = dL/d(position after step k) (device, pos_out layout), writes
+ *   dactions: device [n_rows][row_elems] — dL/d(command) per action row (sum over the
+ *             steps of the row; zero outside the clip range); rows the rollout did not
+ *             use are left untouched;
+ *   dparams : device [18 * n_pad_total] — per class at 18 * (padded offset), rows
+ *             0-5 dL/d(d_L), 6-11 dL/d(d_Q), 12-17 dL/d(M_A diagonal) (through the
+ *             Coriolis, current and mass-inverse terms).
+ * Either output may be NULL. MGX_E_STATE if no forward pass is recorded. Asynchronous. */
+mgx_status mgx_rollout_backward(mgx_batch* b, const void* dpos, void* dactions, void* dparams);
+
+/* Diagnostic (host only, double precision): evaluates the kernels' step body and its
+ * hand-written adjoint for one environment, so the adjoint can be checked against finite
+ * differences without a GPU. cls: Bk[6][8] (layout columns times gains), alpha[8],
+ * deadzone[8], inertia[3], rb[3], g0, dt (74 doubles); rec: the 30 record fields (dt M^-1[6],
+ * m, M_A[6], d_L[6], d_Q[6], W - B, B, V_c[3]); state/xbar_in/state_out/xbar_out: 13 + m;
+ * actions/abar_out: m; gparams_out: 24 = adjoints of d_L[6], d_Q[6], M_A[6] (direct
+ * terms only), dt M^-1[6]. Used by no device path. */
+mgx_status mgx_host_step_vjp(int32_t m, uint32_t batch_flags, const double* cls, const double* rec, const double* state,
+                             const double* actions, const double* xbar_in, double* state_out, double* xbar_out,
+                             double* abar_out, double* gparams_out);
+
 /* ------------------------------------------------------------------ captured chunks */
 
 typedef struct mgx_graph mgx_graph;

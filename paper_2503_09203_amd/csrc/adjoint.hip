@@ -1,0 +1,455 @@
+// Differentiable rollout: forward pass with checkpoints, and the reverse sweep with
+// per-segment recomputation. One environment per lane; the adjoint state and the parameter
+// adjoints stay in registers for the whole sweep.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+
+#include "adjoint.hpp"
+#include "env_loop.hpp"
+#include "kernels.hpp"
+#include "mgx.h"
+#include "runtime_internal.hpp"
+
+namespace mgx {
+
+template <typename T, int M>
+__device__ __forceinline__ void load_state(const T* S, int64_t np, int64_t e, StateT<T, M>& s) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) s.p[j] = S[j * np + e];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s.q[j] = S[(3 + j) * np + e];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) s.nu[j] = S[(7 + j) * np + e];
+#pragma unroll
+    for (int i = 0; i < M; ++i) s.n[i] = S[(kStateFixed + i) * np + e];
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void store_state(T* S, int64_t np, int64_t e, const StateT<T, M>& s) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) S[j * np + e] = s.p[j];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) S[(3 + j) * np + e] = s.q[j];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) S[(7 + j) * np + e] = s.nu[j];
+#pragma unroll
+    for (int i = 0; i < M; ++i) S[(kStateFixed + i) * np + e] = s.n[i];
+}
+
+template <typename T>
+__device__ __forceinline__ void load_env(const T* Rc, int64_t np, int64_t e, EnvT<T>& E) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        E.dtMinv[j] = Rc[(kRecDtMinv + j) * np + e];
+        E.A[j] = Rc[(kRecAdded + j) * np + e];
+        E.dL[j] = Rc[(kRecDlin + j) * np + e];
+        E.dQ[j] = Rc[(kRecDquad + j) * np + e];
+    }
+    E.mass = Rc[kRecMass * np + e];
+    E.wmb = Rc[kRecWmB * np + e];
+    E.buoy = Rc[kRecBuoy * np + e];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) E.Vc[j] = Rc[(kRecCurrent + j) * np + e];
+}
+
+// Row of the action buffer used by global step t (validated on the host).
+__device__ __forceinline__ int64_t action_row(const AdjArgs& A, int64_t t) { return floor_div(t, A.hold) - A.row0; }
+
+template <typename T, int M>
+__device__ __forceinline__ void load_action(const AdjArgs& A, int64_t row, int64_t e, T raw[M]) {
+    const T* src = (const T*)A.actions + row * A.row_stride + e;
+#pragma unroll
+    for (int i = 0; i < M; ++i) raw[i] = src[i * (int64_t)A.npad];
+}
+
+template <typename T, int M, bool kDz>
+__global__ void __launch_bounds__(256) k_rollout_fwd(AdjArgs A, ClassT<T> C) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (A.advance) A.misc->t[A.wr] = A.t0 + A.advance;
+        A.misc->work[A.wr] = 0u;
+        A.misc->exits[A.wr] = 0u;
+    }
+    if (e >= A.npad) return;
+    const int64_t np = A.npad;
+    StateT<T, M> s;
+    load_state<T, M>((const T*)A.state, np, e, s);
+    EnvT<T> E;
+    load_env<T>((const T*)A.rec, np, e, E);
+    T IA2[3], Brb[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        IA2[j] = C.inertia[j] + E.A[3 + j];
+        Brb[j] = E.buoy * C.rb[j];
+    }
+    T* ck = (T*)A.ckpt_buf;
+    T* pos = (T*)A.pos;
+    int64_t row = -1;
+    T a[M];
+    for (int k = 0; k < A.H; ++k) {
+        if (k % A.ckpt == 0) store_state<T, M>(ck + (int64_t)(k / A.ckpt) * A.ckpt_stride, np, e, s);
+        const int64_t r = action_row(A, A.t0 + k);
+        if (r != row) {
+            row = r;
+            load_action<T, M>(A, r, e, a);
+#pragma unroll
+            for (int i = 0; i < M; ++i) a[i] = clip1(a[i]);
+        }
+        step_body<T, M, false, kDz>(C, E, IA2, Brb, s, a);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) pos[(int64_t)k * A.pos_stride + j * np + e] = s.p[j];
+    }
+    store_state<T, M>((T*)A.state, np, e, s);
+}
+
+template <typename T, int M, bool kDz>
+__global__ void __launch_bounds__(256) k_rollout_bwd(AdjArgs A, ClassT<T> C) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= A.npad) return;
+    const int64_t np = A.npad;
+    EnvT<T> E;
+    load_env<T>((const T*)A.rec, np, e, E);
+    T IA2[3], Brb[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        IA2[j] = C.inertia[j] + E.A[3 + j];
+        Brb[j] = E.buoy * C.rb[j];
+    }
+    const T* ck = (const T*)A.ckpt_buf;
+    T* sg = (T*)A.seg_buf;
+    const T* dpos = (const T*)A.pos;
+    T* dact = (T*)A.dactions;
+    StateT<T, M> xb;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) xb.p[j] = T(0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) xb.q[j] = T(0);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) xb.nu[j] = T(0);
+#pragma unroll
+    for (int i = 0; i < M; ++i) xb.n[i] = T(0);
+    T gdL[6], gdQ[6], gA[6], gDt[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) gdL[j] = gdQ[j] = gA[j] = gDt[j] = T(0);
+    int64_t row_cur = -1;
+    T arow[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) arow[i] = T(0);
+
+    const int nseg = (A.H + A.ckpt - 1) / A.ckpt;
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+        const int k0 = seg * A.ckpt;
+        const int k1 = (k0 + A.ckpt < A.H) ? k0 + A.ckpt : A.H;
+        // recompute the segment's states into scratch
+        StateT<T, M> s;
+        load_state<T, M>(ck + (int64_t)seg * A.ckpt_stride, np, e, s);
+        int64_t row = -1;
+        T a[M];
+        for (int k = k0; k < k1; ++k) {
+            store_state<T, M>(sg + (int64_t)(k - k0) * A.ckpt_stride, np, e, s);
+            const int64_t r = action_row(A, A.t0 + k);
+            if (r != row) {
+                row = r;
+                load_action<T, M>(A, r, e, a);
+#pragma unroll
+                for (int i = 0; i < M; ++i) a[i] = clip1(a[i]);
+            }
+            step_body<T, M, false, kDz>(C, E, IA2, Brb, s, a);
+        }
+        // reverse sweep through the segment
+        for (int k = k1 - 1; k >= k0; --k) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) xb.p[j] += dpos[(int64_t)k * A.pos_stride + j * np + e];
+            load_state<T, M>(sg + (int64_t)(k - k0) * A.ckpt_stride, np, e, s);
+            const int64_t r = action_row(A, A.t0 + k);
+            T raw[M], ac[M], ab[M];
+            load_action<T, M>(A, r, e, raw);
+#pragma unroll
+            for (int i = 0; i < M; ++i) ac[i] = clip1(raw[i]);
+            step_vjp<T, M, kDz>(C, E, IA2, Brb, s, ac, xb, ab, gdL, gdQ, gA, gDt);
+            if (r != row_cur) {
+                if (row_cur >= 0 && dact) {
+#pragma unroll
+                    for (int i = 0; i < M; ++i) dact[row_cur * A.row_stride + i * np + e] = arow[i];
+                }
+                row_cur = r;
+#pragma unroll
+                for (int i = 0; i < M; ++i) arow[i] = T(0);
+            }
+#pragma unroll
+            for (int i = 0; i < M; ++i) arow[i] += (raw[i] > T(-1) && raw[i] < T(1)) ? ab[i] : T(0);
+        }
+    }
+    if (row_cur >= 0 && dact) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) dact[row_cur * A.row_stride + i * np + e] = arow[i];
+    }
+    if (A.dparams) {
+        T* gp = (T*)A.dparams;
+        const T inv_dt = C.inv_dt;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            gp[j * np + e] = gdL[j];
+            gp[(6 + j) * np + e] = gdQ[j];
+            // dt M^-1 = dt / (M_RB + M_A): d/dM_A = -(dt M^-1)^2 / dt
+            gp[(12 + j) * np + e] = gA[j] - gDt[j] * E.dtMinv[j] * E.dtMinv[j] * inv_dt;
+        }
+    }
+}
+
+#define MGX_ADJ_CASE(MM)                                                                                         \
+    case MM:                                                                                                     \
+        if (dz)                                                                                                  \
+            hipLaunchKernelGGL((KERNEL<T, MM, true>), dim3(grid), dim3(256), 0, s, A, C);                        \
+        else                                                                                                     \
+            hipLaunchKernelGGL((KERNEL<T, MM, false>), dim3(grid), dim3(256), 0, s, A, C);                       \
+        break;
+
+#define MGX_ADJ_SWITCH          \
+    switch (m) {                \
+        MGX_ADJ_CASE(1)         \
+        MGX_ADJ_CASE(2)         \
+        MGX_ADJ_CASE(3)         \
+        MGX_ADJ_CASE(4)         \
+        MGX_ADJ_CASE(5)         \
+        MGX_ADJ_CASE(6)         \
+        MGX_ADJ_CASE(7)         \
+        MGX_ADJ_CASE(8)         \
+        default:                \
+            return hipErrorInvalidValue; \
+    }
+
+template <typename T>
+hipError_t launch_rollout_fwd(const AdjArgs& A, const ClassT<T>& C, int m, bool dz, hipStream_t s) {
+    const unsigned grid = (unsigned)((A.npad + 255) / 256);
+#define KERNEL k_rollout_fwd
+    MGX_ADJ_SWITCH
+#undef KERNEL
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rollout_bwd(const AdjArgs& A, const ClassT<T>& C, int m, bool dz, hipStream_t s) {
+    const unsigned grid = (unsigned)((A.npad + 255) / 256);
+#define KERNEL k_rollout_bwd
+    MGX_ADJ_SWITCH
+#undef KERNEL
+    return hipGetLastError();
+}
+
+template hipError_t launch_rollout_fwd<float>(const AdjArgs&, const ClassT<float>&, int, bool, hipStream_t);
+template hipError_t launch_rollout_fwd<double>(const AdjArgs&, const ClassT<double>&, int, bool, hipStream_t);
+template hipError_t launch_rollout_bwd<float>(const AdjArgs&, const ClassT<float>&, int, bool, hipStream_t);
+template hipError_t launch_rollout_bwd<double>(const AdjArgs&, const ClassT<double>&, int, bool, hipStream_t);
+
+}  // namespace mgx
+
+using namespace mgx;
+
+static bool class_has_dz(const mgx_batch* b, int c) {
+    for (int i = 0; i < b->m[c]; ++i)
+        if (b->cls[c].deadzone[i] > 0.0) return true;
+    return false;
+}
+
+static AdjArgs adj_args(mgx_batch* b, int c) {
+    const size_t P = (size_t)b->prec;
+    AdjArgs A;
+    std::memset(&A, 0, sizeof A);
+    A.state = b->seg_state(c);
+    A.rec = b->seg_rec(c);
+    A.actions = (const char*)b->ro_actions + P * b->act_off[c];
+    A.row_stride = b->row_elems;
+    A.n_rows = b->ro_n_rows;
+    A.row0 = b->ro_row0;
+    A.hold = b->ro_hold;
+    A.H = b->ro_H;
+    A.ckpt = b->ro_ckpt;
+    A.npad = (int32_t)b->npad[c];
+    A.t0 = b->ro_t0;
+    A.ckpt_buf = (char*)b->d_ckpt + P * b->state_off[c];
+    A.ckpt_stride = b->state_elems;
+    A.seg_buf = (char*)b->d_seg + P * b->state_off[c];
+    A.pos_stride = 3 * b->npad_total;
+    A.misc = b->d_misc;
+    return A;
+}
+
+extern "C" mgx_status mgx_rollout_forward(mgx_batch* b, const void* actions, int64_t n_rows, int64_t row0, int32_t hold,
+                                          int32_t H, int32_t ckpt_every, void* pos_out) {
+    if (!b) return fail(MGX_E_INVALID, "batch is NULL");
+    if (b->faulted) return fail(MGX_E_STATE, "batch faulted by an earlier device error");
+    if (!b->params_set) return fail(MGX_E_STATE, "mgx_batch_set_params has not been called");
+    if (!actions || !pos_out) return fail(MGX_E_INVALID, "actions / pos_out is NULL");
+    if (H < 1 || H > (1 << 20)) return fail(MGX_E_INVALID, "H=%d outside [1, 2^20]", H);
+    if (ckpt_every < 1 || ckpt_every > 4096) return fail(MGX_E_INVALID, "ckpt_every=%d outside [1, 4096]", ckpt_every);
+    if (hold < 1 || n_rows < 1) return fail(MGX_E_INVALID, "hold, n_rows must be >= 1");
+    mgx_status v = validate_rows(b, b->host_t, n_rows, row0, hold, H);
+    if (v != MGX_OK) return v;
+    hipDevice_guard guard(b->device);
+    const int64_t nck = (H + ckpt_every - 1) / ckpt_every;
+    const size_t P = (size_t)b->prec;
+    const size_t ck_bytes = P * (size_t)nck * b->state_elems, seg_bytes = P * (size_t)ckpt_every * b->state_elems;
+    if (ck_bytes > b->ckpt_bytes) {
+        if (b->d_ckpt) (void)hipFree(b->d_ckpt);
+        b->d_ckpt = nullptr;
+        b->ckpt_bytes = 0;
+        hipError_t e = hipMalloc(&b->d_ckpt, ck_bytes);
+        if (e != hipSuccess) return hip_fail(nullptr, e, "hipMalloc(checkpoints)");
+        b->ckpt_bytes = ck_bytes;
+    }
+    if (seg_bytes > b->seg_bytes) {
+        if (b->d_seg) (void)hipFree(b->d_seg);
+        b->d_seg = nullptr;
+        b->seg_bytes = 0;
+        hipError_t e = hipMalloc(&b->d_seg, seg_bytes);
+        if (e != hipSuccess) return hip_fail(nullptr, e, "hipMalloc(segment scratch)");
+        b->seg_bytes = seg_bytes;
+    }
+    b->ro_actions = actions;
+    b->ro_n_rows = n_rows;
+    b->ro_row0 = row0;
+    b->ro_hold = hold;
+    b->ro_H = H;
+    b->ro_ckpt = ckpt_every;
+    b->ro_t0 = b->host_t;
+    b->ro_valid = false;
+    for (int c = 0; c < b->n_classes; ++c) {
+        AdjArgs A = adj_args(b, c);
+        A.pos = (char*)pos_out + P * 3 * b->pad_off[c];
+        A.rd = b->slot;
+        A.wr = 1 - b->slot;
+        A.advance = (c == b->n_classes - 1) ? H : 0;
+        hipError_t e;
+        if (b->prec == MGX_FP32)
+            e = launch_rollout_fwd<float>(A, b->h_class_f[c], b->m[c], class_has_dz(b, c), b->stream);
+        else
+            e = launch_rollout_fwd<double>(A, b->h_class_d[c], b->m[c], class_has_dz(b, c), b->stream);
+        if (e != hipSuccess) return hip_fail(b, e, "rollout forward launch");
+    }
+    b->slot = 1 - b->slot;
+    b->host_t += H;
+    b->ro_valid = true;
+    return MGX_OK;
+}
+
+extern "C" mgx_status mgx_rollout_backward(mgx_batch* b, const void* dpos, void* dactions, void* dparams) {
+    if (!b) return fail(MGX_E_INVALID, "batch is NULL");
+    if (b->faulted) return fail(MGX_E_STATE, "batch faulted by an earlier device error");
+    if (!b->ro_valid) return fail(MGX_E_STATE, "no forward rollout recorded");
+    if (!dpos) return fail(MGX_E_INVALID, "dpos is NULL");
+    hipDevice_guard guard(b->device);
+    const size_t P = (size_t)b->prec;
+    for (int c = 0; c < b->n_classes; ++c) {
+        AdjArgs A = adj_args(b, c);
+        A.pos = (char*)dpos + P * 3 * b->pad_off[c];
+        A.dactions = dactions ? (char*)dactions + P * b->act_off[c] : nullptr;
+        A.dparams = dparams ? (char*)dparams + P * 18 * b->pad_off[c] : nullptr;
+        hipError_t e;
+        if (b->prec == MGX_FP32)
+            e = launch_rollout_bwd<float>(A, b->h_class_f[c], b->m[c], class_has_dz(b, c), b->stream);
+        else
+            e = launch_rollout_bwd<double>(A, b->h_class_d[c], b->m[c], class_has_dz(b, c), b->stream);
+        if (e != hipSuccess) return hip_fail(b, e, "rollout backward launch");
+    }
+    return MGX_OK;
+}
+
+// ----------------------------------------------------------------------------- host check
+
+template <int M>
+static void host_vjp(const ClassT<double>& C, const EnvT<double>& E, const double* state, const double* a,
+                     const double* xbar_in, double* state_out, double* xbar_out, double* abar, double* gp) {
+    double IA2[3], Brb[3];
+    for (int j = 0; j < 3; ++j) {
+        IA2[j] = C.inertia[j] + E.A[3 + j];
+        Brb[j] = E.buoy * C.rb[j];
+    }
+    StateT<double, M> s, s1, xb;
+    auto unpack = [](const double* x, StateT<double, M>& o) {
+        for (int j = 0; j < 3; ++j) o.p[j] = x[j];
+        for (int j = 0; j < 4; ++j) o.q[j] = x[3 + j];
+        for (int j = 0; j < 6; ++j) o.nu[j] = x[7 + j];
+        for (int i = 0; i < M; ++i) o.n[i] = x[13 + i];
+    };
+    auto pack = [](const StateT<double, M>& o, double* x) {
+        for (int j = 0; j < 3; ++j) x[j] = o.p[j];
+        for (int j = 0; j < 4; ++j) x[3 + j] = o.q[j];
+        for (int j = 0; j < 6; ++j) x[7 + j] = o.nu[j];
+        for (int i = 0; i < M; ++i) x[13 + i] = o.n[i];
+    };
+    unpack(state, s);
+    s1 = s;
+    double ac[M];
+    for (int i = 0; i < M; ++i) ac[i] = clip1(a[i]);
+    if (C.has_dz)
+        step_body<double, M, false, true>(C, E, IA2, Brb, s1, ac);
+    else
+        step_body<double, M, false, false>(C, E, IA2, Brb, s1, ac);
+    pack(s1, state_out);
+    unpack(xbar_in, xb);
+    double gdL[6] = {0}, gdQ[6] = {0}, gA[6] = {0}, gDt[6] = {0};
+    if (C.has_dz)
+        step_vjp<double, M, true>(C, E, IA2, Brb, s, ac, xb, abar, gdL, gdQ, gA, gDt);
+    else
+        step_vjp<double, M, false>(C, E, IA2, Brb, s, ac, xb, abar, gdL, gdQ, gA, gDt);
+    pack(xb, xbar_out);
+    for (int j = 0; j < 6; ++j) {
+        gp[j] = gdL[j];
+        gp[6 + j] = gdQ[j];
+        gp[12 + j] = gA[j];
+        gp[18 + j] = gDt[j];
+    }
+}
+
+extern "C" mgx_status mgx_host_step_vjp(int32_t m, uint32_t batch_flags, const double* cls, const double* rec,
+                                        const double* state, const double* actions, const double* xbar_in,
+                                        double* state_out, double* xbar_out, double* abar_out, double* gparams_out) {
+    if (m < 1 || m > 8) return fail(MGX_E_INVALID, "m=%d outside [1,8]", m);
+    if (!cls || !rec || !state || !actions || !xbar_in || !state_out || !xbar_out || !abar_out || !gparams_out)
+        return fail(MGX_E_INVALID, "NULL argument");
+    ClassT<double> C;
+    std::memset(&C, 0, sizeof C);
+    const double* c = cls;
+    for (int j = 0; j < 6; ++j)
+        for (int i = 0; i < kMaxThr; ++i) C.Bk[j][i] = *c++;
+    for (int i = 0; i < kMaxThr; ++i) C.alpha[i] = *c++;
+    int has_dz = 0;
+    for (int i = 0; i < kMaxThr; ++i) {
+        C.dz[i] = *c++;
+        has_dz |= (i < m && C.dz[i] > 0.0);
+    }
+    for (int j = 0; j < 3; ++j) C.inertia[j] = *c++;
+    for (int j = 0; j < 3; ++j) C.rb[j] = *c++;
+    C.g0 = *c++;
+    C.dt = *c++;
+    C.inv_dt = 1.0 / C.dt;
+    C.half_dt = 0.5 * C.dt;
+    C.m = m;
+    C.flags = batch_flags;
+    C.has_dz = has_dz;
+    EnvT<double> E;
+    for (int j = 0; j < 6; ++j) {
+        E.dtMinv[j] = rec[kRecDtMinv + j];
+        E.A[j] = rec[kRecAdded + j];
+        E.dL[j] = rec[kRecDlin + j];
+        E.dQ[j] = rec[kRecDquad + j];
+    }
+    E.mass = rec[kRecMass];
+    E.wmb = rec[kRecWmB];
+    E.buoy = rec[kRecBuoy];
+    for (int j = 0; j < 3; ++j) E.Vc[j] = rec[kRecCurrent + j];
+    switch (m) {
+        case 1: host_vjp<1>(C, E, state, actions, xbar_in, state_out, xbar_out, abar_out, gparams_out); break;
+        case 2: host_vjp<2>(C, E, state, actions, xbar_in, state_out, xbar_out, abar_out, gparams_out); break;
+        case 3: host_vjp<3>(C, E, state, actions, xbar_in, state_out, xbar_out, abar_out, gparams_out); break;
+        case 4: host_vjp<4>(C, E, state, actions, xbar_in, state_out, xbar_out, abar_out, gparams_out); break;
+        case 5: host_vjp<5>(C, E, state, actions, xbar_in, state_out, xbar_out, abar_out, gparams_out); break;
+        case 6: host_vjp<6>(C, E, state, actions, xbar_in, state_out, xbar_out, abar_out, gparams_out); break;
+        case 7: host_vjp<7>(C, E, state, actions, xbar_in, state_out, xbar_out, abar_out, gparams_out); break;
+        default: host_vjp<8>(C, E, state, actions, xbar_in, state_out, xbar_out, abar_out, gparams_out); break;
+    }
+    return MGX_OK;
+}

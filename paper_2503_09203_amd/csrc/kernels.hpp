@@ -89,6 +89,25 @@ struct StepLaunch {
     ClassT<T> cls;
 };
 
+// Differentiable rollout, one class segment.
+struct AdjArgs {
+    void* state;           // class segment, [13+m][npad]
+    const void* rec;       // [30][npad]
+    const void* actions;   // buffer + class action offset
+    int64_t row_stride, n_rows, row0;
+    int32_t hold, H, ckpt, npad;
+    int64_t t0;            // global step at the start of the rollout
+    void* ckpt_buf;        // class segment within each checkpoint row; row stride ckpt_stride
+    int64_t ckpt_stride;   // elements per checkpoint row (state_elems)
+    void* seg_buf;         // recompute buffer, same layout, ckpt rows
+    void* pos;             // class segment within a position row (3 x npad); row stride pos_stride
+    int64_t pos_stride;
+    void* dactions;        // class segment within an action row (m x npad), or null
+    void* dparams;         // class segment [18][npad], or null
+    DevMisc* misc;
+    int32_t rd, wr, advance, pad;
+};
+
 // Host-side launchers (kernels.hip).
 hipError_t launch_set_counter(DevMisc* misc, int slot, int64_t t, hipStream_t s);
 hipError_t launch_class_setup(const ClassDesc64* d_in, ClassT<float>* d_f, ClassT<double>* d_d, int n,
@@ -117,5 +136,9 @@ template <typename T>
 hipError_t launch_step(const StepLaunch<T>& L, int m, int block, hipStream_t s);
 template <typename T>
 hipError_t launch_persistent(const PersistArgs& P, int grid, int block, hipStream_t s);
+template <typename T>
+hipError_t launch_rollout_fwd(const AdjArgs& A, const ClassT<T>& C, int m, bool dz, hipStream_t s);
+template <typename T>
+hipError_t launch_rollout_bwd(const AdjArgs& A, const ClassT<T>& C, int m, bool dz, hipStream_t s);
 
 }  // namespace mgx

@@ -156,7 +156,8 @@ static void* dalloc(size_t bytes, hipError_t* e) {
 
 static void free_batch_mem(mgx_batch* b) {
     void* ptrs[] = {b->d_state, b->d_rec, b->d_misc, b->d_classdesc, b->d_class_f, b->d_class_d, b->d_partials,
-                    b->d_stats, b->d_ids, b->d_param_stage, b->d_tiles, b->d_segs, b->d_tile_partials};
+                    b->d_stats, b->d_ids, b->d_param_stage, b->d_tiles, b->d_segs, b->d_tile_partials,
+                    b->d_ckpt, b->d_seg};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }

@@ -84,6 +84,14 @@ struct mgx_batch {
     int32_t* d_tiles = nullptr;
     mgx::SegDesc* d_segs = nullptr;
     float* d_tile_partials = nullptr;
+    // differentiable rollout: checkpoints, segment scratch, and the last forward's arguments
+    void* d_ckpt = nullptr;
+    void* d_seg = nullptr;
+    size_t ckpt_bytes = 0, seg_bytes = 0;
+    const void* ro_actions = nullptr;
+    int64_t ro_n_rows = 0, ro_row0 = 0, ro_t0 = 0;
+    int32_t ro_hold = 1, ro_H = 0, ro_ckpt = 32;
+    bool ro_valid = false;
 
     void* seg_state(int c) const { return (char*)d_state + (size_t)prec * state_off[c]; }
     void* seg_rec(int c) const { return (char*)d_rec + (size_t)prec * rec_off[c]; }

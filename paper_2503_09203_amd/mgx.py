@@ -118,6 +118,9 @@ SIGNATURES = {
     "mgx_autotune": (I32, [P, P, I64, I64, I32, I32, ctypes.POINTER(LaunchShape)]),
     "mgx_autotune_save": (I32, [ctypes.c_char_p]),
     "mgx_autotune_load": (I32, [ctypes.c_char_p]),
+    "mgx_rollout_forward": (I32, [P, P, I64, I64, I32, I32, I32, P]),
+    "mgx_rollout_backward": (I32, [P, P, P, P]),
+    "mgx_host_step_vjp": (I32, [I32, U32, P, P, P, P, P, P, P, P, P]),
     "mgx_graph_capture": (I32, [P, P, I64, I64, I32, I32, I32, U32, ctypes.POINTER(P)]),
     "mgx_graph_replay": (I32, [P]),
     "mgx_graph_destroy": (I32, [P]),
@@ -294,6 +297,25 @@ def mgx_autotune_save(path):
 
 def mgx_autotune_load(path):
     _call("mgx_autotune_load", str(path).encode())
+
+
+def mgx_rollout_forward(h, actions_ptr, n_rows, row0, hold, H, ckpt_every, pos_ptr):
+    _call("mgx_rollout_forward", h, actions_ptr, int(n_rows), int(row0), int(hold), int(H), int(ckpt_every), pos_ptr)
+
+
+def mgx_rollout_backward(h, dpos_ptr, dactions_ptr, dparams_ptr):
+    _call("mgx_rollout_backward", h, dpos_ptr, dactions_ptr, dparams_ptr)
+
+
+def mgx_host_step_vjp(m, flags, cls, rec, state, actions, xbar):
+    """Host evaluation of the step body and its adjoint (double); numpy in, numpy out."""
+    f = lambda x: np.ascontiguousarray(x, dtype=np.float64)
+    cls, rec, state, actions, xbar = f(cls), f(rec), f(state), f(actions), f(xbar)
+    s_out, xb_out, ab, gp = np.zeros(13 + m), np.zeros(13 + m), np.zeros(m), np.zeros(24)
+    p = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+    _call("mgx_host_step_vjp", int(m), int(flags), p(cls), p(rec), p(state), p(actions), p(xbar), p(s_out),
+          p(xb_out), p(ab), p(gp))
+    return s_out, xb_out, ab, gp
 
 
 def mgx_graph_capture(h, actions_ptr, n_rows, row0, hold, n_steps, K, flags=0):

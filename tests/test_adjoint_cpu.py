@@ -1,0 +1,112 @@
+"""The hand-written adjoint of the step, checked on the host (double precision) against
+central finite differences of the very step body the kernels run. Every Jacobian column
+of the state, the commands, the damping and the added mass (through the Coriolis and
+current terms and through the mass inverse) is compared."""
+import numpy as np
+import pytest
+
+import synth
+from paper_2503_09203_amd import mgx
+
+DT = 0.01
+
+
+def class_flat(c, dt=DT, deadzone=None):
+    e = c.e / np.linalg.norm(c.e, axis=1, keepdims=True)
+    Bk = np.zeros((6, 8))
+    Bk[:3, :c.m] = (e * c.k[:, None]).T
+    Bk[3:, :c.m] = (np.cross(c.r, e) * c.k[:, None]).T
+    alpha = np.zeros(8)
+    alpha[:c.m] = 1 - np.exp(-dt / c.tau)
+    dz = np.zeros(8)
+    if deadzone is not None:
+        dz[:c.m] = deadzone
+    return np.concatenate([Bk.ravel(), alpha, dz, c.inertia, c.rb, [c.g0, dt]])
+
+
+def rec_flat(c, mass, added, dlin, dquad, buoy, current, dt=DT):
+    Mrb = np.array([mass] * 3 + list(c.inertia))
+    return np.concatenate([dt / (Mrb + added), [mass], added, dlin, dquad, [mass * c.g0 - buoy, buoy], current])
+
+
+def setup(seed, m=6, omega_scale=1.0):
+    rng = np.random.default_rng(seed)
+    c = synth.draw_class(m, 7)
+    mass, added, dlin, dquad, buoy = c.mass, c.added.copy(), c.dlin.copy(), c.dquad.copy(), c.buoy * 1.01
+    current = rng.normal(0, 0.3, 3)
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    nu = rng.normal(0, 0.3, 6)
+    nu[3:] *= omega_scale
+    state = np.concatenate([rng.normal(0, 1, 3), q, nu, rng.uniform(-0.9, 0.9, m)])
+    a = rng.uniform(-0.95, 0.95, m)
+    xbar = rng.normal(size=13 + m)
+    return c, (mass, added, dlin, dquad, buoy, current), state, a, xbar
+
+
+def fd_columns(fun, x0, h):
+    cols = []
+    for i in range(len(x0)):
+        xp, xm = x0.copy(), x0.copy()
+        xp[i] += h
+        xm[i] -= h
+        cols.append((fun(xp) - fun(xm)) / (2 * h))
+    return np.array(cols)  # [n_in, n_out]
+
+
+@pytest.mark.parametrize("seed,flags,dz,omega", [(0, 0, None, 1.0), (1, mgx.FLAG_NO_AMC, None, 1.0),
+                                                  (2, 0, 0.1, 1.0), (3, 0, None, 30.0),
+                                                  (4, mgx.FLAG_LAG_EULER, None, 1.0)])
+def test_step_vjp_matches_finite_differences(seed, flags, dz, omega):
+    c, prm, state, a, xbar = setup(seed, omega_scale=omega)
+    m = c.m
+    cls = class_flat(c, deadzone=dz)
+    if flags & mgx.FLAG_LAG_EULER:
+        cls[48:48 + m] = DT / c.tau
+    rec = rec_flat(c, *prm)
+    s1, xb, ab, gp = mgx.mgx_host_step_vjp(m, flags, cls, rec, state, a, xbar)
+    h = 1e-6
+
+    def out_state(x):
+        return mgx.mgx_host_step_vjp(m, flags, cls, rec, x, a, xbar)[0]
+
+    J = fd_columns(out_state, state, h)               # d(out)/d(state_i)
+    fd_xb = J @ xbar
+    scale = np.abs(fd_xb).max()
+    assert np.allclose(xb, fd_xb, rtol=1e-5, atol=1e-6 * scale), np.abs(xb - fd_xb).max()
+
+    def out_act(u):
+        return mgx.mgx_host_step_vjp(m, flags, cls, rec, state, u, xbar)[0]
+
+    fd_ab = fd_columns(out_act, a, h) @ xbar
+    assert np.allclose(ab, fd_ab, rtol=1e-5, atol=1e-6 * np.abs(fd_ab).max())
+
+    mass, added, dlin, dquad, buoy, current = prm
+
+    def out_params(th):
+        r = rec_flat(c, mass, th[12:18], th[:6], th[6:12], buoy, current)
+        return mgx.mgx_host_step_vjp(m, flags, cls, r, state, a, xbar)[0]
+
+    theta = np.concatenate([dlin, dquad, added])
+    fd_th = fd_columns(out_params, theta, 1e-6) @ xbar
+    Mrb = np.array([mass] * 3 + list(c.inertia))
+    dtMinv = DT / (Mrb + added)
+    g_total = np.concatenate([gp[:12], gp[12:18] - gp[18:24] * dtMinv ** 2 / DT])
+    sc = np.abs(fd_th).max()
+    assert np.allclose(g_total, fd_th, rtol=1e-5, atol=1e-6 * sc), np.abs(g_total - fd_th).max()
+
+
+def test_step_body_on_host_is_the_documented_map():
+    """The host evaluation of the kernels' step body agrees with the FP64 oracle (same
+    inputs in double): both implement the same step."""
+    import oracle
+    c, prm, state, a, xbar = setup(5)
+    mass, added, dlin, dquad, buoy, current = prm
+    s1 = mgx.mgx_host_step_vjp(c.m, 0, class_flat(c), rec_flat(c, *prm), state, a, xbar)[0]
+    p = synth.EnvParams(np.array([mass]), added[:, None], dlin[:, None], dquad[:, None], np.array([buoy]),
+                        current[:, None])
+    env = oracle.make_envs(c, p, DT)
+    x = np.zeros(oracle.STATE_LEN)
+    x[:13 + c.m] = state
+    ref = oracle.step(env, x, a)
+    assert np.allclose(s1, ref[:13 + c.m], rtol=1e-12, atol=1e-14)
