@@ -314,6 +314,86 @@ mgx_status mgx_graph_capture(mgx_batch* b, const void* actions, int64_t n_rows, 
 mgx_status mgx_graph_replay(mgx_graph* g);
 mgx_status mgx_graph_destroy(mgx_graph* g);
 
+/* ------------------------------------------------------------------ serving */
+
+/* Continuous-batching server. A scheduler thread owns a device arena of budget_bytes
+ * (one hipMalloc at creation) from which every session's state and parameter record are
+ * carved; requests are admitted first-fit in arrival order as memory frees up. Each
+ * scheduling iteration advances every active request by up to chunk_steps steps in ONE
+ * persistent launch whose tiles carry their own step counts, so requests of different
+ * sizes and horizons share the device; actions are generated inside the kernel from each
+ * request's seed with the generator of mgx_gen_actions (env id local to the session, row
+ * floor(t / hold) with t counted from the session's first step). A session's state stays
+ * resident between its requests. Results are bitwise the same whatever else runs. */
+
+typedef struct mgx_server mgx_server;
+
+#define MGX_SERVE_FIFO 1u  /* one request at a time, its whole horizon in one launch (baseline) */
+
+typedef struct {
+    int32_t n_classes;
+    const int32_t* class_ids;   /* [n_classes] from mgx_class_define */
+    const double* nominal;      /* [n_classes][23]: mass, added[6], dlin[6], dquad[6], buoy, current[3] */
+    double dt;
+    uint32_t batch_flags;       /* MGX_FLAG_* */
+    uint32_t serve_flags;       /* MGX_SERVE_* */
+    int64_t budget_bytes;       /* device memory for session state + records */
+    int32_t chunk_steps;        /* steps per iteration (>= 1) */
+    int32_t max_active;         /* requests advanced together (>= 1) */
+    int32_t device;             /* -1: current device */
+    int32_t reserved;
+} mgx_server_desc;
+
+typedef struct {
+    int32_t class_index;        /* index into mgx_server_desc.class_ids */
+    int32_t hold;               /* action hold (>= 1) */
+    int64_t n_envs;             /* >= 1 (new sessions); ignored when continuing */
+    int32_t horizon;            /* steps to advance (>= 1) */
+    int32_t keep;               /* 1: keep the session resident after this request */
+    int64_t session;            /* -1: new session; else an id returned by an earlier request */
+    uint64_t seed;              /* action stream (and initial state) seed of a new session */
+    double arrival;             /* caller's timestamp (s, steady clock of mgx_server_now); 0 = now */
+} mgx_request;
+
+typedef struct {
+    int32_t state;              /* 0 queued, 1 running, 2 done, 3 cancelled, 4 failed */
+    int32_t pad;
+    int64_t session;            /* session id (valid once admitted) */
+    int64_t steps_done;
+    double t_arrival, t_admit, t_done;   /* mgx_server_now() clock */
+} mgx_request_status;
+
+typedef struct {
+    int64_t submitted, completed, cancelled, queued, active;
+    int64_t env_steps;          /* completed environment-steps */
+    int64_t iterations;         /* launches */
+    int64_t bytes_in_use, bytes_peak, budget_bytes;
+    double p50_latency, p99_latency, mean_latency;   /* s, over completed requests */
+    double wall;                /* s since creation */
+} mgx_server_stats;
+
+/* Seconds on the server clock (steady). */
+double mgx_server_now(void);
+mgx_status mgx_server_create(const mgx_server_desc* d, mgx_server** out);
+/* Thread-safe. MGX_E_BUDGET if the request alone needs more than the budget;
+ * MGX_E_INVALID on bad fields or an unknown / busy session. *request_id receives an id. */
+mgx_status mgx_server_submit(mgx_server* s, const mgx_request* r, int64_t* request_id);
+/* Thread-safe; never blocks on the device. */
+mgx_status mgx_server_poll(mgx_server* s, int64_t request_id, mgx_request_status* out);
+/* Blocks until the request is done, cancelled or failed, or timeout_s elapses (MGX_E_STATE). */
+mgx_status mgx_server_wait(mgx_server* s, int64_t request_id, double timeout_s, mgx_request_status* out);
+/* Thread-safe. A queued request is dropped; a running one stops after its in-flight
+ * iteration; its session is released unless it was kept by an earlier request. */
+mgx_status mgx_server_cancel(mgx_server* s, int64_t request_id);
+/* Copies a resident session's state ([13 + m][n_envs], component-major, float) to host
+ * memory (synchronises with the scheduler). MGX_E_INVALID if the session is not resident. */
+mgx_status mgx_server_read_state(mgx_server* s, int64_t session, float* out, int64_t capacity);
+/* Releases a kept session (after its requests finish). */
+mgx_status mgx_server_release(mgx_server* s, int64_t session);
+mgx_status mgx_server_stats_get(mgx_server* s, mgx_server_stats* out);
+/* Stops the scheduler after draining in-flight work; frees everything. */
+mgx_status mgx_server_destroy(mgx_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,6 +9,84 @@
 
 namespace mgx {
 
+// ----------------------------------------------------------------------------- Philox4x32-10
+// Counter-based generator of Salmon et al. (SC'11): ten rounds of two 32x32->64-bit
+// multiplications by fixed odd constants, the high halves xored with the other counter
+// words and the round key; the key advances by two Weyl constants between rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+__device__ __forceinline__ double u53(uint32_t hi, uint32_t lo) {
+    return ((double)(hi >> 5) * 67108864.0 + (double)(lo >> 6)) * 0x1.0p-53;
+}
+
+constexpr uint32_t kStreamInit = 3u;
+constexpr uint32_t kStreamAction = 4u;
+
+// Per-environment record (dt M^-1, m, M_A, d_L, d_Q, W - B, B, V_c), derived in double
+// (M = M_RB + M_A with M_RB = diag(m, m, m, I)) and rounded once; column i of a segment.
+template <typename T>
+__device__ __forceinline__ void write_record(const double inertia[3], double g0, double dt, double m,
+                                             const double added[6], const double dlin[6], const double dquad[6],
+                                             double buoy, const double cur[3], T* rec, int64_t npad, int64_t i) {
+    for (int j = 0; j < 6; ++j) {
+        const double Mjj = (j < 3 ? m : inertia[j - 3]) + added[j];
+        rec[(kRecDtMinv + j) * npad + i] = (T)(dt / Mjj);
+        rec[(kRecAdded + j) * npad + i] = (T)added[j];
+        rec[(kRecDlin + j) * npad + i] = (T)dlin[j];
+        rec[(kRecDquad + j) * npad + i] = (T)dquad[j];
+    }
+    rec[kRecMass * npad + i] = (T)m;
+    rec[kRecWmB * npad + i] = (T)(m * g0 - buoy);
+    rec[kRecBuoy * npad + i] = (T)buoy;
+    for (int j = 0; j < 3; ++j) rec[(kRecCurrent + j) * npad + i] = (T)cur[j];
+}
+
+// Seeded initial state of global env id g: p = 0, q uniform on S^3 (normalised Gaussian),
+// nu ~ N(0, 0.2^2), n = 0; Box-Muller over Philox words, in double, rounded once.
+template <typename T>
+__device__ __forceinline__ void seeded_state(uint64_t g, uint64_t seed, int m, T* state, int64_t npad, int64_t e) {
+    double u[10];
+    for (int j = 0; j < 5; ++j) {
+        uint32_t c[4] = {(uint32_t)g, 0u, (uint32_t)j, 0u};
+        philox4x32_10(c, (uint32_t)seed, kStreamInit << 24);
+        u[2 * j] = u53(c[0], c[1]);
+        u[2 * j + 1] = u53(c[2], c[3]);
+    }
+    double z[10];
+    for (int j = 0; j < 5; ++j) {
+        double rad = sqrt(-2.0 * log(1.0 - u[2 * j]));
+        double ang = 2.0 * M_PI * u[2 * j + 1];
+        z[2 * j] = rad * cos(ang);
+        z[2 * j + 1] = rad * sin(ang);
+    }
+    double qn = sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2] + z[3] * z[3]);
+    for (int j = 0; j < 3; ++j) state[j * npad + e] = (T)0;
+    for (int j = 0; j < 4; ++j) state[(3 + j) * npad + e] = (T)(z[j] / qn);
+    for (int j = 0; j < 6; ++j) state[(7 + j) * npad + e] = (T)(0.2 * z[4 + j]);
+    for (int i = 0; i < m; ++i) state[(kStateFixed + i) * npad + e] = (T)0;
+}
+
+// Action in [-1, 1) from a generator word: ((w >> 8) - 2^23) 2^-23, exact in float.
+__device__ __forceinline__ float action_from_word(uint32_t w) {
+    return (float)((int32_t)(w >> 8) - (1 << 23)) * 0x1.0p-23f;
+}
+
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

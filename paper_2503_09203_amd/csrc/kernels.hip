@@ -11,33 +11,6 @@
 
 namespace mgx {
 
-// ----------------------------------------------------------------------------- Philox4x32-10
-// Counter-based generator of Salmon et al. (SC'11): ten rounds of two 32x32->64-bit
-// multiplications by fixed odd constants, the high halves xored with the other counter
-// words and the round key; the key advances by two Weyl constants between rounds.
-__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
-        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-    }
-}
-
-__device__ __forceinline__ double u53(uint32_t hi, uint32_t lo) {
-    return ((double)(hi >> 5) * 67108864.0 + (double)(lo >> 6)) * 0x1.0p-53;
-}
-
-constexpr uint32_t kStreamInit = 3u;
-constexpr uint32_t kStreamAction = 4u;
 
 // ----------------------------------------------------------------------------- setup (double)
 
@@ -112,20 +85,14 @@ __global__ void k_env_setup(ParamPtrs p, int64_t env_off, int64_t n, int32_t npa
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t g = env_off + i, N = p.n_total;
-    const ClassDesc64& c = cls[ci];
-    const double m = p.mass[g];
+    double added[6], dlin[6], dquad[6], cur[3];
     for (int j = 0; j < 6; ++j) {
-        const double A = p.added[j * N + g];
-        const double Mjj = (j < 3 ? m : c.inertia[j - 3]) + A;
-        rec[(kRecDtMinv + j) * (int64_t)npad + i] = (T)(dt / Mjj);
-        rec[(kRecAdded + j) * (int64_t)npad + i] = (T)A;
-        rec[(kRecDlin + j) * (int64_t)npad + i] = (T)p.dlin[j * N + g];
-        rec[(kRecDquad + j) * (int64_t)npad + i] = (T)p.dquad[j * N + g];
+        added[j] = p.added[j * N + g];
+        dlin[j] = p.dlin[j * N + g];
+        dquad[j] = p.dquad[j * N + g];
     }
-    rec[kRecMass * (int64_t)npad + i] = (T)m;
-    rec[kRecWmB * (int64_t)npad + i] = (T)(m * c.g0 - p.buoy[g]);
-    rec[kRecBuoy * (int64_t)npad + i] = (T)p.buoy[g];
-    for (int j = 0; j < 3; ++j) rec[(kRecCurrent + j) * (int64_t)npad + i] = (T)p.current[j * N + g];
+    for (int j = 0; j < 3; ++j) cur[j] = p.current[j * N + g];
+    write_record<T>(cls[ci].inertia, cls[ci].g0, dt, p.mass[g], added, dlin, dquad, p.buoy[g], cur, rec, npad, i);
 }
 
 // Every slot of a segment to rest at the identity attitude; record zeroed (dt M^-1 = 0
@@ -147,27 +114,7 @@ __global__ void k_reset_seeded(T* state, int m, int32_t npad, int64_t env_off, i
     if (t >= n_ids) return;
     const int64_t e = ids ? ids[t] : t;
     if (e < 0 || e >= n_local) return;
-    const uint64_t g = (uint64_t)(env_off + e);
-    double u[10];
-    for (int j = 0; j < 5; ++j) {
-        uint32_t c[4] = {(uint32_t)g, 0u, (uint32_t)j, 0u};
-        philox4x32_10(c, (uint32_t)seed, kStreamInit << 24);
-        u[2 * j] = u53(c[0], c[1]);
-        u[2 * j + 1] = u53(c[2], c[3]);
-    }
-    double z[10];
-    for (int j = 0; j < 5; ++j) {
-        double rad = sqrt(-2.0 * log(1.0 - u[2 * j]));
-        double ang = 2.0 * M_PI * u[2 * j + 1];
-        z[2 * j] = rad * cos(ang);
-        z[2 * j + 1] = rad * sin(ang);
-    }
-    double qn = sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2] + z[3] * z[3]);
-    const int64_t np = npad;
-    for (int j = 0; j < 3; ++j) state[j * np + e] = (T)0;
-    for (int j = 0; j < 4; ++j) state[(3 + j) * np + e] = (T)(z[j] / qn);
-    for (int j = 0; j < 6; ++j) state[(7 + j) * np + e] = (T)(0.2 * z[4 + j]);
-    for (int i = 0; i < m; ++i) state[(kStateFixed + i) * np + e] = (T)0;
+    seeded_state<T>((uint64_t)(env_off + e), seed, m, state, npad, e);
 }
 
 template <typename T>
@@ -196,8 +143,7 @@ __global__ void k_gen_actions(T* out, int m, int32_t npad, int64_t n_valid, int6
         uint32_t c[4] = {(uint32_t)g, (uint32_t)(row_offset + row), (uint32_t)(b / 4), 0u};
         philox4x32_10(c, (uint32_t)seed, kStreamAction << 24);
         for (int w = 0; w < 4 && b + w < m; ++w) {
-            const int32_t j = (int32_t)(c[w] >> 8) - (1 << 23);
-            o[(b + w) * (int64_t)npad] = (T)((float)j * 0x1.0p-23f);
+            o[(b + w) * (int64_t)npad] = (T)action_from_word(c[w]);
         }
     }
 }

@@ -104,6 +104,8 @@ struct mgx_batch {
 
 namespace mgx {
 mgx_status hip_fail(mgx_batch* b, hipError_t e, const char* what);
+bool get_class(int32_t id, mgx_class_desc* out);
+ClassDesc64 to_desc64(const mgx_class_desc& c);
 // Enqueues K steps of every class and flips the counter slot.
 mgx_status enqueue_step(mgx_batch* b, const void* actions, int64_t n_rows, int64_t row0, int32_t hold, int32_t K,
                         bool stats, void* traj, void* forces, int block);

@@ -35,6 +35,8 @@ STEP_UNFUSED = 1
 STEP_STATS = 2
 LAUNCH_PER_CLASS = 0
 LAUNCH_PERSISTENT = 1
+SERVE_FIFO = 1
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELLED, REQ_FAILED = 0, 1, 2, 3, 4
 
 
 class MgxError(RuntimeError):
@@ -73,6 +75,32 @@ class LaunchShape(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("K", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("grid_per_cu", ctypes.c_int32), ("us_per_chunk", ctypes.c_double),
                 ("candidates", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
+
+
+class ServerDesc(ctypes.Structure):
+    _fields_ = [("n_classes", ctypes.c_int32), ("class_ids", ctypes.POINTER(ctypes.c_int32)),
+                ("nominal", ctypes.POINTER(ctypes.c_double)), ("dt", ctypes.c_double),
+                ("batch_flags", ctypes.c_uint32), ("serve_flags", ctypes.c_uint32),
+                ("budget_bytes", ctypes.c_int64), ("chunk_steps", ctypes.c_int32), ("max_active", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("class_index", ctypes.c_int32), ("hold", ctypes.c_int32), ("n_envs", ctypes.c_int64),
+                ("horizon", ctypes.c_int32), ("keep", ctypes.c_int32), ("session", ctypes.c_int64),
+                ("seed", ctypes.c_uint64), ("arrival", ctypes.c_double)]
+
+
+class RequestStatus(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("pad", ctypes.c_int32), ("session", ctypes.c_int64),
+                ("steps_done", ctypes.c_int64), ("t_arrival", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "cancelled", "queued", "active", "env_steps",
+                                               "iterations", "bytes_in_use", "bytes_peak", "budget_bytes")] + \
+               [(k, ctypes.c_double) for k in ("p50_latency", "p99_latency", "mean_latency", "wall")]
 
 
 class EnvParams(ctypes.Structure):
@@ -121,6 +149,16 @@ SIGNATURES = {
     "mgx_rollout_forward": (I32, [P, P, I64, I64, I32, I32, I32, P]),
     "mgx_rollout_backward": (I32, [P, P, P, P]),
     "mgx_host_step_vjp": (I32, [I32, U32, P, P, P, P, P, P, P, P, P]),
+    "mgx_server_now": (ctypes.c_double, []),
+    "mgx_server_create": (I32, [ctypes.POINTER(ServerDesc), ctypes.POINTER(P)]),
+    "mgx_server_submit": (I32, [P, ctypes.POINTER(Request), ctypes.POINTER(I64)]),
+    "mgx_server_poll": (I32, [P, I64, ctypes.POINTER(RequestStatus)]),
+    "mgx_server_wait": (I32, [P, I64, F64, ctypes.POINTER(RequestStatus)]),
+    "mgx_server_cancel": (I32, [P, I64]),
+    "mgx_server_read_state": (I32, [P, I64, P, I64]),
+    "mgx_server_release": (I32, [P, I64]),
+    "mgx_server_stats_get": (I32, [P, ctypes.POINTER(ServerStats)]),
+    "mgx_server_destroy": (I32, [P]),
     "mgx_graph_capture": (I32, [P, P, I64, I64, I32, I32, I32, U32, ctypes.POINTER(P)]),
     "mgx_graph_replay": (I32, [P]),
     "mgx_graph_destroy": (I32, [P]),
@@ -522,6 +560,78 @@ class Graph:
             gs = self.batch.__dict__.get("_graphs", [])
             if self in gs:
                 gs.remove(self)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------------------- serving
+
+def mgx_server_now():
+    return lib().mgx_server_now()
+
+
+class Server:
+    """Continuous-batching server (see mgx_server_* in include/mgx.h). ``classes``: vehicle
+    class objects; ``nominal``: per class an object with mass, added[6], dlin[6], dquad[6],
+    buoy, current[3] (scalars / vectors)."""
+
+    def __init__(self, classes, nominal, dt=0.01, budget_bytes=1 << 30, chunk_steps=32, max_active=256,
+                 fifo=False, batch_flags=0, device=-1):
+        ids = [mgx_class_define(c) for c in classes]
+        self.m = [c.m for c in classes]
+        nom = np.zeros((len(classes), 23))
+        for i, p in enumerate(nominal):
+            nom[i] = np.concatenate([[p["mass"]], p["added"], p["dlin"], p["dquad"], [p["buoy"]], p["current"]])
+        self._ids = (I32 * len(ids))(*ids)
+        self._nom = np.ascontiguousarray(nom)
+        d = ServerDesc(len(ids), self._ids, self._nom.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(dt),
+                       int(batch_flags), SERVE_FIFO if fifo else 0, int(budget_bytes), int(chunk_steps),
+                       int(max_active), int(device), 0)
+        h = P()
+        _call("mgx_server_create", ctypes.byref(d), ctypes.byref(h))
+        self.h = h
+
+    def submit(self, class_index, n_envs, horizon, seed, hold=10, keep=False, session=-1, arrival=0.0):
+        r = Request(int(class_index), int(hold), int(n_envs), int(horizon), 1 if keep else 0, int(session), int(seed),
+                    float(arrival))
+        rid = I64()
+        _call("mgx_server_submit", self.h, ctypes.byref(r), ctypes.byref(rid))
+        return rid.value
+
+    def poll(self, rid) -> RequestStatus:
+        st = RequestStatus()
+        _call("mgx_server_poll", self.h, int(rid), ctypes.byref(st))
+        return st
+
+    def wait(self, rid, timeout=60.0) -> RequestStatus:
+        st = RequestStatus()
+        _call("mgx_server_wait", self.h, int(rid), float(timeout), ctypes.byref(st))
+        return st
+
+    def cancel(self, rid):
+        _call("mgx_server_cancel", self.h, int(rid))
+
+    def read_state(self, session, class_index, n_envs):
+        out = np.zeros((STATE_FIXED + self.m[class_index], n_envs), dtype=np.float32)
+        _call("mgx_server_read_state", self.h, int(session), out.ctypes.data_as(ctypes.c_void_p), out.size)
+        return out
+
+    def release(self, session):
+        _call("mgx_server_release", self.h, int(session))
+
+    def stats(self) -> ServerStats:
+        s = ServerStats()
+        _call("mgx_server_stats_get", self.h, ctypes.byref(s))
+        return s
+
+    def close(self):
+        if getattr(self, "h", None):
+            _call("mgx_server_destroy", self.h)
+            self.h = None
 
     def __del__(self):
         try:

