@@ -58,8 +58,13 @@ def main():
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="dr", choices=["dr", "hetero"],
-                    help="dr: the default benchmark line; hetero: five classes in one persistent launch")
+    ap.add_argument("--workload", default="dr", choices=["dr", "hetero", "serve"],
+                    help="dr: the default benchmark line; hetero: five classes in one persistent launch; "
+                         "serve: Poisson request trace through the continuous-batching server and the FIFO baseline")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: requests per second")
+    ap.add_argument("--sweep-rates", default="", help="serve: extra comma-separated rates, 5 s each")
+    ap.add_argument("--duration", type=float, default=60.0, help="serve: trace length (s)")
+    ap.add_argument("--serve-chunk", type=int, default=0, help="serve: steps per iteration (0: whole horizon)")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark line, print launch-duration sweeps over K and N")
     args = ap.parse_args()
@@ -85,6 +90,9 @@ def main():
         return
     if args.workload == "hetero":
         hetero(args)
+        return
+    if args.workload == "serve":
+        serve(args)
         return
     w = synth.randomised(n=N, steps=T)
     cls = w.classes[0]
@@ -266,6 +274,144 @@ def hetero(args):
            "autotune": {"candidates": tuned.candidates, "us_per_chunk": tuned.us_per_chunk}, "tuned": best,
            "baseline": base, "speedup_vs_per_class": best["env_steps_per_s"] / base["env_steps_per_s"]}
     b.close()
+    print(json.dumps(out), flush=True)
+
+
+def run_trace(srv, trace, mgx):
+    """Open-loop replay: each request is submitted at its trace time (server clock). A
+    request continuing a session is submitted in session order once the session is
+    resident, keeping its trace arrival time (so the wait counts in its latency); a
+    session stays resident until its last request. Returns per-request (arrival, admit,
+    done, env-steps) for the requests that completed, and the number that did not."""
+    order = {}
+    last_of = {}
+    for k, r in enumerate(trace):
+        order[k] = order.get(("n", r["session"]), 0)
+        order[("n", r["session"])] = order[k] + 1
+        last_of[r["session"]] = k
+    t0 = mgx.mgx_server_now() + 0.05
+    first_rid, sid_of, queue, dead, ids = {}, {}, {}, set(), []
+
+    def submit(k, r, sess):
+        rid = srv.submit(r["cls"], r["n"], r["horizon"], seed=r["seed"], hold=10, keep=last_of[r["session"]] != k,
+                         session=sess, arrival=t0 + r["arrival"])
+        ids.append((rid, r))
+        return rid
+
+    i = 0
+    last_report = t0
+    n_dropped = 0
+    while i < len(trace) or any(queue.values()):
+        now = mgx.mgx_server_now()
+        if now - last_report > 1.0:
+            last_report = now
+            st = srv.stats()
+            print(f"  t={now - t0:6.1f}s submitted {len(ids)}/{len(trace)} held {sum(map(len, queue.values()))} "
+                  f"queued {st.queued} active {st.active} done {st.completed}", file=sys.stderr, flush=True)
+        while i < len(trace) and t0 + trace[i]["arrival"] <= now:
+            r = trace[i]
+            if order[i] == 0:
+                first_rid[r["session"]] = submit(i, r, -1)
+            else:
+                queue.setdefault(r["session"], []).append((i, r))
+            i += 1
+        for sess, q in queue.items():
+            if not q:
+                continue
+            if sess in dead:
+                n_dropped += len(q)
+                q.clear()
+                continue
+            if sess not in sid_of:
+                st = srv.poll(first_rid[sess])
+                if st.state in (mgx.REQ_CANCELLED, mgx.REQ_FAILED):
+                    dead.add(sess)
+                    continue
+                if st.session < 0:
+                    continue
+                sid_of[sess] = st.session
+            while q:  # in session order; the server admits each when the session is free
+                k, r = q.pop(0)
+                submit(k, r, sid_of[sess])
+        nxt = t0 + trace[i]["arrival"] if i < len(trace) else now + 2e-4
+        time.sleep(max(0.0, min(nxt - mgx.mgx_server_now(), 2e-4)))
+    out = []
+    for k, (rid, r) in enumerate(ids):
+        if k % 500 == 0:
+            st = srv.stats()
+            print(f"  collecting {k}/{len(ids)}: queued {st.queued} active {st.active} done {st.completed}",
+                  file=sys.stderr, flush=True)
+        try:
+            st = srv.wait(rid, timeout=60.0)
+        except mgx.MgxError:
+            n_dropped += 1
+            continue
+        if st.state == mgx.REQ_DONE:
+            out.append((st.t_arrival, st.t_admit, st.t_done, r["n"] * r["horizon"]))
+        else:
+            n_dropped += 1
+    return np.array(out), n_dropped
+
+
+def serve(args):
+    """Config: Poisson arrivals (rate, duration); class uniform over the five classes;
+    environments log-uniform in [64, 16384]; horizon uniform in [1, 500]; half the requests
+    continue an open session (state resident); 64 GB budget. Continuous batching against
+    the FIFO one-request-at-a-time baseline on the same trace."""
+    import synth
+    from paper_2503_09203_amd import mgx
+
+    classes = synth.hetero_classes()
+    nominal = [dict(mass=c.mass, added=c.added, dlin=c.dlin, dquad=c.dquad, buoy=c.buoy, current=np.zeros(3))
+               for c in classes]
+    import faulthandler
+    faulthandler.dump_traceback_later(900, exit=True)
+    trace = synth.serving_trace(rate=args.rate, duration=args.duration)
+    offered = sum(r["n"] * r["horizon"] for r in trace) / args.duration
+    res = {}
+    for mode in ("batched", "fifo"):
+        srv = mgx.Server(classes, nominal, budget_bytes=64 << 30, chunk_steps=args.serve_chunk, fifo=(mode == "fifo"))
+        print(f"{mode}: warm-up", file=sys.stderr, flush=True)
+        warm = [srv.submit(i % 5, 1024, 50, seed=i) for i in range(10)]
+        for w_ in warm:
+            srv.wait(w_, timeout=30.0)
+        print(f"{mode}: trace of {len(trace)} requests", file=sys.stderr, flush=True)
+        a, dropped = run_trace(srv, trace, mgx)
+        st = srv.stats()
+        srv.close()
+        lat = a[:, 2] - a[:, 0]
+        span = a[:, 2].max() - a[:, 0].min()
+        res[mode] = {"requests": int(len(a)), "not_completed": int(dropped), "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
+                     "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
+                     "mean_latency_ms": float(lat.mean() * 1e3),
+                     "p99_queue_ms": float(np.percentile(a[:, 1] - a[:, 0], 99) * 1e3),
+                     "env_steps_per_s": float(a[:, 3].sum() / span), "iterations": int(st.iterations),
+                     "bytes_peak": int(st.bytes_peak)}
+        print(json.dumps({"mode": mode, **res[mode]}), file=sys.stderr, flush=True)
+    out = {"metric": METRIC, "workload": f"serve_{args.rate:g}rps_{args.duration:g}s", "unit": "env-steps/s",
+           "value": res["batched"]["env_steps_per_s"], "offered_env_steps_per_s": offered,
+           "requests": len(trace), "chunk_steps": args.serve_chunk, "budget_bytes": 64 << 30,
+           "batched": res["batched"], "fifo_baseline": res["fifo"],
+           "p99_ratio_fifo_over_batched": res["fifo"]["p99_latency_ms"] / res["batched"]["p99_latency_ms"]}
+    sweep_out = []
+    for rate in [float(x) for x in args.sweep_rates.split(",") if x.strip()]:
+        tr = synth.serving_trace(rate=rate, duration=5.0)
+        point = {"rate": rate, "requests": len(tr),
+                 "offered_env_steps_per_s": sum(r["n"] * r["horizon"] for r in tr) / 5.0}
+        for mode in ("batched", "fifo"):
+            srv = mgx.Server(classes, nominal, budget_bytes=64 << 30, chunk_steps=args.serve_chunk,
+                             fifo=(mode == "fifo"))
+            a, dropped = run_trace(srv, tr, mgx)
+            srv.close()
+            lat = a[:, 2] - a[:, 0]
+            point[mode] = {"p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
+                           "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
+                           "env_steps_per_s": float(a[:, 3].sum() / (a[:, 2].max() - a[:, 0].min())),
+                           "not_completed": int(dropped)}
+            print(json.dumps({"rate": rate, "mode": mode, **point[mode]}), file=sys.stderr, flush=True)
+        sweep_out.append(point)
+    if sweep_out:
+        out["rate_sweep"] = sweep_out
     print(json.dumps(out), flush=True)
 
 

@@ -319,16 +319,19 @@ mgx_status mgx_graph_destroy(mgx_graph* g);
 /* Continuous-batching server. A scheduler thread owns a device arena of budget_bytes
  * (one hipMalloc at creation) from which every session's state and parameter record are
  * carved; requests are admitted first-fit in arrival order as memory frees up. Each
- * scheduling iteration advances every active request by up to chunk_steps steps in ONE
- * persistent launch whose tiles carry their own step counts, so requests of different
- * sizes and horizons share the device; actions are generated inside the kernel from each
- * request's seed with the generator of mgx_gen_actions (env id local to the session, row
- * floor(t / hold) with t counted from the session's first step). A session's state stays
- * resident between its requests. Results are bitwise the same whatever else runs. */
+ * scheduling iteration takes every admitted request that has steps left, advances it by
+ * up to chunk_steps steps (0: all remaining steps) in ONE persistent launch whose tiles
+ * carry their own step counts, and runs on the next free stream of a small pool, so that
+ * requests arriving while others run are launched at once and their work overlaps on the
+ * device; chunks of one request are ordered with events. Actions are generated inside the
+ * kernel from each session's seed with the generator of mgx_gen_actions (env id local to
+ * the session, row floor(t / hold) with t counted from the session's first step). A
+ * session's state stays resident between its requests. Results are bitwise the same
+ * whatever else runs. */
 
 typedef struct mgx_server mgx_server;
 
-#define MGX_SERVE_FIFO 1u  /* one request at a time, its whole horizon in one launch (baseline) */
+#define MGX_SERVE_FIFO 1u  /* one request at a time, its whole horizon in one launch, one stream (baseline) */
 
 typedef struct {
     int32_t n_classes;
@@ -338,10 +341,10 @@ typedef struct {
     uint32_t batch_flags;       /* MGX_FLAG_* */
     uint32_t serve_flags;       /* MGX_SERVE_* */
     int64_t budget_bytes;       /* device memory for session state + records */
-    int32_t chunk_steps;        /* steps per iteration (>= 1) */
-    int32_t max_active;         /* requests advanced together (>= 1) */
+    int32_t chunk_steps;        /* steps per iteration and request (0: all remaining) */
+    int32_t max_active;         /* requests admitted at once (>= 1) */
     int32_t device;             /* -1: current device */
-    int32_t reserved;
+    int32_t streams;            /* concurrent iterations (0: 4; 1..16) */
 } mgx_server_desc;
 
 typedef struct {

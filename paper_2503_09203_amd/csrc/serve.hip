@@ -278,11 +278,25 @@ struct Req {
     int64_t steps_done = 0, steps_sched = 0;
     double t_arr = 0, t_admit = 0, t_done = 0;
     bool cancel = false;
+    bool needs_init = false;      // new session: record and state still to be written
+    hipEvent_t last_ev = nullptr;  // event of the iteration holding this request's latest chunk
 };
 
 struct Iter {
+    int lane = 0;                  // stream of the pool it runs on
     hipEvent_t ev = nullptr;
     std::vector<std::pair<int64_t, int32_t>> work;  // (request, steps)
+};
+
+// One stream of the pool, with its own work counter and tile buffers, so that iterations
+// on different streams may run concurrently.
+struct Lane {
+    hipStream_t stream = nullptr;
+    DevMisc* misc = nullptr;
+    int slot = 0;
+    ServeTile* h_tiles = nullptr;
+    ServeTile* d_tiles = nullptr;
+    bool busy = false;
 };
 
 constexpr int kMaxTiles = 1 << 18;
@@ -292,7 +306,8 @@ constexpr int kMaxTiles = 1 << 18;
 struct mgx_server {
     mgx_server_desc d;
     int device = 0, n_cu = 256;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // set-up work
+    std::vector<Lane> lanes;
     void* arena_mem = nullptr;
     Arena arena;
     ClassDesc64* d_classdesc = nullptr;
@@ -300,11 +315,7 @@ struct mgx_server {
     ClassT<double>* d_class_d = nullptr;
     ClassT<float> h_class[MGX_MAX_CLASSES];
     double* d_nominal = nullptr;
-    DevMisc* d_misc = nullptr;
-    int slot = 0;
-    ServeTile* h_tiles[2] = {nullptr, nullptr};
-    ServeTile* d_tiles[2] = {nullptr, nullptr};
-    int tile_buf = 0;
+    int next_lane = 0;
     std::thread th;
     std::mutex mu;
     std::condition_variable cv, done_cv;
@@ -313,7 +324,7 @@ struct mgx_server {
     std::vector<int64_t> active;
     std::map<int64_t, Req> reqs;
     std::map<int64_t, Session> sessions;
-    std::deque<Iter> inflight;
+    std::vector<Iter> inflight;
     std::vector<double> latencies;
     int64_t next_req = 0, next_session = 0;
     int64_t n_submitted = 0, n_completed = 0, n_cancelled = 0, env_steps = 0, iterations = 0;
@@ -388,11 +399,7 @@ void mgx_server::admit_locked() {
             S.hold = q.r.hold;
             S.keep = q.r.keep != 0;
             S.busy = true;
-            float* base = (float*)((char*)arena_mem + off);
-            float* rec = base + (size_t)(kStateFixed + S.m) * S.npad;
-            hipLaunchKernelGGL(k_session_init, dim3((unsigned)((S.npad + 255) / 256)), dim3(256), 0, stream, base, rec, S.m,
-                               S.n, S.npad, d_classdesc, S.cls, d_nominal, d.dt, S.seed);
-            if (hipGetLastError() != hipSuccess) failed = true;
+            q.needs_init = true;
             sessions[sid] = S;
         }
         q.session = sid;
@@ -405,22 +412,45 @@ void mgx_server::admit_locked() {
 
 bool mgx_server::launch_locked() {
     const bool fifo = (d.serve_flags & MGX_SERVE_FIFO) != 0;
+    int li = -1;
+    for (int k = 0; k < (int)lanes.size(); ++k) {
+        const int c = (next_lane + k) % (int)lanes.size();
+        if (!lanes[c].busy) {
+            li = c;
+            break;
+        }
+    }
+    if (li < 0) return false;
+    Lane& L = lanes[li];
     Iter iter;
-    ServeTile* ht = h_tiles[tile_buf];
+    iter.lane = li;
+    ServeTile* ht = L.h_tiles;
     int n = 0;
+    std::vector<int64_t> picked;
     for (int64_t rid : active) {
         Req& q = reqs[rid];
         if (q.cancel || q.steps_sched >= q.r.horizon) continue;
         Session& S = sessions[q.session];
         const int64_t remaining = q.r.horizon - q.steps_sched;
-        const int32_t steps = (int32_t)(fifo ? remaining : std::min<int64_t>(remaining, d.chunk_steps));
+        const int64_t cap = (fifo || d.chunk_steps <= 0) ? remaining : std::min<int64_t>(remaining, d.chunk_steps);
+        const int32_t steps = (int32_t)cap;
         const int ntile = (int)(S.npad / kWave);
         if (n + ntile > kMaxTiles) break;
         float* base = (float*)((char*)arena_mem + S.off);
+        float* rec = base + (size_t)(kStateFixed + S.m) * S.npad;
+        if (q.needs_init) {
+            hipLaunchKernelGGL(k_session_init, dim3((unsigned)((S.npad + 255) / 256)), dim3(256), 0, L.stream, base, rec,
+                               S.m, S.n, S.npad, d_classdesc, S.cls, d_nominal, d.dt, S.seed);
+            if (hipGetLastError() != hipSuccess) failed = true;
+            q.needs_init = false;
+        } else if (q.last_ev) {
+            // the previous chunk of this request runs on another stream: order after it
+            if (hipStreamWaitEvent(L.stream, q.last_ev, 0) != hipSuccess) failed = true;
+        }
         for (int t = 0; t < ntile; ++t) {
             ServeTile& T = ht[n++];
             T.state = base;
-            T.rec = base + (size_t)(kStateFixed + S.m) * S.npad;
+            T.rec = rec;
             T.t0 = S.t_sched;
             T.seed = S.seed;
             T.npad = (int32_t)S.npad;
@@ -433,30 +463,33 @@ bool mgx_server::launch_locked() {
         S.t_sched += steps;
         q.steps_sched += steps;
         iter.work.push_back({rid, steps});
+        picked.push_back(rid);
     }
     if (n == 0) return false;
-    hipError_t e = hipMemcpyAsync(d_tiles[tile_buf], ht, sizeof(ServeTile) * n, hipMemcpyHostToDevice, stream);
+    hipError_t e = hipMemcpyAsync(L.d_tiles, ht, sizeof(ServeTile) * n, hipMemcpyHostToDevice, L.stream);
     ServeArgs P;
-    P.tiles = d_tiles[tile_buf];
+    P.tiles = L.d_tiles;
     P.cls = d_class;
     P.n_tiles = n;
     P.n_classes = d.n_classes;
-    P.misc = d_misc;
-    P.rd = slot;
-    P.wr = 1 - slot;
-    slot = 1 - slot;
-    int grid = std::min((n + 3) / 4, n_cu * 2);
+    P.misc = L.misc;
+    P.rd = L.slot;
+    P.wr = 1 - L.slot;
+    L.slot = 1 - L.slot;
+    const int grid = std::min((n + 3) / 4, n_cu * 2);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_serve, dim3(grid), dim3(256), 0, stream, P);
+        hipLaunchKernelGGL(k_serve, dim3(grid), dim3(256), 0, L.stream, P);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&iter.ev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventRecord(iter.ev, stream);
+    if (e == hipSuccess) e = hipEventRecord(iter.ev, L.stream);
     if (e != hipSuccess) {
         failed = true;
         return false;
     }
-    tile_buf = 1 - tile_buf;
+    for (int64_t rid : picked) reqs[rid].last_ev = iter.ev;
+    L.busy = true;
+    next_lane = (li + 1) % (int)lanes.size();
     ++iterations;
     inflight.push_back(std::move(iter));
     return true;
@@ -483,6 +516,11 @@ void mgx_server::complete_locked(Iter& it) {
             active.erase(std::remove(active.begin(), active.end(), w.first), active.end());
         }
     }
+    for (auto& w : it.work) {
+        Req& q = reqs[w.first];
+        if (q.last_ev == it.ev) q.last_ev = nullptr;
+    }
+    lanes[it.lane].busy = false;
     (void)hipEventDestroy(it.ev);
     done_cv.notify_all();
 }
@@ -492,12 +530,15 @@ void mgx_server::loop() {
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
         bool progress = false;
-        while (!inflight.empty()) {
-            hipError_t q = hipEventQuery(inflight.front().ev);
-            if (q == hipErrorNotReady) break;
+        for (size_t i = 0; i < inflight.size();) {
+            hipError_t q = hipEventQuery(inflight[i].ev);
+            if (q == hipErrorNotReady) {
+                ++i;
+                continue;
+            }
             if (q != hipSuccess) failed = true;
-            complete_locked(inflight.front());
-            inflight.pop_front();
+            complete_locked(inflight[i]);
+            inflight.erase(inflight.begin() + (long)i);
             progress = true;
         }
         // cancelled requests with nothing in flight leave immediately
@@ -518,7 +559,7 @@ void mgx_server::loop() {
             }
         }
         if (!failed) admit_locked();
-        if (!failed && inflight.size() < 2 && launch_locked()) progress = true;
+        if (!failed && launch_locked()) progress = true;
         if (stop && pending.empty() && active.empty() && inflight.empty()) break;
         if (failed && inflight.empty()) {
             for (auto& kv : reqs)
@@ -537,8 +578,9 @@ extern "C" mgx_status mgx_server_create(const mgx_server_desc* d, mgx_server** o
     *out = nullptr;
     if (d->n_classes < 1 || d->n_classes > MGX_MAX_CLASSES || !d->class_ids || !d->nominal)
         return fail(MGX_E_INVALID, "n_classes in [1,16] with class_ids and nominal parameters");
-    if (!(d->dt > 0) || d->chunk_steps < 1 || d->max_active < 1 || d->budget_bytes < 4096)
-        return fail(MGX_E_INVALID, "dt > 0, chunk_steps >= 1, max_active >= 1, budget >= 4096 bytes");
+    if (!(d->dt > 0) || d->chunk_steps < 0 || d->max_active < 1 || d->budget_bytes < 4096 || d->streams < 0 ||
+        d->streams > 16)
+        return fail(MGX_E_INVALID, "dt > 0, chunk_steps >= 0, max_active >= 1, budget >= 4096 bytes, streams in [0, 16]");
     if (d->batch_flags & ~(MGX_FLAG_NO_AMC | MGX_FLAG_LAG_EULER)) return fail(MGX_E_INVALID, "unknown batch flag");
     std::vector<ClassDesc64> d64(MGX_MAX_CLASSES);
     for (int c = 0; c < d->n_classes; ++c) {
@@ -560,11 +602,13 @@ extern "C" mgx_status mgx_server_create(const mgx_server_desc* d, mgx_server** o
     if (hipGetDeviceProperties(&prop, s->device) == hipSuccess && prop.multiProcessorCount > 0)
         s->n_cu = prop.multiProcessorCount;
     auto cleanup = [s]() {
-        for (int i = 0; i < 2; ++i) {
-            if (s->h_tiles[i]) (void)hipHostFree(s->h_tiles[i]);
-            if (s->d_tiles[i]) (void)hipFree(s->d_tiles[i]);
+        for (Lane& L : s->lanes) {
+            if (L.h_tiles) (void)hipHostFree(L.h_tiles);
+            if (L.d_tiles) (void)hipFree(L.d_tiles);
+            if (L.misc) (void)hipFree(L.misc);
+            if (L.stream) (void)hipStreamDestroy(L.stream);
         }
-        void* ps[] = {s->arena_mem, s->d_classdesc, s->d_class, s->d_class_d, s->d_nominal, s->d_misc};
+        void* ps[] = {s->arena_mem, s->d_classdesc, s->d_class, s->d_class_d, s->d_nominal};
         for (void* p : ps)
             if (p) (void)hipFree(p);
         if (s->stream) (void)hipStreamDestroy(s->stream);
@@ -576,15 +620,19 @@ extern "C" mgx_status mgx_server_create(const mgx_server_desc* d, mgx_server** o
     if (e == hipSuccess) e = hipMalloc((void**)&s->d_class, sizeof(ClassT<float>) * MGX_MAX_CLASSES);
     if (e == hipSuccess) e = hipMalloc((void**)&s->d_class_d, sizeof(ClassT<double>) * MGX_MAX_CLASSES);
     if (e == hipSuccess) e = hipMalloc((void**)&s->d_nominal, sizeof(double) * 23 * d->n_classes);
-    if (e == hipSuccess) e = hipMalloc((void**)&s->d_misc, sizeof(DevMisc));
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
-        e = hipHostMalloc((void**)&s->h_tiles[i], sizeof(ServeTile) * kMaxTiles, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipMalloc((void**)&s->d_tiles[i], sizeof(ServeTile) * kMaxTiles);
+    const int n_lanes = (d->serve_flags & MGX_SERVE_FIFO) ? 1 : (d->streams > 0 ? d->streams : 4);
+    s->lanes.resize(n_lanes);
+    for (int i = 0; i < n_lanes && e == hipSuccess; ++i) {
+        Lane& L = s->lanes[i];
+        e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipMalloc((void**)&L.misc, sizeof(DevMisc));
+        if (e == hipSuccess) e = hipMemset(L.misc, 0, sizeof(DevMisc));
+        if (e == hipSuccess) e = hipHostMalloc((void**)&L.h_tiles, sizeof(ServeTile) * kMaxTiles, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc((void**)&L.d_tiles, sizeof(ServeTile) * kMaxTiles);
     }
     if (e == hipSuccess) e = hipMemcpy(s->d_classdesc, d64.data(), sizeof(ClassDesc64) * MGX_MAX_CLASSES, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(s->d_nominal, d->nominal, sizeof(double) * 23 * d->n_classes, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(s->d_misc, 0, sizeof(DevMisc));
     if (e == hipSuccess) e = launch_class_setup(s->d_classdesc, s->d_class, s->d_class_d, d->n_classes, d->dt,
                                                 d->batch_flags, s->stream);
     if (e == hipSuccess)
@@ -595,6 +643,28 @@ extern "C" mgx_status mgx_server_create(const mgx_server_desc* d, mgx_server** o
         g_hip_err = (int32_t)e;
         cleanup();
         return fail(e == hipErrorOutOfMemory ? MGX_E_NOMEM : MGX_E_DEVICE, "server set-up: %s", hipGetErrorString(e));
+    }
+    // First use of a stream sets up its hardware queue: do it now, not during serving.
+    for (Lane& L : s->lanes) {
+        if (e != hipSuccess) break;
+        ServeArgs P;
+        std::memset(&P, 0, sizeof P);
+        P.tiles = L.d_tiles;
+        P.cls = s->d_class;
+        P.n_tiles = 0;
+        P.n_classes = d->n_classes;
+        P.misc = L.misc;
+        P.rd = L.slot;
+        P.wr = 1 - L.slot;
+        L.slot = 1 - L.slot;
+        hipLaunchKernelGGL(k_serve, dim3(1), dim3(256), 0, L.stream, P);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(L.stream);
+    }
+    if (e != hipSuccess) {
+        g_hip_err = (int32_t)e;
+        cleanup();
+        return fail(MGX_E_DEVICE, "server stream warm-up: %s", hipGetErrorString(e));
     }
     s->arena.init((size_t)d->budget_bytes);
     s->t_create = now_s();
@@ -751,11 +821,14 @@ extern "C" mgx_status mgx_server_destroy(mgx_server* s) {
     if (s->th.joinable()) s->th.join();
     hipDevice_guard g(s->device);
     (void)hipStreamSynchronize(s->stream);
-    for (int i = 0; i < 2; ++i) {
-        if (s->h_tiles[i]) (void)hipHostFree(s->h_tiles[i]);
-        if (s->d_tiles[i]) (void)hipFree(s->d_tiles[i]);
+    for (Lane& L : s->lanes) {
+        if (L.stream) (void)hipStreamSynchronize(L.stream);
+        if (L.h_tiles) (void)hipHostFree(L.h_tiles);
+        if (L.d_tiles) (void)hipFree(L.d_tiles);
+        if (L.misc) (void)hipFree(L.misc);
+        if (L.stream) (void)hipStreamDestroy(L.stream);
     }
-    void* ps[] = {s->arena_mem, s->d_classdesc, s->d_class, s->d_class_d, s->d_nominal, s->d_misc};
+    void* ps[] = {s->arena_mem, s->d_classdesc, s->d_class, s->d_class_d, s->d_nominal};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     (void)hipStreamDestroy(s->stream);

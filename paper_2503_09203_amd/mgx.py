@@ -82,7 +82,7 @@ class ServerDesc(ctypes.Structure):
                 ("nominal", ctypes.POINTER(ctypes.c_double)), ("dt", ctypes.c_double),
                 ("batch_flags", ctypes.c_uint32), ("serve_flags", ctypes.c_uint32),
                 ("budget_bytes", ctypes.c_int64), ("chunk_steps", ctypes.c_int32), ("max_active", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("streams", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -579,8 +579,8 @@ class Server:
     class objects; ``nominal``: per class an object with mass, added[6], dlin[6], dquad[6],
     buoy, current[3] (scalars / vectors)."""
 
-    def __init__(self, classes, nominal, dt=0.01, budget_bytes=1 << 30, chunk_steps=32, max_active=256,
-                 fifo=False, batch_flags=0, device=-1):
+    def __init__(self, classes, nominal, dt=0.01, budget_bytes=1 << 30, chunk_steps=0, max_active=4096,
+                 fifo=False, batch_flags=0, device=-1, streams=0):
         ids = [mgx_class_define(c) for c in classes]
         self.m = [c.m for c in classes]
         nom = np.zeros((len(classes), 23))
@@ -590,7 +590,7 @@ class Server:
         self._nom = np.ascontiguousarray(nom)
         d = ServerDesc(len(ids), self._ids, self._nom.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(dt),
                        int(batch_flags), SERVE_FIFO if fifo else 0, int(budget_bytes), int(chunk_steps),
-                       int(max_active), int(device), 0)
+                       int(max_active), int(device), int(streams))
         h = P()
         _call("mgx_server_create", ctypes.byref(d), ctypes.byref(h))
         self.h = h
