@@ -65,6 +65,9 @@ def main():
     ap.add_argument("--sweep-rates", default="", help="serve: extra comma-separated rates, 5 s each")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: trace length (s)")
     ap.add_argument("--serve-chunk", type=int, default=0, help="serve: steps per iteration (0: whole horizon)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain device copy (negation) of this many MiB, read and written once, so that "
+                         "hardware byte counters collected over this run can be scaled against a known size")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark line, print launch-duration sweeps over K and N")
     args = ap.parse_args()
@@ -85,6 +88,13 @@ def main():
     mgx.lib()  # fail loudly if the HIP library is missing
 
     N, T, K, HOLD = args.n, args.rollout, args.chunk, 10
+    if args.copy_calibration_mib:
+        src = torch.ones(args.copy_calibration_mib << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     if args.sweep:
         sweep(args)
         return
