@@ -41,6 +41,37 @@ def bytes_per_env_step(m, K, hold, prec=4, rec_len=30):
     return (2 * state + rec_len * prec + rows * m * prec) / K
 
 
+# Hardware byte counters cannot be read from inside this process; the per-launch HBM traffic
+# of the step kernel comes from the committed rocprofv3 summary, and only while the kernel
+# sources still hash to the value recorded with those counters (else null).
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_step_dr65536x1000.md")
+KERNEL_SOURCES = ("step.hpp", "env_loop.hpp", "kernels.hip", "kernels.hpp")
+
+
+def kernel_sources_sha256():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2503_09203_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """{K: bytes per launch} from the profile's 'traffic:' line, if its source hash matches."""
+    import re
+
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return {}
+    m = re.search(r"^traffic: (.*); sources sha256 ([0-9a-f]{64})$", text, re.M)
+    if not m or m.group(2) != kernel_sources_sha256():
+        return {}
+    return {int(k): float(v) for k, v in re.findall(r"K=(\d+) (\d+) B/launch", m.group(1))}
+
+
 def parity_errors(gpu, ref):
     """Per-component max_env |gpu - ref| / max(|ref|, rms of the component)."""
     rms = np.sqrt(np.mean(ref * ref, axis=1, keepdims=True))
@@ -58,9 +89,10 @@ def main():
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="dr", choices=["dr", "hetero", "serve"],
+    ap.add_argument("--workload", default="dr", choices=["dr", "hetero", "serve", "adjoint"],
                     help="dr: the default benchmark line; hetero: five classes in one persistent launch; "
-                         "serve: Poisson request trace through the continuous-batching server and the FIFO baseline")
+                         "serve: Poisson request trace through the continuous-batching server and the FIFO baseline; "
+                         "adjoint: checkpointed forward and reverse sweep of the differentiable rollout")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: requests per second")
     ap.add_argument("--sweep-rates", default="", help="serve: extra comma-separated rates, 5 s each")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: trace length (s)")
@@ -103,6 +135,9 @@ def main():
         return
     if args.workload == "serve":
         serve(args)
+        return
+    if args.workload == "adjoint":
+        adjoint(args)
         return
     w = synth.randomised(n=N, steps=T)
     cls = w.classes[0]
@@ -167,6 +202,7 @@ def main():
     single_rate = N * T * reps1 / (time.perf_counter() - t1)
     single_launch = float(np.mean([a.elapsed_time(c) for a, c in ev1[1:]])) * 1e-3 / T
     single_bytes = bytes_per_env_step(cls.m, 1, HOLD) * N
+    traffic = recorded_traffic() if (N, T, HOLD) == (65536, 1000, 10) else {}
 
     out = {
         "metric": METRIC,
@@ -186,7 +222,8 @@ def main():
                    "path": "set_params + reset + graph of fused launches"},
         "roofline": {"bound": "alu", "achieved": fused_flops_per_launch / fused_launch / 1e12,
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
-                     "frac": fused_flops_per_launch / fused_launch / PEAK_FP32_VECTOR, "traffic": None,
+                     "frac": fused_flops_per_launch / fused_launch / PEAK_FP32_VECTOR, "traffic": traffic.get(K),
+                     "traffic_unit": "B/launch",
                      "kernel": f"k_step<float,{cls.m},false> K={K}", "launches_per_step": n_launch,
                      "launch_us_mean": fused_launch * 1e6, "flops_per_env_step": flops_es,
                      "valu_ops_per_env_step": ops_es},
@@ -195,7 +232,8 @@ def main():
                         "roofline": {"bound": "hbm", "achieved": single_bytes / single_launch / 1e9,
                                      "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                                      "frac": single_bytes / single_launch / PEAK_HBM,
-                                     "bytes_per_env_step": bytes_per_env_step(cls.m, 1, HOLD)}},
+                                     "bytes_per_env_step": bytes_per_env_step(cls.m, 1, HOLD),
+                                     "traffic": traffic.get(1), "traffic_unit": "B/launch"}},
     }
 
     if not args.no_cpu_baseline:
@@ -422,6 +460,54 @@ def serve(args):
         sweep_out.append(point)
     if sweep_out:
         out["rate_sweep"] = sweep_out
+    print(json.dumps(out), flush=True)
+
+
+def adjoint(args):
+    """The differentiable rollout: 8192 environments of the 8-thruster class, horizon 256,
+    per-step actions, checkpoints every 32 steps. Times the forward (positions after every
+    step, checkpoints) and the backward (per-segment recomputation and the reverse sweep,
+    gradients for every action and per-environment d_L, d_Q, M_A) through the C ABI."""
+    import ctypes
+
+    import torch
+
+    import synth
+    from paper_2503_09203_amd import mgx
+
+    N, H, CK = 8192, 256, 32
+    w = synth.differentiable(n=N, horizon=H)
+    b = mgx.Batch(w.classes, w.n_envs, w.dt)
+    b.set_params(w.params)
+    init = torch.tensor(b.pack_state([w.state[0].stacked()]), dtype=torch.float32, device="cuda:0")
+    acts = torch.tensor(b.pack_actions([w.actions(H)[0]]), dtype=torch.float32, device="cuda:0")
+    L = b.layout
+    pos = torch.empty((H, 3 * L.n_pad_total), dtype=torch.float32, device="cuda:0")
+    dpos = torch.randn_like(pos)
+    dact = torch.zeros_like(acts)
+    dpar = torch.zeros(18 * L.n_pad_total, dtype=torch.float32, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    vp = lambda t: ctypes.c_void_p(t.data_ptr())
+    fw, bw = [], []
+    for i in range(args.warmup + args.steps):
+        b.set_state(init)
+        b.t = 0
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(stream)
+        mgx.mgx_rollout_forward(b.h, vp(acts), H, 0, 1, H, CK, vp(pos))
+        e[1].record(stream)
+        mgx.mgx_rollout_backward(b.h, vp(dpos), vp(dact), vp(dpar))
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        if i >= args.warmup:
+            fw.append(e[0].elapsed_time(e[1]) * 1e-3)
+            bw.append(e[1].elapsed_time(e[2]) * 1e-3)
+    f, g = float(np.mean(fw)), float(np.mean(bw))
+    out = {"metric": METRIC, "workload": f"adjoint_{N}x{H}", "unit": "env-steps/s", "value": N * H / (f + g),
+           "n_envs": N, "horizon": H, "checkpoint_every": CK, "thrusters": w.classes[0].m,
+           "forward_ms": f * 1e3, "backward_ms": g * 1e3, "forward_env_steps_per_s": N * H / f,
+           "backward_env_steps_per_s": N * H / g, "backward_over_forward": g / f}
+    b.close()
     print(json.dumps(out), flush=True)
 
 

@@ -65,12 +65,12 @@ __device__ __forceinline__ void load_action(const AdjArgs& A, int64_t row, int64
 }
 
 template <typename T, int M, bool kDz>
-__global__ void __launch_bounds__(256) k_rollout_fwd(AdjArgs A, ClassT<T> C) {
+__global__ void __launch_bounds__(256) k_rollout_fwd(AdjArgs A, ClassT<T> Cs) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const ClassT<T> C = class_in_vgpr<T, M>(Cs);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (A.advance) A.misc->t[A.wr] = A.t0 + A.advance;
-        A.misc->work[A.wr] = 0u;
-        A.misc->exits[A.wr] = 0u;
+        prepare_next_slot(A.misc, A.wr);
     }
     if (e >= A.npad) return;
     const int64_t np = A.npad;
@@ -78,6 +78,7 @@ __global__ void __launch_bounds__(256) k_rollout_fwd(AdjArgs A, ClassT<T> C) {
     load_state<T, M>((const T*)A.state, np, e, s);
     EnvT<T> E;
     load_env<T>((const T*)A.rec, np, e, E);
+    set_amc(E, C.flags);
     T IA2[3], Brb[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -105,12 +106,14 @@ __global__ void __launch_bounds__(256) k_rollout_fwd(AdjArgs A, ClassT<T> C) {
 }
 
 template <typename T, int M, bool kDz>
-__global__ void __launch_bounds__(256) k_rollout_bwd(AdjArgs A, ClassT<T> C) {
+__global__ void __launch_bounds__(256) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const ClassT<T> C = class_in_vgpr<T, M>(Cs);
     if (e >= A.npad) return;
     const int64_t np = A.npad;
     EnvT<T> E;
     load_env<T>((const T*)A.rec, np, e, E);
+    set_amc(E, C.flags);
     T IA2[3], Brb[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -441,6 +444,7 @@ extern "C" mgx_status mgx_host_step_vjp(int32_t m, uint32_t batch_flags, const d
     E.wmb = rec[kRecWmB];
     E.buoy = rec[kRecBuoy];
     for (int j = 0; j < 3; ++j) E.Vc[j] = rec[kRecCurrent + j];
+    set_amc(E, C.flags);
     switch (m) {
         case 1: host_vjp<1>(C, E, state, actions, xbar_in, state_out, xbar_out, abar_out, gparams_out); break;
         case 2: host_vjp<2>(C, E, state, actions, xbar_in, state_out, xbar_out, abar_out, gparams_out); break;

@@ -76,6 +76,7 @@ static CostTally measure(uint32_t flags) {
     E.wmb = -1;
     E.buoy = 118;
     for (int j = 0; j < 3; ++j) E.Vc[j] = 0.1 * (j + 1);
+    set_amc(E, flags);
     Cnt IA2[3] = {2, 3, 4}, Brb[3] = {0, 0, -1.18};
     StateT<Cnt, M> s;
     for (int j = 0; j < 3; ++j) s.p[j] = 0;

@@ -139,14 +139,44 @@ __device__ __forceinline__ void final_reduce_stats(const float* partials, unsign
     out[j] = acc;
 }
 
+// A wave-uniform value moved to a vector register and hidden from the uniformity analysis,
+// so the compiler keeps it there. The allocation columns (6 x m values) would otherwise sit
+// in scalar registers, which cannot hold them next to the loop's own scalars for m = 8.
+__device__ __forceinline__ float in_vgpr(float x) {
+    asm("" : "+v"(x));
+    return x;
+}
+__device__ __forceinline__ double in_vgpr(double x) {
+    asm("" : "+v"(x));
+    return x;
+}
+
+// A copy of the class constants for the step loop. With more than six thrusters the
+// per-thruster arrays (k-scaled layout columns, lag factors) move to vector registers;
+// up to six they fit the scalar file next to the loop's own scalars and stay there.
+template <typename T, int M>
+__device__ __forceinline__ ClassT<T> class_in_vgpr(const ClassT<T>& Cs) {
+    ClassT<T> C = Cs;
+    if constexpr (M > 6) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+#pragma unroll
+            for (int j = 0; j < 6; ++j) C.Bk[j][i] = in_vgpr(Cs.Bk[j][i]);
+            C.alpha[i] = in_vgpr(Cs.alpha[i]);
+        }
+    }
+    return C;
+}
+
 // K steps of environment `env` (a slot of the segment described by A) from global step
 // t0. Commands are fetched raw one hold interval before use and clipped when their row
 // becomes current; all prologue loads are drained once before the loop so that the only
 // memory operations in flight inside it are those prefetches.
 template <typename T, int M, bool kOut, bool kDz>
-__device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& C, int64_t env, int64_t t0, int K,
+__device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs, int64_t env, int64_t t0, int K,
                                           float st[kStats]) {
     const int64_t np = A.npad;
+    const ClassT<T> C = class_in_vgpr<T, M>(Cs);
     T* S = (T*)A.state;
     const T* Rc = (const T*)A.rec;
     StateT<T, M> s;
@@ -171,6 +201,7 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& C,
     E.buoy = Rc[kRecBuoy * np + env];
 #pragma unroll
     for (int j = 0; j < 3; ++j) E.Vc[j] = Rc[(kRecCurrent + j) * np + env];
+    set_amc(E, C.flags);
 
     // Action rows, relative to the buffer start, uniform across the wave. Every fetch is
     // issued unconditionally at a row index clamped into the buffer (validity is tracked

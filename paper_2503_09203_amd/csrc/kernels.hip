@@ -159,8 +159,7 @@ __global__ void __launch_bounds__(256) k_step(StepLaunch<T> L) {
     const int64_t t0 = A.misc->t[A.rd];
     if (blockIdx.x == 0 && tid == 0) {
         if (A.advance) A.misc->t[A.wr] = t0 + A.advance;
-        A.misc->work[A.wr] = 0u;  // the next launch may be a persistent one
-        A.misc->exits[A.wr] = 0u;
+        prepare_next_slot(A.misc, A.wr);  // the next launch may be a persistent one
     }
     float st[kStats];
 #pragma unroll
@@ -195,8 +194,7 @@ __global__ void __launch_bounds__(256) k_step(StepLaunch<T> L) {
 __global__ void k_set_counter(DevMisc* misc, int slot, int64_t t) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         misc->t[slot] = t;
-        misc->work[slot] = 0u;
-        misc->exits[slot] = 0u;
+        prepare_next_slot(misc, slot);
     }
 }
 

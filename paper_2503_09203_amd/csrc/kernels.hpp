@@ -36,9 +36,16 @@ struct DevMisc {
     int32_t err;
     int32_t pad;
     uint32_t done[16];
-    uint32_t work[2];   // persistent launch: next tile (slot rd), reset for the next launch (slot wr)
+    uint32_t work[2];   // persistent launches: tiles handed out past the first round (slot rd)
     uint32_t exits[2];  // persistent launch with statistics: waves finished
 };
+
+// Run by one thread of every launch that reads slot rd: clears the counters of slot wr for
+// the launch after it.
+__device__ __forceinline__ void prepare_next_slot(DevMisc* m, int wr) {
+    m->work[wr] = 0u;
+    m->exits[wr] = 0u;
+}
 
 // One class segment as the persistent kernel sees it.
 struct SegDesc {
@@ -58,7 +65,9 @@ struct PersistArgs {
     int64_t row_stride, n_rows, row0;
     int32_t hold, K;
     DevMisc* misc;
-    int32_t rd, wr, advance, pad;
+    int32_t rd, wr, advance;
+    int32_t n_heavy;       // tiles [0, n_heavy) go first to the first wave on each SIMD
+    uint32_t* simd_rank;   // [kSimdKeys] arrival table, or null
     float* tile_partials;  // [n_tiles][kStats] or null
     double* stats;         // [16][kStats]
 };

@@ -1,11 +1,13 @@
 // Persistent heterogeneous launch: every vehicle class of a batch advanced by one kernel.
 //
-// Each block copies every class's constants and segment descriptor into LDS once; its
-// waves then pull 64-environment tiles from a device work counter until the table is
-// exhausted. A tile belongs to one class, so the thruster count is uniform per wave and
-// the `switch` over m selects a fully unrolled step body without divergence. The work
-// counter is double-buffered like the step counter: block 0 clears the slot the next
-// launch will use, so no end-of-launch handshake is needed.
+// Each block copies every class's constants and segment descriptor into LDS once. Wave w
+// of the grid then runs tile w of the table (heaviest class first), and waves that finish
+// pull the tiles beyond the grid from a device counter. The first round takes no atomic:
+// every wave incrementing one counter at launch serialises on that address (about 13 ns
+// each, so a thousand waves would start over 13 us). A tile belongs to one class, so the
+// thruster count is uniform per wave and the `switch` over m selects a fully unrolled step
+// body without divergence. The counter is double-buffered like the step counter: block 0
+// clears the slot the next launch will use, so no end-of-launch handshake is needed.
 #include <hip/hip_runtime.h>
 
 #include "env_loop.hpp"
@@ -76,16 +78,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
     const int64_t t0 = P.misc->t[P.rd];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (P.advance) P.misc->t[P.wr] = t0 + P.advance;
-        P.misc->work[P.wr] = 0u;
-        P.misc->exits[P.wr] = 0u;
+        prepare_next_slot(P.misc, P.wr);
     }
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t n_waves = gridDim.x * (blockDim.x / kWave);
 
-    for (;;) {
-        uint32_t tile = 0;
-        if (lane == 0) tile = atomicAdd(&P.misc->work[P.rd], 1u);
-        tile = __builtin_amdgcn_readfirstlane(__shfl(tile, 0, kWave));
+    uint32_t tile = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    for (;; tile = 0xFFFFFFFFu) {
+        if (tile == 0xFFFFFFFFu) {
+            uint32_t i = 0;
+            if (lane == 0) i = atomicAdd(&P.misc->work[P.rd], 1u);
+            tile = n_waves + __builtin_amdgcn_readfirstlane(__shfl(i, 0, kWave));
+        }
         if (tile >= (uint32_t)P.n_tiles) break;
         const int c = __builtin_amdgcn_readfirstlane(P.tiles[2 * tile]);
         const int env0 = __builtin_amdgcn_readfirstlane(P.tiles[2 * tile + 1]);
@@ -143,8 +148,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
     uint32_t prev = 0;
     if (lane == 0) prev = atomicAdd(&P.misc->exits[P.rd], 1u);
     prev = __builtin_amdgcn_readfirstlane(__shfl(prev, 0, kWave));
-    const uint32_t total_waves = gridDim.x * (blockDim.x / kWave);
-    if (prev != total_waves - 1) return;
+    if (prev != n_waves - 1) return;
     __threadfence();
     if (lane < kStats) {
         const int j = lane;

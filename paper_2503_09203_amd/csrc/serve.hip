@@ -53,7 +53,8 @@ __device__ __forceinline__ void session_actions(uint64_t seed, int64_t e, int64_
 }
 
 template <int M, bool kDz>
-__device__ __forceinline__ void serve_env(const ServeTile& T, const ClassT<float>& C, int64_t e) {
+__device__ __forceinline__ void serve_env(const ServeTile& T, const ClassT<float>& Cs, int64_t e) {
+    const ClassT<float> C = class_in_vgpr<float, M>(Cs);
     const int64_t np = T.npad;
     float* S = T.state;
     const float* Rc = T.rec;
@@ -79,6 +80,7 @@ __device__ __forceinline__ void serve_env(const ServeTile& T, const ClassT<float
     E.buoy = Rc[kRecBuoy * np + e];
 #pragma unroll
     for (int j = 0; j < 3; ++j) E.Vc[j] = Rc[(kRecCurrent + j) * np + e];
+    set_amc(E, C.flags);
     float IA2[3], Brb[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -158,15 +160,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
         for (int i = threadIdx.x; i < nw; i += blockDim.x) dst[i] = src[i];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        P.misc->work[P.wr] = 0u;
-        P.misc->exits[P.wr] = 0u;
+        prepare_next_slot(P.misc, P.wr);
     }
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1);
-    for (;;) {
-        uint32_t tile = 0;
-        if (lane == 0) tile = atomicAdd(&P.misc->work[P.rd], 1u);
-        tile = __builtin_amdgcn_readfirstlane(__shfl(tile, 0, kWave));
+    const uint32_t n_waves = gridDim.x * (blockDim.x / kWave);
+    // Wave w runs tile w; tiles beyond the grid come from the counter (as in the
+    // persistent step kernel, so that the launch does not start behind one atomic).
+    uint32_t tile = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    for (;; tile = 0xFFFFFFFFu) {
+        if (tile == 0xFFFFFFFFu) {
+            uint32_t i = 0;
+            if (lane == 0) i = atomicAdd(&P.misc->work[P.rd], 1u);
+            tile = n_waves + __builtin_amdgcn_readfirstlane(__shfl(i, 0, kWave));
+        }
         if (tile >= (uint32_t)P.n_tiles) break;
         const ServeTile T = P.tiles[tile];
         const int c = __builtin_amdgcn_readfirstlane(T.cls);

@@ -70,7 +70,16 @@ struct EnvT {
     T wmb;
     T buoy;
     T Vc[3];
+    T Ah[3];  // coefficients of the added-mass current term: A1, or 0 with kFlagNoAmc
 };
+
+// Fills EnvT::Ah from the added mass and the batch flags (once per environment, so that
+// the step loop carries no branch on the flag).
+template <typename T>
+__host__ __device__ __forceinline__ void set_amc(EnvT<T>& E, uint32_t flags) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) E.Ah[j] = (flags & kFlagNoAmc) ? T(0) : E.A[j];
+}
 
 template <typename T, int M>
 struct StateT {
@@ -92,6 +101,10 @@ __host__ __device__ __forceinline__ float copysign_(float a, float b) { return _
 __host__ __device__ __forceinline__ double copysign_(double a, double b) { return __builtin_copysign(a, b); }
 __host__ __device__ __forceinline__ float sqrt_(float a) { return __builtin_sqrtf(a); }
 __host__ __device__ __forceinline__ double sqrt_(double a) { return __builtin_sqrt(a); }
+
+// True if the predicate holds on any active lane of the wavefront (on the host: itself).
+__device__ __forceinline__ bool any_lane(bool p) { return __any(p); }
+__host__ __forceinline__ bool any_lane(bool p) { return p; }
 
 // Command clip to [-1, 1] that lets NaN through (a NaN command marks the env non-finite).
 template <typename T>
@@ -119,10 +132,13 @@ __host__ __device__ __forceinline__ void quat_increment(T h, const T w[3], T& c,
         s = wn > 0.0 ? sin(phi) / wn : h;
     } else {
         T phi2 = (h * h) * w2;
-        if (phi2 <= T(0.0025f)) {
-            c = fma_(fma_(phi2, T(1.0f / 24.0f), T(-0.5f)), phi2, T(1.0f));
-            s = h * fma_(fma_(phi2, T(1.0f / 120.0f), T(-1.0f / 6.0f)), phi2, T(1.0f));
-        } else {
+        c = fma_(fma_(phi2, T(1.0f / 24.0f), T(-0.5f)), phi2, T(1.0f));
+        s = h * fma_(fma_(phi2, T(1.0f / 120.0f), T(-1.0f / 6.0f)), phi2, T(1.0f));
+        // the exact form where the series is not accurate enough: evaluated by the whole
+        // wavefront when any lane needs it and selected per lane, so the common case is one
+        // uniform branch with no execution-mask bookkeeping
+        const bool big = !(phi2 <= T(0.0025f));
+        if (any_lane(big)) {
             T phi = sqrt_(phi2);
             T sn, cs;
             if constexpr (std::is_same<T, float>::value) {
@@ -131,8 +147,9 @@ __host__ __device__ __forceinline__ void quat_increment(T h, const T w[3], T& c,
                 sn = sin(phi);
                 cs = cos(phi);
             }
-            c = cs;
-            s = sn * h / phi;
+            const T se = sn * h / phi;
+            c = big ? cs : c;
+            s = big ? se : s;
         }
     }
 }
@@ -207,14 +224,12 @@ __host__ __device__ __forceinline__ void step_body(const ClassT<T>& C, const Env
     cross(vr, A1vr, t1);
 #pragma unroll
     for (int j = 0; j < 3; ++j) cor_ang[j] = cor_ang[j] + t1[j];
-    // added-mass term of the rotating current projection: A1 (w x v_c)
-    T hA[3] = {T(0), T(0), T(0)};
-    if (!(C.flags & kFlagNoAmc)) {
-        T wvc[3];
-        cross(w, vc, wvc);
+    // added-mass term of the rotating current projection: A1 (w x v_c) (coefficients 0
+    // when the term is switched off)
+    T hA[3], wvc[3];
+    cross(w, vc, wvc);
 #pragma unroll
-        for (int j = 0; j < 3; ++j) hA[j] = E.A[j] * wvc[j];
-    }
+    for (int j = 0; j < 3; ++j) hA[j] = E.Ah[j] * wvc[j];
     // damping on nu_r = (v_r, w)
     T damp[6];
 #pragma unroll
