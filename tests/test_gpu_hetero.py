@@ -22,28 +22,31 @@ def _advance(b, acts, steps, K, hold=10):
         done += k
 
 
-@pytest.mark.parametrize("scale", [0.05, 1.0])
-def test_persistent_equals_per_class_bitwise(scale):
+@pytest.mark.parametrize("scale,block,gpc", [(0.05, 256, 2), (1.0, 256, 2), (1.0, 64, 1)])
+def test_persistent_equals_per_class_bitwise(scale, block, gpc):
+    """(1.0, 64, 1): 256 waves for 1,103 tiles, so most tiles come from the device counter
+    after each wave's first one."""
     t = torch()
     w = synth.heterogeneous(scale=scale, steps=64)
     acts = w.actions(8)
     outs = []
     for mode in (mgx.LAUNCH_PER_CLASS, mgx.LAUNCH_PERSISTENT):
         b = make_batch(w)
-        b.set_shape(mode, 16)
+        b.set_shape(mode, 16, block, gpc)
         _advance(b, device_actions(b, acts), 64, 16)
         outs.append(b.get_state())
         b.close()
     assert t.equal(outs[0], outs[1])
 
 
-def test_persistent_statistics_match_per_class():
-    w = synth.heterogeneous(scale=0.1, steps=20)
+@pytest.mark.parametrize("block,gpc", [(256, 2), (64, 1)])
+def test_persistent_statistics_match_per_class(block, gpc):
+    w = synth.heterogeneous(scale=0.5, steps=20)
     acts = w.actions(2)
     st = []
     for mode in (mgx.LAUNCH_PER_CLASS, mgx.LAUNCH_PERSISTENT):
         b = make_batch(w)
-        b.set_shape(mode, 20)
+        b.set_shape(mode, 20, block, gpc)
         b.step(device_actions(b, acts), 20, hold=10, flags=mgx.STEP_STATS)
         st.append(b.stats())
         assert b.check() == (mgx.MGX_OK, 0)

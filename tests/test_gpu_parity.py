@@ -94,6 +94,28 @@ def test_actuator_and_model_variants(flags):
     check(res, {1: 1e-5, 200: 1e-3}, f"variant{flags}")
 
 
+def test_fast_spin_takes_the_exact_attitude_increment():
+    """Odd environments spin at 15-40 rad/s about their largest principal axis (a stable
+    rotation), where |w| dt / 2 > 0.05 and the attitude increment is evaluated exactly with
+    sincos; even ones keep the slow initial rates of the series form, so the lanes of every
+    wavefront take both forms. Angular damping is made small so that the spin persists."""
+    w = synth.randomised(n=256, steps=100)
+    p, c, st = w.params, w.classes[0], w.state[0]
+    p.dquad[3:] = 0.0
+    p.dlin[3:] = float(np.float32(0.05))       # inputs stay exact in float32
+    rng = np.random.default_rng(7)
+    odd = np.arange(1, w.n_total, 2)
+    axis = np.argmax(np.asarray(c.inertia)[:, None] + p.added[3:], axis=0)
+    rate = (rng.uniform(15.0, 40.0, odd.size) * rng.choice([-1.0, 1.0], odd.size)).astype(np.float32)
+    st.nu[3:, odd] = 0.0
+    st.nu[3 + axis[odd], odd] = rate
+    assert np.all(np.abs(st.nu[3:, odd]).max(axis=0) * w.dt / 2 > 0.05)
+    res = run_pair(w, w.actions(10), 10, [1, 100])
+    check(res, {1: 1e-5, 100: 1e-3}, "fast spin")
+    g = res[-1][1][0][0]
+    assert np.abs(g[10:13, odd]).max(axis=0).min() * w.dt / 2 > 0.05   # still on the exact path
+
+
 def test_fused_and_unfused_agree_bitwise():
     w = synth.randomised(n=2048, steps=64)
     t = torch()

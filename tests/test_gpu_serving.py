@@ -125,3 +125,25 @@ def test_cancel_releases_the_session():
     assert st.state == mgx.REQ_CANCELLED
     assert s.stats().bytes_in_use == 0
     s.close()
+
+
+def test_iterations_with_more_tiles_than_waves():
+    """Three 50,000-environment requests share iterations on one stream: 2,346 tiles against
+    the 2,048 waves of a launch, so the last tiles come from the device counter. Each result
+    equals the same request run alone (whose iterations need no counter)."""
+    reqs = [dict(class_index=c, n_envs=50000, horizon=40, seed=70 + c) for c in (1, 3, 4)]
+    alone = []
+    for R in reqs:
+        s = server(chunk_steps=4, streams=1, budget_bytes=1 << 31)
+        st = s.wait(s.submit(**R, keep=True), timeout=60)
+        alone.append(s.read_state(st.session, R["class_index"], R["n_envs"]))
+        s.close()
+    s = server(chunk_steps=4, streams=1, budget_bytes=1 << 31)
+    ids = [s.submit(**R, keep=True) for R in reqs]
+    sts = [s.wait(i, timeout=60) for i in ids]
+    mixed = [s.read_state(st.session, R["class_index"], R["n_envs"]) for st, R in zip(sts, reqs)]
+    stats = s.stats()
+    s.close()
+    for a, m in zip(alone, mixed):
+        assert np.array_equal(a, m)
+    assert stats.completed == 3
