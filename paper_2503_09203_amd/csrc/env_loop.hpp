@@ -233,30 +233,38 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
         Brb[j] = E.buoy * C.rb[j];
     }
 
-    for (int k = 0; k < K; ++k) {
-        if constexpr (kOut) {
-            T f[kForceLen];
-            step_body<T, M, true, kDz>(C, E, IA2, Brb, s, cur, f);
-            if (A.forces) {
-                T* fo = (T*)A.forces + k * A.force_stride + env;
+    // Runs of steps between action-row switches: the inner loop carries only its counter,
+    // and the row bookkeeping happens once per hold interval.
+    int k = 0;
+    while (k < K) {
+        const int64_t left = hold - phase;  // steps until the next row switch, >= 1
+        const int run = (int64_t)(K - k) < left ? K - k : (int)left;
+        for (int j = 0; j < run; ++j, ++k) {
+            if constexpr (kOut) {
+                T f[kForceLen];
+                step_body<T, M, true, kDz>(C, E, IA2, Brb, s, cur, f);
+                if (A.forces) {
+                    T* fo = (T*)A.forces + k * A.force_stride + env;
 #pragma unroll
-                for (int j = 0; j < kForceLen; ++j) fo[j * np] = f[j];
+                    for (int c = 0; c < kForceLen; ++c) fo[c * np] = f[c];
+                }
+                if (A.traj) {
+                    T* to = (T*)A.traj + k * A.traj_stride + env;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) to[c * np] = s.p[c];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) to[(3 + c) * np] = s.q[c];
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) to[(7 + c) * np] = s.nu[c];
+#pragma unroll
+                    for (int i = 0; i < M; ++i) to[(kStateFixed + i) * np] = s.n[i];
+                }
+            } else {
+                step_body<T, M, false, kDz>(C, E, IA2, Brb, s, cur);
             }
-            if (A.traj) {
-                T* to = (T*)A.traj + k * A.traj_stride + env;
-#pragma unroll
-                for (int j = 0; j < 3; ++j) to[j * np] = s.p[j];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) to[(3 + j) * np] = s.q[j];
-#pragma unroll
-                for (int j = 0; j < 6; ++j) to[(7 + j) * np] = s.nu[j];
-#pragma unroll
-                for (int i = 0; i < M; ++i) to[(kStateFixed + i) * np] = s.n[i];
-            }
-        } else {
-            step_body<T, M, false, kDz>(C, E, IA2, Brb, s, cur);
         }
-        if (++phase == hold) {
+        phase += run;
+        if (phase == hold) {
             phase = 0;
             ++r;
 #pragma unroll
@@ -264,7 +272,7 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
             const T* pn = abase + clamp_row(r + 1) * rstride;
 #pragma unroll
             for (int i = 0; i < M; ++i) nxt[i] = pn[i * np];
-            if (k + 1 + hold < K && r + 1 >= nrows) bad = true;
+            if (k + hold < K && r + 1 >= nrows) bad = true;
         }
     }
     if (bad && (threadIdx.x & (kWave - 1)) == 0) atomicOr(&A.misc->err, 1);
