@@ -119,6 +119,14 @@ __host__ __device__ __forceinline__ void cross(const T a[3], const T b[3], T out
     out[2] = fma_(a[0], b[1], -(a[1] * b[0]));
 }
 
+// acc - a x b, component-wise, as two fused multiply-adds per component.
+template <typename T>
+__host__ __device__ __forceinline__ void sub_cross(const T a[3], const T b[3], T acc[3]) {
+    acc[0] = fma_(a[2], b[1], fma_(-a[1], b[2], acc[0]));
+    acc[1] = fma_(a[0], b[2], fma_(-a[2], b[0], acc[1]));
+    acc[2] = fma_(a[1], b[0], fma_(-a[0], b[1], acc[2]));
+}
+
 // Unit-quaternion increment exp(h w) = (cos(phi), sin(phi) w/|w|), phi = h |w|.
 // float: even polynomials in phi^2 (truncation below 3e-11 for phi <= 0.05) with an
 // exact fallback above; double: the exact form.
@@ -208,8 +216,8 @@ __host__ __device__ __forceinline__ void step_body(const ClassT<T>& C, const Env
     const T* v = s.nu;
     const T* w = s.nu + 3;
 
-    // 4. forces
-    // Coriolis, linear rows: m w x v + w x (A1 v_r) = w x (m v + A1 v_r)
+    // 4. forces, accumulated per degree of freedom into the right-hand side F of
+    // M dnu/dt = F (every term evaluated at the step-start velocity)
     T A1vr[3], P[3], L[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -217,62 +225,63 @@ __host__ __device__ __forceinline__ void step_body(const ClassT<T>& C, const Env
         P[j] = fma_(E.mass, v[j], A1vr[j]);
         L[j] = IA2[j] * w[j];
     }
-    T cor_lin[3], cor_ang[3], t1[3];
-    cross(w, P, cor_lin);
-    // angular rows: w x (I w) + w x (A2 w) + v_r x (A1 v_r) = w x ((I + A2) w) + v_r x (A1 v_r)
-    cross(w, L, cor_ang);
-    cross(vr, A1vr, t1);
+    T Fl[3], Fa[3];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) cor_ang[j] = cor_ang[j] + t1[j];
+    for (int j = 0; j < 3; ++j) {
+        Fl[j] = fma_(E.wmb, gb[j], tau[j]);  // restoring, linear rows: -(W - B) g_b moved right
+        Fa[j] = tau[3 + j];
+    }
+    // Coriolis, linear rows: m w x v + w x (A1 v_r) = w x (m v + A1 v_r)
+    sub_cross(w, P, Fl);
+    // angular rows: w x (I w) + w x (A2 w) + v_r x (A1 v_r) = w x ((I + A2) w) + v_r x (A1 v_r)
+    sub_cross(w, L, Fa);
+    sub_cross(vr, A1vr, Fa);
+    // restoring, angular rows: B r_b x g_b
+    sub_cross(Brb, gb, Fa);
     // added-mass term of the rotating current projection: A1 (w x v_c) (coefficients 0
     // when the term is switched off)
-    T hA[3], wvc[3];
+    T wvc[3];
     cross(w, vc, wvc);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) hA[j] = E.Ah[j] * wvc[j];
-    // damping on nu_r = (v_r, w)
-    T damp[6];
+    // damping on nu_r = (v_r, w): (d_L + d_Q |x|) x per degree of freedom
+    T dcl[3], dca[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        damp[j] = fma_(E.dQ[j], abs_(vr[j]), E.dL[j]) * vr[j];
-        damp[3 + j] = fma_(E.dQ[3 + j], abs_(w[j]), E.dL[3 + j]) * w[j];
+        Fl[j] = fma_(-E.Ah[j], wvc[j], Fl[j]);
+        dcl[j] = fma_(E.dQ[j], abs_(vr[j]), E.dL[j]);
+        dca[j] = fma_(E.dQ[3 + j], abs_(w[j]), E.dL[3 + j]);
+        Fl[j] = fma_(-dcl[j], vr[j], Fl[j]);
+        Fa[j] = fma_(-dca[j], w[j], Fa[j]);
     }
-    // restoring: linear -(W - B) g_b, angular B r_b x g_b (moved to the right-hand side)
-    T rmom[3];
-    cross(Brb, gb, rmom);
-    T F[6];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        F[j] = fma_(E.wmb, gb[j], tau[j] - cor_lin[j] - damp[j] - hA[j]);
-        F[3 + j] = tau[3 + j] - cor_ang[j] - damp[3 + j] - rmom[j];
-    }
-
-    // 5. acceleration solve (diagonal M)
-    T dnu[6];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) dnu[j] = E.dtMinv[j] * F[j];
 
     if constexpr (kForces) {  // evaluated with the step-start velocity
-        // hydrodynamic wrench -M_A d(nu)/dt - C_A nu_r - D nu_r - g_A - (A1 (w x v_c); 0)
-        T cal[3], caa[3], A2w[3], t2[3];
+        // actuator wrench, and the hydrodynamic wrench -M_A d(nu)/dt - C_A nu_r - D nu_r -
+        // g_A - (A1 (w x v_c); 0) with d(nu)/dt the solved acceleration
+        T cal[3], caa[3], A2w[3], t1[3], t2[3], rmom[3];
         cross(w, A1vr, cal);
 #pragma unroll
         for (int j = 0; j < 3; ++j) A2w[j] = E.A[3 + j] * w[j];
+        cross(vr, A1vr, t1);
         cross(w, A2w, t2);
+        cross(Brb, gb, rmom);
 #pragma unroll
         for (int j = 0; j < 3; ++j) caa[j] = t1[j] + t2[j];
 #pragma unroll
         for (int j = 0; j < 6; ++j) forces[j] = tau[j];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            forces[6 + j] = -(E.A[j] * dnu[j] * C.inv_dt) - hA[j] - cal[j] - damp[j] - E.buoy * gb[j];
-            forces[9 + j] = -(E.A[3 + j] * dnu[3 + j] * C.inv_dt) - caa[j] - damp[3 + j] - rmom[j];
+            const T dl = E.dtMinv[j] * Fl[j], da = E.dtMinv[3 + j] * Fa[j];
+            forces[6 + j] = -(E.A[j] * dl * C.inv_dt) - E.Ah[j] * wvc[j] - cal[j] - dcl[j] * vr[j] -
+                            E.buoy * gb[j];
+            forces[9 + j] = -(E.A[3 + j] * da * C.inv_dt) - caa[j] - dca[j] * w[j] - rmom[j];
         }
     }
 
-    // velocity update
+    // 5. acceleration solve (diagonal M) and velocity update
 #pragma unroll
-    for (int j = 0; j < 6; ++j) s.nu[j] = s.nu[j] + dnu[j];
+    for (int j = 0; j < 3; ++j) {
+        s.nu[j] = fma_(E.dtMinv[j], Fl[j], s.nu[j]);
+        s.nu[3 + j] = fma_(E.dtMinv[3 + j], Fa[j], s.nu[3 + j]);
+    }
 
     // 6. pose: position with the updated velocity and the step-start attitude
 #pragma unroll
