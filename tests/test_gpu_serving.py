@@ -101,20 +101,28 @@ def test_session_continuation_equals_one_long_request():
 
 
 def test_admission_waits_for_memory():
+    """A budget of three 1024-environment sessions and nine requests: at no admission are
+    more than two other sessions resident, and with 2000-step horizons the first three are
+    still running while the rest are submitted, so later requests wait for memory."""
     c = classes()[3]
     per = 4 * 1024 * (13 + c.m + 30)       # bytes of one 1024-env session of class 3
     s = server(chunk_steps=16, budget_bytes=3 * per)
-    ids = [s.submit(3, 1024, 80, seed=i) for i in range(9)]
+    ids = [s.submit(3, 1024, 2000, seed=i) for i in range(9)]
     with pytest.raises(mgx.MgxError) as e:
         s.submit(3, 4096, 10, seed=1)
     assert e.value.status == mgx.MGX_E_BUDGET
-    sts = [s.wait(i) for i in ids]
+    sts = [s.wait(i, timeout=60) for i in ids]
     st = s.stats()
     s.close()
     assert all(x.state == mgx.REQ_DONE for x in sts)
     assert st.bytes_peak <= 3 * per and st.completed == 9
-    waited = sorted(x.t_admit - x.t_arrival for x in sts)
-    assert waited[-1] > 3 * waited[0]      # later requests were held back until memory freed
+    adm = np.array([x.t_admit for x in sts])
+    done = np.array([x.t_done for x in sts])
+    for j in range(9):
+        resident = sum(1 for i in range(9) if i != j and adm[i] <= adm[j] < done[i])
+        assert resident <= 2, (j, resident)
+    waited = np.sort(adm - np.array([x.t_arrival for x in sts]))
+    assert waited[-1] > 3 * waited[0] and waited[-1] > 1e-4
 
 
 def test_cancel_releases_the_session():
