@@ -57,6 +57,25 @@ __device__ __forceinline__ void load_env(const T* Rc, int64_t np, int64_t e, Env
 // Row of the action buffer used by global step t (validated on the host).
 __device__ __forceinline__ int64_t action_row(const AdjArgs& A, int64_t t) { return floor_div(t, A.hold) - A.row0; }
 
+// Row and phase within the hold interval of a step, advanced one step at a time (no
+// division in the step loops).
+struct RowCursor {
+    int64_t row;
+    int32_t phase, hold;
+    __device__ RowCursor(const AdjArgs& A, int64_t t) : hold(A.hold) {
+        const int64_t q = floor_div(t, (int64_t)A.hold);
+        row = q - A.row0;
+        phase = (int32_t)(t - q * A.hold);
+    }
+    __device__ int64_t next_row() const { return phase + 1 == hold ? row + 1 : row; }
+    __device__ void advance() {
+        if (++phase == hold) {
+            phase = 0;
+            ++row;
+        }
+    }
+};
+
 template <typename T, int M>
 __device__ __forceinline__ void load_action(const AdjArgs& A, int64_t row, int64_t e, T raw[M]) {
     const T* src = (const T*)A.actions + row * A.row_stride + e;
@@ -87,17 +106,17 @@ __global__ void __launch_bounds__(256) k_rollout_fwd(AdjArgs A, ClassT<T> Cs) {
     }
     T* ck = (T*)A.ckpt_buf;
     T* pos = (T*)A.pos;
-    int64_t row = -1;
-    T a[M];
+    // The action row of step k + 1 is in flight while step k runs (with per-step actions a
+    // load issued right before its use would leave every step waiting on memory).
+    RowCursor rc(A, A.t0);
+    T a[M], nxt[M];
+    load_action<T, M>(A, rc.row, e, nxt);
     for (int k = 0; k < A.H; ++k) {
-        if (k % A.ckpt == 0) store_state<T, M>(ck + (int64_t)(k / A.ckpt) * A.ckpt_stride, np, e, s);
-        const int64_t r = action_row(A, A.t0 + k);
-        if (r != row) {
-            row = r;
-            load_action<T, M>(A, r, e, a);
 #pragma unroll
-            for (int i = 0; i < M; ++i) a[i] = clip1(a[i]);
-        }
+        for (int i = 0; i < M; ++i) a[i] = clip1(nxt[i]);
+        load_action<T, M>(A, k + 1 < A.H ? rc.next_row() : rc.row, e, nxt);
+        rc.advance();
+        if (k % A.ckpt == 0) store_state<T, M>(ck + (int64_t)(k / A.ckpt) * A.ckpt_stride, np, e, s);
         step_body<T, M, false, kDz>(C, E, IA2, Brb, s, a);
 #pragma unroll
         for (int j = 0; j < 3; ++j) pos[(int64_t)k * A.pos_stride + j * np + e] = s.p[j];
@@ -145,30 +164,40 @@ __global__ void __launch_bounds__(256) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
     for (int seg = nseg - 1; seg >= 0; --seg) {
         const int k0 = seg * A.ckpt;
         const int k1 = (k0 + A.ckpt < A.H) ? k0 + A.ckpt : A.H;
-        // recompute the segment's states into scratch
+        // recompute the segment's states into scratch (actions one step ahead)
         StateT<T, M> s;
         load_state<T, M>(ck + (int64_t)seg * A.ckpt_stride, np, e, s);
-        int64_t row = -1;
-        T a[M];
+        RowCursor rc(A, A.t0 + k0);
+        T a[M], nxt[M];
+        load_action<T, M>(A, rc.row, e, nxt);
         for (int k = k0; k < k1; ++k) {
-            store_state<T, M>(sg + (int64_t)(k - k0) * A.ckpt_stride, np, e, s);
-            const int64_t r = action_row(A, A.t0 + k);
-            if (r != row) {
-                row = r;
-                load_action<T, M>(A, r, e, a);
 #pragma unroll
-                for (int i = 0; i < M; ++i) a[i] = clip1(a[i]);
-            }
+            for (int i = 0; i < M; ++i) a[i] = clip1(nxt[i]);
+            load_action<T, M>(A, k + 1 < k1 ? rc.next_row() : rc.row, e, nxt);
+            rc.advance();
+            store_state<T, M>(sg + (int64_t)(k - k0) * A.ckpt_stride, np, e, s);
             step_body<T, M, false, kDz>(C, E, IA2, Brb, s, a);
         }
-        // reverse sweep through the segment
-        for (int k = k1 - 1; k >= k0; --k) {
+        // reverse sweep through the segment; the stored state, position adjoint and action
+        // of step k - 1 are fetched while step k runs (at k0 the fetch repeats step k0)
+        StateT<T, M> sn;
+        T dpn[3], rawn[M];
+        auto fetch = [&](int k) {
+            load_state<T, M>(sg + (int64_t)(k - k0) * A.ckpt_stride, np, e, sn);
 #pragma unroll
-            for (int j = 0; j < 3; ++j) xb.p[j] += dpos[(int64_t)k * A.pos_stride + j * np + e];
-            load_state<T, M>(sg + (int64_t)(k - k0) * A.ckpt_stride, np, e, s);
-            const int64_t r = action_row(A, A.t0 + k);
+            for (int j = 0; j < 3; ++j) dpn[j] = dpos[(int64_t)k * A.pos_stride + j * np + e];
+            load_action<T, M>(A, action_row(A, A.t0 + k), e, rawn);
+        };
+        fetch(k1 - 1);
+        for (int k = k1 - 1; k >= k0; --k) {
+            s = sn;
             T raw[M], ac[M], ab[M];
-            load_action<T, M>(A, r, e, raw);
+#pragma unroll
+            for (int i = 0; i < M; ++i) raw[i] = rawn[i];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) xb.p[j] += dpn[j];
+            const int64_t r = action_row(A, A.t0 + k);
+            fetch(k > k0 ? k - 1 : k0);
 #pragma unroll
             for (int i = 0; i < M; ++i) ac[i] = clip1(raw[i]);
             step_vjp<T, M, kDz>(C, E, IA2, Brb, s, ac, xb, ab, gdL, gdQ, gA, gDt);
