@@ -54,11 +54,8 @@ __device__ __forceinline__ void load_env(const T* Rc, int64_t np, int64_t e, Env
     for (int j = 0; j < 3; ++j) E.Vc[j] = Rc[(kRecCurrent + j) * np + e];
 }
 
-// Row of the action buffer used by global step t (validated on the host).
-__device__ __forceinline__ int64_t action_row(const AdjArgs& A, int64_t t) { return floor_div(t, A.hold) - A.row0; }
-
-// Row and phase within the hold interval of a step, advanced one step at a time (no
-// division in the step loops).
+// Row of the action buffer used by a step (rows validated on the host), and its phase
+// within the hold interval, moved one step at a time (no division in the step loops).
 struct RowCursor {
     int64_t row;
     int32_t phase, hold;
@@ -68,10 +65,19 @@ struct RowCursor {
         phase = (int32_t)(t - q * A.hold);
     }
     __device__ int64_t next_row() const { return phase + 1 == hold ? row + 1 : row; }
+    __device__ int64_t prev_row() const { return phase == 0 ? row - 1 : row; }
     __device__ void advance() {
         if (++phase == hold) {
             phase = 0;
             ++row;
+        }
+    }
+    __device__ void retreat() {
+        if (phase == 0) {
+            phase = hold - 1;
+            --row;
+        } else {
+            --phase;
         }
     }
 };
@@ -182,13 +188,14 @@ __global__ void __launch_bounds__(256) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
         // of step k - 1 are fetched while step k runs (at k0 the fetch repeats step k0)
         StateT<T, M> sn;
         T dpn[3], rawn[M];
-        auto fetch = [&](int k) {
+        auto fetch = [&](int k, int64_t row) {
             load_state<T, M>(sg + (int64_t)(k - k0) * A.ckpt_stride, np, e, sn);
 #pragma unroll
             for (int j = 0; j < 3; ++j) dpn[j] = dpos[(int64_t)k * A.pos_stride + j * np + e];
-            load_action<T, M>(A, action_row(A, A.t0 + k), e, rawn);
+            load_action<T, M>(A, row, e, rawn);
         };
-        fetch(k1 - 1);
+        RowCursor rb(A, A.t0 + k1 - 1);
+        fetch(k1 - 1, rb.row);
         for (int k = k1 - 1; k >= k0; --k) {
             s = sn;
             T raw[M], ac[M], ab[M];
@@ -196,8 +203,12 @@ __global__ void __launch_bounds__(256) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
             for (int i = 0; i < M; ++i) raw[i] = rawn[i];
 #pragma unroll
             for (int j = 0; j < 3; ++j) xb.p[j] += dpn[j];
-            const int64_t r = action_row(A, A.t0 + k);
-            fetch(k > k0 ? k - 1 : k0);
+            const int64_t r = rb.row;
+            if (k > k0)
+                fetch(k - 1, rb.prev_row());
+            else
+                fetch(k0, r);
+            rb.retreat();
 #pragma unroll
             for (int i = 0; i < M; ++i) ac[i] = clip1(raw[i]);
             step_vjp<T, M, kDz>(C, E, IA2, Brb, s, ac, xb, ab, gdL, gdQ, gA, gDt);
