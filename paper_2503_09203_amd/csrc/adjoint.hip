@@ -130,11 +130,16 @@ __global__ void __launch_bounds__(256) k_rollout_fwd(AdjArgs A, ClassT<T> Cs) {
     store_state<T, M>((T*)A.state, np, e, s);
 }
 
+// Reverse sweep with per-segment recomputation. Two waves per 64-environment tile (block of
+// 128): wave 1 recomputes segment s - 1 from its checkpoint into one half of the segment
+// buffer while wave 0 sweeps segment s backwards from the other half, so recomputation
+// overlaps the sweep; the block barrier after each segment hands the halves over. The grid
+// covers the padded segment exactly, so both waves reach every barrier.
 template <typename T, int M, bool kDz>
-__global__ void __launch_bounds__(256) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
+    const int role = threadIdx.x / kWave;  // 0: sweep, 1: recompute
+    const int64_t e = (int64_t)blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
     const ClassT<T> C = class_in_vgpr<T, M>(Cs);
-    if (e >= A.npad) return;
     const int64_t np = A.npad;
     EnvT<T> E;
     load_env<T>((const T*)A.rec, np, e, E);
@@ -147,6 +152,39 @@ __global__ void __launch_bounds__(256) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
     }
     const T* ck = (const T*)A.ckpt_buf;
     T* sg = (T*)A.seg_buf;
+    const int nseg = (A.H + A.ckpt - 1) / A.ckpt;
+    auto seg_row = [&](int seg, int k) { return sg + ((int64_t)(seg & 1) * A.ckpt + (k - seg * A.ckpt)) * A.ckpt_stride; };
+
+    // recompute one segment's states into its half of the buffer (actions one step ahead)
+    auto recompute = [&](int seg) {
+        const int k0 = seg * A.ckpt;
+        const int k1 = (k0 + A.ckpt < A.H) ? k0 + A.ckpt : A.H;
+        StateT<T, M> s;
+        load_state<T, M>(ck + (int64_t)seg * A.ckpt_stride, np, e, s);
+        RowCursor rc(A, A.t0 + k0);
+        T a[M], nxt[M];
+        load_action<T, M>(A, rc.row, e, nxt);
+        for (int k = k0; k < k1; ++k) {
+#pragma unroll
+            for (int i = 0; i < M; ++i) a[i] = clip1(nxt[i]);
+            load_action<T, M>(A, k + 1 < k1 ? rc.next_row() : rc.row, e, nxt);
+            rc.advance();
+            store_state<T, M>(seg_row(seg, k), np, e, s);
+            step_body<T, M, false, kDz>(C, E, IA2, Brb, s, a);
+        }
+    };
+
+    if (role == 1) recompute(nseg - 1);
+    __syncthreads();
+
+    if (role == 1) {
+        for (int seg = nseg - 1; seg >= 0; --seg) {
+            if (seg > 0) recompute(seg - 1);
+            __syncthreads();
+        }
+        return;
+    }
+
     const T* dpos = (const T*)A.pos;
     T* dact = (T*)A.dactions;
     StateT<T, M> xb;
@@ -166,30 +204,15 @@ __global__ void __launch_bounds__(256) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
 #pragma unroll
     for (int i = 0; i < M; ++i) arow[i] = T(0);
 
-    const int nseg = (A.H + A.ckpt - 1) / A.ckpt;
     for (int seg = nseg - 1; seg >= 0; --seg) {
         const int k0 = seg * A.ckpt;
         const int k1 = (k0 + A.ckpt < A.H) ? k0 + A.ckpt : A.H;
-        // recompute the segment's states into scratch (actions one step ahead)
-        StateT<T, M> s;
-        load_state<T, M>(ck + (int64_t)seg * A.ckpt_stride, np, e, s);
-        RowCursor rc(A, A.t0 + k0);
-        T a[M], nxt[M];
-        load_action<T, M>(A, rc.row, e, nxt);
-        for (int k = k0; k < k1; ++k) {
-#pragma unroll
-            for (int i = 0; i < M; ++i) a[i] = clip1(nxt[i]);
-            load_action<T, M>(A, k + 1 < k1 ? rc.next_row() : rc.row, e, nxt);
-            rc.advance();
-            store_state<T, M>(sg + (int64_t)(k - k0) * A.ckpt_stride, np, e, s);
-            step_body<T, M, false, kDz>(C, E, IA2, Brb, s, a);
-        }
-        // reverse sweep through the segment; the stored state, position adjoint and action
-        // of step k - 1 are fetched while step k runs (at k0 the fetch repeats step k0)
-        StateT<T, M> sn;
+        // the stored state, position adjoint and action of step k - 1 are fetched while
+        // step k runs (at k0 the fetch repeats step k0)
+        StateT<T, M> s, sn;
         T dpn[3], rawn[M];
         auto fetch = [&](int k, int64_t row) {
-            load_state<T, M>(sg + (int64_t)(k - k0) * A.ckpt_stride, np, e, sn);
+            load_state<T, M>(seg_row(seg, k), np, e, sn);
 #pragma unroll
             for (int j = 0; j < 3; ++j) dpn[j] = dpos[(int64_t)k * A.pos_stride + j * np + e];
             load_action<T, M>(A, row, e, rawn);
@@ -224,6 +247,7 @@ __global__ void __launch_bounds__(256) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
 #pragma unroll
             for (int i = 0; i < M; ++i) arow[i] += (raw[i] > T(-1) && raw[i] < T(1)) ? ab[i] : T(0);
         }
+        __syncthreads();
     }
     if (row_cur >= 0 && dact) {
 #pragma unroll
@@ -245,9 +269,9 @@ __global__ void __launch_bounds__(256) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
 #define MGX_ADJ_CASE(MM)                                                                                         \
     case MM:                                                                                                     \
         if (dz)                                                                                                  \
-            hipLaunchKernelGGL((KERNEL<T, MM, true>), dim3(grid), dim3(256), 0, s, A, C);                        \
+            hipLaunchKernelGGL((KERNEL<T, MM, true>), dim3(grid), dim3(block), 0, s, A, C);                      \
         else                                                                                                     \
-            hipLaunchKernelGGL((KERNEL<T, MM, false>), dim3(grid), dim3(256), 0, s, A, C);                       \
+            hipLaunchKernelGGL((KERNEL<T, MM, false>), dim3(grid), dim3(block), 0, s, A, C);                     \
         break;
 
 #define MGX_ADJ_SWITCH          \
@@ -266,7 +290,7 @@ __global__ void __launch_bounds__(256) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
 
 template <typename T>
 hipError_t launch_rollout_fwd(const AdjArgs& A, const ClassT<T>& C, int m, bool dz, hipStream_t s) {
-    const unsigned grid = (unsigned)((A.npad + 255) / 256);
+    const unsigned grid = (unsigned)((A.npad + 255) / 256), block = 256;
 #define KERNEL k_rollout_fwd
     MGX_ADJ_SWITCH
 #undef KERNEL
@@ -275,7 +299,9 @@ hipError_t launch_rollout_fwd(const AdjArgs& A, const ClassT<T>& C, int m, bool 
 
 template <typename T>
 hipError_t launch_rollout_bwd(const AdjArgs& A, const ClassT<T>& C, int m, bool dz, hipStream_t s) {
-    const unsigned grid = (unsigned)((A.npad + 255) / 256);
+    // one block of two waves per 64-environment tile; npad is a multiple of 64
+    if (A.npad % kWave != 0) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)(A.npad / kWave), block = 2 * kWave;
 #define KERNEL k_rollout_bwd
     MGX_ADJ_SWITCH
 #undef KERNEL
@@ -334,7 +360,7 @@ extern "C" mgx_status mgx_rollout_forward(mgx_batch* b, const void* actions, int
     hipDevice_guard guard(b->device);
     const int64_t nck = (H + ckpt_every - 1) / ckpt_every;
     const size_t P = (size_t)b->prec;
-    const size_t ck_bytes = P * (size_t)nck * b->state_elems, seg_bytes = P * (size_t)ckpt_every * b->state_elems;
+    const size_t ck_bytes = P * (size_t)nck * b->state_elems, seg_bytes = P * (size_t)2 * ckpt_every * b->state_elems;
     if (ck_bytes > b->ckpt_bytes) {
         if (b->d_ckpt) (void)hipFree(b->d_ckpt);
         b->d_ckpt = nullptr;
