@@ -11,6 +11,8 @@
 #include <mutex>
 #include <new>
 #include <thread>
+
+#include <sys/prctl.h>
 #include <vector>
 
 #include "env_loop.hpp"
@@ -534,6 +536,9 @@ void mgx_server::complete_locked(Iter& it) {
 
 void mgx_server::loop() {
     (void)hipSetDevice(device);
+    // Completions are found by polling events; with the default 50 us timer slack a short
+    // timed wait would oversleep by that much on every request.
+    (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
         bool progress = false;
@@ -574,7 +579,7 @@ void mgx_server::loop() {
             done_cv.notify_all();
             if (stop) break;
         }
-        if (!progress) cv.wait_for(lk, std::chrono::microseconds(inflight.empty() ? 500 : 20));
+        if (!progress) cv.wait_for(lk, std::chrono::microseconds(inflight.empty() ? 500 : 5));
     }
 }
 
