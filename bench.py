@@ -100,6 +100,9 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy (negation) of this many MiB, read and written once, so that "
                          "hardware byte counters collected over this run can be scaled against a known size")
+    ap.add_argument("--counter-launches", action="store_true",
+                    help="instead of the benchmark line, run a fixed set of plain launches for hardware counter "
+                         "passes: 4 of K = 16 and 2 of K = 1000 at the default N")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark line, print launch-duration sweeps over K and N")
     args = ap.parse_args()
@@ -129,6 +132,9 @@ def main():
         del src, dst
     if args.sweep:
         sweep(args)
+        return
+    if args.counter_launches:
+        counter_launches(args)
         return
     if args.workload == "hetero":
         hetero(args)
@@ -540,6 +546,29 @@ def adjoint(args):
            "backward_env_steps_per_s": N * H / g, "backward_over_forward": g / f}
     b.close()
     print(json.dumps(out), flush=True)
+
+
+def counter_launches(args):
+    """Six plain launches of the step kernel (no graph) for counter passes: K = 16 four
+    times, then K = 1000 twice, at N environments of the randomised workload."""
+    import torch
+
+    import synth
+    from paper_2503_09203_amd import mgx
+
+    N, HOLD = args.n, 10
+    w = synth.randomised(n=N, steps=1000)
+    b = mgx.Batch(w.classes, [N], w.dt)
+    b.set_params(w.params)
+    init = torch.tensor(b.pack_state([w.state[0].stacked()]), dtype=torch.float32, device="cuda:0")
+    acts = b.gen_actions(101, seed=synth.MASTER_SEED)
+    for K in (16, 16, 16, 16, 1000, 1000):
+        b.set_state(init)
+        b.t = 0
+        b.step(acts, K, hold=HOLD)
+    torch.cuda.synchronize()
+    b.close()
+    print(json.dumps({"counter_launches": [16, 16, 16, 16, 1000, 1000], "n": N}), flush=True)
 
 
 def sweep(args):
