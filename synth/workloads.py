@@ -363,6 +363,16 @@ def hetero_classes(seed: int = MASTER_SEED):
     return [draw_class(m, 1 + i, seed) for i, m in enumerate(HETERO_M)]
 
 
+def many_classes(seed: int = MASTER_SEED, steps: int = 100) -> Workload:
+    """The widest batch the library accepts: 16 classes with 1..8 thrusters (each count
+    twice) and ragged environment counts (1 to 1000, many not multiples of 64), randomised
+    parameters and currents, actions resampled every 10 steps."""
+    ms = [1 + (i % 8) for i in range(16)]
+    classes = [draw_class(m, 20 + i, seed) for i, m in enumerate(ms)]
+    ns = [1, 63, 64, 65, 127, 130, 200, 257, 3, 70, 129, 64, 500, 31, 96, 1000]
+    return _build("many_classes_16", classes, ns, steps, 10, True, 0.3, seed)
+
+
 def plain_small(seed: int = MASTER_SEED, n: int = 1024, steps: int = 1000) -> Workload:
     """One 6-thruster class, 1024 environments at the class nominal, no current, actions
     resampled every 10 steps."""

@@ -36,12 +36,17 @@ def device_actions(b, per_class):
     return t.tensor(b.pack_actions(per_class), dtype=b.dtype, device=b.device)
 
 
-def run_pair(w, per_class_actions, hold, checkpoints, precision=mgx.FP32, flags=0, sample=None, chunk=None):
+def run_pair(w, per_class_actions, hold, checkpoints, precision=mgx.FP32, flags=0, sample=None, chunk=None,
+             shape=None, final_state=None):
     """Advance the device batch and the oracle to each checkpoint step; return a list of
     (k, [(gpu [C,n], ref [C,n]) per class]). ``sample``: per-class env indices given to
     the oracle (all if None). ``chunk``: split each device call into launches of this many
-    steps (the launch configuration of the benchmark)."""
+    steps (the launch configuration of the benchmark). ``shape``: arguments of
+    ``Batch.set_shape`` (launch mode, K, block, blocks per CU). ``final_state``: a list that
+    receives the device state (flat layout, on the host) after the last checkpoint."""
     b = make_batch(w, precision, flags)
+    if shape is not None:
+        b.set_shape(*shape)
     acts = device_actions(b, per_class_actions)
     rows = acts.shape[0]
     ins = oracle_inputs(w, flags)
@@ -69,5 +74,7 @@ def run_pair(w, per_class_actions, hold, checkpoints, precision=mgx.FP32, flags=
             g = gpu[c] if sample is None else gpu[c][:, sample[c]]
             pairs.append((g, oracle.unpack_state(states[c], w.classes[c].m)))
         out.append((k, pairs))
+    if final_state is not None:
+        final_state.append(flat)
     b.close()
     return out

@@ -146,3 +146,23 @@ def test_switching_launch_modes_between_calls():
     b.step(a, 5, hold=10)
     b.close()
     ref.close()
+
+
+def test_sixteen_classes_of_one_to_eight_thrusters():
+    """The widest batch: 16 classes (1..8 thrusters, each twice) with ragged counts from 1
+    to 1000 environments, 100 steps in 16-step launches. Per-class launches and the
+    persistent launch (every class's constants staged in LDS) agree bitwise and match the
+    oracle."""
+    w = synth.many_classes(steps=100)
+    acts = w.actions(11)
+    finals = []
+    for mode in (mgx.LAUNCH_PER_CLASS, mgx.LAUNCH_PERSISTENT):
+        fin = []
+        res = run_pair(w, acts, 10, [1, 100], chunk=16, shape=(mode, 16), final_state=fin)
+        finals.append(fin[0])
+        for k, pairs in res:
+            bar = 1e-5 if k == 1 else 5e-4
+            for c, (g, r) in enumerate(pairs):
+                err = component_errors(g, r)
+                assert np.all(err <= bar), (mode, k, c, err.max())
+    assert np.array_equal(finals[0], finals[1])

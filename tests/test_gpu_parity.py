@@ -63,6 +63,18 @@ def test_randomised_full_size_sampled():
     check(res, {1: 1e-5, 1000: 1e-3}, "dr65536 sampled")
 
 
+def test_large_batch_sampled():
+    """2^20 environments (state and record exceed the 256 MB last-level cache), 100 steps
+    in 16-step launches; 256 sampled environments, first and last included, against the
+    oracle."""
+    w = synth.randomised(n=1 << 20, steps=100)
+    rng = np.random.default_rng(1)
+    s = np.sort(rng.choice(w.n_total, 256, replace=False))
+    s[0], s[-1] = 0, w.n_total - 1
+    res = run_pair(w, w.actions(11), 10, [1, 100], sample=[s], chunk=16)
+    check(res, {1: 1e-5, 100: 5e-4}, "dr2^20 sampled")
+
+
 def test_heterogeneous_small_ragged():
     w = synth.heterogeneous(scale=0.05)
     assert any(n % 64 for n in w.n_envs)
