@@ -230,10 +230,10 @@ def main():
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
                      "frac": fused_flops_per_launch / fused_launch / PEAK_FP32_VECTOR, "traffic": traffic.get(K),
                      "traffic_unit": "B/launch",
-                     "kernel": f"k_step<float,{cls.m},false> K={K}", "launches_per_step": n_launch,
+                     "kernel": f"k_step<float,{cls.m},false,false> K={K}", "launches_per_step": n_launch,
                      "launch_us_mean": fused_launch * 1e6, "flops_per_env_step": flops_es,
                      "valu_ops_per_env_step": ops_es},
-        "single_step": {"env_steps_per_s": single_rate, "kernel": f"k_step<float,{cls.m},false> K=1",
+        "single_step": {"env_steps_per_s": single_rate, "kernel": f"k_step<float,{cls.m},false,true> K=1",
                         "launch_us_mean": single_launch * 1e6,
                         "roofline": {"bound": "hbm", "achieved": single_bytes / single_launch / 1e9,
                                      "peak": PEAK_HBM / 1e9, "unit": "GB/s",

@@ -172,9 +172,12 @@ __device__ __forceinline__ ClassT<T> class_in_vgpr(const ClassT<T>& Cs) {
 // t0. Commands are fetched raw one hold interval before use and clipped when their row
 // becomes current; all prologue loads are drained once before the loop so that the only
 // memory operations in flight inside it are those prefetches.
-template <typename T, int M, bool kOut, bool kDz>
+// kSingle: a launch of exactly one step without outputs (the single-step kernel). Such a
+// launch never reaches the next action row, so it does not fetch it.
+template <typename T, int M, bool kOut, bool kDz, bool kSingle = false>
 __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs, int64_t env, int64_t t0, int K,
                                           float st[kStats]) {
+    static_assert(!(kSingle && kOut), "the single-step form has no per-step outputs");
     const int64_t np = A.npad;
     const ClassT<T> C = class_in_vgpr<T, M>(Cs);
     T* S = (T*)A.state;
@@ -216,12 +219,14 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
     T cur[M], nxt[M];
     {
         const T* p0 = abase + clamp_row(r) * rstride;
-        const T* p1 = abase + clamp_row(r + 1) * rstride;
 #pragma unroll
         for (int i = 0; i < M; ++i) cur[i] = p0[i * np];
+        if constexpr (!kSingle) {
+            const T* p1 = abase + clamp_row(r + 1) * rstride;
 #pragma unroll
-        for (int i = 0; i < M; ++i) nxt[i] = p1[i * np];
-        if (hold - phase < K && r + 1 >= nrows) bad = true;
+            for (int i = 0; i < M; ++i) nxt[i] = p1[i * np];
+            if (hold - phase < K && r + 1 >= nrows) bad = true;
+        }
     }
     __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll
@@ -232,6 +237,9 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
         IA2[j] = C.inertia[j] + E.A[3 + j];
         Brb[j] = E.buoy * C.rb[j];
     }
+    if constexpr (kSingle) {
+        step_body<T, M, false, kDz>(C, E, IA2, Brb, s, cur);
+    } else {
 
     // Runs of steps between action-row switches: the inner loop carries only its counter,
     // and the row bookkeeping happens once per hold interval.
@@ -274,6 +282,7 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
             for (int i = 0; i < M; ++i) nxt[i] = pn[i * np];
             if (k + hold < K && r + 1 >= nrows) bad = true;
         }
+    }
     }
     if (bad && (threadIdx.x & (kWave - 1)) == 0) atomicOr(&A.misc->err, 1);
 

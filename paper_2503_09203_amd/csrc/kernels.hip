@@ -151,7 +151,7 @@ __global__ void k_gen_actions(T* out, int m, int32_t npad, int64_t n_valid, int6
 // ----------------------------------------------------------------------------- step
 
 // K steps of every environment of one class segment; state in registers throughout.
-template <typename T, int M, bool kOut>
+template <typename T, int M, bool kOut, bool kSingle>
 __global__ void __launch_bounds__(256) k_step(StepLaunch<T> L) {
     const StepArgs& A = L.a;
     const int tid = threadIdx.x;
@@ -166,9 +166,9 @@ __global__ void __launch_bounds__(256) k_step(StepLaunch<T> L) {
     for (int j = 0; j < kStats; ++j) st[j] = 0.0f;
     if (env < A.npad) {
         if (L.cls.has_dz)
-            env_steps<T, M, kOut, true>(A, L.cls, env, t0, A.K, st);
+            env_steps<T, M, kOut, true, kSingle>(A, L.cls, env, t0, A.K, st);
         else
-            env_steps<T, M, kOut, false>(A, L.cls, env, t0, A.K, st);
+            env_steps<T, M, kOut, false, kSingle>(A, L.cls, env, t0, A.K, st);
     }
     if (!A.partials) return;
     // Statistics: block partials, then the last block to finish reduces them in order.
@@ -258,15 +258,18 @@ hipError_t launch_gen_actions(T* out_seg, int m, int32_t npad, int64_t n_valid, 
 #define MGX_STEP_CASE(MM)                                                                              \
     case MM:                                                                                           \
         if (out)                                                                                       \
-            hipLaunchKernelGGL((k_step<T, MM, true>), dim3(grid), dim3(block), 0, s, L);               \
+            hipLaunchKernelGGL((k_step<T, MM, true, false>), dim3(grid), dim3(block), 0, s, L);        \
+        else if (single)                                                                               \
+            hipLaunchKernelGGL((k_step<T, MM, false, true>), dim3(grid), dim3(block), 0, s, L);        \
         else                                                                                           \
-            hipLaunchKernelGGL((k_step<T, MM, false>), dim3(grid), dim3(block), 0, s, L);              \
+            hipLaunchKernelGGL((k_step<T, MM, false, false>), dim3(grid), dim3(block), 0, s, L);       \
         break;
 
 template <typename T>
 hipError_t launch_step(const StepLaunch<T>& L, int m, int block, hipStream_t s) {
     const unsigned grid = (unsigned)((L.a.npad + block - 1) / block);
     const bool out = L.a.traj != nullptr || L.a.forces != nullptr;
+    const bool single = L.a.K == 1;
     switch (m) {
         MGX_STEP_CASE(1)
         MGX_STEP_CASE(2)
