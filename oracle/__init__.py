@@ -31,7 +31,8 @@ ENV_DTYPE = np.dtype([
     ("dlin", np.float64, 6), ("dquad", np.float64, 6), ("buoy", np.float64),
     ("rb", np.float64, 3), ("current", np.float64, 3), ("r", np.float64, (MAX_THR, 3)),
     ("e", np.float64, (MAX_THR, 3)), ("k", np.float64, MAX_THR), ("tau", np.float64, MAX_THR),
-    ("deadzone", np.float64, MAX_THR)], align=True)
+    ("deadzone", np.float64, MAX_THR), ("k_rev", np.float64, MAX_THR),
+    ("reaction", np.float64, MAX_THR)], align=True)
 
 _lib = None
 
@@ -119,6 +120,12 @@ def make_envs(cls, params, dt: float, flags: int = 0, idx=None) -> np.ndarray:
     tau = np.zeros(MAX_THR); tau[:cls.m] = cls.tau
     dz = np.zeros(MAX_THR); dz[:cls.m] = cls.deadzone
     env["r"], env["e"], env["k"], env["tau"], env["deadzone"] = r, e, k, tau, dz
+    krev = np.zeros(MAX_THR); react = np.zeros(MAX_THR)
+    if getattr(cls, "k_rev", None) is not None:
+        krev[:cls.m] = cls.k_rev
+    if getattr(cls, "reaction", None) is not None:
+        react[:cls.m] = cls.reaction
+    env["k_rev"], env["reaction"] = krev, react
     return env
 
 

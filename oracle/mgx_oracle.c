@@ -78,15 +78,19 @@ double orc_lag_factor(const orc_env* env, int32_t i) {
 }
 
 /* Propeller thrust, Sec. III-D: quadratic in the rotor state beyond a dead zone,
- * f_i = k_i s_i |s_i| with s_i = sgn(n_i) max(|n_i| - delta_i, 0). Each force acts along
- * the thruster axis e_i at the thruster position r_i, giving the wrench
- * sum_i f_i [e_i ; r_i x e_i] about the CoG. */
+ * f_i = k_i s_i |s_i| with s_i = sgn(n_i) max(|n_i| - delta_i, 0). The gain may differ by
+ * direction (k_i for s_i >= 0, the reverse gain for s_i < 0; unset = symmetric). Each force
+ * acts along the thruster axis e_i at the thruster position r_i; the spinning propeller
+ * also turns the hull about its own axis with a torque c_i f_i (c_i signed by the
+ * propeller's handedness). About the CoG the wrench is sum_i f_i [e_i ; r_i x e_i + c_i e_i]. */
 void orc_thrust_wrench(const orc_env* env, const double n[ORC_MAX_THR], double tau[6]) {
     for (int j = 0; j < 6; ++j) tau[j] = 0.0;
     for (int i = 0; i < env->m; ++i) {
         double mag = fabs(n[i]) - env->deadzone[i];
         double s = mag > 0.0 ? (n[i] >= 0.0 ? mag : -mag) : 0.0;
-        double f = env->k[i] * s * fabs(s);
+        double gain = env->k[i];
+        if (s < 0.0 && env->k_rev[i] > 0.0) gain = env->k_rev[i];
+        double f = gain * s * fabs(s);
         double e[3], len = sqrt(env->e[i][0] * env->e[i][0] + env->e[i][1] * env->e[i][1] +
                                 env->e[i][2] * env->e[i][2]);
         for (int j = 0; j < 3; ++j) e[j] = env->e[i][j] / len;
@@ -94,7 +98,7 @@ void orc_thrust_wrench(const orc_env* env, const double n[ORC_MAX_THR], double t
         cross3(env->r[i], e, mom);
         for (int j = 0; j < 3; ++j) {
             tau[j] += f * e[j];
-            tau[3 + j] += f * mom[j];
+            tau[3 + j] += f * mom[j] + env->reaction[i] * f * e[j];
         }
     }
 }

@@ -38,6 +38,9 @@ typedef struct {
     double k[ORC_MAX_THR];      /* thrust gain */
     double tau[ORC_MAX_THR];    /* rotor time constant; 0 = zero-order model */
     double deadzone[ORC_MAX_THR];
+    double k_rev[ORC_MAX_THR];  /* reverse thrust gain (N at n = -1); 0 = same as k */
+    double reaction[ORC_MAX_THR]; /* shaft torque per unit thrust about e (m), signed by
+                                     the propeller's handedness */
 } orc_env;
 
 typedef struct {

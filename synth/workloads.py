@@ -18,7 +18,7 @@ of buoyancy 0-2 cm above the centre of gravity, thrust gain 20-40 N, lag time co
 """
 from __future__ import annotations
 
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 
@@ -90,6 +90,8 @@ class VehicleClass:
     buoy: float            # buoyancy force (N)
     attempts: int = 1
     index: int = 0
+    k_rev: np.ndarray | None = None     # [m] reverse thrust gain (N at n = -1); None = k
+    reaction: np.ndarray | None = None  # [m] shaft torque per unit thrust about e (m); None = 0
 
 
 @dataclass
@@ -223,6 +225,18 @@ def draw_class(m: int, class_index: int = 0, seed: int = MASTER_SEED, dt: float 
             continue
         return cls
     raise RuntimeError("no class passed the screens")
+
+
+def propeller_variants(cls: VehicleClass, seed: int = MASTER_SEED) -> VehicleClass:
+    """The same class with the propeller variants switched on: a dead zone U[0.05, 0.15] on
+    |n|, a reverse gain U[0.6, 0.85] times the forward gain (propellers push less astern),
+    and a shaft torque of U[0.02, 0.05] m per unit thrust, handedness alternating with the
+    thruster index (counter-rotating pairs)."""
+    m = cls.m
+    u = _uniforms(seed, STREAM_CLASS, 40 + cls.index, 0, 1, 3 * m)[0]
+    sign = np.where(np.arange(m) % 2 == 0, 1.0, -1.0)
+    return replace(cls, deadzone=f32(0.05 + 0.10 * u[:m]), k_rev=f32(cls.k * (0.6 + 0.25 * u[m:2 * m])),
+                   reaction=f32(sign * (0.02 + 0.03 * u[2 * m:])))
 
 
 def nominal_params(cls: VehicleClass, n: int) -> EnvParams:
@@ -383,6 +397,13 @@ def randomised(seed: int = MASTER_SEED, n: int = 65536, steps: int = 1000) -> Wo
     """The same class, 65,536 environments, +-20% per-environment randomisation and a
     constant N(0, 0.3^2) world current per environment, actions resampled every 10 steps."""
     return _build(f"dr_{n}x{steps}", [plain_class(seed)], [n], steps, 10, True, 0.3, seed)
+
+
+def propellers(seed: int = MASTER_SEED, n: int = 65536, steps: int = 1000) -> Workload:
+    """The randomised workload with the propeller variants of ``propeller_variants``: dead
+    zones, direction-dependent gains and shaft torques on every thruster."""
+    return _build(f"prop_{n}x{steps}", [propeller_variants(plain_class(seed), seed)], [n], steps, 10, True, 0.3,
+                  seed)
 
 
 def heterogeneous(seed: int = MASTER_SEED, scale: float = 1.0, steps: int = 1000) -> Workload:

@@ -38,7 +38,15 @@ MUTANTS = {
     "attitude_full_angle": ("double half = 0.5 * wn * env->dt;", "double half = wn * env->dt;"),
     "rotation_sign": ("R[0][1] = 2.0 * (x * y - w * z);", "R[0][1] = 2.0 * (x * y + w * z);"),
     "thrust_moment_order": ("cross3(env->r[i], e, mom);", "cross3(e, env->r[i], mom);"),
-    "thrust_no_sign": ("double f = env->k[i] * s * fabs(s);", "double f = env->k[i] * s * s;"),
+    "thrust_no_sign": ("double f = gain * s * fabs(s);", "double f = gain * s * s;"),
+    "reverse_gain_ignored": ("if (s < 0.0 && env->k_rev[i] > 0.0) gain = env->k_rev[i];", ""),
+    "reverse_gain_forward": ("if (s < 0.0 && env->k_rev[i] > 0.0) gain = env->k_rev[i];",
+                             "if (s > 0.0 && env->k_rev[i] > 0.0) gain = env->k_rev[i];"),
+    "shaft_torque_sign": ("tau[3 + j] += f * mom[j] + env->reaction[i] * f * e[j];",
+                          "tau[3 + j] += f * mom[j] - env->reaction[i] * f * e[j];"),
+    "shaft_torque_dropped": ("tau[3 + j] += f * mom[j] + env->reaction[i] * f * e[j];", "tau[3 + j] += f * mom[j];"),
+    "shaft_torque_unsigned": ("tau[3 + j] += f * mom[j] + env->reaction[i] * f * e[j];",
+                              "tau[3 + j] += f * mom[j] + env->reaction[i] * fabs(f) * e[j];"),
     "lag_euler_always": ("return 1.0 - exp(-env->dt / env->tau[i]);", "return env->dt / env->tau[i];"),
     "lag_before_clip": ("nl[i] = env->tau[i] > 0.0 ? s->n[i] + orc_lag_factor(env, i) * (c - s->n[i]) : c;",
                         "nl[i] = env->tau[i] > 0.0 ? s->n[i] + orc_lag_factor(env, i) * (a[i] - s->n[i]) : c;"),

@@ -124,6 +124,47 @@ def test_p2_power_of_point_forces():
         assert abs(tau @ nu - power) < 1e-12 * (1 + abs(power))
 
 
+def test_p2_reverse_gain_and_reaction_torque():
+    """One thruster off the centre line: forward gain 30, reverse gain 18, shaft torque
+    0.04 m per unit thrust. Worked by hand: at n = 0.5 the thrust is 30 * 0.25 = 7.5 N
+    along x at r = (0, 0.1, 0), so the moment is r x f e = (0, 0, -0.75) plus the shaft
+    torque 0.04 * 7.5 = 0.3 about x; at n = -0.5 the reverse gain gives -4.5 N."""
+    env = env1(m=1)
+    env["r"][0, 0] = [0.0, 0.1, 0.0]
+    env["k"][0, 0] = 30.0
+    env["k_rev"][0, 0] = 18.0
+    env["reaction"][0, 0] = 0.04
+    assert np.allclose(oracle.thrust_wrench(env, [0.5]), [7.5, 0, 0, 0.3, 0, -0.75], rtol=0, atol=1e-14)
+    assert np.allclose(oracle.thrust_wrench(env, [-0.5]), [-4.5, 0, 0, -0.18, 0, 0.45], rtol=0, atol=1e-14)
+    env["k_rev"][0, 0] = 0.0                  # unset: symmetric
+    assert np.allclose(oracle.thrust_wrench(env, [-0.5]), [-7.5, 0, 0, -0.3, 0, 0.75], rtol=0, atol=1e-14)
+
+
+def test_p2_power_with_reverse_gain_and_shaft_torque():
+    """Power identity with direction-dependent gains and shaft torques: for any body
+    velocity, tau . nu = sum_i f_i e_i . (v + w x r_i) + sum_i c_i f_i e_i . w, with f_i
+    taken with the gain of its own direction."""
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        m = int(rng.integers(1, 9))
+        env = env1(m=m)
+        env["r"][0, :m] = rng.uniform(-0.3, 0.3, (m, 3))
+        e = rng.normal(size=(m, 3))
+        env["e"][0, :m] = e
+        kf = rng.uniform(20, 40, m)
+        kr = kf * rng.uniform(0.5, 0.9, m)
+        c = rng.uniform(-0.05, 0.05, m)
+        env["k"][0, :m], env["k_rev"][0, :m], env["reaction"][0, :m] = kf, kr, c
+        n = rng.uniform(-1, 1, m)
+        tau = oracle.thrust_wrench(env, n)
+        nu = rng.normal(size=6)
+        eu = e / np.linalg.norm(e, axis=1, keepdims=True)
+        f = np.where(n >= 0, kf, kr) * n * np.abs(n)
+        pts = nu[:3] + np.cross(nu[3:], env["r"][0, :m])
+        power = np.sum(f * np.sum(eu * pts, axis=1)) + np.sum(c * f * (eu @ nu[3:]))
+        assert abs(tau @ nu - power) < 1e-12 * (1 + abs(power))
+
+
 # ----------------------------------------------------------------------------- P3 kinematics
 
 def euler_zyx_matrix(phi, th, psi):
@@ -263,6 +304,41 @@ def test_p5_thrust_acts_on_the_lagged_rotor_state():
         _, tr = run(env, state1(), [0.5, 0.5], 1)
         s = 0.5 * factor
         assert abs(tr[0, 0, 7] - 0.01 * 2 * 30.0 * s * s / 15.0) < 1e-15
+
+
+@pytest.mark.parametrize("a", [0.8, -0.8])
+def test_p5_surge_and_roll_from_one_propeller_closed_form(a):
+    """One zero-order propeller at the CoG along x with a dead zone, a reverse gain and a
+    shaft torque; neutral, CoB at the CoG, linear damping only, no current. Surge and roll
+    then stay decoupled (every Coriolis and restoring term vanishes for v and w both along
+    x) and the map reduces to two scalar recurrences with exact solutions:
+    u_k = u* (1 - r_u^k), u* = f / d_u, r_u = 1 - dt d_u / (m + A_11); the same for the roll
+    rate with torque c f and I_x + A_44; x_k = dt sum_{j<=k} u_j and
+    q_k = (cos(phi_k / 2), sin(phi_k / 2), 0, 0) with phi_k = dt sum_{j<=k} p_j."""
+    dt, steps = 0.01, 400
+    env = env1(m=1, dt=dt, dquad=np.zeros(6), rb=[0, 0, 0])
+    env["tau"][0, 0] = 0.0
+    env["deadzone"][0, 0] = 0.1
+    env["k"][0, 0], env["k_rev"][0, 0], env["reaction"][0, 0] = 30.0, 19.0, 0.035
+    assert env["buoy"][0] == env["mass"][0] * G0
+    gain = 30.0 if a > 0 else 19.0
+    f = gain * np.sign(a) * (abs(a) - 0.1) ** 2
+    du, dp = env["dlin"][0, 0], env["dlin"][0, 3]
+    Mu, Mp = env["mass"][0] + env["added"][0, 0], env["inertia"][0, 0] + env["added"][0, 3]
+    k = np.arange(1, steps + 1)
+    u = f / du * (1 - (1 - dt * du / Mu) ** k)
+    pr = 0.035 * f / dp * (1 - (1 - dt * dp / Mp) ** k)
+    x = dt * np.cumsum(u)
+    phi = dt * np.cumsum(pr)
+    _, tr = run(env, state1(), [a], steps)
+    g = tr[0]
+    scale = np.abs(g).max(axis=0) + 1e-300
+    assert np.max(np.abs(g[:, 7] - u) / np.abs(u).max()) < 1e-12
+    assert np.max(np.abs(g[:, 10] - pr) / np.abs(pr).max()) < 1e-12
+    assert np.max(np.abs(g[:, 0] - x) / np.abs(x).max()) < 1e-12
+    assert np.max(np.abs(g[:, 3] - np.cos(phi / 2))) < 1e-12
+    assert np.max(np.abs(g[:, 4] - np.sin(phi / 2))) < 1e-12
+    assert np.all(g[:, [1, 2, 5, 6, 8, 9, 11, 12]] == 0.0), scale
 
 
 def test_p5_damping_continuous_decay_first_order():
