@@ -89,8 +89,9 @@ def main():
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="dr", choices=["dr", "hetero", "serve", "adjoint"],
-                    help="dr: the default benchmark line; hetero: five classes in one persistent launch; "
+    ap.add_argument("--workload", default="dr", choices=["dr", "propellers", "hetero", "serve", "adjoint"],
+                    help="dr: the default benchmark line; propellers: the same line with dead zones, reverse "
+                         "gains and shaft torques on every thruster; hetero: five classes in one persistent launch; "
                          "serve: Poisson request trace through the continuous-batching server and the FIFO baseline; "
                          "adjoint: checkpointed forward and reverse sweep of the differentiable rollout")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: requests per second")
@@ -145,7 +146,8 @@ def main():
     if args.workload == "adjoint":
         adjoint(args)
         return
-    w = synth.randomised(n=N, steps=T)
+    shaped = args.workload == "propellers"
+    w = synth.propellers(n=N, steps=T) if shaped else synth.randomised(n=N, steps=T)
     cls = w.classes[0]
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream(dev)
@@ -185,7 +187,7 @@ def main():
     # Fused kernel: HIP events on the batch's stream around every graph replay (the
     # rollout's n_launch kernel launches back to back); average launch duration =
     # elapsed / n_launch, so inter-kernel gaps count against the kernel.
-    flops_es, ops_es = mgx.mgx_step_cost(cls.m)
+    flops_es, ops_es = mgx.mgx_step_cost(cls.m, mgx.COST_SHAPED if shaped else 0)
     graph_s = np.array([a.elapsed_time(c) for a, c in ev]) * 1e-3
     fused_launch = float(graph_s.mean()) / n_launch
     fused_flops_per_launch = flops_es * N * T / n_launch
@@ -208,7 +210,7 @@ def main():
     single_rate = N * T * reps1 / (time.perf_counter() - t1)
     single_launch = float(np.mean([a.elapsed_time(c) for a, c in ev1[1:]])) * 1e-3 / T
     single_bytes = bytes_per_env_step(cls.m, 1, HOLD) * N
-    traffic = recorded_traffic() if (N, T, HOLD) == (65536, 1000, 10) else {}
+    traffic = recorded_traffic() if (N, T, HOLD) == (65536, 1000, 10) and not shaped else {}
 
     out = {
         "metric": METRIC,
@@ -223,17 +225,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"dr_{N}x{T}", "n_envs": N, "rollout_steps": T, "thrusters": cls.m, "hold": HOLD,
+        "config": {"workload": f"{'prop' if shaped else 'dr'}_{N}x{T}", "n_envs": N, "rollout_steps": T, "thrusters": cls.m, "hold": HOLD,
                    "launch_steps_K": K, "dt": w.dt, "current_sigma": 0.3, "randomisation": 0.2,
                    "path": "set_params + reset + graph of fused launches"},
         "roofline": {"bound": "alu", "achieved": fused_flops_per_launch / fused_launch / 1e12,
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
                      "frac": fused_flops_per_launch / fused_launch / PEAK_FP32_VECTOR, "traffic": traffic.get(K),
                      "traffic_unit": "B/launch",
-                     "kernel": f"k_step<float,{cls.m},false,false> K={K}", "launches_per_step": n_launch,
+                     "kernel": f"k_step<float,{cls.m},false,false,{str(shaped).lower()}> K={K}", "launches_per_step": n_launch,
                      "launch_us_mean": fused_launch * 1e6, "flops_per_env_step": flops_es,
                      "valu_ops_per_env_step": ops_es},
-        "single_step": {"env_steps_per_s": single_rate, "kernel": f"k_step<float,{cls.m},false,true> K=1",
+        "single_step": {"env_steps_per_s": single_rate, "kernel": f"k_step<float,{cls.m},false,true,{str(shaped).lower()}> K=1",
                         "launch_us_mean": single_launch * 1e6,
                         "roofline": {"bound": "hbm", "achieved": single_bytes / single_launch / 1e9,
                                      "peak": PEAK_HBM / 1e9, "unit": "GB/s",

@@ -77,13 +77,21 @@ mgx_status mgx_device_count(int32_t* count);
 /* Algorithmic cost of one environment advanced by one step for a class with m thrusters,
  * counted on the host over the same step body the kernels run: flops (add, sub, mul = 1,
  * fused multiply-add = 2) and vector ALU operations (every add/sub/mul/fma/min/max/
- * select = 1; negation and absolute value are free operand modifiers). */
+ * select = 1; negation and absolute value are free operand modifiers). batch_flags:
+ * MGX_FLAG_* plus MGX_COST_SHAPED to count the body of classes with dead zones or
+ * reverse gains instead of the plain one. */
+#define MGX_COST_SHAPED 0x80000000u
 mgx_status mgx_step_cost(int32_t m, uint32_t batch_flags, double* flops, double* valu_ops);
 
 /* ------------------------------------------------------------------ vehicle classes */
 
 /* One vehicle class: the thruster layout and rotor models (Sec. III-D), principal
- * inertia about the centre of gravity, centre of buoyancy. Host memory, copied. */
+ * inertia about the centre of gravity, centre of buoyancy. Host memory, copied.
+ * Thruster i with rotor state n_i (after the lag) pushes f_i = k_i s|s| when s >= 0 and
+ * k_rev_i s|s| when s < 0, s = sgn(n_i) max(|n_i| - deadzone_i, 0), along e_i at r_i, and
+ * turns the hull about e_i with the shaft torque reaction_i f_i: the wrench about the CoG
+ * is f_i [e_i ; r_i x e_i + reaction_i e_i]. Zero-filled trailing fields keep the plain
+ * symmetric propeller with no shaft torque. */
 typedef struct {
     int32_t m;                          /* thrusters, 1..MGX_MAX_THRUSTERS */
     int32_t reserved;
@@ -95,6 +103,9 @@ typedef struct {
     double inertia[3];                  /* principal moments about the CoG (kg m^2), > 0 */
     double rb[3];                       /* centre of buoyancy, body frame (m) */
     double g0;                          /* gravitational acceleration (m/s^2), > 0 */
+    double k_rev[MGX_MAX_THRUSTERS];    /* reverse thrust gain (N at n = -1), >= 0; 0 = k */
+    double reaction[MGX_MAX_THRUSTERS]; /* shaft torque per unit thrust about e (m), signed
+                                           by the propeller's handedness; finite */
 } mgx_class_desc;
 
 /* Registers a class; *class_id receives its id (process-wide, never reused).
@@ -286,7 +297,8 @@ mgx_status mgx_rollout_backward(mgx_batch* b, const void* dpos, void* dactions, 
 /* Diagnostic (host only, double precision): evaluates the kernels' step body and its
  * hand-written adjoint for one environment, so the adjoint can be checked against finite
  * differences without a GPU. cls: Bk[6][8] (layout columns times gains), alpha[8],
- * deadzone[8], inertia[3], rb[3], g0, dt (74 doubles); rec: the 30 record fields (dt M^-1[6],
+ * deadzone[8], inertia[3], rb[3], g0, dt, reverse-to-forward gain ratios[8] (82 doubles);
+ * rec: the 30 record fields (dt M^-1[6],
  * m, M_A[6], d_L[6], d_Q[6], W - B, B, V_c[3]); state/xbar_in/state_out/xbar_out: 13 + m;
  * actions/abar_out: m; gparams_out: 24 = adjoints of d_L[6], d_Q[6], M_A[6] (direct
  * terms only), dt M^-1[6]. Used by no device path. */

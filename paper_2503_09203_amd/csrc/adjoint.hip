@@ -89,7 +89,7 @@ __device__ __forceinline__ void load_action(const AdjArgs& A, int64_t row, int64
     for (int i = 0; i < M; ++i) raw[i] = src[i * (int64_t)A.npad];
 }
 
-template <typename T, int M, bool kDz>
+template <typename T, int M, bool kShaped>
 __global__ void __launch_bounds__(256) k_rollout_fwd(AdjArgs A, ClassT<T> Cs) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const ClassT<T> C = class_in_vgpr<T, M>(Cs);
@@ -123,7 +123,7 @@ __global__ void __launch_bounds__(256) k_rollout_fwd(AdjArgs A, ClassT<T> Cs) {
         load_action<T, M>(A, k + 1 < A.H ? rc.next_row() : rc.row, e, nxt);
         rc.advance();
         if (k % A.ckpt == 0) store_state<T, M>(ck + (int64_t)(k / A.ckpt) * A.ckpt_stride, np, e, s);
-        step_body<T, M, false, kDz>(C, E, IA2, Brb, s, a);
+        step_body<T, M, false, kShaped>(C, E, IA2, Brb, s, a);
 #pragma unroll
         for (int j = 0; j < 3; ++j) pos[(int64_t)k * A.pos_stride + j * np + e] = s.p[j];
     }
@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(256) k_rollout_fwd(AdjArgs A, ClassT<T> Cs) {
 // buffer while wave 0 sweeps segment s backwards from the other half, so recomputation
 // overlaps the sweep; the block barrier after each segment hands the halves over. The grid
 // covers the padded segment exactly, so both waves reach every barrier.
-template <typename T, int M, bool kDz>
+template <typename T, int M, bool kShaped>
 __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
     const int role = threadIdx.x / kWave;  // 0: sweep, 1: recompute
     const int64_t e = (int64_t)blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
             load_action<T, M>(A, k + 1 < k1 ? rc.next_row() : rc.row, e, nxt);
             rc.advance();
             store_state<T, M>(seg_row(seg, k), np, e, s);
-            step_body<T, M, false, kDz>(C, E, IA2, Brb, s, a);
+            step_body<T, M, false, kShaped>(C, E, IA2, Brb, s, a);
         }
     };
 
@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
             rb.retreat();
 #pragma unroll
             for (int i = 0; i < M; ++i) ac[i] = clip1(raw[i]);
-            step_vjp<T, M, kDz>(C, E, IA2, Brb, s, ac, xb, ab, gdL, gdQ, gA, gDt);
+            step_vjp<T, M, kShaped>(C, E, IA2, Brb, s, ac, xb, ab, gdL, gdQ, gA, gDt);
             if (r != row_cur) {
                 if (row_cur >= 0 && dact) {
 #pragma unroll
@@ -268,7 +268,7 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
 
 #define MGX_ADJ_CASE(MM)                                                                                         \
     case MM:                                                                                                     \
-        if (dz)                                                                                                  \
+        if (shaped)                                                                                              \
             hipLaunchKernelGGL((KERNEL<T, MM, true>), dim3(grid), dim3(block), 0, s, A, C);                      \
         else                                                                                                     \
             hipLaunchKernelGGL((KERNEL<T, MM, false>), dim3(grid), dim3(block), 0, s, A, C);                     \
@@ -289,7 +289,7 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
     }
 
 template <typename T>
-hipError_t launch_rollout_fwd(const AdjArgs& A, const ClassT<T>& C, int m, bool dz, hipStream_t s) {
+hipError_t launch_rollout_fwd(const AdjArgs& A, const ClassT<T>& C, int m, bool shaped, hipStream_t s) {
     const unsigned grid = (unsigned)((A.npad + 255) / 256), block = 256;
 #define KERNEL k_rollout_fwd
     MGX_ADJ_SWITCH
@@ -298,7 +298,7 @@ hipError_t launch_rollout_fwd(const AdjArgs& A, const ClassT<T>& C, int m, bool 
 }
 
 template <typename T>
-hipError_t launch_rollout_bwd(const AdjArgs& A, const ClassT<T>& C, int m, bool dz, hipStream_t s) {
+hipError_t launch_rollout_bwd(const AdjArgs& A, const ClassT<T>& C, int m, bool shaped, hipStream_t s) {
     // one block of two waves per 64-environment tile; npad is a multiple of 64
     if (A.npad % kWave != 0) return hipErrorInvalidValue;
     const unsigned grid = (unsigned)(A.npad / kWave), block = 2 * kWave;
@@ -317,11 +317,7 @@ template hipError_t launch_rollout_bwd<double>(const AdjArgs&, const ClassT<doub
 
 using namespace mgx;
 
-static bool class_has_dz(const mgx_batch* b, int c) {
-    for (int i = 0; i < b->m[c]; ++i)
-        if (b->cls[c].deadzone[i] > 0.0) return true;
-    return false;
-}
+static bool class_shaped(const mgx_batch* b, int c) { return shaped_thrust(to_desc64(b->cls[c])); }
 
 static AdjArgs adj_args(mgx_batch* b, int c) {
     const size_t P = (size_t)b->prec;
@@ -393,9 +389,9 @@ extern "C" mgx_status mgx_rollout_forward(mgx_batch* b, const void* actions, int
         A.advance = (c == b->n_classes - 1) ? H : 0;
         hipError_t e;
         if (b->prec == MGX_FP32)
-            e = launch_rollout_fwd<float>(A, b->h_class_f[c], b->m[c], class_has_dz(b, c), b->stream);
+            e = launch_rollout_fwd<float>(A, b->h_class_f[c], b->m[c], class_shaped(b, c), b->stream);
         else
-            e = launch_rollout_fwd<double>(A, b->h_class_d[c], b->m[c], class_has_dz(b, c), b->stream);
+            e = launch_rollout_fwd<double>(A, b->h_class_d[c], b->m[c], class_shaped(b, c), b->stream);
         if (e != hipSuccess) return hip_fail(b, e, "rollout forward launch");
     }
     b->slot = 1 - b->slot;
@@ -418,9 +414,9 @@ extern "C" mgx_status mgx_rollout_backward(mgx_batch* b, const void* dpos, void*
         A.dparams = dparams ? (char*)dparams + P * 18 * b->pad_off[c] : nullptr;
         hipError_t e;
         if (b->prec == MGX_FP32)
-            e = launch_rollout_bwd<float>(A, b->h_class_f[c], b->m[c], class_has_dz(b, c), b->stream);
+            e = launch_rollout_bwd<float>(A, b->h_class_f[c], b->m[c], class_shaped(b, c), b->stream);
         else
-            e = launch_rollout_bwd<double>(A, b->h_class_d[c], b->m[c], class_has_dz(b, c), b->stream);
+            e = launch_rollout_bwd<double>(A, b->h_class_d[c], b->m[c], class_shaped(b, c), b->stream);
         if (e != hipSuccess) return hip_fail(b, e, "rollout backward launch");
     }
     return MGX_OK;
@@ -453,14 +449,14 @@ static void host_vjp(const ClassT<double>& C, const EnvT<double>& E, const doubl
     s1 = s;
     double ac[M];
     for (int i = 0; i < M; ++i) ac[i] = clip1(a[i]);
-    if (C.has_dz)
+    if (C.shaped)
         step_body<double, M, false, true>(C, E, IA2, Brb, s1, ac);
     else
         step_body<double, M, false, false>(C, E, IA2, Brb, s1, ac);
     pack(s1, state_out);
     unpack(xbar_in, xb);
     double gdL[6] = {0}, gdQ[6] = {0}, gA[6] = {0}, gDt[6] = {0};
-    if (C.has_dz)
+    if (C.shaped)
         step_vjp<double, M, true>(C, E, IA2, Brb, s, ac, xb, abar, gdL, gdQ, gA, gDt);
     else
         step_vjp<double, M, false>(C, E, IA2, Brb, s, ac, xb, abar, gdL, gdQ, gA, gDt);
@@ -485,20 +481,24 @@ extern "C" mgx_status mgx_host_step_vjp(int32_t m, uint32_t batch_flags, const d
     for (int j = 0; j < 6; ++j)
         for (int i = 0; i < kMaxThr; ++i) C.Bk[j][i] = *c++;
     for (int i = 0; i < kMaxThr; ++i) C.alpha[i] = *c++;
-    int has_dz = 0;
+    int shaped = 0;
     for (int i = 0; i < kMaxThr; ++i) {
         C.dz[i] = *c++;
-        has_dz |= (i < m && C.dz[i] > 0.0);
+        shaped |= (i < m && C.dz[i] > 0.0);
     }
     for (int j = 0; j < 3; ++j) C.inertia[j] = *c++;
     for (int j = 0; j < 3; ++j) C.rb[j] = *c++;
     C.g0 = *c++;
     C.dt = *c++;
+    for (int i = 0; i < kMaxThr; ++i) {
+        C.rev[i] = *c++;
+        shaped |= (i < m && C.rev[i] != 1.0);
+    }
     C.inv_dt = 1.0 / C.dt;
     C.half_dt = 0.5 * C.dt;
     C.m = m;
     C.flags = batch_flags;
-    C.has_dz = has_dz;
+    C.shaped = shaped;
     EnvT<double> E;
     for (int j = 0; j < 6; ++j) {
         E.dtMinv[j] = rec[kRecDtMinv + j];

@@ -67,7 +67,7 @@ __host__ __device__ __forceinline__ void cross_bar(const T x[3], const T y[3], c
     yb[2] += t[2];
 }
 
-template <typename T, int M, bool kDz = false>
+template <typename T, int M, bool kShaped = false>
 __host__ __device__ __forceinline__ void step_vjp(const ClassT<T>& C, const EnvT<T>& E, const T IA2[3], const T Brb[3],
                                                   const StateT<T, M>& s, const T a[M], StateT<T, M>& xb, T abar[M],
                                                   T gdL[6], T gdQ[6], T gA[6], T gDt[6]) {
@@ -78,10 +78,11 @@ __host__ __device__ __forceinline__ void step_vjp(const ClassT<T>& C, const EnvT
     for (int i = 0; i < M; ++i) {
         nl[i] = fma_(C.alpha[i], a[i] - s.n[i], s.n[i]);
         T f;
-        if constexpr (kDz) {
+        if constexpr (kShaped) {
             const T mag = max_(abs_(nl[i]) - C.dz[i], T(0));
-            f = copysign_(mag * mag, nl[i]);
-            fd[i] = T(2) * mag;
+            const T g = select_(nl[i] < T(0), C.rev[i], T(1));
+            f = copysign_(g * (mag * mag), nl[i]);
+            fd[i] = T(2) * g * mag;
         } else {
             f = nl[i] * abs_(nl[i]);
             fd[i] = T(2) * abs_(nl[i]);

@@ -41,6 +41,7 @@ static inline Cnt fma_(Cnt a, Cnt b, Cnt c) { return tally(std::fma(a.v, b.v, c.
 static inline Cnt abs_(Cnt a) { return Cnt(std::fabs(a.v)); }
 static inline Cnt max_(Cnt a, Cnt b) { return tally(std::fmax(a.v, b.v), 0, 1); }
 static inline Cnt copysign_(Cnt a, Cnt b) { return tally(std::copysign(a.v, b.v), 0, 1); }
+static inline Cnt select_(bool c, Cnt a, Cnt b) { return tally(c ? a.v : b.v, 0, 1); }
 static inline Cnt sqrt_(Cnt a) { return tally(std::sqrt(a.v), 1, 1); }
 static inline Cnt sin(Cnt a) { return tally(std::sin(a.v), 1, 1); }
 static inline Cnt cos(Cnt a) { return tally(std::cos(a.v), 1, 1); }
@@ -52,7 +53,8 @@ static CostTally measure(uint32_t flags) {
         for (int i = 0; i < kMaxThr; ++i) C.Bk[j][i] = Cnt(3.0 * (i + 1) + 0.3 * j);
     for (int i = 0; i < kMaxThr; ++i) {
         C.alpha[i] = 0.1;
-        C.dz[i] = 0;
+        C.dz[i] = (flags & MGX_COST_SHAPED) ? 0.05 : 0.0;
+        C.rev[i] = (flags & MGX_COST_SHAPED) ? 0.7 : 1.0;
     }
     for (int j = 0; j < 3; ++j) {
         C.inertia[j] = 1.0 + j;
@@ -63,8 +65,8 @@ static CostTally measure(uint32_t flags) {
     C.inv_dt = 100;
     C.half_dt = 0.005;
     C.m = M;
-    C.flags = flags;
-    C.has_dz = 0;
+    C.flags = flags & ~MGX_COST_SHAPED;
+    C.shaped = (flags & MGX_COST_SHAPED) ? 1 : 0;
     EnvT<Cnt> E;
     for (int j = 0; j < 6; ++j) {
         E.dtMinv[j] = 0.001;
@@ -76,7 +78,7 @@ static CostTally measure(uint32_t flags) {
     E.wmb = -1;
     E.buoy = 118;
     for (int j = 0; j < 3; ++j) E.Vc[j] = 0.1 * (j + 1);
-    set_amc(E, flags);
+    set_amc(E, flags & ~MGX_COST_SHAPED);
     Cnt IA2[3] = {2, 3, 4}, Brb[3] = {0, 0, -1.18};
     StateT<Cnt, M> s;
     for (int j = 0; j < 3; ++j) s.p[j] = 0;
@@ -89,7 +91,10 @@ static CostTally measure(uint32_t flags) {
     Cnt a[M];
     for (int i = 0; i < M; ++i) a[i] = 0.5 - 0.1 * i;
     g_tally = CostTally();
-    step_body<Cnt, M, false>(C, E, IA2, Brb, s, a);
+    if (flags & MGX_COST_SHAPED)
+        step_body<Cnt, M, false, true>(C, E, IA2, Brb, s, a);
+    else
+        step_body<Cnt, M, false>(C, E, IA2, Brb, s, a);
     return g_tally;
 }
 

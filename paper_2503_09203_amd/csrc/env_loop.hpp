@@ -174,7 +174,7 @@ __device__ __forceinline__ ClassT<T> class_in_vgpr(const ClassT<T>& Cs) {
 // memory operations in flight inside it are those prefetches.
 // kSingle: a launch of exactly one step without outputs (the single-step kernel). Such a
 // launch never reaches the next action row, so it does not fetch it.
-template <typename T, int M, bool kOut, bool kDz, bool kSingle = false>
+template <typename T, int M, bool kOut, bool kShaped, bool kSingle = false>
 __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs, int64_t env, int64_t t0, int K,
                                           float st[kStats]) {
     static_assert(!(kSingle && kOut), "the single-step form has no per-step outputs");
@@ -238,7 +238,7 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
         Brb[j] = E.buoy * C.rb[j];
     }
     if constexpr (kSingle) {
-        step_body<T, M, false, kDz>(C, E, IA2, Brb, s, cur);
+        step_body<T, M, false, kShaped>(C, E, IA2, Brb, s, cur);
     } else {
 
     // Runs of steps between action-row switches: the inner loop carries only its counter,
@@ -250,7 +250,7 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
         for (int j = 0; j < run; ++j, ++k) {
             if constexpr (kOut) {
                 T f[kForceLen];
-                step_body<T, M, true, kDz>(C, E, IA2, Brb, s, cur, f);
+                step_body<T, M, true, kShaped>(C, E, IA2, Brb, s, cur, f);
                 if (A.forces) {
                     T* fo = (T*)A.forces + k * A.force_stride + env;
 #pragma unroll
@@ -268,7 +268,7 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
                     for (int i = 0; i < M; ++i) to[(kStateFixed + i) * np] = s.n[i];
                 }
             } else {
-                step_body<T, M, false, kDz>(C, E, IA2, Brb, s, cur);
+                step_body<T, M, false, kShaped>(C, E, IA2, Brb, s, cur);
             }
         }
         phase += run;

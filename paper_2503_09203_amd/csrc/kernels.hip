@@ -20,7 +20,7 @@ __global__ void k_class_setup(const ClassDesc64* in, ClassT<float>* outf, ClassT
     if (c >= n) return;
     const ClassDesc64& d = in[c];
     ClassT<double> D;
-    int has_dz = 0;
+    const int shaped = shaped_thrust(d) ? 1 : 0;
     for (int i = 0; i < kMaxThr; ++i) {
         if (i < d.m) {
             double len = sqrt(d.e[i][0] * d.e[i][0] + d.e[i][1] * d.e[i][1] + d.e[i][2] * d.e[i][2]);
@@ -30,17 +30,20 @@ __global__ void k_class_setup(const ClassDesc64* in, ClassT<float>* outf, ClassT
             D.Bk[0][i] = k * e[0];
             D.Bk[1][i] = k * e[1];
             D.Bk[2][i] = k * e[2];
-            D.Bk[3][i] = k * (r[1] * e[2] - r[2] * e[1]);
-            D.Bk[4][i] = k * (r[2] * e[0] - r[0] * e[2]);
-            D.Bk[5][i] = k * (r[0] * e[1] - r[1] * e[0]);
+            // moment about the CoG plus the shaft torque c_i about the thrust axis
+            const double c = d.reaction[i];
+            D.Bk[3][i] = k * ((r[1] * e[2] - r[2] * e[1]) + c * e[0]);
+            D.Bk[4][i] = k * ((r[2] * e[0] - r[0] * e[2]) + c * e[1]);
+            D.Bk[5][i] = k * ((r[0] * e[1] - r[1] * e[0]) + c * e[2]);
             double tau = d.tau[i];
             D.alpha[i] = tau > 0.0 ? ((flags & kFlagLagEuler) ? dt / tau : 1.0 - exp(-dt / tau)) : 1.0;
             D.dz[i] = d.dz[i];
-            has_dz |= d.dz[i] > 0.0;
+            D.rev[i] = reverse_ratio(d, i);
         } else {
             for (int j = 0; j < 6; ++j) D.Bk[j][i] = 0.0;
             D.alpha[i] = 0.0;
             D.dz[i] = 0.0;
+            D.rev[i] = 1.0;
         }
     }
     for (int j = 0; j < 3; ++j) {
@@ -53,13 +56,14 @@ __global__ void k_class_setup(const ClassDesc64* in, ClassT<float>* outf, ClassT
     D.half_dt = 0.5 * dt;
     D.m = d.m;
     D.flags = flags;
-    D.has_dz = has_dz;
+    D.shaped = shaped;
     D.pad2 = 0;
     ClassT<float> F;
     for (int i = 0; i < kMaxThr; ++i) {
         for (int j = 0; j < 6; ++j) F.Bk[j][i] = (float)D.Bk[j][i];
         F.alpha[i] = (float)D.alpha[i];
         F.dz[i] = (float)D.dz[i];
+        F.rev[i] = (float)D.rev[i];
     }
     for (int j = 0; j < 3; ++j) {
         F.inertia[j] = (float)D.inertia[j];
@@ -71,7 +75,7 @@ __global__ void k_class_setup(const ClassDesc64* in, ClassT<float>* outf, ClassT
     F.half_dt = (float)D.half_dt;
     F.m = D.m;
     F.flags = flags;
-    F.has_dz = has_dz;
+    F.shaped = shaped;
     F.pad2 = 0;
     outd[c] = D;
     outf[c] = F;
@@ -151,7 +155,10 @@ __global__ void k_gen_actions(T* out, int m, int32_t npad, int64_t n_valid, int6
 // ----------------------------------------------------------------------------- step
 
 // K steps of every environment of one class segment; state in registers throughout.
-template <typename T, int M, bool kOut, bool kSingle>
+// kShaped: the class has dead zones or direction-dependent gains. It is a separate
+// instantiation (chosen on the host from the class) rather than a branch in one kernel, so
+// that the plain body's register allocation does not pay for the shaped one.
+template <typename T, int M, bool kOut, bool kSingle, bool kShaped>
 __global__ void __launch_bounds__(256) k_step(StepLaunch<T> L) {
     const StepArgs& A = L.a;
     const int tid = threadIdx.x;
@@ -164,12 +171,7 @@ __global__ void __launch_bounds__(256) k_step(StepLaunch<T> L) {
     float st[kStats];
 #pragma unroll
     for (int j = 0; j < kStats; ++j) st[j] = 0.0f;
-    if (env < A.npad) {
-        if (L.cls.has_dz)
-            env_steps<T, M, kOut, true, kSingle>(A, L.cls, env, t0, A.K, st);
-        else
-            env_steps<T, M, kOut, false, kSingle>(A, L.cls, env, t0, A.K, st);
-    }
+    if (env < A.npad) env_steps<T, M, kOut, kShaped, kSingle>(A, L.cls, env, t0, A.K, st);
     if (!A.partials) return;
     // Statistics: block partials, then the last block to finish reduces them in order.
     __shared__ float red[256 / kWave][kStats];
@@ -255,14 +257,29 @@ hipError_t launch_gen_actions(T* out_seg, int m, int32_t npad, int64_t n_valid, 
     return hipGetLastError();
 }
 
-#define MGX_STEP_CASE(MM)                                                                              \
-    case MM:                                                                                           \
-        if (out)                                                                                       \
-            hipLaunchKernelGGL((k_step<T, MM, true, false>), dim3(grid), dim3(block), 0, s, L);        \
-        else if (single)                                                                               \
-            hipLaunchKernelGGL((k_step<T, MM, false, true>), dim3(grid), dim3(block), 0, s, L);        \
-        else                                                                                           \
-            hipLaunchKernelGGL((k_step<T, MM, false, false>), dim3(grid), dim3(block), 0, s, L);       \
+template <typename T, int M>
+static void launch_step_m(const StepLaunch<T>& L, unsigned grid, int block, bool out, bool single, bool shaped,
+                          hipStream_t s) {
+    if (shaped) {
+        if (out)
+            hipLaunchKernelGGL((k_step<T, M, true, false, true>), dim3(grid), dim3(block), 0, s, L);
+        else if (single)
+            hipLaunchKernelGGL((k_step<T, M, false, true, true>), dim3(grid), dim3(block), 0, s, L);
+        else
+            hipLaunchKernelGGL((k_step<T, M, false, false, true>), dim3(grid), dim3(block), 0, s, L);
+    } else {
+        if (out)
+            hipLaunchKernelGGL((k_step<T, M, true, false, false>), dim3(grid), dim3(block), 0, s, L);
+        else if (single)
+            hipLaunchKernelGGL((k_step<T, M, false, true, false>), dim3(grid), dim3(block), 0, s, L);
+        else
+            hipLaunchKernelGGL((k_step<T, M, false, false, false>), dim3(grid), dim3(block), 0, s, L);
+    }
+}
+
+#define MGX_STEP_CASE(MM)                                                 \
+    case MM:                                                              \
+        launch_step_m<T, MM>(L, grid, block, out, single, shaped, s);     \
         break;
 
 template <typename T>
@@ -270,6 +287,7 @@ hipError_t launch_step(const StepLaunch<T>& L, int m, int block, hipStream_t s) 
     const unsigned grid = (unsigned)((L.a.npad + block - 1) / block);
     const bool out = L.a.traj != nullptr || L.a.forces != nullptr;
     const bool single = L.a.K == 1;
+    const bool shaped = L.cls.shaped != 0;
     switch (m) {
         MGX_STEP_CASE(1)
         MGX_STEP_CASE(2)

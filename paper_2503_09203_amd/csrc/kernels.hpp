@@ -24,8 +24,22 @@ enum StatSlot : int {
 struct ClassDesc64 {
     int32_t m, pad;
     double r[kMaxThr][3], e[kMaxThr][3], k[kMaxThr], tau[kMaxThr], dz[kMaxThr];
+    double k_rev[kMaxThr], reaction[kMaxThr];
     double inertia[3], rb[3], g0;
 };
+
+// Reverse thrust gain over forward gain of thruster i (1 when the reverse gain is unset).
+__host__ __device__ inline double reverse_ratio(const ClassDesc64& d, int i) {
+    return (d.k_rev[i] > 0.0 && d.k_rev[i] != d.k[i]) ? d.k_rev[i] / d.k[i] : 1.0;
+}
+
+// True when some thruster has a dead zone or a direction-dependent gain: such classes run
+// the shaped-thrust instantiation of the step body.
+__host__ __device__ inline bool shaped_thrust(const ClassDesc64& d) {
+    bool s = false;
+    for (int i = 0; i < d.m && i < kMaxThr; ++i) s = s || d.dz[i] > 0.0 || reverse_ratio(d, i) != 1.0;
+    return s;
+}
 
 // Device bookkeeping of a batch. The step counter is double-buffered: a launch reads
 // slot rd and (if it moves the counter) its first block writes slot wr = 1 - rd, so the
@@ -52,7 +66,7 @@ struct SegDesc {
     void* state;
     const void* rec;
     int64_t act_off;   // elements from the start of an action row
-    int32_t npad, nvalid, m, has_dz;
+    int32_t npad, nvalid, m, shaped;
 };
 
 // Arguments of the persistent heterogeneous kernel (all classes, one launch).
@@ -146,8 +160,8 @@ hipError_t launch_step(const StepLaunch<T>& L, int m, int block, hipStream_t s);
 template <typename T>
 hipError_t launch_persistent(const PersistArgs& P, int grid, int block, hipStream_t s);
 template <typename T>
-hipError_t launch_rollout_fwd(const AdjArgs& A, const ClassT<T>& C, int m, bool dz, hipStream_t s);
+hipError_t launch_rollout_fwd(const AdjArgs& A, const ClassT<T>& C, int m, bool shaped, hipStream_t s);
 template <typename T>
-hipError_t launch_rollout_bwd(const AdjArgs& A, const ClassT<T>& C, int m, bool dz, hipStream_t s);
+hipError_t launch_rollout_bwd(const AdjArgs& A, const ClassT<T>& C, int m, bool shaped, hipStream_t s);
 
 }  // namespace mgx

@@ -35,6 +35,7 @@ __device__ __forceinline__ ClassT<T> class_to_sgpr(const ClassT<T>& L) {
     for (int i = 0; i < M; ++i) {
         C.alpha[i] = rfl(L.alpha[i]);
         C.dz[i] = rfl(L.dz[i]);
+        C.rev[i] = rfl(L.rev[i]);
     }
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -47,15 +48,15 @@ __device__ __forceinline__ ClassT<T> class_to_sgpr(const ClassT<T>& L) {
     C.half_dt = rfl(L.half_dt);
     C.m = M;
     C.flags = __builtin_amdgcn_readfirstlane(L.flags);
-    C.has_dz = __builtin_amdgcn_readfirstlane(L.has_dz);
+    C.shaped = __builtin_amdgcn_readfirstlane(L.shaped);
     return C;
 }
 
 template <typename T, int M>
-__device__ __forceinline__ void run_tile(const StepArgs& A, const ClassT<T>& L, bool dz, int64_t env, int64_t t0,
+__device__ __forceinline__ void run_tile(const StepArgs& A, const ClassT<T>& L, bool shaped, int64_t env, int64_t t0,
                                          int K, float st[kStats]) {
     const ClassT<T> C = class_to_sgpr<T, M>(L);
-    if (dz)
+    if (shaped)
         env_steps<T, M, false, true>(A, C, env, t0, K, st);
     else
         env_steps<T, M, false, false>(A, C, env, t0, K, st);
@@ -118,20 +119,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
         A.partials = P.tile_partials;
         A.stats = nullptr;
         const ClassT<T>& C = lds_cls[c];
-        const bool dz = sd.has_dz != 0;
+        const bool shaped = sd.shaped != 0;
         const int64_t env = env0 + lane;
         float st[kStats];
 #pragma unroll
         for (int j = 0; j < kStats; ++j) st[j] = 0.0f;
         switch (sd.m) {
-            case 1: run_tile<T, 1>(A, C, dz, env, t0, P.K, st); break;
-            case 2: run_tile<T, 2>(A, C, dz, env, t0, P.K, st); break;
-            case 3: run_tile<T, 3>(A, C, dz, env, t0, P.K, st); break;
-            case 4: run_tile<T, 4>(A, C, dz, env, t0, P.K, st); break;
-            case 5: run_tile<T, 5>(A, C, dz, env, t0, P.K, st); break;
-            case 6: run_tile<T, 6>(A, C, dz, env, t0, P.K, st); break;
-            case 7: run_tile<T, 7>(A, C, dz, env, t0, P.K, st); break;
-            default: run_tile<T, 8>(A, C, dz, env, t0, P.K, st); break;
+            case 1: run_tile<T, 1>(A, C, shaped, env, t0, P.K, st); break;
+            case 2: run_tile<T, 2>(A, C, shaped, env, t0, P.K, st); break;
+            case 3: run_tile<T, 3>(A, C, shaped, env, t0, P.K, st); break;
+            case 4: run_tile<T, 4>(A, C, shaped, env, t0, P.K, st); break;
+            case 5: run_tile<T, 5>(A, C, shaped, env, t0, P.K, st); break;
+            case 6: run_tile<T, 6>(A, C, shaped, env, t0, P.K, st); break;
+            case 7: run_tile<T, 7>(A, C, shaped, env, t0, P.K, st); break;
+            default: run_tile<T, 8>(A, C, shaped, env, t0, P.K, st); break;
         }
         if (P.tile_partials) {
 #pragma unroll

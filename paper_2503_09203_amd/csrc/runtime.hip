@@ -57,6 +57,8 @@ ClassDesc64 to_desc64(const mgx_class_desc& c) {
     std::memcpy(d.k, c.k, sizeof d.k);
     std::memcpy(d.tau, c.tau, sizeof d.tau);
     std::memcpy(d.dz, c.deadzone, sizeof d.dz);
+    std::memcpy(d.k_rev, c.k_rev, sizeof d.k_rev);
+    std::memcpy(d.reaction, c.reaction, sizeof d.reaction);
     std::memcpy(d.inertia, c.inertia, sizeof d.inertia);
     std::memcpy(d.rb, c.rb, sizeof d.rb);
     d.g0 = c.g0;
@@ -133,6 +135,8 @@ extern "C" mgx_status mgx_class_define(const mgx_class_desc* d, int32_t* class_i
         if (!(d->k[i] > 0) || !is_fin(d->k[i])) return fail(MGX_E_INVALID, "thruster %d: k must be > 0", i);
         if (!(d->tau[i] >= 0) || !is_fin(d->tau[i])) return fail(MGX_E_INVALID, "thruster %d: tau must be >= 0", i);
         if (!(d->deadzone[i] >= 0 && d->deadzone[i] < 1)) return fail(MGX_E_INVALID, "thruster %d: deadzone in [0,1)", i);
+        if (!(d->k_rev[i] >= 0) || !is_fin(d->k_rev[i])) return fail(MGX_E_INVALID, "thruster %d: k_rev must be >= 0", i);
+        if (!is_fin(d->reaction[i])) return fail(MGX_E_INVALID, "thruster %d: reaction must be finite", i);
     }
     for (int j = 0; j < 3; ++j) {
         if (!(d->inertia[j] > 0) || !is_fin(d->inertia[j])) return fail(MGX_E_INVALID, "inertia must be > 0");
@@ -277,9 +281,7 @@ extern "C" mgx_status mgx_batch_create(const mgx_batch_desc* d, mgx_batch** out)
         segs[c].npad = (int32_t)b->npad[c];
         segs[c].nvalid = (int32_t)b->n[c];
         segs[c].m = b->m[c];
-        bool dz = false;
-        for (int i = 0; i < b->m[c]; ++i) dz |= cls[c].deadzone[i] > 0.0;
-        segs[c].has_dz = dz ? 1 : 0;
+        segs[c].shaped = shaped_thrust(d64[c]) ? 1 : 0;
     }
     {
         hipDeviceProp_t prop;

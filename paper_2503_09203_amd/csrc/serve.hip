@@ -54,7 +54,7 @@ __device__ __forceinline__ void session_actions(uint64_t seed, int64_t e, int64_
     }
 }
 
-template <int M, bool kDz>
+template <int M, bool kShaped>
 __device__ __forceinline__ void serve_env(const ServeTile& T, const ClassT<float>& Cs, int64_t e) {
     const ClassT<float> C = class_in_vgpr<float, M>(Cs);
     const int64_t np = T.npad;
@@ -95,7 +95,7 @@ __device__ __forceinline__ void serve_env(const ServeTile& T, const ClassT<float
     float a[M];
     session_actions<M>(T.seed, e, row, a);
     for (int k = 0; k < T.steps; ++k) {
-        step_body<float, M, false, kDz>(C, E, IA2, Brb, s, a);
+        step_body<float, M, false, kShaped>(C, E, IA2, Brb, s, a);
         if (++phase == hold) {
             phase = 0;
             ++row;
@@ -134,6 +134,7 @@ __device__ __forceinline__ void serve_tile(const ServeTile& T, const ClassT<floa
     for (int i = 0; i < M; ++i) {
         C.alpha[i] = rfl_f(L.alpha[i]);
         C.dz[i] = rfl_f(L.dz[i]);
+        C.rev[i] = rfl_f(L.rev[i]);
     }
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -146,8 +147,8 @@ __device__ __forceinline__ void serve_tile(const ServeTile& T, const ClassT<floa
     C.half_dt = rfl_f(L.half_dt);
     C.m = M;
     C.flags = __builtin_amdgcn_readfirstlane(L.flags);
-    C.has_dz = __builtin_amdgcn_readfirstlane(L.has_dz);
-    if (C.has_dz)
+    C.shaped = __builtin_amdgcn_readfirstlane(L.shaped);
+    if (C.shaped)
         serve_env<M, true>(T, C, e);
     else
         serve_env<M, false>(T, C, e);

@@ -56,8 +56,9 @@ struct ClassT {
     T g0, dt, inv_dt, half_dt;
     int32_t m;
     uint32_t flags;    // batch flags
-    int32_t has_dz;    // any dead zone > 0
+    int32_t shaped;    // any dead zone or direction-dependent gain
     int32_t pad2;
+    T rev[kMaxThr];    // reverse gain over forward gain (1 when symmetric)
 };
 
 template <typename T>
@@ -110,6 +111,12 @@ __host__ __forceinline__ bool any_lane(bool p) { return p; }
 template <typename T>
 __host__ __device__ __forceinline__ T clip1(T a) {
     return a < T(-1) ? T(-1) : (a > T(1) ? T(1) : a);
+}
+
+// Per-lane selection (a vector select on the device).
+template <typename T>
+__host__ __device__ __forceinline__ T select_(bool c, T a, T b) {
+    return c ? a : b;
 }
 
 template <typename T>
@@ -166,7 +173,7 @@ __host__ __device__ __forceinline__ void quat_increment(T h, const T w[3], T& c,
 // are per-environment constants hoisted out of the step loop by the caller. `forces`
 // (optional, 12 values) receives the actuator wrench and the hydrodynamic wrench of
 // Eq. (3) with d(nu)/dt the solved acceleration.
-template <typename T, int M, bool kForces = false, bool kDeadZone = false>
+template <typename T, int M, bool kForces = false, bool kShaped = false>
 __host__ __device__ __forceinline__ void step_body(const ClassT<T>& C, const EnvT<T>& E, const T IA2[3],
                                                    const T Brb[3], StateT<T, M>& s, const T a[M],
                                                    T* forces = nullptr) {
@@ -179,10 +186,12 @@ __host__ __device__ __forceinline__ void step_body(const ClassT<T>& C, const Env
     T tau[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-        T f;  // thrust divided by the gain k_i (folded into Bk)
-        if constexpr (kDeadZone) {
+        T f;  // thrust divided by the forward gain k_i (folded into Bk)
+        if constexpr (kShaped) {
+            // dead zone, and the reverse gain as a ratio to the forward one
             T mag = max_(abs_(nl[i]) - C.dz[i], T(0));
-            f = copysign_(mag * mag, nl[i]);
+            const T g = select_(nl[i] < T(0), C.rev[i], T(1));
+            f = copysign_(g * (mag * mag), nl[i]);
         } else {
             f = nl[i] * abs_(nl[i]);
         }

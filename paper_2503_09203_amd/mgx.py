@@ -31,6 +31,7 @@ FP32 = 4
 FP64 = 8
 FLAG_NO_AMC = 1
 FLAG_LAG_EULER = 2
+COST_SHAPED = 0x80000000
 STEP_UNFUSED = 1
 STEP_STATS = 2
 LAUNCH_PER_CLASS = 0
@@ -50,7 +51,8 @@ class ClassDesc(ctypes.Structure):
                 ("r", (ctypes.c_double * 3) * MAX_THRUSTERS), ("e", (ctypes.c_double * 3) * MAX_THRUSTERS),
                 ("k", ctypes.c_double * MAX_THRUSTERS), ("tau", ctypes.c_double * MAX_THRUSTERS),
                 ("deadzone", ctypes.c_double * MAX_THRUSTERS), ("inertia", ctypes.c_double * 3),
-                ("rb", ctypes.c_double * 3), ("g0", ctypes.c_double)]
+                ("rb", ctypes.c_double * 3), ("g0", ctypes.c_double),
+                ("k_rev", ctypes.c_double * MAX_THRUSTERS), ("reaction", ctypes.c_double * MAX_THRUSTERS)]
 
 
 class BatchDesc(ctypes.Structure):
@@ -218,7 +220,7 @@ def mgx_step_cost(m, flags=0):
 
 def mgx_class_define(cls) -> int:
     """Register a vehicle class given any object with m, r, e, k, tau, deadzone,
-    inertia, rb, g0 attributes (e.g. a ``synth.VehicleClass``)."""
+    inertia, rb, g0 attributes and optional k_rev, reaction (e.g. a ``synth.VehicleClass``)."""
     d = ClassDesc()
     d.m = int(cls.m)
     for i in range(cls.m):
@@ -228,6 +230,10 @@ def mgx_class_define(cls) -> int:
         d.k[i] = float(cls.k[i])
         d.tau[i] = float(cls.tau[i])
         d.deadzone[i] = float(cls.deadzone[i])
+    k_rev, reaction = getattr(cls, "k_rev", None), getattr(cls, "reaction", None)
+    for i in range(cls.m):
+        d.k_rev[i] = 0.0 if k_rev is None else float(k_rev[i])
+        d.reaction[i] = 0.0 if reaction is None else float(reaction[i])
     for j in range(3):
         d.inertia[j] = float(cls.inertia[j])
         d.rb[j] = float(cls.rb[j])

@@ -47,6 +47,11 @@ def test_step_cost_counts():
     assert f8 - f6 == 2 * (1 + 2 + 1 + 12)
     with pytest.raises(mgx.MgxError):
         mgx.mgx_step_cost(9)
+    # shaped thrust per thruster: |n| - dead zone (1 flop), max, mag^2 (1 flop), the
+    # direction's gain ratio (select, 1-flop product), sign: +2 flops and +5 operations
+    # over the plain n|n|
+    fs, os_ = mgx.mgx_step_cost(6, mgx.COST_SHAPED)
+    assert fs - f6 == 2 * 6 and os_ - o6 == 5 * 6
 
 
 def test_class_validation():
@@ -93,3 +98,38 @@ def test_null_batch_calls_are_rejected():
     L = mgx.lib()
     assert L.mgx_batch_step(None, None, 1, 0, 1, 1, 0, None, None) == mgx.MGX_E_INVALID
     assert L.mgx_batch_destroy(None) == mgx.MGX_OK
+
+
+def test_binding_structures_match_the_header(tmp_path):
+    """Every ctypes mirror has the size of its C struct (compiled from the header with
+    gcc), so a field added to one side only cannot go unnoticed."""
+    pairs = {"mgx_class_desc": mgx.ClassDesc, "mgx_batch_desc": mgx.BatchDesc, "mgx_layout": mgx.Layout,
+             "mgx_env_params": mgx.EnvParams, "mgx_stats": mgx.Stats, "mgx_launch_shape": mgx.LaunchShape,
+             "mgx_server_desc": mgx.ServerDesc, "mgx_request": mgx.Request,
+             "mgx_request_status": mgx.RequestStatus, "mgx_server_stats": mgx.ServerStats}
+    src = tmp_path / "sizes.c"
+    body = "".join(f'    printf("{n} %zu\\n", sizeof({n}));\n' for n in pairs)
+    src.write_text(f'#include <stdio.h>\n#include "mgx.h"\nint main(void) {{\n{body}    return 0;\n}}\n')
+    exe = tmp_path / "sizes"
+    import subprocess
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True)
+    sizes = {line.split()[0]: int(line.split()[1]) for line in out.splitlines()}
+    for name, cls in pairs.items():
+        assert ctypes.sizeof(cls) == sizes[name], (name, ctypes.sizeof(cls), sizes[name])
+
+
+def test_propeller_variant_validation():
+    bad = synth.propeller_variants(synth.plain_class())
+    bad.k_rev = bad.k_rev.copy()
+    bad.k_rev[2] = -1.0
+    with pytest.raises(mgx.MgxError) as e:
+        mgx.mgx_class_define(bad)
+    assert "k_rev must be >= 0" in str(e.value)
+    bad = synth.propeller_variants(synth.plain_class())
+    bad.reaction = bad.reaction.copy()
+    bad.reaction[0] = float("nan")
+    with pytest.raises(mgx.MgxError) as e:
+        mgx.mgx_class_define(bad)
+    assert "reaction must be finite" in str(e.value)
+    assert mgx.mgx_class_define(synth.propeller_variants(synth.plain_class())) >= 0

@@ -12,16 +12,22 @@ DT = 0.01
 
 
 def class_flat(c, dt=DT, deadzone=None):
+    """The host diagnostic's class layout: k-scaled layout columns (with the shaft torque in
+    the moment rows), lag factors, dead zones, inertia, r_b, g0, dt, reverse-gain ratios."""
     e = c.e / np.linalg.norm(c.e, axis=1, keepdims=True)
+    react = np.zeros(c.m) if c.reaction is None else c.reaction
     Bk = np.zeros((6, 8))
     Bk[:3, :c.m] = (e * c.k[:, None]).T
-    Bk[3:, :c.m] = (np.cross(c.r, e) * c.k[:, None]).T
+    Bk[3:, :c.m] = ((np.cross(c.r, e) + react[:, None] * e) * c.k[:, None]).T
     alpha = np.zeros(8)
     alpha[:c.m] = 1 - np.exp(-dt / c.tau)
     dz = np.zeros(8)
     if deadzone is not None:
         dz[:c.m] = deadzone
-    return np.concatenate([Bk.ravel(), alpha, dz, c.inertia, c.rb, [c.g0, dt]])
+    rev = np.ones(8)
+    if c.k_rev is not None:
+        rev[:c.m] = c.k_rev / c.k
+    return np.concatenate([Bk.ravel(), alpha, dz, c.inertia, c.rb, [c.g0, dt], rev])
 
 
 def rec_flat(c, mass, added, dlin, dquad, buoy, current, dt=DT):
@@ -29,9 +35,11 @@ def rec_flat(c, mass, added, dlin, dquad, buoy, current, dt=DT):
     return np.concatenate([dt / (Mrb + added), [mass], added, dlin, dquad, [mass * c.g0 - buoy, buoy], current])
 
 
-def setup(seed, m=6, omega_scale=1.0):
+def setup(seed, m=6, omega_scale=1.0, variants=False):
     rng = np.random.default_rng(seed)
     c = synth.draw_class(m, 7)
+    if variants:
+        c = synth.propeller_variants(c)
     mass, added, dlin, dquad, buoy = c.mass, c.added.copy(), c.dlin.copy(), c.dquad.copy(), c.buoy * 1.01
     current = rng.normal(0, 0.3, 3)
     q = rng.normal(size=4)
@@ -54,13 +62,14 @@ def fd_columns(fun, x0, h):
     return np.array(cols)  # [n_in, n_out]
 
 
-@pytest.mark.parametrize("seed,flags,dz,omega", [(0, 0, None, 1.0), (1, mgx.FLAG_NO_AMC, None, 1.0),
-                                                  (2, 0, 0.1, 1.0), (3, 0, None, 30.0),
-                                                  (4, mgx.FLAG_LAG_EULER, None, 1.0)])
-def test_step_vjp_matches_finite_differences(seed, flags, dz, omega):
-    c, prm, state, a, xbar = setup(seed, omega_scale=omega)
+@pytest.mark.parametrize("seed,flags,dz,omega,variants", [(0, 0, None, 1.0, False), (1, mgx.FLAG_NO_AMC, None, 1.0, False),
+                                                           (2, 0, 0.1, 1.0, False), (3, 0, None, 30.0, False),
+                                                           (4, mgx.FLAG_LAG_EULER, None, 1.0, False),
+                                                           (6, 0, "class", 1.0, True)])
+def test_step_vjp_matches_finite_differences(seed, flags, dz, omega, variants):
+    c, prm, state, a, xbar = setup(seed, omega_scale=omega, variants=variants)
     m = c.m
-    cls = class_flat(c, deadzone=dz)
+    cls = class_flat(c, deadzone=c.deadzone if dz == "class" else dz)
     if flags & mgx.FLAG_LAG_EULER:
         cls[48:48 + m] = DT / c.tau
     rec = rec_flat(c, *prm)
@@ -96,13 +105,16 @@ def test_step_vjp_matches_finite_differences(seed, flags, dz, omega):
     assert np.allclose(g_total, fd_th, rtol=1e-5, atol=1e-6 * sc), np.abs(g_total - fd_th).max()
 
 
-def test_step_body_on_host_is_the_documented_map():
+@pytest.mark.parametrize("variants", [False, True])
+def test_step_body_on_host_is_the_documented_map(variants):
     """The host evaluation of the kernels' step body agrees with the FP64 oracle (same
-    inputs in double): both implement the same step."""
+    inputs in double): both implement the same step, with and without the propeller
+    variants (dead zone, reverse gain, shaft torque)."""
     import oracle
-    c, prm, state, a, xbar = setup(5)
+    c, prm, state, a, xbar = setup(5, variants=variants)
     mass, added, dlin, dquad, buoy, current = prm
-    s1 = mgx.mgx_host_step_vjp(c.m, 0, class_flat(c), rec_flat(c, *prm), state, a, xbar)[0]
+    cls = class_flat(c, deadzone=c.deadzone)
+    s1 = mgx.mgx_host_step_vjp(c.m, 0, cls, rec_flat(c, *prm), state, a, xbar)[0]
     p = synth.EnvParams(np.array([mass]), added[:, None], dlin[:, None], dquad[:, None], np.array([buoy]),
                         current[:, None])
     env = oracle.make_envs(c, p, DT)

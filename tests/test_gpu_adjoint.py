@@ -25,10 +25,12 @@ H = 256
 FD_H = 1e-4
 
 
-def _setup(n, precision):
+def _setup(n, precision, variants=False):
     t = torch()
     from paper_2503_09203_amd.autograd import DiffRollout
     w = synth.differentiable(n=n, horizon=H)
+    if variants:
+        w.classes[0] = synth.propeller_variants(w.classes[0])
     b = mgx.Batch(w.classes, w.n_envs, w.dt, precision)
     init = t.tensor(b.pack_state([w.state[0].stacked()]), dtype=b.dtype, device=b.device)
     ro = DiffRollout(b, w.params, init, H, hold=1)
@@ -91,11 +93,13 @@ def _check_block(g, g_fd, tol, mask=None, label=""):
     assert err.max() <= tol, (label, err.max())
 
 
-@pytest.mark.parametrize("precision,tol", [(mgx.FP64, 1e-5), (mgx.FP32, 1e-3)])
-def test_rollout_gradients_match_oracle_finite_differences(precision, tol):
+@pytest.mark.parametrize("precision,tol,variants", [(mgx.FP64, 1e-5, False), (mgx.FP32, 1e-3, False),
+                                                    (mgx.FP32, 1e-3, True)])
+def test_rollout_gradients_match_oracle_finite_differences(precision, tol, variants):
+    """variants: the class with dead zones, reverse gains and shaft torques."""
     t = torch()
     n = 16
-    w, b, ro, acts_np, actions, dl, dq, am = _setup(n, precision)
+    w, b, ro, acts_np, actions, dl, dq, am = _setup(n, precision, variants)
     wp = t.tensor(w.extra["waypoints"], dtype=t.float64, device=b.device)
     loss = _loss(ro, actions, dl, dq, am, wp)
     loss.backward()

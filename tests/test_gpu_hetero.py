@@ -166,3 +166,24 @@ def test_sixteen_classes_of_one_to_eight_thrusters():
                 err = component_errors(g, r)
                 assert np.all(err <= bar), (mode, k, c, err.max())
     assert np.array_equal(finals[0], finals[1])
+
+
+def test_propeller_variant_classes_in_the_persistent_launch():
+    """Two of the five classes with dead zones, reverse gains and shaft torques next to
+    three plain ones: the persistent launch takes the shaped-thrust body per tile and
+    agrees bitwise with per-class launches, and both match the oracle."""
+    w = synth.heterogeneous(scale=0.05, steps=64)
+    w.classes[1] = synth.propeller_variants(w.classes[1])
+    w.classes[3] = synth.propeller_variants(w.classes[3])
+    acts = w.actions(8)
+    finals = []
+    for mode in (mgx.LAUNCH_PER_CLASS, mgx.LAUNCH_PERSISTENT):
+        fin = []
+        res = run_pair(w, acts, 10, [1, 64], chunk=16, shape=(mode, 16), final_state=fin)
+        finals.append(fin[0])
+        for k, pairs in res:
+            bar = 1e-5 if k == 1 else 5e-4
+            for c, (g, r) in enumerate(pairs):
+                err = component_errors(g, r)
+                assert np.all(err <= bar), (mode, k, c, err.max())
+    assert np.array_equal(finals[0], finals[1])

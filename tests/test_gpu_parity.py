@@ -106,6 +106,29 @@ def test_actuator_and_model_variants(flags):
     check(res, {1: 1e-5, 200: 1e-3}, f"variant{flags}")
 
 
+def test_propeller_variants():
+    """Dead zones, reverse gains and shaft torques on every thruster (the shaped-thrust
+    instantiation), ragged size, fused 16-step launches and one-step launches."""
+    w = synth.propellers(n=1000, steps=200)
+    c = w.classes[0]
+    assert np.all(c.k_rev < c.k) and np.all(c.deadzone > 0) and np.all(np.abs(c.reaction) > 0)
+    acts = w.actions(20)
+    check(run_pair(w, acts, 10, [1, 10, 200], chunk=16), {1: 1e-5, 10: 1e-4, 200: 1e-3}, "propellers")
+    check(run_pair(w, acts, 10, [1, 10]), {1: 1e-5, 10: 1e-4}, "propellers unchunked")
+    check(run_pair(w, acts, 10, [1, 50], precision=mgx.FP64), 1e-9, "propellers fp64")
+
+
+def test_propellers_full_size_sampled():
+    """65,536 environments with the propeller variants in 16-step launches; 512 sampled
+    environments against the oracle after 1 and 1000 steps."""
+    w = synth.propellers()
+    rng = np.random.default_rng(1)
+    s = np.sort(rng.choice(w.n_total, 512, replace=False))
+    s[0], s[-1] = 0, w.n_total - 1
+    res = run_pair(w, w.actions(100), 10, [1, 1000], sample=[s], chunk=16)
+    check(res, {1: 1e-5, 1000: 1e-3}, "propellers 65536 sampled")
+
+
 def test_fast_spin_takes_the_exact_attitude_increment():
     """Odd environments spin at 15-40 rad/s about their largest principal axis (a stable
     rotation), where |w| dt / 2 > 0.05 and the attitude increment is evaluated exactly with

@@ -155,3 +155,24 @@ def test_iterations_with_more_tiles_than_waves():
     for a, m in zip(alone, mixed):
         assert np.array_equal(a, m)
     assert stats.completed == 3
+
+
+def test_propeller_variant_class_is_served():
+    """A class with dead zones, reverse gains and shaft torques, served next to the plain
+    classes, matches the oracle."""
+    cs = list(classes()) + [synth.propeller_variants(classes()[2])]
+    s = mgx.Server(cs, [nominal(c) for c in cs], chunk_steps=32)
+    r = s.submit(class_index=5, n_envs=700, horizon=90, seed=13, keep=True)
+    other = s.submit(class_index=2, n_envs=300, horizon=40, seed=14)
+    st = s.wait(r)
+    s.wait(other)
+    got = s.read_state(st.session, 5, 700)
+    s.close()
+    c = cs[5]
+    ini = synth.initial_state(700, c.m, 13)
+    x = oracle.pack_state(ini.p, ini.q, ini.nu, ini.n)
+    a = synth.actions(700, c.m, 90 // 10 + 1, 13)
+    envs = oracle.make_envs(c, synth.nominal_params(c, 700), 0.01)
+    x, _, _ = oracle.rollout(envs, x, oracle.pack_actions(a), 10, 90)
+    ref = oracle.unpack_state(x, c.m)
+    assert component_errors(got.astype(np.float64), ref).max() <= 5e-4
