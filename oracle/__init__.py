@@ -32,7 +32,11 @@ ENV_DTYPE = np.dtype([
     ("rb", np.float64, 3), ("current", np.float64, 3), ("r", np.float64, (MAX_THR, 3)),
     ("e", np.float64, (MAX_THR, 3)), ("k", np.float64, MAX_THR), ("tau", np.float64, MAX_THR),
     ("deadzone", np.float64, MAX_THR), ("k_rev", np.float64, MAX_THR),
-    ("reaction", np.float64, MAX_THR)], align=True)
+    ("reaction", np.float64, MAX_THR), ("kind", np.int32, MAX_THR), ("span", np.float64, (MAX_THR, 3)),
+    ("fin_max", np.float64, MAX_THR), ("fin_lift", np.float64, MAX_THR), ("fin_drag0", np.float64, MAX_THR),
+    ("fin_drag", np.float64, MAX_THR)], align=True)
+PROPELLER = 0
+FIN = 1
 
 _lib = None
 
@@ -68,6 +72,7 @@ def lib():
         L.orc_rotation.argtypes = [P, P]
         L.orc_quat_mul.argtypes = [P, P, P]
         L.orc_thrust_wrench.argtypes = [P, P, P]
+        L.orc_fin_wrench.argtypes = [P, P, P, P, P]
         L.orc_terms_eval.argtypes = [P, P, P, P, P]
         L.orc_step.argtypes = [P, P, P, P]
         L.orc_rollout.restype = ctypes.c_int32
@@ -126,6 +131,13 @@ def make_envs(cls, params, dt: float, flags: int = 0, idx=None) -> np.ndarray:
     if getattr(cls, "reaction", None) is not None:
         react[:cls.m] = cls.reaction
     env["k_rev"], env["reaction"] = krev, react
+    if getattr(cls, "kind", None) is not None:
+        kind = np.zeros(MAX_THR, dtype=np.int32); kind[:cls.m] = cls.kind
+        span = np.zeros((MAX_THR, 3)); span[:cls.m] = cls.span
+        env["kind"], env["span"] = kind, span
+        for f in ("fin_max", "fin_lift", "fin_drag0", "fin_drag"):
+            a = np.zeros(MAX_THR); a[:cls.m] = getattr(cls, f)
+            env[f] = a
     return env
 
 
@@ -209,6 +221,17 @@ def thrust_wrench(env_one, n):
     nn = np.zeros(MAX_THR)
     nn[:len(n)] = n
     lib().orc_thrust_wrench(_p(env_one), _p(nn), _p(out))
+    return out
+
+
+def fin_wrench(env_one, n, vr, w):
+    """Wrench of the fins of one environment at rotor state n, relative velocity vr, rate w."""
+    out = np.zeros(6)
+    nn = np.zeros(MAX_THR)
+    nn[:len(n)] = n
+    vr = np.ascontiguousarray(vr, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    lib().orc_fin_wrench(_p(env_one), _p(nn), _p(vr), _p(w), _p(out))
     return out
 
 

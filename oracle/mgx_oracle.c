@@ -86,6 +86,7 @@ double orc_lag_factor(const orc_env* env, int32_t i) {
 void orc_thrust_wrench(const orc_env* env, const double n[ORC_MAX_THR], double tau[6]) {
     for (int j = 0; j < 6; ++j) tau[j] = 0.0;
     for (int i = 0; i < env->m; ++i) {
+        if (env->kind[i] == ORC_FIN) continue;
         double mag = fabs(n[i]) - env->deadzone[i];
         double s = mag > 0.0 ? (n[i] >= 0.0 ? mag : -mag) : 0.0;
         double gain = env->k[i];
@@ -99,6 +100,53 @@ void orc_thrust_wrench(const orc_env* env, const double n[ORC_MAX_THR], double t
         for (int j = 0; j < 3; ++j) {
             tau[j] += f * e[j];
             tau[3 + j] += f * mom[j] + env->reaction[i] * f * e[j];
+        }
+    }
+}
+
+/* Rudder (fin) forces, Sec. III-D: a simplified lift and drag law whose forces depend on
+ * the flow speed at the fin, its area and lift and drag coefficients that vary with the
+ * angle of attack. Fin i sits at r_i and moves through the water with u = v_r + w x r_i.
+ * Its plane is normal to the span axis s; in that plane the chord at zero deflection is c
+ * (e_i without its span component) and nn = s x c. The rotor state n_i (after the shared
+ * lag) sets the deflection delta = delta_max n_i, turning the chord toward nn. With
+ * u_p the in-plane part of u and beta = atan2(u_p . nn, u_p . c) its direction, the angle
+ * of attack is alpha = delta - beta. Flat-plate coefficients: lift K_L sin(alpha)cos(alpha)
+ * |u_p|^2 along s x u_p / |u_p|, drag (K_D0 + K_D sin^2(alpha)) |u_p|^2 against u_p. The
+ * force acts at r_i: the wrench [F ; r_i x F] is added to tau. */
+void orc_fin_wrench(const orc_env* env, const double n[ORC_MAX_THR], const double vr[3], const double w[3],
+                    double tau[6]) {
+    for (int i = 0; i < env->m; ++i) {
+        if (env->kind[i] != ORC_FIN) continue;
+        double s[3], c[3], nn[3], u[3], wxr[3];
+        double sl = sqrt(env->span[i][0] * env->span[i][0] + env->span[i][1] * env->span[i][1] +
+                         env->span[i][2] * env->span[i][2]);
+        for (int j = 0; j < 3; ++j) s[j] = env->span[i][j] / sl;
+        double es = env->e[i][0] * s[0] + env->e[i][1] * s[1] + env->e[i][2] * s[2];
+        for (int j = 0; j < 3; ++j) c[j] = env->e[i][j] - es * s[j];
+        double cl = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        for (int j = 0; j < 3; ++j) c[j] /= cl;
+        cross3(s, c, nn);
+        cross3(w, env->r[i], wxr);
+        for (int j = 0; j < 3; ++j) u[j] = vr[j] + wxr[j];
+        double uc = u[0] * c[0] + u[1] * c[1] + u[2] * c[2];
+        double un = u[0] * nn[0] + u[1] * nn[1] + u[2] * nn[2];
+        double speed2 = uc * uc + un * un;
+        if (speed2 == 0.0) continue;
+        double speed = sqrt(speed2);
+        double up[3], lift_dir[3];
+        for (int j = 0; j < 3; ++j) up[j] = (uc * c[j] + un * nn[j]) / speed;
+        cross3(s, up, lift_dir);
+        double alpha = env->fin_max[i] * n[i] - atan2(un, uc);
+        double sa = sin(alpha), ca = cos(alpha);
+        double L = env->fin_lift[i] * sa * ca * speed2;
+        double D = (env->fin_drag0[i] + env->fin_drag[i] * sa * sa) * speed2;
+        double F[3], mom[3];
+        for (int j = 0; j < 3; ++j) F[j] = L * lift_dir[j] - D * up[j];
+        cross3(env->r[i], F, mom);
+        for (int j = 0; j < 3; ++j) {
+            tau[j] += F[j];
+            tau[3 + j] += mom[j];
         }
     }
 }
@@ -125,6 +173,7 @@ void orc_terms_eval(const orc_env* env, const double q[4], const double nu[6],
         vr[j] = v[j] - vc[j];
     }
     orc_thrust_wrench(env, n_lagged, out->tau);
+    orc_fin_wrench(env, n_lagged, vr, w, out->tau);
 
     double t3[3], Iw[3], A1vr[3], A2w[3], t4[3];
     cross3(w, v, t3);

@@ -22,6 +22,9 @@
 #define ORC_FLAG_NO_AMC 1u          /* drop the added-mass term from the rotating current */
 #define ORC_FLAG_LAG_EULER 2u       /* rotor lag factor dt/tau instead of the exact hold */
 
+#define ORC_PROPELLER 0
+#define ORC_FIN 1
+
 typedef struct {
     int32_t m;                  /* thrusters, 1..8 */
     uint32_t flags;
@@ -41,6 +44,13 @@ typedef struct {
     double k_rev[ORC_MAX_THR];  /* reverse thrust gain (N at n = -1); 0 = same as k */
     double reaction[ORC_MAX_THR]; /* shaft torque per unit thrust about e (m), signed by
                                      the propeller's handedness */
+    int32_t kind[ORC_MAX_THR];  /* ORC_PROPELLER or ORC_FIN */
+    double span[ORC_MAX_THR][3];  /* fin: hinge (span) axis; e is then the chord at zero
+                                     deflection (the component along the span is dropped) */
+    double fin_max[ORC_MAX_THR];  /* fin: deflection at n = 1 (rad) */
+    double fin_lift[ORC_MAX_THR]; /* fin: K_L = rho A c_L / 2 (kg/m) */
+    double fin_drag0[ORC_MAX_THR]; /* fin: K_D0 = rho A c_D0 / 2 (kg/m) */
+    double fin_drag[ORC_MAX_THR]; /* fin: K_D = rho A c_D / 2 (kg/m) */
 } orc_env;
 
 typedef struct {
@@ -67,6 +77,8 @@ void orc_rotation(const double q[4], double R[3][3]);
 void orc_quat_mul(const double a[4], const double b[4], double out[4]);
 double orc_lag_factor(const orc_env* env, int32_t i);
 void orc_thrust_wrench(const orc_env* env, const double n[ORC_MAX_THR], double tau[6]);
+void orc_fin_wrench(const orc_env* env, const double n[ORC_MAX_THR], const double vr[3], const double w[3],
+                    double tau[6]);
 void orc_terms_eval(const orc_env* env, const double q[4], const double nu[6],
                     const double n_lagged[ORC_MAX_THR], orc_terms* out);
 

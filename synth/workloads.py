@@ -92,6 +92,12 @@ class VehicleClass:
     index: int = 0
     k_rev: np.ndarray | None = None     # [m] reverse thrust gain (N at n = -1); None = k
     reaction: np.ndarray | None = None  # [m] shaft torque per unit thrust about e (m); None = 0
+    kind: np.ndarray | None = None      # [m] 0 propeller, 1 fin (rudder); None = all propellers
+    span: np.ndarray | None = None      # [m,3] fin hinge axes (e is then the chord)
+    fin_max: np.ndarray | None = None   # [m] fin deflection at n = 1 (rad)
+    fin_lift: np.ndarray | None = None  # [m] rho A c_L / 2 (kg/m)
+    fin_drag0: np.ndarray | None = None  # [m] rho A c_D0 / 2 (kg/m)
+    fin_drag: np.ndarray | None = None  # [m] rho A c_D / 2 (kg/m)
 
 
 @dataclass
@@ -237,6 +243,36 @@ def propeller_variants(cls: VehicleClass, seed: int = MASTER_SEED) -> VehicleCla
     sign = np.where(np.arange(m) % 2 == 0, 1.0, -1.0)
     return replace(cls, deadzone=f32(0.05 + 0.10 * u[:m]), k_rev=f32(cls.k * (0.6 + 0.25 * u[m:2 * m])),
                    reaction=f32(sign * (0.02 + 0.03 * u[2 * m:])))
+
+
+def rudder_class(seed: int = MASTER_SEED) -> VehicleClass:
+    """A rudder-propeller vehicle (a main propeller astern and a cruciform tail): the hull
+    of a drawn class, one propeller on the centre line pushing along x, and four fins at
+    the tail with their chords along x, two with a horizontal hinge (pitch) and two with a
+    vertical hinge (yaw). Fin deflection U[0.35, 0.5] rad at full command, servo lag
+    U[0.05, 0.1] s, lift gain rho A c_L / 2 U[8, 15] kg/m, drag gains U[0.2, 0.4] and U[3, 6]
+    kg/m (fins of about 0.01 m^2 in sea water)."""
+    hull = draw_class(6, 30, seed)
+    u = _uniforms(seed, STREAM_CLASS, 50, 0, 2, 32)[0]
+    it = iter(u)
+
+    def U(lo, hi):
+        return lo + (hi - lo) * next(it)
+
+    m = 5
+    r = np.array([[-0.6, 0.0, 0.0], [-0.5, 0.1, 0.0], [-0.5, -0.1, 0.0], [-0.5, 0.0, 0.1], [-0.5, 0.0, -0.1]])
+    e = np.tile([1.0, 0.0, 0.0], (m, 1))
+    span = np.array([[0.0, 0.0, 1.0], [0.0, 1.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0], [0.0, 0.0, 1.0]])
+    k = np.array([U(40.0, 60.0), 0.0, 0.0, 0.0, 0.0])
+    tau = np.array([U(0.05, 0.15)] + [U(0.05, 0.10) for _ in range(4)])
+    fin_max = np.array([0.0] + [U(0.35, 0.5) for _ in range(4)])
+    fin_lift = np.array([0.0] + [U(8.0, 15.0) for _ in range(4)])
+    fin_drag0 = np.array([0.0] + [U(0.2, 0.4) for _ in range(4)])
+    fin_drag = np.array([0.0] + [U(3.0, 6.0) for _ in range(4)])
+    return replace(hull, m=m, r=f32(r), e=f32(e), k=f32(k), tau=f32(tau), deadzone=np.zeros(m), k_rev=None,
+                   reaction=None, kind=np.array([0, 1, 1, 1, 1], dtype=np.int32), span=f32(span),
+                   fin_max=f32(fin_max), fin_lift=f32(fin_lift), fin_drag0=f32(fin_drag0), fin_drag=f32(fin_drag),
+                   index=30)
 
 
 def nominal_params(cls: VehicleClass, n: int) -> EnvParams:
@@ -404,6 +440,12 @@ def propellers(seed: int = MASTER_SEED, n: int = 65536, steps: int = 1000) -> Wo
     zones, direction-dependent gains and shaft torques on every thruster."""
     return _build(f"prop_{n}x{steps}", [propeller_variants(plain_class(seed), seed)], [n], steps, 10, True, 0.3,
                   seed)
+
+
+def rudders(seed: int = MASTER_SEED, n: int = 65536, steps: int = 1000) -> Workload:
+    """The rudder-propeller class of ``rudder_class`` with the randomisation and currents of
+    the randomised workload, commands resampled every 10 steps."""
+    return _build(f"rudder_{n}x{steps}", [rudder_class(seed)], [n], steps, 10, True, 0.3, seed)
 
 
 def heterogeneous(seed: int = MASTER_SEED, scale: float = 1.0, steps: int = 1000) -> Workload:

@@ -45,6 +45,17 @@ MUTANTS = {
     "shaft_torque_sign": ("tau[3 + j] += f * mom[j] + env->reaction[i] * f * e[j];",
                           "tau[3 + j] += f * mom[j] - env->reaction[i] * f * e[j];"),
     "shaft_torque_dropped": ("tau[3 + j] += f * mom[j] + env->reaction[i] * f * e[j];", "tau[3 + j] += f * mom[j];"),
+    "fin_alpha_sign": ("double alpha = env->fin_max[i] * n[i] - atan2(un, uc);",
+                       "double alpha = env->fin_max[i] * n[i] + atan2(un, uc);"),
+    "fin_lift_direction": ("cross3(s, up, lift_dir);", "cross3(up, s, lift_dir);"),
+    "fin_drag_sign": ("F[j] = L * lift_dir[j] - D * up[j];", "F[j] = L * lift_dir[j] + D * up[j];"),
+    "fin_ignores_rotation": ("u[j] = vr[j] + wxr[j];", "u[j] = vr[j];"),
+    "fin_rotation_order": ("cross3(w, env->r[i], wxr);", "cross3(env->r[i], w, wxr);"),
+    "fin_moment_order": ("cross3(env->r[i], F, mom);", "cross3(F, env->r[i], mom);"),
+    "fin_keeps_span_flow": ("double speed2 = uc * uc + un * un;",
+                            "double speed2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];"),
+    "fin_not_deflected": ("double alpha = env->fin_max[i] * n[i] - atan2(un, uc);",
+                          "double alpha = -atan2(un, uc);"),
     "shaft_torque_unsigned": ("tau[3 + j] += f * mom[j] + env->reaction[i] * f * e[j];",
                               "tau[3 + j] += f * mom[j] + env->reaction[i] * fabs(f) * e[j];"),
     "lag_euler_always": ("return 1.0 - exp(-env->dt / env->tau[i]);", "return env->dt / env->tau[i];"),

@@ -165,6 +165,104 @@ def test_p2_power_with_reverse_gain_and_shaft_torque():
         assert abs(tau @ nu - power) < 1e-12 * (1 + abs(power))
 
 
+# ----------------------------------------------------------------------------- P12 rudder fins
+
+def fin_env(r=(0.0, 0.0, 0.0), span=(0.0, 0.0, 1.0), chord=(1.0, 0.0, 0.0), kl=15.0, kd0=0.3, kd=6.0, dmax=0.5):
+    """One fin and nothing else: span axis, chord at zero deflection, lift/drag gains."""
+    e = env1(m=1)
+    e["k"][0, 0] = 0.0
+    e["kind"][0, 0] = oracle.FIN
+    e["r"][0, 0], e["span"][0, 0], e["e"][0, 0] = r, span, chord
+    e["fin_max"][0, 0], e["fin_lift"][0, 0], e["fin_drag0"][0, 0], e["fin_drag"][0, 0] = dmax, kl, kd0, kd
+    return e
+
+
+def test_p12_fin_worked_example():
+    """Worked by hand: a vertical fin (span z, chord x) moving ahead at 2 m/s and turned by
+    0.3 rad toward +y meets the water at 0.3 rad. The flat-plate law pushes it toward +y with
+    15 sin(0.3)cos(0.3) 2^2 = 16.94 N and back with (0.3 + 6 sin^2(0.3)) 2^2 = 3.30 N; at
+    r = (-0.7, 0, 0.1) that force turns the hull by r x F. The propeller law gives nothing
+    for a fin, and the fin law nothing for a propeller."""
+    env = fin_env(r=(-0.7, 0.0, 0.1))
+    tau = oracle.fin_wrench(env, [0.6], [2.0, 0.0, 0.0], [0.0, 0.0, 0.0])
+    lift = 15.0 * np.sin(0.3) * np.cos(0.3) * 4.0
+    drag = (0.3 + 6.0 * np.sin(0.3) ** 2) * 4.0
+    assert abs(lift - 16.9393) < 1e-4 and abs(drag - 3.2960) < 1e-4
+    F = np.array([-drag, lift, 0.0])
+    assert np.allclose(tau[:3], F, rtol=0, atol=1e-12)
+    assert np.allclose(tau[3:], np.cross([-0.7, 0.0, 0.1], F), rtol=0, atol=1e-12)
+    assert np.all(oracle.thrust_wrench(env, [0.6]) == 0.0)
+    prop = env1(m=1)
+    assert np.all(oracle.fin_wrench(prop, [0.6], [2.0, 0.0, 0.0], [0.0, 0.0, 0.0]) == 0.0)
+
+
+def _rand_fin(rng):
+    span = rng.normal(size=3)
+    chord = rng.normal(size=3)
+    return fin_env(r=rng.uniform(-0.8, 0.8, 3), span=span, chord=chord, kl=rng.uniform(5, 30),
+                   kd0=rng.uniform(0.1, 1.0), kd=rng.uniform(1, 10), dmax=rng.uniform(0.2, 0.7))
+
+
+def _in_plane_flow(env, vr, w):
+    s = env["span"][0, 0] / np.linalg.norm(env["span"][0, 0])
+    u = vr + np.cross(w, env["r"][0, 0])
+    return u - (u @ s) * s
+
+
+def test_p12_fin_lift_does_no_work_and_drag_dissipates():
+    """Power identities: lift is normal to the in-plane flow, so a fin with only lift does
+    no work on the body (tau . [v_r; w] = 0); with only the angle-independent drag the power
+    is -K_D0 |u_p|^3, u_p the flow at the fin point without its span component."""
+    rng = np.random.default_rng(21)
+    for _ in range(30):
+        env = _rand_fin(rng)
+        vr, w, n = rng.normal(0, 1, 3), rng.normal(0, 1, 3), rng.uniform(-1, 1)
+        nur = np.concatenate([vr, w])
+        lift_only = env.copy()
+        lift_only["fin_drag0"], lift_only["fin_drag"] = 0.0, 0.0
+        t = oracle.fin_wrench(lift_only, [n], vr, w)
+        assert np.abs(t).max() > 1e-3
+        assert abs(t @ nur) < 1e-12 * np.abs(t).max() * np.abs(nur).max()
+        drag0 = env.copy()
+        drag0["fin_lift"], drag0["fin_drag"] = 0.0, 0.0
+        up = _in_plane_flow(env, vr, w)
+        t = oracle.fin_wrench(drag0, [n], vr, w)
+        ref = -env["fin_drag0"][0, 0] * np.linalg.norm(up) ** 3
+        assert abs(t @ nur - ref) < 1e-12 * abs(ref)
+
+
+def test_p12_fin_angle_of_attack_is_deflection_minus_flow_angle():
+    """A fin turned to the flow's own in-plane direction meets it edge-on: no lift, drag
+    K_D0 |u_p|^2 exactly against the flow. Flow along the span gives no force at all."""
+    rng = np.random.default_rng(22)
+    for _ in range(20):
+        beta = rng.uniform(-0.45, 0.45)
+        env = fin_env(dmax=0.5)
+        U = rng.uniform(0.5, 2.0)
+        vr = np.array([U * np.cos(beta), U * np.sin(beta), rng.normal()])   # z is the span
+        t = oracle.fin_wrench(env, [beta / 0.5], vr, np.zeros(3))
+        F = -0.3 * U * U * np.array([np.cos(beta), np.sin(beta), 0.0])
+        assert np.allclose(t[:3], F, rtol=0, atol=1e-12)
+    assert np.all(oracle.fin_wrench(fin_env(), [0.7], [0.0, 0.0, 1.3], [0.0, 0.0, 0.0]) == 0.0)
+
+
+def test_p12_fin_small_angle_lift_slope_and_mirror():
+    """Thin-fin limit: moving along the chord at U with a small deflection delta, the lift
+    tends to K_L delta U^2 (relative error O(delta^2)). Mirroring the deflection and the
+    cross flow mirrors the normal force and keeps the chordwise one."""
+    env = fin_env(kl=12.0, dmax=0.5)
+    for d in (1e-2, 1e-3):
+        t = oracle.fin_wrench(env, [d / 0.5], [1.5, 0.0, 0.0], np.zeros(3))
+        assert abs(t[1] / (12.0 * d * 1.5 ** 2) - 1) < 2 * d * d
+    rng = np.random.default_rng(23)
+    for _ in range(10):
+        n = rng.uniform(-1, 1)
+        vr = np.array([rng.uniform(0.3, 2), rng.normal(), rng.normal()])
+        a = oracle.fin_wrench(env, [n], vr, np.zeros(3))
+        b = oracle.fin_wrench(env, [-n], vr * [1, -1, 1], np.zeros(3))
+        assert np.allclose([a[0], a[1]], [b[0], -b[1]], rtol=0, atol=1e-12)
+
+
 # ----------------------------------------------------------------------------- P3 kinematics
 
 def euler_zyx_matrix(phi, th, psi):
