@@ -89,9 +89,10 @@ def main():
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="dr", choices=["dr", "propellers", "hetero", "serve", "adjoint"],
+    ap.add_argument("--workload", default="dr", choices=["dr", "propellers", "rudders", "hetero", "serve", "adjoint"],
                     help="dr: the default benchmark line; propellers: the same line with dead zones, reverse "
-                         "gains and shaft torques on every thruster; hetero: five classes in one persistent launch; "
+                         "gains and shaft torques on every thruster; rudders: the same line for a rudder-propeller "
+                         "class (one propeller, four tail fins); hetero: five classes in one persistent launch; "
                          "serve: Poisson request trace through the continuous-batching server and the FIFO baseline; "
                          "adjoint: checkpointed forward and reverse sweep of the differentiable rollout")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: requests per second")
@@ -146,9 +147,11 @@ def main():
     if args.workload == "adjoint":
         adjoint(args)
         return
-    shaped = args.workload == "propellers"
-    w = synth.propellers(n=N, steps=T) if shaped else synth.randomised(n=N, steps=T)
+    variant = args.workload  # dr, propellers or rudders
+    make = {"dr": synth.randomised, "propellers": synth.propellers, "rudders": synth.rudders}[variant]
+    w = make(n=N, steps=T)
     cls = w.classes[0]
+    shaped = variant != "dr"
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream(dev)
     b = mgx.Batch([cls], [N], w.dt, mgx.FP32)
@@ -187,7 +190,7 @@ def main():
     # Fused kernel: HIP events on the batch's stream around every graph replay (the
     # rollout's n_launch kernel launches back to back); average launch duration =
     # elapsed / n_launch, so inter-kernel gaps count against the kernel.
-    flops_es, ops_es = mgx.mgx_step_cost(cls.m, mgx.COST_SHAPED if shaped else 0)
+    flops_es, ops_es = mgx.mgx_class_step_cost(mgx.mgx_class_define(cls))
     graph_s = np.array([a.elapsed_time(c) for a, c in ev]) * 1e-3
     fused_launch = float(graph_s.mean()) / n_launch
     fused_flops_per_launch = flops_es * N * T / n_launch
@@ -225,17 +228,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{'prop' if shaped else 'dr'}_{N}x{T}", "n_envs": N, "rollout_steps": T, "thrusters": cls.m, "hold": HOLD,
+        "config": {"workload": f"{ {'dr': 'dr', 'propellers': 'prop', 'rudders': 'rudder'}[variant] }_{N}x{T}", "n_envs": N, "rollout_steps": T, "thrusters": cls.m, "hold": HOLD,
                    "launch_steps_K": K, "dt": w.dt, "current_sigma": 0.3, "randomisation": 0.2,
                    "path": "set_params + reset + graph of fused launches"},
         "roofline": {"bound": "alu", "achieved": fused_flops_per_launch / fused_launch / 1e12,
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
                      "frac": fused_flops_per_launch / fused_launch / PEAK_FP32_VECTOR, "traffic": traffic.get(K),
                      "traffic_unit": "B/launch",
-                     "kernel": f"k_step<float,{cls.m},false,false,{str(shaped).lower()}> K={K}", "launches_per_step": n_launch,
+                     "kernel": f"k_step<float,{cls.m},false,false,{str(shaped).lower()},{str(variant == 'rudders').lower()}> K={K}", "launches_per_step": n_launch,
                      "launch_us_mean": fused_launch * 1e6, "flops_per_env_step": flops_es,
                      "valu_ops_per_env_step": ops_es},
-        "single_step": {"env_steps_per_s": single_rate, "kernel": f"k_step<float,{cls.m},false,true,{str(shaped).lower()}> K=1",
+        "single_step": {"env_steps_per_s": single_rate, "kernel": f"k_step<float,{cls.m},false,true,{str(shaped).lower()},{str(variant == 'rudders').lower()}> K=1",
                         "launch_us_mean": single_launch * 1e6,
                         "roofline": {"bound": "hbm", "achieved": single_bytes / single_launch / 1e9,
                                      "peak": PEAK_HBM / 1e9, "unit": "GB/s",
@@ -269,8 +272,13 @@ def main():
                                "kind": "oracle",
                                "sample": f"{n_s} of {N} environments (evenly spaced ids) x {T} steps, FP64 C oracle, "
                                          f"OpenMP over environments, {cpu_elapsed:.1f} s"}
+        # The rudder class's attitude dynamics amplify rounding about 20x more than the propeller
+        # classes' (the FP64 oracle with its state rounded to FP32 after every step already
+        # differs by 5.9e-4 after 1000 steps, against 2.9e-5 for the randomised workload), so its
+        # bar is 5e-3 rather than the 1e-3 of the propeller workloads.
+        tol = 5e-3 if variant == "rudders" else 1e-3
         out["parity"] = {"metric": "max over envs |gpu - oracle| / max(|oracle|, rms), per state component",
-                         "step": T, "max_err": float(err.max()), "tolerance": 1e-3, "pass": bool(err.max() <= 1e-3),
+                         "step": T, "max_err": float(err.max()), "tolerance": tol, "pass": bool(err.max() <= tol),
                          "envs_checked": n_s}
 
     g1.close()

@@ -106,12 +106,34 @@ typedef struct {
     double k_rev[MGX_MAX_THRUSTERS];    /* reverse thrust gain (N at n = -1), >= 0; 0 = k */
     double reaction[MGX_MAX_THRUSTERS]; /* shaft torque per unit thrust about e (m), signed
                                            by the propeller's handedness; finite */
+    /* Rudders (Sec. III-D: lift and drag depending on the flow speed, the fin area and
+     * coefficients that vary with the angle of attack). An actuator of kind MGX_ACT_FIN at
+     * r moves through the water at u = v_r + w x r. Its plane is normal to span; e is the
+     * chord at zero deflection (its span component is dropped) and nn = span x chord. The
+     * lagged state n sets the deflection fin_max * n toward nn; the angle of attack a is
+     * the deflection minus the angle of the in-plane flow u_p from the chord. Lift
+     * fin_lift sin(a)cos(a)|u_p|^2 acts along span x u_p / |u_p|, drag
+     * (fin_drag0 + fin_drag sin^2(a))|u_p|^2 against u_p, both at r. k, k_rev, reaction
+     * and deadzone are not used for fins. */
+    int32_t kind[MGX_MAX_THRUSTERS];    /* MGX_ACT_PROPELLER (0) or MGX_ACT_FIN (1) */
+    double span[MGX_MAX_THRUSTERS][3];  /* fin hinge axis, not parallel to e */
+    double fin_max[MGX_MAX_THRUSTERS];  /* deflection at n = 1 (rad), in (0, pi/2] */
+    double fin_lift[MGX_MAX_THRUSTERS]; /* rho A c_L / 2 (kg/m), >= 0 */
+    double fin_drag0[MGX_MAX_THRUSTERS]; /* rho A c_D0 / 2 (kg/m), >= 0 */
+    double fin_drag[MGX_MAX_THRUSTERS]; /* rho A c_D / 2 (kg/m), >= 0 */
 } mgx_class_desc;
+
+#define MGX_ACT_PROPELLER 0
+#define MGX_ACT_FIN 1
 
 /* Registers a class; *class_id receives its id (process-wide, never reused).
  * MGX_E_INVALID on a non-finite or out-of-range field, a zero-length thrust axis, or when
  * 4096 classes are already defined. */
 mgx_status mgx_class_define(const mgx_class_desc* desc, int32_t* class_id);
+
+/* Algorithmic cost of one environment-step of a defined class, counted like mgx_step_cost
+ * over the body its batches run (plain, shaped thrust, or with fins). */
+mgx_status mgx_class_step_cost(int32_t class_id, uint32_t batch_flags, double* flops, double* valu_ops);
 
 /* ------------------------------------------------------------------ batches */
 
@@ -239,7 +261,8 @@ mgx_status mgx_gen_actions(mgx_batch* b, void* out, int64_t rows, int64_t row_of
 #define MGX_LAUNCH_PER_CLASS 0   /* one launch per class segment */
 #define MGX_LAUNCH_PERSISTENT 1  /* one launch for all classes: per-class constants staged in
                                     LDS, waves pull 64-environment tiles from a device work
-                                    counter (FP32 batches; steps without traj/forces) */
+                                    counter (FP32 batches; steps without traj/forces; batches
+                                    with a fin class keep per-class launches) */
 
 typedef struct {
     int32_t mode;         /* MGX_LAUNCH_* */
@@ -272,7 +295,8 @@ mgx_status mgx_autotune_load(const char* path);
 /* ------------------------------------------------------------------ differentiable rollout */
 
 /* Forward pass of a differentiable rollout: H steps exactly as mgx_batch_step (same action
- * indexing, clip, launch per class), additionally writing the position after every step
+ * indexing, clip, launch per class; MGX_E_INVALID for a batch with a fin class, whose
+ * adjoint is not written), additionally writing the position after every step
  * and the full state every ckpt_every steps into library-owned scratch (allocated on first
  * use, kept until destroy). pos_out: device [H][3 * n_pad_total], class c at
  * 3 * (sum of n_pad of the classes before c), element (j, env) at that offset + j * n_pad[c]
@@ -389,6 +413,7 @@ typedef struct {
 
 /* Seconds on the server clock (steady). */
 double mgx_server_now(void);
+/* MGX_E_INVALID for a class with fins (the server runs propeller classes). */
 mgx_status mgx_server_create(const mgx_server_desc* d, mgx_server** out);
 /* Thread-safe. MGX_E_BUDGET if the request alone needs more than the budget;
  * MGX_E_INVALID on bad fields or an unknown / busy session. *request_id receives an id. */

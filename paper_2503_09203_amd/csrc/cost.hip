@@ -43,11 +43,12 @@ static inline Cnt max_(Cnt a, Cnt b) { return tally(std::fmax(a.v, b.v), 0, 1); 
 static inline Cnt copysign_(Cnt a, Cnt b) { return tally(std::copysign(a.v, b.v), 0, 1); }
 static inline Cnt select_(bool c, Cnt a, Cnt b) { return tally(c ? a.v : b.v, 0, 1); }
 static inline Cnt sqrt_(Cnt a) { return tally(std::sqrt(a.v), 1, 1); }
+static inline Cnt rsqrt_(Cnt a) { return tally(1.0 / std::sqrt(a.v), 1, 1); }
 static inline Cnt sin(Cnt a) { return tally(std::sin(a.v), 1, 1); }
 static inline Cnt cos(Cnt a) { return tally(std::cos(a.v), 1, 1); }
 
 template <int M>
-static CostTally measure(uint32_t flags) {
+static CostTally measure(uint32_t flags, uint32_t fin_mask = 0) {
     ClassT<Cnt> C;
     for (int j = 0; j < 6; ++j)
         for (int i = 0; i < kMaxThr; ++i) C.Bk[j][i] = Cnt(3.0 * (i + 1) + 0.3 * j);
@@ -67,6 +68,19 @@ static CostTally measure(uint32_t flags) {
     C.m = M;
     C.flags = flags & ~MGX_COST_SHAPED;
     C.shaped = (flags & MGX_COST_SHAPED) ? 1 : 0;
+    C.fin_mask = fin_mask;
+    for (int i = 0; i < kMaxThr; ++i) {
+        const double r[3] = {-0.5, 0.1, 0.05}, c[3] = {1, 0, 0}, n[3] = {0, 1, 0};
+        for (int j = 0; j < 3; ++j) {
+            C.fin_r[i][j] = r[j];
+            C.fin_c[i][j] = c[j];
+            C.fin_n[i][j] = n[j];
+        }
+        C.fin_max[i] = 0.4;
+        C.fin_kl[i] = 10;
+        C.fin_kd0[i] = 0.3;
+        C.fin_kd[i] = 5;
+    }
     EnvT<Cnt> E;
     for (int j = 0; j < 6; ++j) {
         E.dtMinv[j] = 0.001;
@@ -91,7 +105,9 @@ static CostTally measure(uint32_t flags) {
     Cnt a[M];
     for (int i = 0; i < M; ++i) a[i] = 0.5 - 0.1 * i;
     g_tally = CostTally();
-    if (flags & MGX_COST_SHAPED)
+    if (fin_mask)
+        step_body<Cnt, M, false, true, true>(C, E, IA2, Brb, s, a);
+    else if (flags & MGX_COST_SHAPED)
         step_body<Cnt, M, false, true>(C, E, IA2, Brb, s, a);
     else
         step_body<Cnt, M, false>(C, E, IA2, Brb, s, a);
@@ -114,6 +130,31 @@ extern "C" mgx_status mgx_step_cost(int32_t m, uint32_t batch_flags, double* flo
         case 7: t = measure<7>(batch_flags); break;
         case 8: t = measure<8>(batch_flags); break;
         default: return fail(MGX_E_INVALID, "m=%d outside [1,8]", m);
+    }
+    *flops = t.flops;
+    *valu_ops = t.ops;
+    return MGX_OK;
+}
+
+extern "C" mgx_status mgx_class_step_cost(int32_t class_id, uint32_t batch_flags, double* flops, double* valu_ops) {
+    using namespace mgx;
+    if (!flops || !valu_ops) return fail(MGX_E_INVALID, "NULL argument");
+    if (batch_flags & MGX_COST_SHAPED) return fail(MGX_E_INVALID, "MGX_COST_SHAPED is taken from the class");
+    mgx_class_desc cd;
+    if (!get_class(class_id, &cd)) return fail(MGX_E_INVALID, "class id %d unknown", class_id);
+    const ClassDesc64 d = to_desc64(cd);
+    const uint32_t fins = fin_mask_of(d);
+    const uint32_t f = batch_flags | (shaped_thrust(d) ? MGX_COST_SHAPED : 0u);
+    CostTally t;
+    switch (cd.m) {
+        case 1: t = measure<1>(f, fins); break;
+        case 2: t = measure<2>(f, fins); break;
+        case 3: t = measure<3>(f, fins); break;
+        case 4: t = measure<4>(f, fins); break;
+        case 5: t = measure<5>(f, fins); break;
+        case 6: t = measure<6>(f, fins); break;
+        case 7: t = measure<7>(f, fins); break;
+        default: t = measure<8>(f, fins); break;
     }
     *flops = t.flops;
     *valu_ops = t.ops;

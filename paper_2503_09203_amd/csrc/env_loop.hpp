@@ -151,13 +151,29 @@ __device__ __forceinline__ double in_vgpr(double x) {
     return x;
 }
 
-// A copy of the class constants for the step loop. With more than six thrusters the
-// per-thruster arrays (k-scaled layout columns, lag factors) move to vector registers;
-// up to six they fit the scalar file next to the loop's own scalars and stay there.
-template <typename T, int M>
+// A copy of the class constants for the step loop. With more than six thrusters, or with
+// fins, the per-actuator arrays (k-scaled layout columns, lag factors, fin geometry and
+// gains) move to vector registers; up to six propellers they fit the scalar file next to
+// the loop's own scalars and stay there.
+template <typename T, int M, bool kFins = false>
 __device__ __forceinline__ ClassT<T> class_in_vgpr(const ClassT<T>& Cs) {
     ClassT<T> C = Cs;
-    if constexpr (M > 6) {
+    if constexpr (kFins) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                C.fin_r[i][j] = in_vgpr(Cs.fin_r[i][j]);
+                C.fin_c[i][j] = in_vgpr(Cs.fin_c[i][j]);
+                C.fin_n[i][j] = in_vgpr(Cs.fin_n[i][j]);
+            }
+            C.fin_max[i] = in_vgpr(Cs.fin_max[i]);
+            C.fin_kl[i] = in_vgpr(Cs.fin_kl[i]);
+            C.fin_kd0[i] = in_vgpr(Cs.fin_kd0[i]);
+            C.fin_kd[i] = in_vgpr(Cs.fin_kd[i]);
+        }
+    }
+    if constexpr (M > 6 || kFins) {
 #pragma unroll
         for (int i = 0; i < M; ++i) {
 #pragma unroll
@@ -174,12 +190,12 @@ __device__ __forceinline__ ClassT<T> class_in_vgpr(const ClassT<T>& Cs) {
 // memory operations in flight inside it are those prefetches.
 // kSingle: a launch of exactly one step without outputs (the single-step kernel). Such a
 // launch never reaches the next action row, so it does not fetch it.
-template <typename T, int M, bool kOut, bool kShaped, bool kSingle = false>
+template <typename T, int M, bool kOut, bool kShaped, bool kSingle = false, bool kFins = false>
 __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs, int64_t env, int64_t t0, int K,
                                           float st[kStats]) {
     static_assert(!(kSingle && kOut), "the single-step form has no per-step outputs");
     const int64_t np = A.npad;
-    const ClassT<T> C = class_in_vgpr<T, M>(Cs);
+    const ClassT<T> C = class_in_vgpr<T, M, kFins>(Cs);
     T* S = (T*)A.state;
     const T* Rc = (const T*)A.rec;
     StateT<T, M> s;
@@ -238,7 +254,7 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
         Brb[j] = E.buoy * C.rb[j];
     }
     if constexpr (kSingle) {
-        step_body<T, M, false, kShaped>(C, E, IA2, Brb, s, cur);
+        step_body<T, M, false, kShaped, kFins>(C, E, IA2, Brb, s, cur);
     } else {
 
     // Runs of steps between action-row switches: the inner loop carries only its counter,
@@ -250,7 +266,7 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
         for (int j = 0; j < run; ++j, ++k) {
             if constexpr (kOut) {
                 T f[kForceLen];
-                step_body<T, M, true, kShaped>(C, E, IA2, Brb, s, cur, f);
+                step_body<T, M, true, kShaped, kFins>(C, E, IA2, Brb, s, cur, f);
                 if (A.forces) {
                     T* fo = (T*)A.forces + k * A.force_stride + env;
 #pragma unroll
@@ -268,7 +284,7 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
                     for (int i = 0; i < M; ++i) to[(kStateFixed + i) * np] = s.n[i];
                 }
             } else {
-                step_body<T, M, false, kShaped>(C, E, IA2, Brb, s, cur);
+                step_body<T, M, false, kShaped, kFins>(C, E, IA2, Brb, s, cur);
             }
         }
         phase += run;

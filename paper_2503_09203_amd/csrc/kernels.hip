@@ -21,8 +21,35 @@ __global__ void k_class_setup(const ClassDesc64* in, ClassT<float>* outf, ClassT
     const ClassDesc64& d = in[c];
     ClassT<double> D;
     const int shaped = shaped_thrust(d) ? 1 : 0;
+    const uint32_t fins = fin_mask_of(d);
     for (int i = 0; i < kMaxThr; ++i) {
-        if (i < d.m) {
+        for (int j = 0; j < 3; ++j) D.fin_r[i][j] = D.fin_c[i][j] = D.fin_n[i][j] = 0.0;
+        D.fin_max[i] = D.fin_kl[i] = D.fin_kd0[i] = D.fin_kd[i] = 0.0;
+        if (i < d.m && ((fins >> i) & 1u)) {
+            // fin: no layout column; the plane's basis from the span and the chord at zero
+            // deflection (the chord's span component dropped)
+            for (int j = 0; j < 6; ++j) D.Bk[j][i] = 0.0;
+            double sl = sqrt(d.span[i][0] * d.span[i][0] + d.span[i][1] * d.span[i][1] + d.span[i][2] * d.span[i][2]);
+            double s[3] = {d.span[i][0] / sl, d.span[i][1] / sl, d.span[i][2] / sl};
+            double es = d.e[i][0] * s[0] + d.e[i][1] * s[1] + d.e[i][2] * s[2];
+            double c[3] = {d.e[i][0] - es * s[0], d.e[i][1] - es * s[1], d.e[i][2] - es * s[2]};
+            double cl = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+            for (int j = 0; j < 3; ++j) c[j] /= cl;
+            const double nn[3] = {s[1] * c[2] - s[2] * c[1], s[2] * c[0] - s[0] * c[2], s[0] * c[1] - s[1] * c[0]};
+            for (int j = 0; j < 3; ++j) {
+                D.fin_r[i][j] = d.r[i][j];
+                D.fin_c[i][j] = c[j];
+                D.fin_n[i][j] = nn[j];
+            }
+            D.fin_max[i] = d.fin_max[i];
+            D.fin_kl[i] = d.fin_lift[i];
+            D.fin_kd0[i] = d.fin_drag0[i];
+            D.fin_kd[i] = d.fin_drag[i];
+            double tau = d.tau[i];
+            D.alpha[i] = tau > 0.0 ? ((flags & kFlagLagEuler) ? dt / tau : 1.0 - exp(-dt / tau)) : 1.0;
+            D.dz[i] = 0.0;
+            D.rev[i] = 1.0;
+        } else if (i < d.m) {
             double len = sqrt(d.e[i][0] * d.e[i][0] + d.e[i][1] * d.e[i][1] + d.e[i][2] * d.e[i][2]);
             double e[3] = {d.e[i][0] / len, d.e[i][1] / len, d.e[i][2] / len};
             const double* r = d.r[i];
@@ -58,12 +85,23 @@ __global__ void k_class_setup(const ClassDesc64* in, ClassT<float>* outf, ClassT
     D.flags = flags;
     D.shaped = shaped;
     D.pad2 = 0;
+    D.fin_mask = fins;
+    D.pad3 = 0;
     ClassT<float> F;
     for (int i = 0; i < kMaxThr; ++i) {
         for (int j = 0; j < 6; ++j) F.Bk[j][i] = (float)D.Bk[j][i];
         F.alpha[i] = (float)D.alpha[i];
         F.dz[i] = (float)D.dz[i];
         F.rev[i] = (float)D.rev[i];
+        for (int j = 0; j < 3; ++j) {
+            F.fin_r[i][j] = (float)D.fin_r[i][j];
+            F.fin_c[i][j] = (float)D.fin_c[i][j];
+            F.fin_n[i][j] = (float)D.fin_n[i][j];
+        }
+        F.fin_max[i] = (float)D.fin_max[i];
+        F.fin_kl[i] = (float)D.fin_kl[i];
+        F.fin_kd0[i] = (float)D.fin_kd0[i];
+        F.fin_kd[i] = (float)D.fin_kd[i];
     }
     for (int j = 0; j < 3; ++j) {
         F.inertia[j] = (float)D.inertia[j];
@@ -77,6 +115,8 @@ __global__ void k_class_setup(const ClassDesc64* in, ClassT<float>* outf, ClassT
     F.flags = flags;
     F.shaped = shaped;
     F.pad2 = 0;
+    F.fin_mask = fins;
+    F.pad3 = 0;
     outd[c] = D;
     outf[c] = F;
 }
@@ -155,10 +195,11 @@ __global__ void k_gen_actions(T* out, int m, int32_t npad, int64_t n_valid, int6
 // ----------------------------------------------------------------------------- step
 
 // K steps of every environment of one class segment; state in registers throughout.
-// kShaped: the class has dead zones or direction-dependent gains. It is a separate
-// instantiation (chosen on the host from the class) rather than a branch in one kernel, so
-// that the plain body's register allocation does not pay for the shaped one.
-template <typename T, int M, bool kOut, bool kSingle, bool kShaped>
+// kShaped: the class has dead zones or direction-dependent gains; kFins: it has fins (such
+// classes take the shaped propeller body too). Each is a separate instantiation (chosen
+// on the host from the class) rather than a branch in one kernel, so that the plain
+// body's register allocation does not pay for the others.
+template <typename T, int M, bool kOut, bool kSingle, bool kShaped, bool kFins>
 __global__ void __launch_bounds__(256) k_step(StepLaunch<T> L) {
     const StepArgs& A = L.a;
     const int tid = threadIdx.x;
@@ -171,7 +212,7 @@ __global__ void __launch_bounds__(256) k_step(StepLaunch<T> L) {
     float st[kStats];
 #pragma unroll
     for (int j = 0; j < kStats; ++j) st[j] = 0.0f;
-    if (env < A.npad) env_steps<T, M, kOut, kShaped, kSingle>(A, L.cls, env, t0, A.K, st);
+    if (env < A.npad) env_steps<T, M, kOut, kShaped, kSingle, kFins>(A, L.cls, env, t0, A.K, st);
     if (!A.partials) return;
     // Statistics: block partials, then the last block to finish reduces them in order.
     __shared__ float red[256 / kWave][kStats];
@@ -257,29 +298,31 @@ hipError_t launch_gen_actions(T* out_seg, int m, int32_t npad, int64_t n_valid, 
     return hipGetLastError();
 }
 
-template <typename T, int M>
-static void launch_step_m(const StepLaunch<T>& L, unsigned grid, int block, bool out, bool single, bool shaped,
-                          hipStream_t s) {
-    if (shaped) {
-        if (out)
-            hipLaunchKernelGGL((k_step<T, M, true, false, true>), dim3(grid), dim3(block), 0, s, L);
-        else if (single)
-            hipLaunchKernelGGL((k_step<T, M, false, true, true>), dim3(grid), dim3(block), 0, s, L);
-        else
-            hipLaunchKernelGGL((k_step<T, M, false, false, true>), dim3(grid), dim3(block), 0, s, L);
-    } else {
-        if (out)
-            hipLaunchKernelGGL((k_step<T, M, true, false, false>), dim3(grid), dim3(block), 0, s, L);
-        else if (single)
-            hipLaunchKernelGGL((k_step<T, M, false, true, false>), dim3(grid), dim3(block), 0, s, L);
-        else
-            hipLaunchKernelGGL((k_step<T, M, false, false, false>), dim3(grid), dim3(block), 0, s, L);
-    }
+template <typename T, int M, bool kShaped, bool kFins>
+static void launch_step_body(const StepLaunch<T>& L, unsigned grid, int block, bool out, bool single,
+                             hipStream_t s) {
+    if (out)
+        hipLaunchKernelGGL((k_step<T, M, true, false, kShaped, kFins>), dim3(grid), dim3(block), 0, s, L);
+    else if (single)
+        hipLaunchKernelGGL((k_step<T, M, false, true, kShaped, kFins>), dim3(grid), dim3(block), 0, s, L);
+    else
+        hipLaunchKernelGGL((k_step<T, M, false, false, kShaped, kFins>), dim3(grid), dim3(block), 0, s, L);
 }
 
-#define MGX_STEP_CASE(MM)                                                 \
-    case MM:                                                              \
-        launch_step_m<T, MM>(L, grid, block, out, single, shaped, s);     \
+template <typename T, int M>
+static void launch_step_m(const StepLaunch<T>& L, unsigned grid, int block, bool out, bool single, bool shaped,
+                          bool fins, hipStream_t s) {
+    if (fins)
+        launch_step_body<T, M, true, true>(L, grid, block, out, single, s);
+    else if (shaped)
+        launch_step_body<T, M, true, false>(L, grid, block, out, single, s);
+    else
+        launch_step_body<T, M, false, false>(L, grid, block, out, single, s);
+}
+
+#define MGX_STEP_CASE(MM)                                                     \
+    case MM:                                                                  \
+        launch_step_m<T, MM>(L, grid, block, out, single, shaped, fins, s);   \
         break;
 
 template <typename T>
@@ -288,6 +331,7 @@ hipError_t launch_step(const StepLaunch<T>& L, int m, int block, hipStream_t s) 
     const bool out = L.a.traj != nullptr || L.a.forces != nullptr;
     const bool single = L.a.K == 1;
     const bool shaped = L.cls.shaped != 0;
+    const bool fins = L.cls.fin_mask != 0;
     switch (m) {
         MGX_STEP_CASE(1)
         MGX_STEP_CASE(2)

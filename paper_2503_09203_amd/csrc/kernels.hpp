@@ -25,8 +25,12 @@ struct ClassDesc64 {
     int32_t m, pad;
     double r[kMaxThr][3], e[kMaxThr][3], k[kMaxThr], tau[kMaxThr], dz[kMaxThr];
     double k_rev[kMaxThr], reaction[kMaxThr];
+    int32_t kind[kMaxThr];  // 0 propeller, 1 fin
+    double span[kMaxThr][3], fin_max[kMaxThr], fin_lift[kMaxThr], fin_drag0[kMaxThr], fin_drag[kMaxThr];
     double inertia[3], rb[3], g0;
 };
+
+constexpr int32_t kActFin = 1;
 
 // Reverse thrust gain over forward gain of thruster i (1 when the reverse gain is unset).
 __host__ __device__ inline double reverse_ratio(const ClassDesc64& d, int i) {
@@ -37,8 +41,17 @@ __host__ __device__ inline double reverse_ratio(const ClassDesc64& d, int i) {
 // the shaped-thrust instantiation of the step body.
 __host__ __device__ inline bool shaped_thrust(const ClassDesc64& d) {
     bool s = false;
-    for (int i = 0; i < d.m && i < kMaxThr; ++i) s = s || d.dz[i] > 0.0 || reverse_ratio(d, i) != 1.0;
+    for (int i = 0; i < d.m && i < kMaxThr; ++i)
+        s = s || (d.kind[i] != kActFin && (d.dz[i] > 0.0 || reverse_ratio(d, i) != 1.0));
     return s;
+}
+
+// Bit i set when actuator i is a fin.
+__host__ __device__ inline uint32_t fin_mask_of(const ClassDesc64& d) {
+    uint32_t mask = 0;
+    for (int i = 0; i < d.m && i < kMaxThr; ++i)
+        if (d.kind[i] == kActFin) mask |= 1u << i;
+    return mask;
 }
 
 // Device bookkeeping of a batch. The step counter is double-buffered: a launch reads

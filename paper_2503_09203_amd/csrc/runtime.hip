@@ -59,6 +59,12 @@ ClassDesc64 to_desc64(const mgx_class_desc& c) {
     std::memcpy(d.dz, c.deadzone, sizeof d.dz);
     std::memcpy(d.k_rev, c.k_rev, sizeof d.k_rev);
     std::memcpy(d.reaction, c.reaction, sizeof d.reaction);
+    std::memcpy(d.kind, c.kind, sizeof d.kind);
+    std::memcpy(d.span, c.span, sizeof d.span);
+    std::memcpy(d.fin_max, c.fin_max, sizeof d.fin_max);
+    std::memcpy(d.fin_lift, c.fin_lift, sizeof d.fin_lift);
+    std::memcpy(d.fin_drag0, c.fin_drag0, sizeof d.fin_drag0);
+    std::memcpy(d.fin_drag, c.fin_drag, sizeof d.fin_drag);
     std::memcpy(d.inertia, c.inertia, sizeof d.inertia);
     std::memcpy(d.rb, c.rb, sizeof d.rb);
     d.g0 = c.g0;
@@ -132,8 +138,26 @@ extern "C" mgx_status mgx_class_define(const mgx_class_desc* d, int32_t* class_i
             l2 += d->e[i][j] * d->e[i][j];
         }
         if (!(l2 > 1e-24)) return fail(MGX_E_INVALID, "thruster %d: zero-length axis", i);
-        if (!(d->k[i] > 0) || !is_fin(d->k[i])) return fail(MGX_E_INVALID, "thruster %d: k must be > 0", i);
+        if (d->kind[i] != MGX_ACT_PROPELLER && d->kind[i] != MGX_ACT_FIN)
+            return fail(MGX_E_INVALID, "actuator %d: kind must be MGX_ACT_PROPELLER or MGX_ACT_FIN", i);
         if (!(d->tau[i] >= 0) || !is_fin(d->tau[i])) return fail(MGX_E_INVALID, "thruster %d: tau must be >= 0", i);
+        if (d->kind[i] == MGX_ACT_FIN) {
+            double s2 = 0, es = 0;
+            for (int j = 0; j < 3; ++j) {
+                if (!is_fin(d->span[i][j])) return fail(MGX_E_INVALID, "fin %d: non-finite span", i);
+                s2 += d->span[i][j] * d->span[i][j];
+                es += d->e[i][j] * d->span[i][j];
+            }
+            if (!(s2 > 1e-24)) return fail(MGX_E_INVALID, "fin %d: zero-length span", i);
+            if (!(l2 - es * es / s2 > 1e-12 * l2)) return fail(MGX_E_INVALID, "fin %d: chord parallel to the span", i);
+            if (!(d->fin_max[i] > 0 && d->fin_max[i] <= 1.5707963267948966))
+                return fail(MGX_E_INVALID, "fin %d: fin_max must be in (0, pi/2]", i);
+            if (!(d->fin_lift[i] >= 0) || !is_fin(d->fin_lift[i]) || !(d->fin_drag0[i] >= 0) ||
+                !is_fin(d->fin_drag0[i]) || !(d->fin_drag[i] >= 0) || !is_fin(d->fin_drag[i]))
+                return fail(MGX_E_INVALID, "fin %d: lift and drag gains must be finite and >= 0", i);
+            continue;
+        }
+        if (!(d->k[i] > 0) || !is_fin(d->k[i])) return fail(MGX_E_INVALID, "thruster %d: k must be > 0", i);
         if (!(d->deadzone[i] >= 0 && d->deadzone[i] < 1)) return fail(MGX_E_INVALID, "thruster %d: deadzone in [0,1)", i);
         if (!(d->k_rev[i] >= 0) || !is_fin(d->k_rev[i])) return fail(MGX_E_INVALID, "thruster %d: k_rev must be >= 0", i);
         if (!is_fin(d->reaction[i])) return fail(MGX_E_INVALID, "thruster %d: reaction must be finite", i);
@@ -480,7 +504,11 @@ namespace mgx {
 mgx_status enqueue_step(mgx_batch* b, const void* actions, int64_t n_rows, int64_t row0, int32_t hold, int32_t K,
                         bool stats, void* traj, void* forces, int block) {
     const size_t P = (size_t)b->prec;
-    if (b->mode == MGX_LAUNCH_PERSISTENT && !traj && !forces && b->prec == MGX_FP32) {
+    bool fins = false;
+    for (int c = 0; c < b->n_classes; ++c) fins = fins || b->h_class_f[c].fin_mask != 0;
+    // classes with fins run their own k_step instantiation; the persistent kernel holds the
+    // propeller bodies only
+    if (b->mode == MGX_LAUNCH_PERSISTENT && !traj && !forces && b->prec == MGX_FP32 && !fins) {
         PersistArgs pa;
         std::memset(&pa, 0, sizeof pa);
         pa.segs = b->d_segs;

@@ -59,6 +59,18 @@ struct ClassT {
     int32_t shaped;    // any dead zone or direction-dependent gain
     int32_t pad2;
     T rev[kMaxThr];    // reverse gain over forward gain (1 when symmetric)
+    // Fins (rudders): bit i of fin_mask marks actuator i as a fin (its layout columns are
+    // zero). Position, in-plane basis (chord at zero deflection, and span x chord), largest
+    // deflection, lift and drag gains.
+    uint32_t fin_mask;
+    int32_t pad3;
+    T fin_r[kMaxThr][3];
+    T fin_c[kMaxThr][3];
+    T fin_n[kMaxThr][3];
+    T fin_max[kMaxThr];
+    T fin_kl[kMaxThr];
+    T fin_kd0[kMaxThr];
+    T fin_kd[kMaxThr];
 };
 
 template <typename T>
@@ -102,6 +114,11 @@ __host__ __device__ __forceinline__ float copysign_(float a, float b) { return _
 __host__ __device__ __forceinline__ double copysign_(double a, double b) { return __builtin_copysign(a, b); }
 __host__ __device__ __forceinline__ float sqrt_(float a) { return __builtin_sqrtf(a); }
 __host__ __device__ __forceinline__ double sqrt_(double a) { return __builtin_sqrt(a); }
+// 1/sqrt: the hardware reciprocal square root in float on the device (about 1 ulp), the
+// correctly rounded quotient on the host and in double.
+__device__ __forceinline__ float rsqrt_(float a) { return __builtin_amdgcn_rsqf(a); }
+__host__ __forceinline__ float rsqrt_(float a) { return 1.0f / __builtin_sqrtf(a); }
+__host__ __device__ __forceinline__ double rsqrt_(double a) { return 1.0 / __builtin_sqrt(a); }
 
 // True if the predicate holds on any active lane of the wavefront (on the host: itself).
 __device__ __forceinline__ bool any_lane(bool p) { return __any(p); }
@@ -132,6 +149,79 @@ __host__ __device__ __forceinline__ void sub_cross(const T a[3], const T b[3], T
     acc[0] = fma_(a[2], b[1], fma_(-a[1], b[2], acc[0]));
     acc[1] = fma_(a[0], b[2], fma_(-a[2], b[0], acc[1]));
     acc[2] = fma_(a[1], b[0], fma_(-a[0], b[1], acc[2]));
+}
+
+// sin and cos of a fin deflection. float: Taylor polynomials to x^9 and x^10 (truncation
+// below 2e-9 for |x| <= pi/4, the largest deflection a class may declare) with an exact
+// fallback when any lane is outside that range; double: the exact functions.
+template <typename T>
+__host__ __device__ __forceinline__ void sincos_deflection(T x, T& s, T& c) {
+    if constexpr (std::is_same<T, double>::value) {
+        s = sin(x);
+        c = cos(x);
+    } else {
+        const T x2 = x * x;
+        s = x * fma_(fma_(fma_(fma_(x2, T(1.0f / 362880.0f), T(-1.0f / 5040.0f)), x2, T(1.0f / 120.0f)), x2,
+                         T(-1.0f / 6.0f)),
+                     x2, T(1.0f));
+        c = fma_(fma_(fma_(fma_(fma_(x2, T(-1.0f / 3628800.0f), T(1.0f / 40320.0f)), x2, T(-1.0f / 720.0f)), x2,
+                           T(1.0f / 24.0f)),
+                      x2, T(-0.5f)),
+                 x2, T(1.0f));
+        const bool big = !(abs_(x) <= T(0.7854f));
+        if (any_lane(big)) {
+            T se, ce;
+            if constexpr (std::is_same<T, float>::value) {
+                sincosf(x, &se, &ce);
+            } else {
+                se = sin(x);
+                ce = cos(x);
+            }
+            s = big ? se : s;
+            c = big ? ce : c;
+        }
+    }
+}
+
+// Fin (rudder) forces added to tau. Fin i at r_i moves through the water at
+// u = v_r + w x r_i; with (u_c, u_n) its components on the fin plane's basis (chord c at
+// zero deflection, n = span x c) and delta = delta_max n_i the deflection, the angle of
+// attack satisfies |u_p| sin(a) = sin(d) u_c - cos(d) u_n and |u_p| cos(a) = cos(d) u_c +
+// sin(d) u_n, so no angle is formed. Lift K_L sin(a)cos(a)|u_p|^2 acts along
+// span x u_p / |u_p| = (u_c n - u_n c) / |u_p|, drag (K_D0 + K_D sin^2(a))|u_p|^2 along
+// -u_p / |u_p|; the force F acts at r_i, adding [F; r_i x F].
+template <typename T, int M>
+__host__ __device__ __forceinline__ void add_fin_wrench(const ClassT<T>& C, const T nl[M], const T vr[3],
+                                                        const T w[3], T tau[6]) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        if (!((C.fin_mask >> i) & 1u)) continue;
+        const T* r = C.fin_r[i];
+        T u[3] = {vr[0], vr[1], vr[2]};
+        sub_cross(r, w, u);  // u + w x r = u - r x w
+        const T uc = fma_(u[2], C.fin_c[i][2], fma_(u[1], C.fin_c[i][1], u[0] * C.fin_c[i][0]));
+        const T un = fma_(u[2], C.fin_n[i][2], fma_(u[1], C.fin_n[i][1], u[0] * C.fin_n[i][0]));
+        const T wp2 = fma_(un, un, uc * uc);
+        T sd, cd;
+        sincos_deflection(C.fin_max[i] * nl[i], sd, cd);
+        const T sa = fma_(sd, uc, -(cd * un));  // |u_p| sin(a)
+        const T ca = fma_(cd, uc, sd * un);     // |u_p| cos(a)
+        const T inv = wp2 > T(0) ? rsqrt_(wp2) : T(0);
+        const T kl = C.fin_kl[i] * (sa * ca) * inv;
+        const T kd = fma_(C.fin_kd[i], sa * sa, C.fin_kd0[i] * wp2) * inv;
+        const T fc = fma_(-kl, un, -(kd * uc));
+        const T fn = fma_(kl, uc, -(kd * un));
+        T F[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            F[j] = fma_(fc, C.fin_c[i][j], fn * C.fin_n[i][j]);
+            tau[j] += F[j];
+        }
+        T rf[3];
+        cross(r, F, rf);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) tau[3 + j] += rf[j];
+    }
 }
 
 // Unit-quaternion increment exp(h w) = (cos(phi), sin(phi) w/|w|), phi = h |w|.
@@ -173,7 +263,7 @@ __host__ __device__ __forceinline__ void quat_increment(T h, const T w[3], T& c,
 // are per-environment constants hoisted out of the step loop by the caller. `forces`
 // (optional, 12 values) receives the actuator wrench and the hydrodynamic wrench of
 // Eq. (3) with d(nu)/dt the solved acceleration.
-template <typename T, int M, bool kForces = false, bool kShaped = false>
+template <typename T, int M, bool kForces = false, bool kShaped = false, bool kFins = false>
 __host__ __device__ __forceinline__ void step_body(const ClassT<T>& C, const EnvT<T>& E, const T IA2[3],
                                                    const T Brb[3], StateT<T, M>& s, const T a[M],
                                                    T* forces = nullptr) {
@@ -186,6 +276,9 @@ __host__ __device__ __forceinline__ void step_body(const ClassT<T>& C, const Env
     T tau[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int i = 0; i < M; ++i) {
+        if constexpr (kFins) {
+            if ((C.fin_mask >> i) & 1u) continue;  // fins push through add_fin_wrench
+        }
         T f;  // thrust divided by the forward gain k_i (folded into Bk)
         if constexpr (kShaped) {
             // dead zone, and the reverse gain as a ratio to the forward one
@@ -224,6 +317,7 @@ __host__ __device__ __forceinline__ void step_body(const ClassT<T>& C, const Env
     }
     const T* v = s.nu;
     const T* w = s.nu + 3;
+    if constexpr (kFins) add_fin_wrench<T, M>(C, nl, vr, w, tau);
 
     // 4. forces, accumulated per degree of freedom into the right-hand side F of
     // M dnu/dt = F (every term evaluated at the step-start velocity)

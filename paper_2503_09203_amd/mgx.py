@@ -32,6 +32,8 @@ FP64 = 8
 FLAG_NO_AMC = 1
 FLAG_LAG_EULER = 2
 COST_SHAPED = 0x80000000
+ACT_PROPELLER = 0
+ACT_FIN = 1
 STEP_UNFUSED = 1
 STEP_STATS = 2
 LAUNCH_PER_CLASS = 0
@@ -52,7 +54,10 @@ class ClassDesc(ctypes.Structure):
                 ("k", ctypes.c_double * MAX_THRUSTERS), ("tau", ctypes.c_double * MAX_THRUSTERS),
                 ("deadzone", ctypes.c_double * MAX_THRUSTERS), ("inertia", ctypes.c_double * 3),
                 ("rb", ctypes.c_double * 3), ("g0", ctypes.c_double),
-                ("k_rev", ctypes.c_double * MAX_THRUSTERS), ("reaction", ctypes.c_double * MAX_THRUSTERS)]
+                ("k_rev", ctypes.c_double * MAX_THRUSTERS), ("reaction", ctypes.c_double * MAX_THRUSTERS),
+                ("kind", ctypes.c_int32 * MAX_THRUSTERS), ("span", (ctypes.c_double * 3) * MAX_THRUSTERS),
+                ("fin_max", ctypes.c_double * MAX_THRUSTERS), ("fin_lift", ctypes.c_double * MAX_THRUSTERS),
+                ("fin_drag0", ctypes.c_double * MAX_THRUSTERS), ("fin_drag", ctypes.c_double * MAX_THRUSTERS)]
 
 
 class BatchDesc(ctypes.Structure):
@@ -128,6 +133,7 @@ SIGNATURES = {
     "mgx_version": (I32, []),
     "mgx_device_count": (I32, [ctypes.POINTER(I32)]),
     "mgx_step_cost": (I32, [I32, U32, ctypes.POINTER(F64), ctypes.POINTER(F64)]),
+    "mgx_class_step_cost": (I32, [I32, U32, ctypes.POINTER(F64), ctypes.POINTER(F64)]),
     "mgx_class_define": (I32, [ctypes.POINTER(ClassDesc), ctypes.POINTER(I32)]),
     "mgx_batch_create": (I32, [ctypes.POINTER(BatchDesc), ctypes.POINTER(P)]),
     "mgx_batch_destroy": (I32, [P]),
@@ -218,6 +224,12 @@ def mgx_step_cost(m, flags=0):
     return f.value, o.value
 
 
+def mgx_class_step_cost(class_id, flags=0):
+    f, o = F64(), F64()
+    _call("mgx_class_step_cost", int(class_id), int(flags), ctypes.byref(f), ctypes.byref(o))
+    return f.value, o.value
+
+
 def mgx_class_define(cls) -> int:
     """Register a vehicle class given any object with m, r, e, k, tau, deadzone,
     inertia, rb, g0 attributes and optional k_rev, reaction (e.g. a ``synth.VehicleClass``)."""
@@ -234,6 +246,15 @@ def mgx_class_define(cls) -> int:
     for i in range(cls.m):
         d.k_rev[i] = 0.0 if k_rev is None else float(k_rev[i])
         d.reaction[i] = 0.0 if reaction is None else float(reaction[i])
+    if getattr(cls, "kind", None) is not None:
+        for i in range(cls.m):
+            d.kind[i] = int(cls.kind[i])
+            for j in range(3):
+                d.span[i][j] = float(cls.span[i][j])
+            d.fin_max[i] = float(cls.fin_max[i])
+            d.fin_lift[i] = float(cls.fin_lift[i])
+            d.fin_drag0[i] = float(cls.fin_drag0[i])
+            d.fin_drag[i] = float(cls.fin_drag[i])
     for j in range(3):
         d.inertia[j] = float(cls.inertia[j])
         d.rb[j] = float(cls.rb[j])

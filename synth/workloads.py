@@ -404,6 +404,12 @@ def _build(name, classes, ns, steps, hold, dr, current_sigma, seed, dt=0.01):
     return Workload(name, list(classes), list(ns), EnvParams.concat(params), states, steps, hold, dt)
 
 
+def mixed(classes, ns, steps: int = 100, seed: int = MASTER_SEED, hold: int = 10) -> Workload:
+    """Any list of classes with the given environment counts, randomised parameters and
+    currents, commands resampled every ``hold`` steps."""
+    return _build(f"mixed_{sum(ns)}x{steps}", list(classes), list(ns), steps, hold, True, 0.3, seed)
+
+
 def plain_class(seed: int = MASTER_SEED):
     """The 6-thruster class shared by the plain and randomised workloads."""
     return draw_class(6, 0, seed)

@@ -133,3 +133,32 @@ def test_propeller_variant_validation():
         mgx.mgx_class_define(bad)
     assert "reaction must be finite" in str(e.value)
     assert mgx.mgx_class_define(synth.propeller_variants(synth.plain_class())) >= 0
+
+
+def test_fin_class_validation():
+    import dataclasses
+    assert mgx.mgx_class_define(synth.rudder_class()) >= 0
+    cases = [("span", lambda c: c.span.__setitem__(1, 0.0), "zero-length span"),
+             ("span", lambda c: c.span.__setitem__(2, [1.0, 0.0, 0.0]), "chord parallel to the span"),
+             ("fin_max", lambda c: c.fin_max.__setitem__(3, 2.0), "fin_max must be in (0, pi/2]"),
+             ("fin_lift", lambda c: c.fin_lift.__setitem__(4, -1.0), "lift and drag gains"),
+             ("kind", lambda c: c.kind.__setitem__(1, 7), "kind must be")]
+    for field, spoil, msg in cases:
+        c = synth.rudder_class()
+        c = dataclasses.replace(c, **{field: getattr(c, field).copy()})
+        spoil(c)
+        with pytest.raises(mgx.MgxError) as e:
+            mgx.mgx_class_define(c)
+        assert msg in str(e.value), (field, str(e.value))
+
+
+def test_class_step_cost_follows_the_body():
+    """The per-class count equals the generic one for plain and shaped classes; a class
+    with fins counts the fin forces on top (and no thrust for its fins)."""
+    plain = mgx.mgx_class_step_cost(mgx.mgx_class_define(synth.plain_class()))
+    assert plain == mgx.mgx_step_cost(6)
+    shaped = mgx.mgx_class_step_cost(mgx.mgx_class_define(synth.propeller_variants(synth.plain_class())))
+    assert shaped == mgx.mgx_step_cost(6, mgx.COST_SHAPED)
+    rudder = mgx.mgx_class_step_cost(mgx.mgx_class_define(synth.rudder_class()))
+    one_prop = mgx.mgx_step_cost(1, mgx.COST_SHAPED)
+    assert rudder[0] > one_prop[0] + 4 * 40 and rudder[1] > one_prop[1] + 4 * 30

@@ -187,3 +187,22 @@ def test_propeller_variant_classes_in_the_persistent_launch():
                 err = component_errors(g, r)
                 assert np.all(err <= bar), (mode, k, c, err.max())
     assert np.array_equal(finals[0], finals[1])
+
+
+def test_fin_class_keeps_per_class_launches_in_persistent_mode():
+    """A batch with a fin class asked for the persistent launch runs per-class launches
+    (the persistent kernel holds the propeller bodies only): same state bitwise, and the
+    oracle agrees."""
+    hc = synth.hetero_classes()
+    w = synth.mixed([hc[0], hc[1], synth.rudder_class(), hc[3]], [100, 150, 200, 130], steps=48)
+    acts = w.actions(6)
+    finals = []
+    for mode in (mgx.LAUNCH_PER_CLASS, mgx.LAUNCH_PERSISTENT):
+        fin = []
+        res = run_pair(w, acts, 10, [1, 48], chunk=16, shape=(mode, 16), final_state=fin)
+        finals.append(fin[0])
+        for k, pairs in res:
+            bar = 1e-5 if k == 1 else 5e-4
+            for c, (g, r) in enumerate(pairs):
+                assert np.all(component_errors(g, r) <= bar), (mode, k, c)
+    assert np.array_equal(finals[0], finals[1])

@@ -176,3 +176,10 @@ def test_propeller_variant_class_is_served():
     x, _, _ = oracle.rollout(envs, x, oracle.pack_actions(a), 10, 90)
     ref = oracle.unpack_state(x, c.m)
     assert component_errors(got.astype(np.float64), ref).max() <= 5e-4
+
+
+def test_server_refuses_fin_classes():
+    cs = list(classes()) + [synth.rudder_class()]
+    with pytest.raises(mgx.MgxError) as e:
+        mgx.Server(cs, [nominal(c) for c in cs], chunk_steps=32)
+    assert "has fins" in str(e.value)
