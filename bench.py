@@ -89,12 +89,14 @@ def main():
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="dr", choices=["dr", "propellers", "rudders", "hetero", "serve", "adjoint"],
+    ap.add_argument("--workload", default="dr",
+                    choices=["dr", "propellers", "rudders", "hetero", "serve", "adjoint", "resample"],
                     help="dr: the default benchmark line; propellers: the same line with dead zones, reverse "
                          "gains and shaft torques on every thruster; rudders: the same line for a rudder-propeller "
                          "class (one propeller, four tail fins); hetero: five classes in one persistent launch; "
                          "serve: Poisson request trace through the continuous-batching server and the FIFO baseline; "
-                         "adjoint: checkpointed forward and reverse sweep of the differentiable rollout")
+                         "adjoint: checkpointed forward and reverse sweep of the differentiable rollout; "
+                         "resample: on-device domain randomisation of every environment's parameters")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: requests per second")
     ap.add_argument("--sweep-rates", default="", help="serve: extra comma-separated rates, 5 s each")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: trace length (s)")
@@ -146,6 +148,9 @@ def main():
         return
     if args.workload == "adjoint":
         adjoint(args)
+        return
+    if args.workload == "resample":
+        resample(args)
         return
     variant = args.workload  # dr, propellers or rudders
     make = {"dr": synth.randomised, "propellers": synth.propellers, "rudders": synth.rudders}[variant]
@@ -554,6 +559,50 @@ def adjoint(args):
            "n_envs": N, "horizon": H, "checkpoint_every": CK, "thrusters": w.classes[0].m,
            "forward_ms": f * 1e3, "backward_ms": g * 1e3, "forward_env_steps_per_s": N * H / f,
            "backward_env_steps_per_s": N * H / g, "backward_over_forward": g / f}
+    b.close()
+    print(json.dumps(out), flush=True)
+
+
+def resample(args):
+    """On-device domain randomisation: every environment of the randomised workload's class
+    redrawn (uniform mass and buoyancy, Gaussian added mass per entry and current per axis,
+    piecewise shared linear damping, absolute uniform quadratic damping) and its record
+    rebuilt; timed with HIP events over repeated calls (a new epoch each)."""
+    import torch
+
+    import synth
+    from paper_2503_09203_amd import mgx
+
+    N = args.n
+    w = synth.randomised(n=N, steps=8)
+    c = w.classes[0]
+    b = mgx.Batch([c], [N], w.dt, mgx.FP32)
+    nominal = np.concatenate([[c.mass], c.added, c.dlin, c.dquad, [c.buoy], np.zeros(3)])[None]
+    spec = {"mass": {"kind": mgx.DR_UNIFORM, "lo": 0.8, "hi": 1.2},
+            "added": {"kind": mgx.DR_GAUSSIAN, "mean": 1.0, "std": 0.1, "lo": 0.7, "hi": 1.3},
+            "dlin": {"kind": mgx.DR_PIECEWISE, "edges": [0.5, 0.9, 1.0, 1.3, 2.0], "weights": [2, 0, 5, 1],
+                     "shared": 1},
+            "dquad": {"kind": mgx.DR_UNIFORM, "lo": 5.0, "hi": 50.0, "relative": 0},
+            "buoy": {"kind": mgx.DR_UNIFORM, "lo": 0.99, "hi": 1.03},
+            "current": {"kind": mgx.DR_GAUSSIAN, "mean": 0.0, "std": 0.3, "lo": -1.0, "hi": 1.0, "relative": 0}}
+    s = torch.cuda.current_stream()
+    for e in range(args.warmup):
+        b.resample(spec, nominal, seed=1, epoch=e)
+    reps = max(args.steps, 10)
+    a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(s)
+    for e in range(reps):
+        b.resample(spec, nominal, seed=1, epoch=1000 + e)
+    z.record(s)
+    torch.cuda.synchronize()
+    per = a.elapsed_time(z) * 1e-3 / reps
+    rec_bytes = 30 * 4
+    out = {"metric": METRIC, "workload": f"resample_{N}", "unit": "envs/s", "value": N / per,
+           "launch_us_mean": per * 1e6, "n_envs": N,
+           "roofline": {"bound": "hbm (record writes)", "achieved": N * rec_bytes / per / 1e9, "peak": PEAK_HBM / 1e9,
+                        "unit": "GB/s", "frac": N * rec_bytes / per / PEAK_HBM, "bytes_per_env": rec_bytes},
+           "note": "46 Philox uniforms, 10 Box-Muller draws in double and the record rebuild per environment"}
     b.close()
     print(json.dumps(out), flush=True)
 

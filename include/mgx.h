@@ -201,6 +201,53 @@ typedef struct {
  * Must be called before the first step (MGX_E_STATE otherwise). */
 mgx_status mgx_batch_set_params(mgx_batch* b, const mgx_env_params* p, int32_t on_device);
 
+/* ------------------------------------------------------------------ domain randomisation */
+
+/* Sec. III-C: each parameter group of the per-environment record is drawn from a uniform,
+ * a Gaussian or a custom piecewise distribution, for the environments chosen, and the
+ * distributions may change between calls (curriculum). */
+#define MGX_DR_FIXED 0      /* the class nominal itself */
+#define MGX_DR_UNIFORM 1    /* lo + (hi - lo) u */
+#define MGX_DR_GAUSSIAN 2   /* mean + std z (Box-Muller), clipped to [lo, hi] */
+#define MGX_DR_PIECEWISE 3  /* piecewise-constant density over n_bins bins */
+#define MGX_DR_MAX_BINS 8
+
+typedef struct {
+    int32_t kind;                       /* MGX_DR_* */
+    int32_t relative;                   /* 1: the draw multiplies the class nominal; 0: it is the value */
+    int32_t shared;                     /* vector groups: 1 = one draw for every entry */
+    int32_t n_bins;                     /* piecewise: 1..MGX_DR_MAX_BINS */
+    double lo, hi;                      /* uniform range; Gaussian clip range; lo <= hi */
+    double mean, std;                   /* Gaussian; std >= 0 */
+    double edges[MGX_DR_MAX_BINS + 1];  /* piecewise: n_bins + 1 increasing edges */
+    double weights[MGX_DR_MAX_BINS];    /* piecewise: weights >= 0 with a positive sum */
+} mgx_dr_dist;
+
+typedef struct {
+    mgx_dr_dist mass, added, dlin, dquad, buoy, current;
+} mgx_dr_spec;
+
+/* Redraws the parameters of environments (env_ids: host array of n global ids, or NULL
+ * for all) and rebuilds their records exactly as mgx_batch_set_params would from the
+ * drawn values. nominal: host, 23 doubles per class (mass, added[6], dlin[6], dquad[6],
+ * buoyancy, current[3]). Draws: Philox4x32-10 with key (seed mod 2^32, 7 << 24) and
+ * counter (global env id, epoch mod 2^32, j, 0), j = 0..22, two 53-bit uniforms per call;
+ * uniform pairs per group: mass 0-1, added entry i 2+2i, linear damping 14+2i, quadratic
+ * 26+2i, buoyancy 38, current axis a 40+2a (a shared group uses its first pair); Gaussian
+ * from the pair by Box-Muller with the cosine branch; piecewise by inverting the running
+ * weight sums. Every value a spec can produce must be a valid parameter (mass > 0, the
+ * others >= 0, current any): MGX_E_INVALID otherwise, and on a bad spec, nominal or id.
+ * Without a prior mgx_batch_set_params, env_ids must be NULL. Asynchronous on the batch
+ * stream (the id upload is synchronous). */
+mgx_status mgx_batch_resample(mgx_batch* b, const mgx_dr_spec* spec, const double* nominal, const int64_t* env_ids,
+                              int64_t n, uint64_t seed, uint64_t epoch);
+
+/* Reads every environment's parameters back from its record (host arrays laid out as in
+ * mgx_env_params, n_total entries per row; values as rounded to the batch precision).
+ * Synchronous. */
+mgx_status mgx_batch_get_params(const mgx_batch* b, double* mass, double* added, double* dlin, double* dquad,
+                                double* buoy, double* current);
+
 /* Resets environments. env_ids: host array of n global env ids, or NULL for all.
  * init_state: device pointer to a full state buffer in this batch's layout and precision;
  * the listed environments are copied from it. NULL: seeded state — p = 0, q uniform on

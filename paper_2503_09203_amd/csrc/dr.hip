@@ -1,0 +1,228 @@
+// On-device domain randomisation (Sec. III-C): per-environment parameters drawn from
+// uniform, Gaussian or piecewise distributions for chosen environments, then the record
+// rebuilt from them in double, as the parameter setup does.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "env_loop.hpp"
+#include "kernels.hpp"
+#include "mgx.h"
+#include "runtime_internal.hpp"
+
+namespace mgx {
+
+constexpr uint32_t kStreamDr = 7u;
+
+struct DrNominal {
+    double v[23];  // mass, added[6], dlin[6], dquad[6], buoyancy, current[3]
+};
+
+// One draw of a distribution from a pair of uniforms.
+__device__ double dr_draw(const mgx_dr_dist& d, double u1, double u2) {
+    if (d.kind == MGX_DR_UNIFORM) return d.lo + (d.hi - d.lo) * u1;
+    if (d.kind == MGX_DR_GAUSSIAN) {
+        const double z = sqrt(-2.0 * log(1.0 - u1)) * cos(2.0 * M_PI * u2);
+        return fmin(fmax(d.mean + d.std * z, d.lo), d.hi);
+    }
+    // piecewise: invert the running sums of the bin weights
+    double S[MGX_DR_MAX_BINS + 1];
+    S[0] = 0.0;
+    int last = 0;
+    for (int k = 0; k < d.n_bins; ++k) {
+        S[k + 1] = S[k] + d.weights[k];
+        if (d.weights[k] > 0.0) last = k;
+    }
+    const double t = u1 * S[d.n_bins];
+    int k = last;
+    for (int j = 0; j < d.n_bins; ++j)
+        if (t < S[j + 1]) {
+            k = j;
+            break;
+        }
+    return fmin(d.edges[k] + (t - S[k]) / d.weights[k] * (d.edges[k + 1] - d.edges[k]), d.edges[k + 1]);
+}
+
+// Values of one group (size entries starting at nominal offset off, uniform pairs from
+// slot) into out.
+__device__ void dr_group(const mgx_dr_dist& d, const double* nom, const double* u, int slot, int size, double* out) {
+    for (int i = 0; i < size; ++i) {
+        if (d.kind == MGX_DR_FIXED) {
+            out[i] = nom[i];
+            continue;
+        }
+        const int s = d.shared ? slot : slot + 2 * i;
+        const double x = dr_draw(d, u[s], u[s + 1]);
+        out[i] = d.relative ? nom[i] * x : x;
+    }
+}
+
+template <typename T>
+__global__ void k_dr_resample(mgx_dr_spec spec, DrNominal nom, const ClassDesc64* cls, int ci, double dt, T* rec,
+                              int64_t npad, int64_t env_off, const int64_t* ids, int64_t n_ids, uint64_t seed,
+                              uint64_t epoch) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_ids) return;
+    const int64_t e = ids ? ids[t] : t;
+    const uint64_t g = (uint64_t)(env_off + e);
+    double u[46];
+    for (int j = 0; j < 23; ++j) {
+        uint32_t c[4] = {(uint32_t)g, (uint32_t)epoch, (uint32_t)j, 0u};
+        philox4x32_10(c, (uint32_t)seed, kStreamDr << 24);
+        u[2 * j] = u53(c[0], c[1]);
+        u[2 * j + 1] = u53(c[2], c[3]);
+    }
+    double mass, added[6], dlin[6], dquad[6], buoy, cur[3];
+    dr_group(spec.mass, nom.v + 0, u, 0, 1, &mass);
+    dr_group(spec.added, nom.v + 1, u, 2, 6, added);
+    dr_group(spec.dlin, nom.v + 7, u, 14, 6, dlin);
+    dr_group(spec.dquad, nom.v + 13, u, 26, 6, dquad);
+    dr_group(spec.buoy, nom.v + 19, u, 38, 1, &buoy);
+    dr_group(spec.current, nom.v + 20, u, 40, 3, cur);
+    write_record<T>(cls[ci].inertia, cls[ci].g0, dt, mass, added, dlin, dquad, buoy, cur, rec, npad, e);
+}
+
+// Smallest value a distribution can produce (for validation).
+static double dist_min(const mgx_dr_dist& d) {
+    if (d.kind == MGX_DR_PIECEWISE) return d.edges[0];
+    return d.lo;
+}
+
+static mgx_status check_dist(const mgx_dr_dist& d, const char* name, int size, const double* nom_all, int n_classes,
+                             int off, bool positive, bool any_sign) {
+    if (d.kind < MGX_DR_FIXED || d.kind > MGX_DR_PIECEWISE) return fail(MGX_E_INVALID, "%s: unknown kind", name);
+    if (d.kind == MGX_DR_FIXED) return MGX_OK;
+    if (d.kind == MGX_DR_UNIFORM || d.kind == MGX_DR_GAUSSIAN) {
+        if (!std::isfinite(d.lo) || !std::isfinite(d.hi) || !(d.lo <= d.hi))
+            return fail(MGX_E_INVALID, "%s: need finite lo <= hi", name);
+        if (d.kind == MGX_DR_GAUSSIAN && (!std::isfinite(d.mean) || !(d.std >= 0) || !std::isfinite(d.std)))
+            return fail(MGX_E_INVALID, "%s: need a finite mean and std >= 0", name);
+    } else {
+        if (d.n_bins < 1 || d.n_bins > MGX_DR_MAX_BINS) return fail(MGX_E_INVALID, "%s: n_bins outside [1, 8]", name);
+        double sum = 0;
+        for (int k = 0; k <= d.n_bins; ++k) {
+            if (!std::isfinite(d.edges[k])) return fail(MGX_E_INVALID, "%s: non-finite edge", name);
+            if (k > 0 && !(d.edges[k] > d.edges[k - 1])) return fail(MGX_E_INVALID, "%s: edges must increase", name);
+        }
+        for (int k = 0; k < d.n_bins; ++k) {
+            if (!(d.weights[k] >= 0) || !std::isfinite(d.weights[k])) return fail(MGX_E_INVALID, "%s: bad weight", name);
+            sum += d.weights[k];
+        }
+        if (!(sum > 0)) return fail(MGX_E_INVALID, "%s: weights sum to zero", name);
+    }
+    if (any_sign) return MGX_OK;
+    const double lo = dist_min(d);
+    for (int c = 0; c < n_classes; ++c)
+        for (int i = 0; i < size; ++i) {
+            const double v = d.relative ? lo * nom_all[23 * c + off + i] : lo;
+            if (positive ? !(v > 0) : !(v >= 0))
+                return fail(MGX_E_INVALID, "%s: the distribution can produce %g for class %d", name, v, c);
+        }
+    return MGX_OK;
+}
+
+}  // namespace mgx
+
+using namespace mgx;
+
+#define HIP_TRY_DR(b, call)                                       \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return hip_fail((b), e_, #call);    \
+    } while (0)
+
+extern "C" mgx_status mgx_batch_resample(mgx_batch* b, const mgx_dr_spec* spec, const double* nominal,
+                                         const int64_t* env_ids, int64_t n, uint64_t seed, uint64_t epoch) {
+    if (!b) return fail(MGX_E_INVALID, "batch is NULL");
+    if (b->faulted) return fail(MGX_E_STATE, "batch faulted by an earlier device error");
+    if (!spec || !nominal) return fail(MGX_E_INVALID, "spec / nominal is NULL");
+    if (env_ids && !b->params_set) return fail(MGX_E_STATE, "resample every environment (env_ids = NULL) first");
+    if (env_ids && (n < 0 || n > b->n_total)) return fail(MGX_E_INVALID, "n outside [0, n_total]");
+    for (int c = 0; c < b->n_classes; ++c)
+        for (int j = 0; j < 23; ++j) {
+            const double v = nominal[23 * c + j];
+            if (!std::isfinite(v) || (j < 20 && !(v >= 0)) || (j == 0 && !(v > 0)))
+                return fail(MGX_E_INVALID, "nominal value %d of class %d invalid", j, c);
+        }
+    mgx_status s;
+    if ((s = check_dist(spec->mass, "mass", 1, nominal, b->n_classes, 0, true, false)) != MGX_OK) return s;
+    if ((s = check_dist(spec->added, "added", 6, nominal, b->n_classes, 1, false, false)) != MGX_OK) return s;
+    if ((s = check_dist(spec->dlin, "dlin", 6, nominal, b->n_classes, 7, false, false)) != MGX_OK) return s;
+    if ((s = check_dist(spec->dquad, "dquad", 6, nominal, b->n_classes, 13, false, false)) != MGX_OK) return s;
+    if ((s = check_dist(spec->buoy, "buoy", 1, nominal, b->n_classes, 19, false, false)) != MGX_OK) return s;
+    if ((s = check_dist(spec->current, "current", 3, nominal, b->n_classes, 20, false, true)) != MGX_OK) return s;
+    hipDevice_guard g(b->device);
+    std::vector<int64_t> local;
+    std::vector<int64_t> cnt(b->n_classes, 0), start(b->n_classes, 0);
+    if (env_ids) {
+        std::vector<std::vector<int64_t>> per(b->n_classes);
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t gid = env_ids[i];
+            if (gid < 0 || gid >= b->n_total) return fail(MGX_E_INVALID, "env id %lld out of range", (long long)gid);
+            const int c = b->class_of(gid);
+            per[c].push_back(gid - b->env_off[c]);
+        }
+        for (int c = 0; c < b->n_classes; ++c) {
+            start[c] = (int64_t)local.size();
+            cnt[c] = (int64_t)per[c].size();
+            local.insert(local.end(), per[c].begin(), per[c].end());
+        }
+        if (!local.empty())
+            HIP_TRY_DR(b, hipMemcpy(b->d_ids, local.data(), sizeof(int64_t) * local.size(), hipMemcpyHostToDevice));
+    }
+    for (int c = 0; c < b->n_classes; ++c) {
+        const int64_t* ids = env_ids ? b->d_ids + start[c] : nullptr;
+        const int64_t nid = env_ids ? cnt[c] : b->n[c];
+        if (nid == 0) continue;
+        DrNominal nom;
+        for (int j = 0; j < 23; ++j) nom.v[j] = nominal[23 * c + j];
+        const unsigned grid = (unsigned)((nid + 127) / 128);
+        if (b->prec == MGX_FP32)
+            hipLaunchKernelGGL(k_dr_resample<float>, dim3(grid), dim3(128), 0, b->stream, *spec, nom, b->d_classdesc, c,
+                               b->dt, (float*)b->seg_rec(c), b->npad[c], b->env_off[c], ids, nid, seed, epoch);
+        else
+            hipLaunchKernelGGL(k_dr_resample<double>, dim3(grid), dim3(128), 0, b->stream, *spec, nom, b->d_classdesc,
+                               c, b->dt, (double*)b->seg_rec(c), b->npad[c], b->env_off[c], ids, nid, seed, epoch);
+        HIP_TRY_DR(b, hipGetLastError());
+    }
+    if (!env_ids) b->params_set = true;
+    return MGX_OK;
+}
+
+extern "C" mgx_status mgx_batch_get_params(const mgx_batch* b, double* mass, double* added, double* dlin,
+                                           double* dquad, double* buoy, double* current) {
+    if (!b) return fail(MGX_E_INVALID, "batch is NULL");
+    if (!mass || !added || !dlin || !dquad || !buoy || !current) return fail(MGX_E_INVALID, "NULL output");
+    if (!b->params_set) return fail(MGX_E_STATE, "no parameters set");
+    hipDevice_guard g(b->device);
+    const int64_t N = b->n_total;
+    for (int c = 0; c < b->n_classes; ++c) {
+        const int64_t np = b->npad[c], n = b->n[c], off = b->env_off[c];
+        std::vector<double> r((size_t)kRecLen * np);
+        if (b->prec == MGX_FP32) {
+            std::vector<float> f((size_t)kRecLen * np);
+            if (hipMemcpyAsync(f.data(), b->seg_rec(c), sizeof(float) * f.size(), hipMemcpyDeviceToHost, b->stream) !=
+                    hipSuccess ||
+                hipStreamSynchronize(b->stream) != hipSuccess)
+                return fail(MGX_E_DEVICE, "record copy failed");
+            for (size_t k = 0; k < f.size(); ++k) r[k] = f[k];
+        } else {
+            if (hipMemcpyAsync(r.data(), b->seg_rec(c), sizeof(double) * r.size(), hipMemcpyDeviceToHost, b->stream) !=
+                    hipSuccess ||
+                hipStreamSynchronize(b->stream) != hipSuccess)
+                return fail(MGX_E_DEVICE, "record copy failed");
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            mass[off + i] = r[(size_t)kRecMass * np + i];
+            buoy[off + i] = r[(size_t)kRecBuoy * np + i];
+            for (int j = 0; j < 6; ++j) {
+                added[j * N + off + i] = r[(size_t)(kRecAdded + j) * np + i];
+                dlin[j * N + off + i] = r[(size_t)(kRecDlin + j) * np + i];
+                dquad[j * N + off + i] = r[(size_t)(kRecDquad + j) * np + i];
+            }
+            for (int j = 0; j < 3; ++j) current[j * N + off + i] = r[(size_t)(kRecCurrent + j) * np + i];
+        }
+    }
+    return MGX_OK;
+}

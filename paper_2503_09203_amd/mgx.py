@@ -114,6 +114,39 @@ class EnvParams(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in ("mass", "added", "dlin", "dquad", "buoy", "current")]
 
 
+class DrDist(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("relative", ctypes.c_int32), ("shared", ctypes.c_int32),
+                ("n_bins", ctypes.c_int32), ("lo", ctypes.c_double), ("hi", ctypes.c_double), ("mean", ctypes.c_double),
+                ("std", ctypes.c_double), ("edges", ctypes.c_double * 9), ("weights", ctypes.c_double * 8)]
+
+
+class DrSpec(ctypes.Structure):
+    _fields_ = [(k, DrDist) for k in ("mass", "added", "dlin", "dquad", "buoy", "current")]
+
+
+DR_FIXED, DR_UNIFORM, DR_GAUSSIAN, DR_PIECEWISE = 0, 1, 2, 3
+
+
+def dr_spec(groups: dict) -> DrSpec:
+    """A DrSpec from {group: {kind, relative=1, shared=0, lo, hi, mean, std, edges, weights}}
+    (groups left out are fixed at the nominal)."""
+    s = DrSpec()
+    for name, d in groups.items():
+        g = getattr(s, name)
+        g.kind = int(d["kind"])
+        g.relative = int(d.get("relative", 1))
+        g.shared = int(d.get("shared", 0))
+        g.lo, g.hi = float(d.get("lo", 0.0)), float(d.get("hi", 0.0))
+        g.mean, g.std = float(d.get("mean", 0.0)), float(d.get("std", 0.0))
+        edges, weights = d.get("edges", []), d.get("weights", [])
+        g.n_bins = len(weights)
+        for k, v in enumerate(edges):
+            g.edges[k] = float(v)
+        for k, v in enumerate(weights):
+            g.weights[k] = float(v)
+    return s
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("n_nonfinite", ctypes.c_int64 * MAX_CLASSES),
                 ("n_renorm64", ctypes.c_int64 * MAX_CLASSES),
@@ -140,6 +173,8 @@ SIGNATURES = {
     "mgx_batch_layout": (I32, [P, ctypes.POINTER(Layout)]),
     "mgx_batch_set_params": (I32, [P, ctypes.POINTER(EnvParams), I32]),
     "mgx_batch_reset": (I32, [P, P, I64, P, U64]),
+    "mgx_batch_resample": (I32, [P, ctypes.POINTER(DrSpec), P, P, I64, U64, U64]),
+    "mgx_batch_get_params": (I32, [P, P, P, P, P, P, P]),
     "mgx_batch_step": (I32, [P, P, I64, I64, I32, I32, U32, P, P]),
     "mgx_batch_get_step": (I32, [P, ctypes.POINTER(I64)]),
     "mgx_batch_set_step": (I32, [P, I64]),
@@ -473,6 +508,25 @@ class Batch:
             n = len(ids)
         mgx_batch_reset(self.h, None if ids is None else ids.ctypes.data_as(ctypes.c_void_p), n,
                         _ptr(init_state), seed)
+
+    def resample(self, groups: dict, nominal, env_ids=None, seed=0, epoch=0):
+        """Redraw parameters on the device (``groups`` as for ``dr_spec``; ``nominal``:
+        [n_classes, 23] float64)."""
+        spec = dr_spec(groups)
+        nom = np.ascontiguousarray(nominal, dtype=np.float64).reshape(-1)
+        ids = None if env_ids is None else np.ascontiguousarray(env_ids, dtype=np.int64)
+        _call("mgx_batch_resample", self.h, ctypes.byref(spec), nom.ctypes.data_as(ctypes.c_void_p),
+              None if ids is None else ids.ctypes.data_as(ctypes.c_void_p), 0 if ids is None else len(ids),
+              int(seed), int(epoch))
+
+    def get_params(self) -> dict:
+        """Every environment's parameters as stored (float64 arrays, mgx_env_params layout)."""
+        N = self.layout.n_total
+        out = {"mass": np.zeros(N), "added": np.zeros((6, N)), "dlin": np.zeros((6, N)),
+               "dquad": np.zeros((6, N)), "buoy": np.zeros(N), "current": np.zeros((3, N))}
+        _call("mgx_batch_get_params", self.h,
+              *[out[k].ctypes.data_as(ctypes.c_void_p) for k in ("mass", "added", "dlin", "dquad", "buoy", "current")])
+        return out
 
     def step(self, actions, K, hold=1, row0=0, flags=0, traj=None, forces=None):
         mgx_batch_step(self.h, _ptr(actions), actions.shape[0], row0, hold, K, flags, _ptr(traj), _ptr(forces))

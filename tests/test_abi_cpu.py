@@ -104,6 +104,7 @@ def test_binding_structures_match_the_header(tmp_path):
     """Every ctypes mirror has the size of its C struct (compiled from the header with
     gcc), so a field added to one side only cannot go unnoticed."""
     pairs = {"mgx_class_desc": mgx.ClassDesc, "mgx_batch_desc": mgx.BatchDesc, "mgx_layout": mgx.Layout,
+             "mgx_dr_dist": mgx.DrDist, "mgx_dr_spec": mgx.DrSpec,
              "mgx_env_params": mgx.EnvParams, "mgx_stats": mgx.Stats, "mgx_launch_shape": mgx.LaunchShape,
              "mgx_server_desc": mgx.ServerDesc, "mgx_request": mgx.Request,
              "mgx_request_status": mgx.RequestStatus, "mgx_server_stats": mgx.ServerStats}
