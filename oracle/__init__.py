@@ -34,7 +34,7 @@ ENV_DTYPE = np.dtype([
     ("deadzone", np.float64, MAX_THR), ("k_rev", np.float64, MAX_THR),
     ("reaction", np.float64, MAX_THR), ("kind", np.int32, MAX_THR), ("span", np.float64, (MAX_THR, 3)),
     ("fin_max", np.float64, MAX_THR), ("fin_lift", np.float64, MAX_THR), ("fin_drag0", np.float64, MAX_THR),
-    ("fin_drag", np.float64, MAX_THR)], align=True)
+    ("fin_drag", np.float64, MAX_THR), ("rg", np.float64, 3)], align=True)
 PROPELLER = 0
 FIN = 1
 
@@ -73,6 +73,7 @@ def lib():
         L.orc_quat_mul.argtypes = [P, P, P]
         L.orc_thrust_wrench.argtypes = [P, P, P]
         L.orc_fin_wrench.argtypes = [P, P, P, P, P]
+        L.orc_mass_matrix.argtypes = [P, P]
         L.orc_terms_eval.argtypes = [P, P, P, P, P]
         L.orc_step.argtypes = [P, P, P, P]
         L.orc_rollout.restype = ctypes.c_int32
@@ -131,6 +132,8 @@ def make_envs(cls, params, dt: float, flags: int = 0, idx=None) -> np.ndarray:
     if getattr(cls, "reaction", None) is not None:
         react[:cls.m] = cls.reaction
     env["k_rev"], env["reaction"] = krev, react
+    if getattr(cls, "rg", None) is not None:
+        env["rg"] = cls.rg
     if getattr(cls, "kind", None) is not None:
         kind = np.zeros(MAX_THR, dtype=np.int32); kind[:cls.m] = cls.kind
         span = np.zeros((MAX_THR, 3)); span[:cls.m] = cls.span
@@ -222,6 +225,13 @@ def thrust_wrench(env_one, n):
     nn[:len(n)] = n
     lib().orc_thrust_wrench(_p(env_one), _p(nn), _p(out))
     return out
+
+
+def mass_matrix(env_one):
+    """M = M_RB + M_A (6x6) of one environment."""
+    out = np.zeros(36)
+    lib().orc_mass_matrix(_p(env_one), _p(out))
+    return out.reshape(6, 6)
 
 
 def fin_wrench(env_one, n, vr, w):

@@ -151,9 +151,74 @@ void orc_fin_wrench(const orc_env* env, const double n[ORC_MAX_THR], const doubl
     }
 }
 
+/* Rigid-body inertia about the body origin when the centre of gravity sits at r_g from it
+ * (a payload): I_o = I_g + m (|r_g|^2 1 - r_g r_g^T) (parallel axes), I_g diagonal. */
+static void inertia_origin(const orc_env* env, double Io[3][3]) {
+    const double* r = env->rg;
+    double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            Io[i][j] = (i == j ? env->inertia[i] + env->mass * r2 : 0.0) - env->mass * r[i] * r[j];
+}
+
+/* M = M_RB + M_A with M_RB = [m 1, -m S(r_g); m S(r_g), I_o] (Eq. (2), body origin away from
+ * the CoG) and M_A diagonal; S(x) y = x x y. */
+void orc_mass_matrix(const orc_env* env, double M[36]) {
+    double Io[3][3];
+    inertia_origin(env, Io);
+    const double* r = env->rg;
+    const double m = env->mass;
+    double S[3][3] = {{0.0, -r[2], r[1]}, {r[2], 0.0, -r[0]}, {-r[1], r[0], 0.0}};
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) M[6 * i + j] = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        M[6 * i + i] = m;
+        for (int j = 0; j < 3; ++j) {
+            M[6 * i + 3 + j] = -m * S[i][j];
+            M[6 * (3 + i) + j] = m * S[i][j];
+            M[6 * (3 + i) + 3 + j] = Io[i][j];
+        }
+    }
+    for (int j = 0; j < 6; ++j) M[6 * j + j] += env->added[j];
+}
+
+/* Solves M x = b (6x6) by Gaussian elimination with partial pivoting. */
+static void solve6(const double M_in[36], const double b_in[6], double x[6]) {
+    double M[36], b[6];
+    memcpy(M, M_in, sizeof M);
+    memcpy(b, b_in, sizeof b);
+    for (int c = 0; c < 6; ++c) {
+        int p = c;
+        for (int i = c + 1; i < 6; ++i)
+            if (fabs(M[6 * i + c]) > fabs(M[6 * p + c])) p = i;
+        if (p != c) {
+            for (int j = 0; j < 6; ++j) {
+                double t = M[6 * c + j];
+                M[6 * c + j] = M[6 * p + j];
+                M[6 * p + j] = t;
+            }
+            double t = b[c];
+            b[c] = b[p];
+            b[p] = t;
+        }
+        for (int i = c + 1; i < 6; ++i) {
+            double f = M[6 * i + c] / M[6 * c + c];
+            if (f == 0.0) continue;
+            for (int j = c; j < 6; ++j) M[6 * i + j] -= f * M[6 * c + j];
+            b[i] -= f * b[c];
+        }
+    }
+    for (int i = 5; i >= 0; --i) {
+        double s = b[i];
+        for (int j = i + 1; j < 6; ++j) s -= M[6 * i + j] * x[j];
+        x[i] = s / M[6 * i + i];
+    }
+}
+
 /* Right-hand-side terms of Eqs. (1)-(3) at attitude q and velocity nu, with the
  * already-lagged rotor state n_lagged:
- *   C_RB(nu) nu  = [m w x v ; w x (I w)]                           (origin at the CoG)
+ *   C_RB(nu) nu  = [m w x (v + w x r_g) ; m r_g x (w x v) + w x (I_o w)]
+ *                  (reduces to [m w x v ; w x (I w)] with the origin at the CoG)
  *   C_A(nu_r) nu_r = [w x (A1 v_r) ; v_r x (A1 v_r) + w x (A2 w)]  (diagonal added mass)
  *   D(nu_r) nu_r = (d_L + d_Q |nu_r|) nu_r per DOF
  *   g(eta) = [-(W - B) g_b ; B r_b x g_b], g_b = R^T e_z, W = m g0
@@ -175,13 +240,19 @@ void orc_terms_eval(const orc_env* env, const double q[4], const double nu[6],
     orc_thrust_wrench(env, n_lagged, out->tau);
     orc_fin_wrench(env, n_lagged, vr, w, out->tau);
 
-    double t3[3], Iw[3], A1vr[3], A2w[3], t4[3];
-    cross3(w, v, t3);
-    for (int j = 0; j < 3; ++j) Iw[j] = env->inertia[j] * w[j];
+    double t3[3], Iw[3], A1vr[3], A2w[3], t4[3], Io[3][3], wxr[3], vw[3], t5[3];
+    inertia_origin(env, Io);
+    cross3(w, env->rg, wxr);
+    for (int j = 0; j < 3; ++j) vw[j] = v[j] + wxr[j];
+    cross3(w, vw, t3);
+    for (int j = 0; j < 3; ++j) Iw[j] = Io[j][0] * w[0] + Io[j][1] * w[1] + Io[j][2] * w[2];
     cross3(w, Iw, t4);
+    double wxv[3];
+    cross3(w, v, wxv);
+    cross3(env->rg, wxv, t5);
     for (int j = 0; j < 3; ++j) {
         out->crb[j] = env->mass * t3[j];
-        out->crb[3 + j] = t4[j];
+        out->crb[3 + j] = env->mass * t5[j] + t4[j];
     }
 
     for (int j = 0; j < 3; ++j) {
@@ -201,11 +272,12 @@ void orc_terms_eval(const orc_env* env, const double q[4], const double nu[6],
     for (int j = 0; j < 6; ++j) out->damp[j] = (env->dlin[j] + env->dquad[j] * fabs(nur[j])) * nur[j];
 
     double W = env->mass * env->g0;
-    double rbxg[3];
+    double rbxg[3], rgxg[3];
     cross3(env->rb, gb, rbxg);
+    cross3(env->rg, gb, rgxg);
     for (int j = 0; j < 3; ++j) {
         out->restore[j] = -(W - env->buoy) * gb[j];
-        out->restore[3 + j] = env->buoy * rbxg[j];
+        out->restore[3 + j] = env->buoy * rbxg[j] - W * rgxg[j];
     }
 
     double wxvc[3];
@@ -221,8 +293,11 @@ void orc_terms_eval(const orc_env* env, const double q[4], const double nu[6],
                         out->hadd[j];
 }
 
-static double mass_diag(const orc_env* env, int j) {
-    return (j < 3 ? env->mass : env->inertia[j - 3]) + env->added[j];
+/* d(nu)/dt = M^{-1} F (Eq. (1) solved for the acceleration). */
+static void accel(const orc_env* env, const double F[6], double acc[6]) {
+    double M[36];
+    orc_mass_matrix(env, M);
+    solve6(M, F, acc);
 }
 
 static void normalise4(double q[4]) {
@@ -249,10 +324,8 @@ void orc_step(const orc_env* env, orc_state* s, const double* a, double* forces)
     double R[3][3];
     orc_rotation(s->q, R);
     double acc[6], nun[6];
-    for (int j = 0; j < 6; ++j) {
-        acc[j] = t.total[j] / mass_diag(env, j);
-        nun[j] = s->nu[j] + env->dt * acc[j];
-    }
+    accel(env, t.total, acc);
+    for (int j = 0; j < 6; ++j) nun[j] = s->nu[j] + env->dt * acc[j];
     if (forces) {
         double gb[3] = {R[2][0], R[2][1], R[2][2]}, rbxg[3];
         cross3(env->rb, gb, rbxg);
@@ -359,7 +432,7 @@ static void deriv(const orc_env* env, const double* a, const double x[ORC_STATE_
     double om[4] = {0.0, s.nu[3], s.nu[4], s.nu[5]}, qd[4];
     orc_quat_mul(s.q, om, qd);
     for (int j = 0; j < 4; ++j) dx[3 + j] = 0.5 * qd[j];
-    for (int j = 0; j < 6; ++j) dx[7 + j] = t.total[j] / mass_diag(env, j);
+    accel(env, t.total, dx + 7);
 }
 
 void orc_rk4_smooth(int64_t n_envs, const orc_env* envs, orc_state* states,

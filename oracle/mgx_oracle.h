@@ -51,6 +51,8 @@ typedef struct {
     double fin_lift[ORC_MAX_THR]; /* fin: K_L = rho A c_L / 2 (kg/m) */
     double fin_drag0[ORC_MAX_THR]; /* fin: K_D0 = rho A c_D0 / 2 (kg/m) */
     double fin_drag[ORC_MAX_THR]; /* fin: K_D = rho A c_D / 2 (kg/m) */
+    double rg[3];               /* centre of gravity relative to the body origin (payload);
+                                   inertia is given about the centre of gravity */
 } orc_env;
 
 typedef struct {
@@ -81,6 +83,8 @@ void orc_fin_wrench(const orc_env* env, const double n[ORC_MAX_THR], const doubl
                     double tau[6]);
 void orc_terms_eval(const orc_env* env, const double q[4], const double nu[6],
                     const double n_lagged[ORC_MAX_THR], orc_terms* out);
+/* M = M_RB + M_A, 6x6 row-major. */
+void orc_mass_matrix(const orc_env* env, double M[36]);
 
 /* One step; a = commanded actions [m]; forces (optional) = actuator wrench[6], hydro wrench[6]. */
 void orc_step(const orc_env* env, orc_state* s, const double* a, double* forces);

@@ -98,6 +98,7 @@ class VehicleClass:
     fin_lift: np.ndarray | None = None  # [m] rho A c_L / 2 (kg/m)
     fin_drag0: np.ndarray | None = None  # [m] rho A c_D0 / 2 (kg/m)
     fin_drag: np.ndarray | None = None  # [m] rho A c_D / 2 (kg/m)
+    rg: np.ndarray | None = None        # [3] centre of gravity from the body origin (payload); None = 0
 
 
 @dataclass
@@ -275,6 +276,16 @@ def rudder_class(seed: int = MASTER_SEED) -> VehicleClass:
                    index=30)
 
 
+def payload_class(seed: int = MASTER_SEED) -> VehicleClass:
+    """The 6-thruster class carrying an off-centre payload: the centre of gravity moves to
+    r_g = (U[-3, 3], U[-2, 2], U[0.5, 3]) cm from the body origin (below it, so the body
+    stays upright), the inertia stays given about the centre of gravity."""
+    c = plain_class(seed)
+    u = _uniforms(seed, STREAM_CLASS, 60, 0, 3, 4)[0]
+    rg = np.array([-0.03 + 0.06 * u[0], -0.02 + 0.04 * u[1], 0.005 + 0.025 * u[2]])
+    return replace(c, rg=f32(rg), index=60)
+
+
 def nominal_params(cls: VehicleClass, n: int) -> EnvParams:
     """Every environment at the class nominal, no current."""
     return EnvParams(np.full(n, cls.mass), np.repeat(cls.added[:, None], n, 1),
@@ -446,6 +457,11 @@ def propellers(seed: int = MASTER_SEED, n: int = 65536, steps: int = 1000) -> Wo
     zones, direction-dependent gains and shaft torques on every thruster."""
     return _build(f"prop_{n}x{steps}", [propeller_variants(plain_class(seed), seed)], [n], steps, 10, True, 0.3,
                   seed)
+
+
+def payload(seed: int = MASTER_SEED, n: int = 65536, steps: int = 1000) -> Workload:
+    """The randomised workload with the payload class of ``payload_class``."""
+    return _build(f"payload_{n}x{steps}", [payload_class(seed)], [n], steps, 10, True, 0.3, seed)
 
 
 def rudders(seed: int = MASTER_SEED, n: int = 65536, steps: int = 1000) -> Workload:

@@ -12,24 +12,29 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "mgx_oracle.c")
 
 MUTANTS = {
-    "crb_sign": ("cross3(w, v, t3);", "cross3(v, w, t3);"),
+    "crb_sign": ("cross3(w, vw, t3);", "cross3(vw, w, t3);"),
+    "payload_coriolis_order": ("cross3(env->rg, wxv, t5);", "cross3(wxv, env->rg, t5);"),
     "crb_rot_sign": ("cross3(w, Iw, t4);", "cross3(Iw, w, t4);"),
     "ca_lin_sign": ("cross3(w, A1vr, c1);", "cross3(A1vr, w, c1);"),
     "ca_ang_sign": ("cross3(vr, A1vr, c2);", "cross3(A1vr, vr, c2);"),
     "ca_uses_v_not_vr": ("A1vr[j] = env->added[j] * vr[j];", "A1vr[j] = env->added[j] * v[j];"),
     "damp_no_abs": ("fabs(nur[j])) * nur[j]", "nur[j]) * nur[j]"),
     "restore_sign": ("out->restore[j] = -(W - env->buoy) * gb[j];", "out->restore[j] = (W - env->buoy) * gb[j];"),
-    "restore_moment_order": ("cross3(env->rb, gb, rbxg);\n    for (int j = 0; j < 3; ++j) {\n        out->restore",
-                             "cross3(gb, env->rb, rbxg);\n    for (int j = 0; j < 3; ++j) {\n        out->restore"),
+    "restore_moment_order": ("cross3(env->rb, gb, rbxg);\n    cross3(env->rg", "cross3(gb, env->rb, rbxg);\n    cross3(env->rg"),
     "gravity_row": ("gb[j] = R[2][j];", "gb[j] = R[j][2];"),
     "current_transposed": ("vc[j] = R[0][j] * env->current[0] + R[1][j] * env->current[1] + R[2][j] * env->current[2];",
                            "vc[j] = R[j][0] * env->current[0] + R[j][1] * env->current[1] + R[j][2] * env->current[2];"),
     "vr_sign": ("vr[j] = v[j] - vc[j];", "vr[j] = v[j] + vc[j];"),
     "no_hadd": ("int amc = !(env->flags & ORC_FLAG_NO_AMC);", "int amc = 0;"),
     "hadd_order": ("cross3(w, vc, wxvc);", "cross3(vc, w, wxvc);"),
-    "mass_no_added": ("return (j < 3 ? env->mass : env->inertia[j - 3]) + env->added[j];",
-                      "return (j < 3 ? env->mass : env->inertia[j - 3]);"),
-    "inertia_index": ("Iw[j] = env->inertia[j] * w[j];", "Iw[j] = env->inertia[(j + 1) % 3] * w[j];"),
+    "mass_no_added": ("for (int j = 0; j < 6; ++j) M[6 * j + j] += env->added[j];", ""),
+    "inertia_index": ("(i == j ? env->inertia[i] + env->mass * r2 : 0.0)",
+                      "(i == j ? env->inertia[(i + 1) % 3] + env->mass * r2 : 0.0)"),
+    "payload_rotation_order": ("cross3(w, env->rg, wxr);", "cross3(env->rg, w, wxr);"),
+    "payload_restoring_sign": ("env->buoy * rbxg[j] - W * rgxg[j]", "env->buoy * rbxg[j] + W * rgxg[j]"),
+    "parallel_axis_sign": ("- env->mass * r[i] * r[j];", "+ env->mass * r[i] * r[j];"),
+    "mass_coupling_sign": ("M[6 * i + 3 + j] = -m * S[i][j];", "M[6 * i + 3 + j] = m * S[i][j];"),
+    "payload_coriolis_dropped": ("out->crb[3 + j] = env->mass * t5[j] + t4[j];", "out->crb[3 + j] = t4[j];"),
     "position_transposed": ("s->p[j] += env->dt * (R[j][0] * nun[0] + R[j][1] * nun[1] + R[j][2] * nun[2]);",
                             "s->p[j] += env->dt * (R[0][j] * nun[0] + R[1][j] * nun[1] + R[2][j] * nun[2]);"),
     "position_old_velocity": ("s->p[j] += env->dt * (R[j][0] * nun[0] + R[j][1] * nun[1] + R[j][2] * nun[2]);",

@@ -263,6 +263,74 @@ def test_p12_fin_small_angle_lift_slope_and_mirror():
         assert np.allclose([a[0], a[1]], [b[0], -b[1]], rtol=0, atol=1e-12)
 
 
+# ----------------------------------------------------------------------------- P13 payload
+
+def _general_kirchhoff(env, x):
+    M = oracle.mass_matrix(env)
+    nu = x[7:13]
+    Pv = M @ nu
+    P, L = Pv[:3], Pv[3:]
+    R = oracle.rotation(x[3:7])
+    return np.array([0.5 * nu @ Pv, P @ P, P @ L, *(R @ P)])
+
+
+def test_p13_mass_matrix_with_a_payload():
+    """M_RB with the CoG at r_g: symmetric, positive definite, the origin inertia is the
+    CoG inertia moved by the parallel-axis theorem, and its kinetic energy is that of the
+    CoG's motion plus the spin about the CoG."""
+    rng = np.random.default_rng(31)
+    env = env1(m=1, added=np.zeros(6), rg=[0.05, -0.03, 0.08])
+    M = oracle.mass_matrix(env)
+    assert np.allclose(M, M.T, atol=0) and np.all(np.linalg.eigvalsh(M) > 0)
+    for _ in range(10):
+        nu = rng.normal(size=6)
+        v_cg = nu[:3] + np.cross(nu[3:], env["rg"][0])
+        T = 0.5 * env["mass"][0] * v_cg @ v_cg + 0.5 * nu[3:] @ (env["inertia"][0] * nu[3:])
+        assert abs(0.5 * nu @ M @ nu - T) < 1e-12 * T
+
+
+def test_p13_kirchhoff_invariants_with_a_payload():
+    """Kirchhoff's invariants hold for any symmetric inertia: with a payload (CoG off the
+    origin), added mass, and no thrust, damping, restoring or current, RK4 conserves
+    T = nu^T M nu / 2, |P|^2, P.L and the world impulse R P to its own error."""
+    rng = np.random.default_rng(32)
+    x0 = state1(q=rand_quat(rng), nu=[0.4, -0.3, 0.2, 0.3, -0.5, 0.4])
+    env = _free_env(0.01, rg=[0.06, -0.04, 0.09])
+    env["rb"] = env["rg"]
+    inv0 = _general_kirchhoff(env, x0[0])
+    ref = oracle.rk4_smooth(env, x0, np.zeros((1, 24)), 1e-3, 1000)
+    assert np.max(np.abs(_general_kirchhoff(env, ref[0]) - inv0)) < 1e-10
+
+
+def test_p13_spin_about_the_centre_of_gravity():
+    """Torque-free spin about the CoG: isotropic CoG inertia, no added mass, CoB at the
+    CoG of a neutral body, no damping. With v = -w x r_g the CoG is at rest; the Coriolis
+    terms then cancel exactly, so the discrete map leaves nu unchanged."""
+    rg = np.array([0.05, -0.02, 0.07])
+    env = env1(m=1, added=np.zeros(6), dlin=np.zeros(6), dquad=np.zeros(6), inertia=[0.9, 0.9, 0.9], rg=rg,
+               k=np.zeros(8))
+    env["rb"] = rg
+    w = np.array([0.7, -1.1, 0.4])
+    nu = np.concatenate([-np.cross(w, rg), w])
+    _, tr = run(env, state1(nu=nu), [0.0], 200)
+    assert np.max(np.abs(tr[0, :, 7:13] - nu)) < 1e-13
+
+
+def test_p13_payload_tilts_the_equilibrium():
+    """A neutral body with the CoB 3 cm above the origin and a payload moving the CoG 2 cm
+    forward and 1 cm down rests pitched so that the CoG hangs straight below the CoB:
+    tan(theta) = x_g / (z_g - z_b) (nose down). Started there at rest it stays there."""
+    rg, rb = np.array([0.02, 0.0, 0.01]), np.array([0.0, 0.0, -0.03])
+    env = env1(m=1, rg=rg, rb=rb, k=np.zeros(8))
+    th = -np.arctan2(rg[0], rg[2] - rb[2])
+    q = np.array([np.cos(th / 2), 0.0, np.sin(th / 2), 0.0])
+    _, tr = run(env, state1(q=q), [0.0], 2000)
+    assert np.max(np.abs(tr[0, :, 7:13])) < 1e-12
+    # and at zero pitch the same body starts to pitch nose down
+    _, tr = run(env, state1(), [0.0], 10)
+    assert tr[0, -1, 11] < -1e-4
+
+
 # ----------------------------------------------------------------------------- P3 kinematics
 
 def euler_zyx_matrix(phi, th, psi):
