@@ -90,10 +90,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="dr",
-                    choices=["dr", "propellers", "rudders", "hetero", "serve", "adjoint", "resample"],
+                    choices=["dr", "propellers", "rudders", "payload", "hetero", "serve", "adjoint", "resample"],
                     help="dr: the default benchmark line; propellers: the same line with dead zones, reverse "
                          "gains and shaft torques on every thruster; rudders: the same line for a rudder-propeller "
-                         "class (one propeller, four tail fins); hetero: five classes in one persistent launch; "
+                         "class (one propeller, four tail fins); payload: the same line with the centre of gravity "
+                         "off the body origin (full mass matrix); hetero: five classes in one persistent launch; "
                          "serve: Poisson request trace through the continuous-batching server and the FIFO baseline; "
                          "adjoint: checkpointed forward and reverse sweep of the differentiable rollout; "
                          "resample: on-device domain randomisation of every environment's parameters")
@@ -153,10 +154,13 @@ def main():
         resample(args)
         return
     variant = args.workload  # dr, propellers or rudders
-    make = {"dr": synth.randomised, "propellers": synth.propellers, "rudders": synth.rudders}[variant]
+    make = {"dr": synth.randomised, "propellers": synth.propellers, "rudders": synth.rudders,
+            "payload": synth.payload}[variant]
     w = make(n=N, steps=T)
     cls = w.classes[0]
     shaped = variant != "dr"
+    # the remaining template arguments of k_step: fins, payload
+    tmpl_tail = f"{str(variant == 'rudders').lower()},{str(variant == 'payload').lower()}"
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream(dev)
     b = mgx.Batch([cls], [N], w.dt, mgx.FP32)
@@ -217,7 +221,8 @@ def main():
     torch.cuda.synchronize()
     single_rate = N * T * reps1 / (time.perf_counter() - t1)
     single_launch = float(np.mean([a.elapsed_time(c) for a, c in ev1[1:]])) * 1e-3 / T
-    single_bytes = bytes_per_env_step(cls.m, 1, HOLD) * N
+    rec_len = 45 if variant == "payload" else 30
+    single_bytes = bytes_per_env_step(cls.m, 1, HOLD, rec_len=rec_len) * N
     traffic = recorded_traffic() if (N, T, HOLD) == (65536, 1000, 10) and not shaped else {}
 
     out = {
@@ -233,22 +238,22 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{ {'dr': 'dr', 'propellers': 'prop', 'rudders': 'rudder'}[variant] }_{N}x{T}", "n_envs": N, "rollout_steps": T, "thrusters": cls.m, "hold": HOLD,
+        "config": {"workload": f"{ {'dr': 'dr', 'propellers': 'prop', 'rudders': 'rudder', 'payload': 'payload'}[variant] }_{N}x{T}", "n_envs": N, "rollout_steps": T, "thrusters": cls.m, "hold": HOLD,
                    "launch_steps_K": K, "dt": w.dt, "current_sigma": 0.3, "randomisation": 0.2,
                    "path": "set_params + reset + graph of fused launches"},
         "roofline": {"bound": "alu", "achieved": fused_flops_per_launch / fused_launch / 1e12,
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
                      "frac": fused_flops_per_launch / fused_launch / PEAK_FP32_VECTOR, "traffic": traffic.get(K),
                      "traffic_unit": "B/launch",
-                     "kernel": f"k_step<float,{cls.m},false,false,{str(shaped).lower()},{str(variant == 'rudders').lower()}> K={K}", "launches_per_step": n_launch,
+                     "kernel": f"k_step<float,{cls.m},false,false,{str(shaped).lower()},{tmpl_tail}> K={K}", "launches_per_step": n_launch,
                      "launch_us_mean": fused_launch * 1e6, "flops_per_env_step": flops_es,
                      "valu_ops_per_env_step": ops_es},
-        "single_step": {"env_steps_per_s": single_rate, "kernel": f"k_step<float,{cls.m},false,true,{str(shaped).lower()},{str(variant == 'rudders').lower()}> K=1",
+        "single_step": {"env_steps_per_s": single_rate, "kernel": f"k_step<float,{cls.m},false,true,{str(shaped).lower()},{tmpl_tail}> K=1",
                         "launch_us_mean": single_launch * 1e6,
                         "roofline": {"bound": "hbm", "achieved": single_bytes / single_launch / 1e9,
                                      "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                                      "frac": single_bytes / single_launch / PEAK_HBM,
-                                     "bytes_per_env_step": bytes_per_env_step(cls.m, 1, HOLD),
+                                     "bytes_per_env_step": bytes_per_env_step(cls.m, 1, HOLD, rec_len=rec_len),
                                      "traffic": traffic.get(1), "traffic_unit": "B/launch"}},
     }
 

@@ -121,6 +121,14 @@ typedef struct {
     double fin_lift[MGX_MAX_THRUSTERS]; /* rho A c_L / 2 (kg/m), >= 0 */
     double fin_drag0[MGX_MAX_THRUSTERS]; /* rho A c_D0 / 2 (kg/m), >= 0 */
     double fin_drag[MGX_MAX_THRUSTERS]; /* rho A c_D / 2 (kg/m), >= 0 */
+    /* Payload (Table II's external loads): the centre of gravity at rg from the body origin
+     * (where positions, added mass, damping and the centre of buoyancy are given); inertia
+     * stays given about the centre of gravity. Non-zero rg makes M_RB full,
+     * [m 1, -m S(rg); m S(rg), I_g + m(|rg|^2 1 - rg rg^T)], adds the matching Coriolis terms
+     * m w x (w x rg) and m rg x (w x v), and the weight's moment -W rg x g_b; dt M^-1 is then
+     * inverted in double per environment (Cholesky). Such classes run per-class launches;
+     * the server and the adjoint refuse them. |rg_j| < 10 m. */
+    double rg[3];
 } mgx_class_desc;
 
 #define MGX_ACT_PROPELLER 0

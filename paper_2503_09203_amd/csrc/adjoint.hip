@@ -348,9 +348,12 @@ extern "C" mgx_status mgx_rollout_forward(mgx_batch* b, const void* actions, int
     if (b->faulted) return fail(MGX_E_STATE, "batch faulted by an earlier device error");
     if (!b->params_set) return fail(MGX_E_STATE, "mgx_batch_set_params has not been called");
     if (!actions || !pos_out) return fail(MGX_E_INVALID, "actions / pos_out is NULL");
-    for (int c = 0; c < b->n_classes; ++c)
+    for (int c = 0; c < b->n_classes; ++c) {
         if (b->h_class_f[c].fin_mask != 0)
             return fail(MGX_E_INVALID, "class %d has fins: the adjoint covers propeller classes only", c);
+        if (b->h_class_f[c].payload != 0)
+            return fail(MGX_E_INVALID, "class %d has a payload: the adjoint covers classes without one", c);
+    }
     if (H < 1 || H > (1 << 20)) return fail(MGX_E_INVALID, "H=%d outside [1, 2^20]", H);
     if (ckpt_every < 1 || ckpt_every > 4096) return fail(MGX_E_INVALID, "ckpt_every=%d outside [1, 4096]", ckpt_every);
     if (hold < 1 || n_rows < 1) return fail(MGX_E_INVALID, "hold, n_rows must be >= 1");

@@ -48,7 +48,7 @@ static inline Cnt sin(Cnt a) { return tally(std::sin(a.v), 1, 1); }
 static inline Cnt cos(Cnt a) { return tally(std::cos(a.v), 1, 1); }
 
 template <int M>
-static CostTally measure(uint32_t flags, uint32_t fin_mask = 0) {
+static CostTally measure(uint32_t flags, uint32_t fin_mask = 0, bool payload = false) {
     ClassT<Cnt> C;
     for (int j = 0; j < 6; ++j)
         for (int i = 0; i < kMaxThr; ++i) C.Bk[j][i] = Cnt(3.0 * (i + 1) + 0.3 * j);
@@ -60,6 +60,7 @@ static CostTally measure(uint32_t flags, uint32_t fin_mask = 0) {
     for (int j = 0; j < 3; ++j) {
         C.inertia[j] = 1.0 + j;
         C.rb[j] = j == 2 ? -0.01 : 0.0;
+        C.rg[j] = payload ? 0.01 * (j + 1) : 0.0;
     }
     C.g0 = 9.81;
     C.dt = 0.01;
@@ -69,6 +70,7 @@ static CostTally measure(uint32_t flags, uint32_t fin_mask = 0) {
     C.flags = flags & ~MGX_COST_SHAPED;
     C.shaped = (flags & MGX_COST_SHAPED) ? 1 : 0;
     C.fin_mask = fin_mask;
+    C.payload = payload ? 1 : 0;
     for (int i = 0; i < kMaxThr; ++i) {
         const double r[3] = {-0.5, 0.1, 0.05}, c[3] = {1, 0, 0}, n[3] = {0, 1, 0};
         for (int j = 0; j < 3; ++j) {
@@ -104,8 +106,15 @@ static CostTally measure(uint32_t flags, uint32_t fin_mask = 0) {
     for (int i = 0; i < M; ++i) s.n[i] = 0.1 * i - 0.3;
     Cnt a[M];
     for (int i = 0; i < M; ++i) a[i] = 0.5 - 0.1 * i;
+    for (int k = 0; k < 15; ++k) E.dtMinvOff[k] = 1e-5;
+    for (int j = 0; j < 6; ++j) E.IoA[j] = j < 3 ? 2.0 + j : 0.01;
+    for (int j = 0; j < 3; ++j) E.mrg[j] = 0.1 * (j + 1);
     g_tally = CostTally();
-    if (fin_mask)
+    if (payload && fin_mask)
+        step_body<Cnt, M, false, true, true, true>(C, E, IA2, Brb, s, a);
+    else if (payload)
+        step_body<Cnt, M, false, true, false, true>(C, E, IA2, Brb, s, a);
+    else if (fin_mask)
         step_body<Cnt, M, false, true, true>(C, E, IA2, Brb, s, a);
     else if (flags & MGX_COST_SHAPED)
         step_body<Cnt, M, false, true>(C, E, IA2, Brb, s, a);
@@ -144,17 +153,18 @@ extern "C" mgx_status mgx_class_step_cost(int32_t class_id, uint32_t batch_flags
     if (!get_class(class_id, &cd)) return fail(MGX_E_INVALID, "class id %d unknown", class_id);
     const ClassDesc64 d = to_desc64(cd);
     const uint32_t fins = fin_mask_of(d);
+    const bool pl = has_payload(d);
     const uint32_t f = batch_flags | (shaped_thrust(d) ? MGX_COST_SHAPED : 0u);
     CostTally t;
     switch (cd.m) {
-        case 1: t = measure<1>(f, fins); break;
-        case 2: t = measure<2>(f, fins); break;
-        case 3: t = measure<3>(f, fins); break;
-        case 4: t = measure<4>(f, fins); break;
-        case 5: t = measure<5>(f, fins); break;
-        case 6: t = measure<6>(f, fins); break;
-        case 7: t = measure<7>(f, fins); break;
-        default: t = measure<8>(f, fins); break;
+        case 1: t = measure<1>(f, fins, pl); break;
+        case 2: t = measure<2>(f, fins, pl); break;
+        case 3: t = measure<3>(f, fins, pl); break;
+        case 4: t = measure<4>(f, fins, pl); break;
+        case 5: t = measure<5>(f, fins, pl); break;
+        case 6: t = measure<6>(f, fins, pl); break;
+        case 7: t = measure<7>(f, fins, pl); break;
+        default: t = measure<8>(f, fins, pl); break;
     }
     *flops = t.flops;
     *valu_ops = t.ops;

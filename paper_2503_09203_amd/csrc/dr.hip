@@ -80,7 +80,7 @@ __global__ void k_dr_resample(mgx_dr_spec spec, DrNominal nom, const ClassDesc64
     dr_group(spec.dquad, nom.v + 13, u, 26, 6, dquad);
     dr_group(spec.buoy, nom.v + 19, u, 38, 1, &buoy);
     dr_group(spec.current, nom.v + 20, u, 40, 3, cur);
-    write_record<T>(cls[ci].inertia, cls[ci].g0, dt, mass, added, dlin, dquad, buoy, cur, rec, npad, e);
+    write_record<T>(cls[ci].inertia, cls[ci].g0, dt, mass, added, dlin, dquad, buoy, cur, rec, npad, e, cls[ci].rg);
 }
 
 // Smallest value a distribution can produce (for validation).

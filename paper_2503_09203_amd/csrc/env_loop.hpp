@@ -37,15 +37,70 @@ __device__ __forceinline__ double u53(uint32_t hi, uint32_t lo) {
 constexpr uint32_t kStreamInit = 3u;
 constexpr uint32_t kStreamAction = 4u;
 
+// dt M^-1 for a class with a payload (centre of gravity at rg from the body origin):
+// M = [m 1 + A_1, -m S(rg); m S(rg), I_o + A_2] with I_o = I_g + m(|rg|^2 1 - rg rg^T),
+// symmetric positive definite; inverted by Cholesky factorisation in double.
+__device__ __forceinline__ void payload_minv(const double inertia[3], const double rg[3], double m,
+                                             const double added[6], double dt, double out[6][6]) {
+    double M[6][6];
+    const double S[3][3] = {{0.0, -rg[2], rg[1]}, {rg[2], 0.0, -rg[0]}, {-rg[1], rg[0], 0.0}};
+    const double r2 = rg[0] * rg[0] + rg[1] * rg[1] + rg[2] * rg[2];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            M[i][j] = (i == j) ? m : 0.0;
+            M[i][3 + j] = -m * S[i][j];
+            M[3 + i][j] = m * S[i][j];
+            M[3 + i][3 + j] = ((i == j) ? inertia[i] + m * r2 : 0.0) - m * rg[i] * rg[j];
+        }
+    for (int j = 0; j < 6; ++j) M[j][j] += added[j];
+    double L[6][6] = {};
+    for (int j = 0; j < 6; ++j) {
+        double d = M[j][j];
+        for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+        L[j][j] = sqrt(d);
+        for (int i = j + 1; i < 6; ++i) {
+            double v = M[i][j];
+            for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+            L[i][j] = v / L[j][j];
+        }
+    }
+    for (int c = 0; c < 6; ++c) {  // column c of M^-1: L y = e_c, then L^T x = y
+        double y[6], x[6];
+        for (int i = 0; i < 6; ++i) {
+            double v = (i == c) ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) v -= L[i][k] * y[k];
+            y[i] = v / L[i][i];
+        }
+        for (int i = 5; i >= 0; --i) {
+            double v = y[i];
+            for (int k = i + 1; k < 6; ++k) v -= L[k][i] * x[k];
+            x[i] = v / L[i][i];
+        }
+        for (int i = 0; i < 6; ++i) out[i][c] = dt * x[i];
+    }
+}
+
 // Per-environment record (dt M^-1, m, M_A, d_L, d_Q, W - B, B, V_c), derived in double
 // (M = M_RB + M_A with M_RB = diag(m, m, m, I)) and rounded once; column i of a segment.
+// With a payload (rg non-null and non-zero) dt M^-1 is the full symmetric inverse: its
+// diagonal in the usual rows, the off-diagonal entries in the 15 rows from kRecMinvOff.
 template <typename T>
 __device__ __forceinline__ void write_record(const double inertia[3], double g0, double dt, double m,
                                              const double added[6], const double dlin[6], const double dquad[6],
-                                             double buoy, const double cur[3], T* rec, int64_t npad, int64_t i) {
+                                             double buoy, const double cur[3], T* rec, int64_t npad, int64_t i,
+                                             const double* rg = nullptr) {
+    const bool payload = rg && (rg[0] != 0.0 || rg[1] != 0.0 || rg[2] != 0.0);
+    if (payload) {
+        double Mi[6][6];
+        payload_minv(inertia, rg, m, added, dt, Mi);
+        int k = 0;
+        for (int a = 0; a < 6; ++a)
+            for (int b = a + 1; b < 6; ++b, ++k) rec[(kRecMinvOff + k) * npad + i] = (T)(0.5 * (Mi[a][b] + Mi[b][a]));
+        for (int j = 0; j < 6; ++j) rec[(kRecDtMinv + j) * npad + i] = (T)Mi[j][j];
+    }
     for (int j = 0; j < 6; ++j) {
         const double Mjj = (j < 3 ? m : inertia[j - 3]) + added[j];
-        rec[(kRecDtMinv + j) * npad + i] = (T)(dt / Mjj);
+        if (!payload) rec[(kRecDtMinv + j) * npad + i] = (T)(dt / Mjj);
         rec[(kRecAdded + j) * npad + i] = (T)added[j];
         rec[(kRecDlin + j) * npad + i] = (T)dlin[j];
         rec[(kRecDquad + j) * npad + i] = (T)dquad[j];
@@ -190,7 +245,7 @@ __device__ __forceinline__ ClassT<T> class_in_vgpr(const ClassT<T>& Cs) {
 // memory operations in flight inside it are those prefetches.
 // kSingle: a launch of exactly one step without outputs (the single-step kernel). Such a
 // launch never reaches the next action row, so it does not fetch it.
-template <typename T, int M, bool kOut, bool kShaped, bool kSingle = false, bool kFins = false>
+template <typename T, int M, bool kOut, bool kShaped, bool kSingle = false, bool kFins = false, bool kPayload = false>
 __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs, int64_t env, int64_t t0, int K,
                                           float st[kStats]) {
     static_assert(!(kSingle && kOut), "the single-step form has no per-step outputs");
@@ -220,6 +275,10 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
     E.buoy = Rc[kRecBuoy * np + env];
 #pragma unroll
     for (int j = 0; j < 3; ++j) E.Vc[j] = Rc[(kRecCurrent + j) * np + env];
+    if constexpr (kPayload) {
+#pragma unroll
+        for (int k = 0; k < 15; ++k) E.dtMinvOff[k] = Rc[(kRecMinvOff + k) * np + env];
+    }
     set_amc(E, C.flags);
 
     // Action rows, relative to the buffer start, uniform across the wave. Every fetch is
@@ -253,8 +312,24 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
         IA2[j] = C.inertia[j] + E.A[3 + j];
         Brb[j] = E.buoy * C.rb[j];
     }
+    if constexpr (kPayload) {
+        // I_o + A_2 = I_g + m(|r_g|^2 1 - r_g r_g^T) + A_2; m r_g; (B r_b - W r_g)
+        const T* r = C.rg;
+        const T m = E.mass, W = E.mass * C.g0;
+        E.IoA[0] = IA2[0] + m * (r[1] * r[1] + r[2] * r[2]);
+        E.IoA[1] = IA2[1] + m * (r[0] * r[0] + r[2] * r[2]);
+        E.IoA[2] = IA2[2] + m * (r[0] * r[0] + r[1] * r[1]);
+        E.IoA[3] = -(m * r[0] * r[1]);
+        E.IoA[4] = -(m * r[0] * r[2]);
+        E.IoA[5] = -(m * r[1] * r[2]);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            E.mrg[j] = m * r[j];
+            Brb[j] = fma_(-W, r[j], Brb[j]);
+        }
+    }
     if constexpr (kSingle) {
-        step_body<T, M, false, kShaped, kFins>(C, E, IA2, Brb, s, cur);
+        step_body<T, M, false, kShaped, kFins, kPayload>(C, E, IA2, Brb, s, cur);
     } else {
 
     // Runs of steps between action-row switches: the inner loop carries only its counter,
@@ -266,7 +341,7 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
         for (int j = 0; j < run; ++j, ++k) {
             if constexpr (kOut) {
                 T f[kForceLen];
-                step_body<T, M, true, kShaped, kFins>(C, E, IA2, Brb, s, cur, f);
+                step_body<T, M, true, kShaped, kFins, kPayload>(C, E, IA2, Brb, s, cur, f);
                 if (A.forces) {
                     T* fo = (T*)A.forces + k * A.force_stride + env;
 #pragma unroll
@@ -284,7 +359,7 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
                     for (int i = 0; i < M; ++i) to[(kStateFixed + i) * np] = s.n[i];
                 }
             } else {
-                step_body<T, M, false, kShaped, kFins>(C, E, IA2, Brb, s, cur);
+                step_body<T, M, false, kShaped, kFins, kPayload>(C, E, IA2, Brb, s, cur);
             }
         }
         phase += run;

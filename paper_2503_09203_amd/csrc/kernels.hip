@@ -87,6 +87,9 @@ __global__ void k_class_setup(const ClassDesc64* in, ClassT<float>* outf, ClassT
     D.pad2 = 0;
     D.fin_mask = fins;
     D.pad3 = 0;
+    for (int j = 0; j < 3; ++j) D.rg[j] = d.rg[j];
+    D.payload = has_payload(d) ? 1 : 0;
+    D.pad4 = 0;
     ClassT<float> F;
     for (int i = 0; i < kMaxThr; ++i) {
         for (int j = 0; j < 6; ++j) F.Bk[j][i] = (float)D.Bk[j][i];
@@ -117,6 +120,9 @@ __global__ void k_class_setup(const ClassDesc64* in, ClassT<float>* outf, ClassT
     F.pad2 = 0;
     F.fin_mask = fins;
     F.pad3 = 0;
+    for (int j = 0; j < 3; ++j) F.rg[j] = (float)D.rg[j];
+    F.payload = D.payload;
+    F.pad4 = 0;
     outd[c] = D;
     outf[c] = F;
 }
@@ -136,17 +142,18 @@ __global__ void k_env_setup(ParamPtrs p, int64_t env_off, int64_t n, int32_t npa
         dquad[j] = p.dquad[j * N + g];
     }
     for (int j = 0; j < 3; ++j) cur[j] = p.current[j * N + g];
-    write_record<T>(cls[ci].inertia, cls[ci].g0, dt, p.mass[g], added, dlin, dquad, p.buoy[g], cur, rec, npad, i);
+    write_record<T>(cls[ci].inertia, cls[ci].g0, dt, p.mass[g], added, dlin, dquad, p.buoy[g], cur, rec, npad, i,
+                    cls[ci].rg);
 }
 
 // Every slot of a segment to rest at the identity attitude; record zeroed (dt M^-1 = 0
 // keeps padded slots fixed).
 template <typename T>
-__global__ void k_init_padding(T* state, T* rec, int m, int32_t npad, int64_t first) {
+__global__ void k_init_padding(T* state, T* rec, int m, int32_t npad, int64_t first, int rec_len) {
     int64_t i = first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npad) return;
     for (int j = 0; j < kStateFixed + m; ++j) state[j * (int64_t)npad + i] = (T)(j == 3 ? 1 : 0);
-    for (int j = 0; j < kRecLen; ++j) rec[j * (int64_t)npad + i] = (T)0;
+    for (int j = 0; j < rec_len; ++j) rec[j * (int64_t)npad + i] = (T)0;
 }
 
 // ----------------------------------------------------------------------------- reset
@@ -195,11 +202,12 @@ __global__ void k_gen_actions(T* out, int m, int32_t npad, int64_t n_valid, int6
 // ----------------------------------------------------------------------------- step
 
 // K steps of every environment of one class segment; state in registers throughout.
-// kShaped: the class has dead zones or direction-dependent gains; kFins: it has fins (such
-// classes take the shaped propeller body too). Each is a separate instantiation (chosen
+// kShaped: the class has dead zones or direction-dependent gains; kFins: it has fins;
+// kPayload: its centre of gravity is off the body origin (fin and payload classes take the
+// shaped propeller body too). Each is a separate instantiation (chosen
 // on the host from the class) rather than a branch in one kernel, so that the plain
 // body's register allocation does not pay for the others.
-template <typename T, int M, bool kOut, bool kSingle, bool kShaped, bool kFins>
+template <typename T, int M, bool kOut, bool kSingle, bool kShaped, bool kFins, bool kPayload>
 __global__ void __launch_bounds__(256) k_step(StepLaunch<T> L) {
     const StepArgs& A = L.a;
     const int tid = threadIdx.x;
@@ -212,7 +220,7 @@ __global__ void __launch_bounds__(256) k_step(StepLaunch<T> L) {
     float st[kStats];
 #pragma unroll
     for (int j = 0; j < kStats; ++j) st[j] = 0.0f;
-    if (env < A.npad) env_steps<T, M, kOut, kShaped, kSingle, kFins>(A, L.cls, env, t0, A.K, st);
+    if (env < A.npad) env_steps<T, M, kOut, kShaped, kSingle, kFins, kPayload>(A, L.cls, env, t0, A.K, st);
     if (!A.partials) return;
     // Statistics: block partials, then the last block to finish reduces them in order.
     __shared__ float red[256 / kWave][kStats];
@@ -263,11 +271,12 @@ hipError_t launch_env_setup(ParamPtrs p, int64_t env_off, int64_t n, int32_t npa
 }
 
 template <typename T>
-hipError_t launch_init_padding(T* state_seg, T* rec_seg, int m, int32_t npad, int64_t first, hipStream_t s) {
+hipError_t launch_init_padding(T* state_seg, T* rec_seg, int m, int32_t npad, int64_t first, hipStream_t s,
+                               int rec_len) {
     const int64_t n = npad - first;
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_init_padding<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, state_seg, rec_seg, m,
-                       npad, first);
+                       npad, first, rec_len);
     return hipGetLastError();
 }
 
@@ -298,21 +307,28 @@ hipError_t launch_gen_actions(T* out_seg, int m, int32_t npad, int64_t n_valid, 
     return hipGetLastError();
 }
 
-template <typename T, int M, bool kShaped, bool kFins>
+template <typename T, int M, bool kShaped, bool kFins, bool kPayload = false>
 static void launch_step_body(const StepLaunch<T>& L, unsigned grid, int block, bool out, bool single,
                              hipStream_t s) {
     if (out)
-        hipLaunchKernelGGL((k_step<T, M, true, false, kShaped, kFins>), dim3(grid), dim3(block), 0, s, L);
+        hipLaunchKernelGGL((k_step<T, M, true, false, kShaped, kFins, kPayload>), dim3(grid), dim3(block), 0, s, L);
     else if (single)
-        hipLaunchKernelGGL((k_step<T, M, false, true, kShaped, kFins>), dim3(grid), dim3(block), 0, s, L);
+        hipLaunchKernelGGL((k_step<T, M, false, true, kShaped, kFins, kPayload>), dim3(grid), dim3(block), 0, s, L);
     else
-        hipLaunchKernelGGL((k_step<T, M, false, false, kShaped, kFins>), dim3(grid), dim3(block), 0, s, L);
+        hipLaunchKernelGGL((k_step<T, M, false, false, kShaped, kFins, kPayload>), dim3(grid), dim3(block), 0, s, L);
 }
 
+// Five bodies: plain; shaped propellers; fins (with shaped propellers); payload (with
+// shaped propellers); payload with fins and shaped propellers, the most general one. The
+// payload body without fins keeps the fin geometry out of its registers.
 template <typename T, int M>
 static void launch_step_m(const StepLaunch<T>& L, unsigned grid, int block, bool out, bool single, bool shaped,
-                          bool fins, hipStream_t s) {
-    if (fins)
+                          bool fins, bool payload, hipStream_t s) {
+    if (payload && fins)
+        launch_step_body<T, M, true, true, true>(L, grid, block, out, single, s);
+    else if (payload)
+        launch_step_body<T, M, true, false, true>(L, grid, block, out, single, s);
+    else if (fins)
         launch_step_body<T, M, true, true>(L, grid, block, out, single, s);
     else if (shaped)
         launch_step_body<T, M, true, false>(L, grid, block, out, single, s);
@@ -322,7 +338,7 @@ static void launch_step_m(const StepLaunch<T>& L, unsigned grid, int block, bool
 
 #define MGX_STEP_CASE(MM)                                                     \
     case MM:                                                                  \
-        launch_step_m<T, MM>(L, grid, block, out, single, shaped, fins, s);   \
+        launch_step_m<T, MM>(L, grid, block, out, single, shaped, fins, payload, s);   \
         break;
 
 template <typename T>
@@ -332,6 +348,7 @@ hipError_t launch_step(const StepLaunch<T>& L, int m, int block, hipStream_t s) 
     const bool single = L.a.K == 1;
     const bool shaped = L.cls.shaped != 0;
     const bool fins = L.cls.fin_mask != 0;
+    const bool payload = L.cls.payload != 0;
     switch (m) {
         MGX_STEP_CASE(1)
         MGX_STEP_CASE(2)
@@ -350,7 +367,7 @@ hipError_t launch_step(const StepLaunch<T>& L, int m, int block, hipStream_t s) 
 #define MGX_INSTANTIATE(T)                                                                                          \
     template hipError_t launch_env_setup<T>(ParamPtrs, int64_t, int64_t, int32_t, const ClassDesc64*, int, double,   \
                                             T*, hipStream_t);                                                         \
-    template hipError_t launch_init_padding<T>(T*, T*, int, int32_t, int64_t, hipStream_t);                         \
+    template hipError_t launch_init_padding<T>(T*, T*, int, int32_t, int64_t, hipStream_t, int);                    \
     template hipError_t launch_reset_seeded<T>(T*, int, int32_t, int64_t, int64_t, const int64_t*, int64_t, uint64_t, \
                                                hipStream_t);                                                          \
     template hipError_t launch_reset_copy<T>(T*, const T*, int, int32_t, const int64_t*, int64_t, hipStream_t);     \

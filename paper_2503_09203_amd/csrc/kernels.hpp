@@ -28,7 +28,13 @@ struct ClassDesc64 {
     int32_t kind[kMaxThr];  // 0 propeller, 1 fin
     double span[kMaxThr][3], fin_max[kMaxThr], fin_lift[kMaxThr], fin_drag0[kMaxThr], fin_drag[kMaxThr];
     double inertia[3], rb[3], g0;
+    double rg[3];  // payload: centre of gravity from the body origin
 };
+
+// True when the class carries a payload (centre of gravity off the body origin).
+__host__ __device__ inline bool has_payload(const ClassDesc64& d) {
+    return d.rg[0] != 0.0 || d.rg[1] != 0.0 || d.rg[2] != 0.0;
+}
 
 constexpr int32_t kActFin = 1;
 
@@ -164,7 +170,8 @@ template <typename T>
 hipError_t launch_reset_copy(T* state_seg, const T* tmpl_seg, int m, int32_t npad, const int64_t* d_local_ids,
                              int64_t n_ids, hipStream_t s);
 template <typename T>
-hipError_t launch_init_padding(T* state_seg, T* rec_seg, int m, int32_t npad, int64_t nvalid, hipStream_t s);
+hipError_t launch_init_padding(T* state_seg, T* rec_seg, int m, int32_t npad, int64_t nvalid, hipStream_t s,
+                               int rec_len = kRecLen);
 template <typename T>
 hipError_t launch_gen_actions(T* out_seg, int m, int32_t npad, int64_t n_valid, int64_t env_off, int64_t rows,
                               int64_t row_stride, int64_t row_offset, uint64_t seed, hipStream_t s);

@@ -65,6 +65,7 @@ ClassDesc64 to_desc64(const mgx_class_desc& c) {
     std::memcpy(d.fin_lift, c.fin_lift, sizeof d.fin_lift);
     std::memcpy(d.fin_drag0, c.fin_drag0, sizeof d.fin_drag0);
     std::memcpy(d.fin_drag, c.fin_drag, sizeof d.fin_drag);
+    std::memcpy(d.rg, c.rg, sizeof d.rg);
     std::memcpy(d.inertia, c.inertia, sizeof d.inertia);
     std::memcpy(d.rb, c.rb, sizeof d.rb);
     d.g0 = c.g0;
@@ -165,6 +166,7 @@ extern "C" mgx_status mgx_class_define(const mgx_class_desc* d, int32_t* class_i
     for (int j = 0; j < 3; ++j) {
         if (!(d->inertia[j] > 0) || !is_fin(d->inertia[j])) return fail(MGX_E_INVALID, "inertia must be > 0");
         if (!is_fin(d->rb[j])) return fail(MGX_E_INVALID, "r_b must be finite");
+        if (!is_fin(d->rg[j]) || !(std::fabs(d->rg[j]) < 10.0)) return fail(MGX_E_INVALID, "r_g must be finite and within 10 m");
     }
     if (!(d->g0 > 0) || !is_fin(d->g0)) return fail(MGX_E_INVALID, "g0 must be > 0");
     std::lock_guard<std::mutex> lk(g_cls_mu);
@@ -244,7 +246,7 @@ extern "C" mgx_status mgx_batch_create(const mgx_batch_desc* d, mgx_batch** out)
         eoff += n;
         poff += np;
         soff += (kStateFixed + m) * np;
-        roff += (int64_t)kRecLen * np;
+        roff += (int64_t)b->rec_len(c) * np;
         aoff += (int64_t)m * np;
         foff += (int64_t)kForceLen * np;
         max_blocks += np / kWave;
@@ -333,10 +335,10 @@ extern "C" mgx_status mgx_batch_create(const mgx_batch_desc* d, mgx_batch** out)
         for (int c = 0; c < b->n_classes; ++c) {
             if (b->prec == MGX_FP32) {
                 HIP_TRY(b, launch_init_padding<float>((float*)b->seg_state(c), (float*)b->seg_rec(c), b->m[c],
-                                                      (int32_t)b->npad[c], 0, b->stream));
+                                                      (int32_t)b->npad[c], 0, b->stream, b->rec_len(c)));
             } else {
                 HIP_TRY(b, launch_init_padding<double>((double*)b->seg_state(c), (double*)b->seg_rec(c), b->m[c],
-                                                       (int32_t)b->npad[c], 0, b->stream));
+                                                       (int32_t)b->npad[c], 0, b->stream, b->rec_len(c)));
             }
         }
         HIP_TRY(b, hipStreamSynchronize(b->stream));
@@ -505,9 +507,9 @@ mgx_status enqueue_step(mgx_batch* b, const void* actions, int64_t n_rows, int64
                         bool stats, void* traj, void* forces, int block) {
     const size_t P = (size_t)b->prec;
     bool fins = false;
-    for (int c = 0; c < b->n_classes; ++c) fins = fins || b->h_class_f[c].fin_mask != 0;
-    // classes with fins run their own k_step instantiation; the persistent kernel holds the
-    // propeller bodies only
+    for (int c = 0; c < b->n_classes; ++c) fins = fins || b->h_class_f[c].fin_mask != 0 || b->h_class_f[c].payload != 0;
+    // classes with fins or a payload run their own k_step instantiations; the persistent
+    // kernel holds the plain and shaped propeller bodies only
     if (b->mode == MGX_LAUNCH_PERSISTENT && !traj && !forces && b->prec == MGX_FP32 && !fins) {
         PersistArgs pa;
         std::memset(&pa, 0, sizeof pa);

@@ -95,6 +95,11 @@ struct mgx_batch {
 
     void* seg_state(int c) const { return (char*)d_state + (size_t)prec * state_off[c]; }
     void* seg_rec(int c) const { return (char*)d_rec + (size_t)prec * rec_off[c]; }
+    // record rows of class c: the off-diagonal dt M^-1 rows only for a payload class
+    int rec_len(int c) const {
+        const mgx_class_desc& d = cls[c];
+        return (d.rg[0] != 0.0 || d.rg[1] != 0.0 || d.rg[2] != 0.0) ? mgx::kRecLenPayload : mgx::kRecLen;
+    }
     int class_of(int64_t gid) const {
         int c = 0;
         while (c + 1 < n_classes && gid >= env_off[c + 1]) ++c;

@@ -601,6 +601,8 @@ extern "C" mgx_status mgx_server_create(const mgx_server_desc* d, mgx_server** o
         if (!get_class(d->class_ids[c], &cd)) return fail(MGX_E_INVALID, "class id %d unknown", d->class_ids[c]);
         if (fin_mask_of(to_desc64(cd)) != 0)
             return fail(MGX_E_INVALID, "class %d has fins: the server runs propeller classes only", c);
+        if (has_payload(to_desc64(cd)))
+            return fail(MGX_E_INVALID, "class %d has a payload: the server runs classes without one", c);
         d64[c] = to_desc64(cd);
         const double* p = d->nominal + 23 * c;
         if (!(p[0] > 0)) return fail(MGX_E_INVALID, "nominal mass of class %d must be > 0", c);

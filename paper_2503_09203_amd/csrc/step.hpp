@@ -26,6 +26,10 @@ namespace mgx {
 constexpr int kMaxThr = 8;
 constexpr int kStateFixed = 13;
 constexpr int kRecLen = 30;
+// Classes with a payload (centre of gravity off the body origin) store the off-diagonal
+// entries of the symmetric dt M^-1 in 15 more rows, (0,1), (0,2), ..., (4,5) row by row.
+constexpr int kRecMinvOff = 30;
+constexpr int kRecLenPayload = 45;
 constexpr int kForceLen = 12;
 constexpr int kWave = 64;
 
@@ -71,6 +75,10 @@ struct ClassT {
     T fin_kl[kMaxThr];
     T fin_kd0[kMaxThr];
     T fin_kd[kMaxThr];
+    // Payload: centre of gravity from the body origin (inertia given about it).
+    T rg[3];
+    int32_t payload;
+    int32_t pad4;
 };
 
 template <typename T>
@@ -84,6 +92,10 @@ struct EnvT {
     T buoy;
     T Vc[3];
     T Ah[3];  // coefficients of the added-mass current term: A1, or 0 with kFlagNoAmc
+    // payload only: off-diagonal dt M^-1, I_o + A_2 (xx, yy, zz, xy, xz, yz), m r_g
+    T dtMinvOff[15];
+    T IoA[6];
+    T mrg[3];
 };
 
 // Fills EnvT::Ah from the added mass and the batch flags (once per environment, so that
@@ -259,11 +271,27 @@ __host__ __device__ __forceinline__ void quat_increment(T h, const T w[3], T& c,
     }
 }
 
+// dnu = (dt M^-1) F with the symmetric dt M^-1 of a payload class: diagonal entries in
+// dtMinv, the others (0,1), (0,2), ..., (4,5) in dtMinvOff.
+template <typename T>
+__host__ __device__ __forceinline__ void payload_solve(const EnvT<T>& E, const T F[6], T dnu[6]) {
+    constexpr int kOff[6][6] = {{-1, 0, 1, 2, 3, 4},   {0, -1, 5, 6, 7, 8},    {1, 5, -1, 9, 10, 11},
+                                {2, 6, 9, -1, 12, 13}, {3, 7, 10, 12, -1, 14}, {4, 8, 11, 13, 14, -1}};
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        T acc = E.dtMinv[i] * F[i];
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            if (j != i) acc = fma_(E.dtMinvOff[kOff[i][j]], F[j], acc);
+        dnu[i] = acc;
+    }
+}
+
 // One step. `a` holds commands already clipped to [-1, 1]. IA2 = I + A_2 and Brb = B r_b
 // are per-environment constants hoisted out of the step loop by the caller. `forces`
 // (optional, 12 values) receives the actuator wrench and the hydrodynamic wrench of
 // Eq. (3) with d(nu)/dt the solved acceleration.
-template <typename T, int M, bool kForces = false, bool kShaped = false, bool kFins = false>
+template <typename T, int M, bool kForces = false, bool kShaped = false, bool kFins = false, bool kPayload = false>
 __host__ __device__ __forceinline__ void step_body(const ClassT<T>& C, const EnvT<T>& E, const T IA2[3],
                                                    const T Brb[3], StateT<T, M>& s, const T a[M],
                                                    T* forces = nullptr) {
@@ -326,7 +354,16 @@ __host__ __device__ __forceinline__ void step_body(const ClassT<T>& C, const Env
     for (int j = 0; j < 3; ++j) {
         A1vr[j] = E.A[j] * vr[j];
         P[j] = fma_(E.mass, v[j], A1vr[j]);
-        L[j] = IA2[j] * w[j];
+        if constexpr (!kPayload) L[j] = IA2[j] * w[j];
+    }
+    if constexpr (kPayload) {
+        // with the centre of gravity at r_g: m w x (v + w x r_g) in the linear rows, so
+        // P gains w x (m r_g); the angular rows use the full I_o + A_2
+        sub_cross(E.mrg, w, P);
+        // IoA: xx, yy, zz, xy, xz, yz
+        L[0] = fma_(E.IoA[4], w[2], fma_(E.IoA[3], w[1], E.IoA[0] * w[0]));
+        L[1] = fma_(E.IoA[5], w[2], fma_(E.IoA[1], w[1], E.IoA[3] * w[0]));
+        L[2] = fma_(E.IoA[2], w[2], fma_(E.IoA[5], w[1], E.IoA[4] * w[0]));
     }
     T Fl[3], Fa[3];
 #pragma unroll
@@ -339,7 +376,14 @@ __host__ __device__ __forceinline__ void step_body(const ClassT<T>& C, const Env
     // angular rows: w x (I w) + w x (A2 w) + v_r x (A1 v_r) = w x ((I + A2) w) + v_r x (A1 v_r)
     sub_cross(w, L, Fa);
     sub_cross(vr, A1vr, Fa);
-    // restoring, angular rows: B r_b x g_b
+    if constexpr (kPayload) {
+        // payload: m r_g x (w x v) in the angular rows
+        T wxv[3];
+        cross(w, v, wxv);
+        sub_cross(E.mrg, wxv, Fa);
+    }
+    // restoring, angular rows: B r_b x g_b (with a payload, (B r_b - W r_g) x g_b: the
+    // caller folds the weight's moment into Brb)
     sub_cross(Brb, gb, Fa);
     // added-mass term of the rotating current projection: A1 (w x v_c) (coefficients 0
     // when the term is switched off)
@@ -365,25 +409,49 @@ __host__ __device__ __forceinline__ void step_body(const ClassT<T>& C, const Env
         for (int j = 0; j < 3; ++j) A2w[j] = E.A[3 + j] * w[j];
         cross(vr, A1vr, t1);
         cross(w, A2w, t2);
-        cross(Brb, gb, rmom);
+        if constexpr (kPayload) {
+            T Bb[3] = {E.buoy * C.rb[0], E.buoy * C.rb[1], E.buoy * C.rb[2]};
+            cross(Bb, gb, rmom);
+        } else {
+            cross(Brb, gb, rmom);
+        }
 #pragma unroll
         for (int j = 0; j < 3; ++j) caa[j] = t1[j] + t2[j];
 #pragma unroll
         for (int j = 0; j < 6; ++j) forces[j] = tau[j];
+        T dnu[6];
+        if constexpr (kPayload) {
+            const T F6[6] = {Fl[0], Fl[1], Fl[2], Fa[0], Fa[1], Fa[2]};
+            payload_solve(E, F6, dnu);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                dnu[j] = E.dtMinv[j] * Fl[j];
+                dnu[3 + j] = E.dtMinv[3 + j] * Fa[j];
+            }
+        }
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            const T dl = E.dtMinv[j] * Fl[j], da = E.dtMinv[3 + j] * Fa[j];
-            forces[6 + j] = -(E.A[j] * dl * C.inv_dt) - E.Ah[j] * wvc[j] - cal[j] - dcl[j] * vr[j] -
+            forces[6 + j] = -(E.A[j] * dnu[j] * C.inv_dt) - E.Ah[j] * wvc[j] - cal[j] - dcl[j] * vr[j] -
                             E.buoy * gb[j];
-            forces[9 + j] = -(E.A[3 + j] * da * C.inv_dt) - caa[j] - dca[j] * w[j] - rmom[j];
+            forces[9 + j] = -(E.A[3 + j] * dnu[3 + j] * C.inv_dt) - caa[j] - dca[j] * w[j] - rmom[j];
         }
     }
 
-    // 5. acceleration solve (diagonal M) and velocity update
+    // 5. acceleration solve and velocity update: diagonal M, or the full symmetric
+    // dt M^-1 of a class with a payload
+    if constexpr (kPayload) {
+        const T F6[6] = {Fl[0], Fl[1], Fl[2], Fa[0], Fa[1], Fa[2]};
+        T dnu[6];
+        payload_solve(E, F6, dnu);
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        s.nu[j] = fma_(E.dtMinv[j], Fl[j], s.nu[j]);
-        s.nu[3 + j] = fma_(E.dtMinv[3 + j], Fa[j], s.nu[3 + j]);
+        for (int j = 0; j < 6; ++j) s.nu[j] += dnu[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            s.nu[j] = fma_(E.dtMinv[j], Fl[j], s.nu[j]);
+            s.nu[3 + j] = fma_(E.dtMinv[3 + j], Fa[j], s.nu[3 + j]);
+        }
     }
 
     // 6. pose: position with the updated velocity and the step-start attitude

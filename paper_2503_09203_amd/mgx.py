@@ -57,7 +57,8 @@ class ClassDesc(ctypes.Structure):
                 ("k_rev", ctypes.c_double * MAX_THRUSTERS), ("reaction", ctypes.c_double * MAX_THRUSTERS),
                 ("kind", ctypes.c_int32 * MAX_THRUSTERS), ("span", (ctypes.c_double * 3) * MAX_THRUSTERS),
                 ("fin_max", ctypes.c_double * MAX_THRUSTERS), ("fin_lift", ctypes.c_double * MAX_THRUSTERS),
-                ("fin_drag0", ctypes.c_double * MAX_THRUSTERS), ("fin_drag", ctypes.c_double * MAX_THRUSTERS)]
+                ("fin_drag0", ctypes.c_double * MAX_THRUSTERS), ("fin_drag", ctypes.c_double * MAX_THRUSTERS),
+                ("rg", ctypes.c_double * 3)]
 
 
 class BatchDesc(ctypes.Structure):
@@ -290,9 +291,11 @@ def mgx_class_define(cls) -> int:
             d.fin_lift[i] = float(cls.fin_lift[i])
             d.fin_drag0[i] = float(cls.fin_drag0[i])
             d.fin_drag[i] = float(cls.fin_drag[i])
+    rg = getattr(cls, "rg", None)
     for j in range(3):
         d.inertia[j] = float(cls.inertia[j])
         d.rb[j] = float(cls.rb[j])
+        d.rg[j] = 0.0 if rg is None else float(rg[j])
     d.g0 = float(cls.g0)
     cid = I32()
     _call("mgx_class_define", ctypes.byref(d), ctypes.byref(cid))

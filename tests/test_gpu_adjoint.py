@@ -150,14 +150,15 @@ def test_backward_requires_a_forward():
     b.close()
 
 
-def test_fin_classes_are_refused():
+@pytest.mark.parametrize("make,word", [(synth.rudders, "has fins"), (synth.payload, "payload")])
+def test_fin_and_payload_classes_are_refused(make, word):
     t = torch()
-    w = synth.rudders(n=64, steps=8)
+    w = make(n=64, steps=8)
     b = mgx.Batch(w.classes, w.n_envs, w.dt)
     b.set_params(w.params)
     acts = b.gen_actions(8, seed=1)
     pos = t.zeros((8, 3 * b.layout.n_pad_total), dtype=b.dtype, device=b.device)
     with pytest.raises(mgx.MgxError) as e:
         mgx.mgx_rollout_forward(b.h, acts.data_ptr(), acts.shape[0], 0, 1, 8, 4, pos.data_ptr())
-    assert "has fins" in str(e.value)
+    assert word in str(e.value)
     b.close()

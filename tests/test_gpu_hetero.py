@@ -206,3 +206,21 @@ def test_fin_class_keeps_per_class_launches_in_persistent_mode():
             for c, (g, r) in enumerate(pairs):
                 assert np.all(component_errors(g, r) <= bar), (mode, k, c)
     assert np.array_equal(finals[0], finals[1])
+
+
+def test_payload_class_in_a_mixed_batch():
+    """A payload class (its records hold 15 more rows) between propeller and rudder
+    classes: per-class and persistent-shaped launches agree bitwise and match the oracle."""
+    hc = synth.hetero_classes()
+    w = synth.mixed([hc[0], synth.payload_class(), synth.rudder_class(), hc[3]], [100, 150, 200, 130], steps=48)
+    acts = w.actions(6)
+    finals = []
+    for mode in (mgx.LAUNCH_PER_CLASS, mgx.LAUNCH_PERSISTENT):
+        fin = []
+        res = run_pair(w, acts, 10, [1, 48], chunk=16, shape=(mode, 16), final_state=fin)
+        finals.append(fin[0])
+        for k, pairs in res:
+            bar = 1e-5 if k == 1 else 5e-4
+            for c, (g, r) in enumerate(pairs):
+                assert np.all(component_errors(g, r) <= bar), (mode, k, c)
+    assert np.array_equal(finals[0], finals[1])

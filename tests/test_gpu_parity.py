@@ -166,6 +166,40 @@ def test_rudders_full_size_sampled():
     check(res, {1: 1e-5, 1000: 5e-3}, "rudders 65536 sampled")
 
 
+def test_payload_class():
+    """A payload moves the centre of gravity off the body origin: full M_RB, its Coriolis
+    terms, the weight's moment, and dt M^-1 inverted per environment in double on the
+    device. Fused and one-step launches, FP64, and the force read-back (whose hydrodynamic
+    part uses the full solve) against the oracle."""
+    w = synth.payload(n=1000, steps=200)
+    assert np.any(w.classes[0].rg != 0)
+    acts = w.actions(20)
+    check(run_pair(w, acts, 10, [1, 10, 200], chunk=16), {1: 1e-5, 10: 1e-4, 200: 1e-3}, "payload")
+    check(run_pair(w, acts, 10, [1, 10]), {1: 1e-5, 10: 1e-4}, "payload unchunked")
+    check(run_pair(w, acts, 10, [1, 50], precision=mgx.FP64), 1e-9, "payload fp64")
+    t = torch()
+    b = make_batch(w)
+    K = 12
+    forces = t.zeros((K, b.layout.force_row_elems), dtype=b.dtype, device=b.device)
+    b.step(device_actions(b, acts), K, hold=10, forces=forces)
+    envs, st = oracle_inputs(w)[0]
+    _, _, ofo = oracle.rollout(envs, st.copy(), oracle.pack_actions(acts[0]), 10, K, forces=True)
+    gfo = b.unpack_forces(forces.cpu().numpy().astype(np.float64))[0]
+    for k in (0, 11):
+        assert component_errors(gfo[k], ofo[:, k, :].T).max() <= 1e-4
+    b.close()
+
+
+def test_payload_full_size_sampled():
+    """65,536 payload environments in 16-step launches; 512 sampled against the oracle."""
+    w = synth.payload()
+    rng = np.random.default_rng(3)
+    s = np.sort(rng.choice(w.n_total, 512, replace=False))
+    s[0], s[-1] = 0, w.n_total - 1
+    res = run_pair(w, w.actions(100), 10, [1, 1000], sample=[s], chunk=16)
+    check(res, {1: 1e-5, 1000: 1e-3}, "payload 65536 sampled")
+
+
 def test_fast_spin_takes_the_exact_attitude_increment():
     """Odd environments spin at 15-40 rad/s about their largest principal axis (a stable
     rotation), where |w| dt / 2 > 0.05 and the attitude increment is evaluated exactly with

@@ -183,3 +183,10 @@ def test_server_refuses_fin_classes():
     with pytest.raises(mgx.MgxError) as e:
         mgx.Server(cs, [nominal(c) for c in cs], chunk_steps=32)
     assert "has fins" in str(e.value)
+
+
+def test_server_refuses_payload_classes():
+    cs = list(classes()) + [synth.payload_class()]
+    with pytest.raises(mgx.MgxError) as e:
+        mgx.Server(cs, [nominal(c) for c in cs], chunk_steps=32)
+    assert "payload" in str(e.value)
