@@ -90,14 +90,16 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="dr",
-                    choices=["dr", "propellers", "rudders", "payload", "hetero", "serve", "adjoint", "resample"],
+                    choices=["dr", "propellers", "rudders", "payload", "hetero", "serve", "adjoint", "resample", "station"],
                     help="dr: the default benchmark line; propellers: the same line with dead zones, reverse "
                          "gains and shaft torques on every thruster; rudders: the same line for a rudder-propeller "
                          "class (one propeller, four tail fins); payload: the same line with the centre of gravity "
                          "off the body origin (full mass matrix); hetero: five classes in one persistent launch; "
                          "serve: Poisson request trace through the continuous-batching server and the FIFO baseline; "
                          "adjoint: checkpointed forward and reverse sweep of the differentiable rollout; "
-                         "resample: on-device domain randomisation of every environment's parameters")
+                         "resample: on-device domain randomisation of every environment's parameters; "
+                         "station: the station-keeping task step (step, observation, reward, termination and "
+                         "auto-reset in one kernel)")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: requests per second")
     ap.add_argument("--sweep-rates", default="", help="serve: extra comma-separated rates, 5 s each")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: trace length (s)")
@@ -152,6 +154,9 @@ def main():
         return
     if args.workload == "resample":
         resample(args)
+        return
+    if args.workload == "station":
+        station(args)
         return
     variant = args.workload  # dr, propellers or rudders
     make = {"dr": synth.randomised, "propellers": synth.propellers, "rudders": synth.rudders,
@@ -610,6 +615,116 @@ def resample(args):
            "note": "46 Philox uniforms, 10 Box-Muller draws in double and the record rebuild per environment"}
     b.close()
     print(json.dumps(out), flush=True)
+
+
+def station(args):
+    """Station-keeping task steps of the randomised workload's 65,536 environments: each
+    launch advances every environment one step under its command, then writes its
+    observation (and the pre-reset one), reward and flags and restarts ended episodes.
+    Timed with HIP events on the batch stream over `steps` calls of 100 task steps each,
+    with every output kept per step; parity on 256 sampled environments over one call."""
+    import time
+
+    import torch
+
+    import oracle
+    import synth
+    from oracle import station as S
+    from paper_2503_09203_amd import mgx
+
+    N, CH = args.n, 100
+    desc = dict(mgx.STATION_DEFAULTS)
+    w = synth.randomised(n=N, steps=8)
+    c = w.classes[0]
+    b = mgx.Batch([c], [N], w.dt, mgx.FP32)
+    b.set_params(w.params)
+    st = mgx.Station(b, **desc)
+    acts = b.gen_actions(CH, seed=17)
+    out = st.empty_outputs(CH)
+    s = torch.cuda.current_stream()
+    st.reset(99)
+    for _ in range(args.warmup):
+        st.step(acts, out)
+    reps = max(args.steps, 10)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        st.step(acts, out)
+    e1.record(s)
+    torch.cuda.synchronize()
+    elapsed = e0.elapsed_time(e1) * 1e-3
+    per_launch = elapsed / (reps * CH)
+    m, P = c.m, 4
+    # state read and written, record, target, command, observation and pre-reset observation,
+    # reward, two flag bytes, episode index and step count read and written
+    bytes_es = P * (2 * (13 + m) + 30 + 7 + m + 2 * (13 + m) + 1) + 2 + 4 * 4
+    ep, _ = st.episodes()
+
+    # parity: 256 sampled environments over one call of 100 task steps from a fresh reset
+    st.reset(99)
+    st.step(acts, out)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(4)
+    ids = np.sort(rng.choice(N, 256, replace=False))
+    sd = S.StationDesc(**desc)
+    envs = oracle.make_envs(c, w.params.subset(ids), w.dt)
+    o = S.StationOracle(sd, envs, m, ids=ids)
+    o.reset(99)
+    host_acts = b.unpack_actions(acts.cpu().numpy().astype(np.float64))[0]
+    obs_all = out["obs"].cpu().numpy().astype(np.float64)
+    rew = out["reward"].cpu().numpy().astype(np.float64)
+    term = out["terminated"].cpu().numpy().astype(bool)
+    ok = np.ones(ids.size, bool)
+    worst, flags_ok = 0.0, True
+
+    def near(obs):
+        d = np.linalg.norm(obs[:, 0:3], axis=1)
+        up = 1.0 - 2.0 * (obs[:, 4] ** 2 + obs[:, 5] ** 2)
+        return (np.abs(d - sd.d_max) < 2e-3) | (np.abs(up - np.cos(sd.tilt_max)) < 2e-3) | (np.abs(obs[:, 3]) < 2e-3)
+
+    for k in range(CH):
+        ro, rr, rt, _, rf = o.step(host_acts[k][:, ids].T)
+        ok &= ~near(ro) & ~near(rf)
+        dev = b.unpack_state(obs_all[k])[0][:, ids].T
+        rms = np.sqrt(np.mean(ro[ok] ** 2, axis=0))
+        worst = max(worst, float(np.max(np.abs(dev[ok] - ro[ok]) / np.maximum(np.abs(ro[ok]), rms), initial=0)),
+                    float(np.max(np.abs(rew[k, ids][ok] - rr[ok]), initial=0)))
+        flags_ok &= bool(np.array_equal(term[k, ids][ok], rt[ok]))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        n_cpu = 4096
+        cids = np.arange(0, N, N // n_cpu)[:n_cpu]
+        oc = S.StationOracle(sd, oracle.make_envs(c, w.params.subset(cids), w.dt), m, ids=cids)
+        oc.reset(99)
+        a_cpu = host_acts[:, :, cids]
+        t0 = time.perf_counter()
+        for k in range(CH):
+            oc.step(a_cpu[k].T)
+        dt_cpu = time.perf_counter() - t0
+        cpu = {"value": n_cpu * CH / dt_cpu, "unit": "env-steps/s", "cores": oracle.get_threads(), "kind": "oracle",
+               "sample": f"{n_cpu} of {N} environments (evenly spaced ids) x {CH} task steps, FP64 oracle "
+                         f"(C step with OpenMP, numpy observation/reward/reset), {dt_cpu:.1f} s"}
+    out_line = {
+        "metric": "station-keeping task env-steps/s (step, observation, reward, termination, auto-reset)",
+        "value": N / per_launch, "unit": "env-steps/s", "n_gpus": 1, "steps": reps, "warmup": args.warmup,
+        "ms_per_step": elapsed / reps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"station_{N}", "n_envs": N, "task_steps_per_call": CH, "thrusters": m,
+                   "station": desc, "path": "station step: one launch per task step, all outputs kept per step"},
+        "roofline": {"bound": "hbm", "achieved": N * bytes_es / per_launch / 1e9, "peak": PEAK_HBM / 1e9,
+                     "unit": "GB/s", "frac": N * bytes_es / per_launch / PEAK_HBM, "traffic": None,
+                     "kernel": f"k_station_step<float,{m},false,false,false>", "launch_us_mean": per_launch * 1e6,
+                     "bytes_per_env_step": bytes_es},
+        "episodes_started_per_env": float(np.mean(ep)),
+        "cpu_baseline": cpu,
+        "parity": {"metric": "max over sampled envs and steps of obs relative error and reward abs error",
+                   "max_err": worst, "tolerance": 2e-4, "flags_equal": flags_ok, "pass": worst <= 2e-4 and flags_ok,
+                   "envs_checked": int(ok.sum()), "steps": CH}}
+    st.close()
+    b.close()
+    print(json.dumps(out_line), flush=True)
 
 
 def counter_launches(args):

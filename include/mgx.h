@@ -405,6 +405,74 @@ mgx_status mgx_graph_capture(mgx_batch* b, const void* actions, int64_t n_rows, 
 mgx_status mgx_graph_replay(mgx_graph* g);
 mgx_status mgx_graph_destroy(mgx_graph* g);
 
+/* ------------------------------------------------------------------ station-keeping task */
+
+/* Station keeping (Sec. IV-B): each environment must reach and hold a target pose in
+ * moving water, keeping its position error small and its attitude within limits. The task
+ * runs on a batch's environments and state: every task step advances them under one held
+ * command, then forms the observation, reward and termination in the same kernel, and an
+ * environment whose episode ended starts the next one at once. The paper does not give the
+ * observation, reward or termination; this library fixes the following.
+ *   Episode start of global env g, episode k (seed from mgx_station_reset): 14 uniforms on
+ *   [0, 1) of 53 bits from Philox4x32-10 at key (seed mod 2^32, 8 << 24) and counter
+ *   (g, k, j, 0), j = 0..6, pairs (w0, w1) then (w2, w3) as in mgx_batch_resample. Target
+ *   p* = target_box (2 u[0..2] - 1); target attitude a pure yaw pi (2 u3 - 1). Start at
+ *   p = 0 with yaw pi (2 u4 - 1), roll tilt0 (2 u5 - 1), pitch tilt0 (2 u6 - 1),
+ *   q0 = q_z(yaw) q_y(pitch) q_x(roll), nu_j = v0 (2 u[7+j] - 1), rotor states 0; in
+ *   double, rounded once.
+ *   Observation, in the state's layout (13 + m rows): the target position in the body frame
+ *   R(q)^T (p* - p); the attitude error q*^-1 q with its scalar part >= 0; nu; the rotor
+ *   states.
+ *   Reward of a transition, on the state it ends in (a = the clipped command):
+ *   exp(-|p* - p| / sigma_p) - w_att (1 - q_e,w^2) - w_act mean_i a_i^2; 0 if that state
+ *   is not finite.
+ *   terminated: not finite, or |p* - p| > d_max, or the body z axis leans more than
+ *   tilt_max from the world z axis. truncated: the episode has taken max_steps task steps.
+ *   An episode that ends restarts as episode k + 1 in the same step: obs is then the new
+ *   episode's first observation; final_obs holds the observation of the state the
+ *   transition ended in. */
+typedef struct mgx_station mgx_station;
+
+typedef struct {
+    double target_box;   /* half-width of the target position box (m), [0, 1e4] */
+    double tilt0;        /* start roll and pitch half-range (rad), [0, pi/2] */
+    double v0;           /* start velocity half-range per component, [0, 100] */
+    double sigma_p;      /* reward position scale (m), > 0 */
+    double w_att;        /* attitude penalty weight, >= 0 */
+    double w_act;        /* command penalty weight, >= 0 */
+    double d_max;        /* terminate beyond this distance from the target (m), > 0 */
+    double tilt_max;     /* terminate beyond this lean from upright (rad), (0, pi] */
+    int32_t max_steps;   /* truncate after this many task steps, >= 1 */
+    int32_t substeps;    /* dynamics steps per task step with the command held, [1, 1000] */
+} mgx_station_desc;
+
+/* Creates the task on a batch (device buffers for the targets and episode counters,
+ * hipMalloc; synchronous). The batch outlives it: mgx_batch_destroy returns MGX_E_STATE
+ * while a task is alive. MGX_E_INVALID on a field outside its range. */
+mgx_status mgx_station_create(mgx_batch* b, const mgx_station_desc* d, mgx_station** out);
+mgx_status mgx_station_destroy(mgx_station* s);   /* synchronises the batch's stream; NULL is OK */
+
+/* Starts episode 0 of every environment from `seed`: overwrites the batch state, draws the
+ * targets, zeroes the episode counters. obs: NULL or device [state_elems] (batch layout and
+ * precision), the first observations. Does not move the batch step counter. Asynchronous. */
+mgx_status mgx_station_reset(mgx_station* s, uint64_t seed, void* obs);
+
+/* n_steps >= 1 task steps (n_steps launches per class; a Gym step is n_steps = 1). Step k
+ * reads command row k of `actions` (device, n_steps rows of row_elems, the batch's action
+ * layout and precision) and writes row k of every output, all device memory:
+ *   obs, final_obs: [n_steps][state_elems], the batch's state layout (final_obs may be NULL);
+ *   reward: [n_steps][n_pad_total], batch precision; terminated, truncated:
+ *   [n_steps][n_pad_total] bytes (0 / 1). Environment e of class c sits at slot
+ *   sum_{c' < c} n_pad[c'] + e; padded slots get reward 0 and flags 0.
+ * Does not move the batch step counter. MGX_E_STATE before mgx_batch_set_params or
+ * mgx_station_reset. Asynchronous. */
+mgx_status mgx_station_step(mgx_station* s, const void* actions, int32_t n_steps, void* obs, void* reward,
+                            uint8_t* terminated, uint8_t* truncated, void* final_obs);
+
+/* Episode index and steps taken in the current episode, per global env id (host arrays of
+ * n_total). Synchronises the stream. */
+mgx_status mgx_station_episodes(mgx_station* s, int32_t* episode, int32_t* steps);
+
 /* ------------------------------------------------------------------ serving */
 
 /* Continuous-batching server. A scheduler thread owns a device arena of budget_bytes

@@ -151,11 +151,13 @@ def reward_done(desc: StationDesc, state: np.ndarray, target: np.ndarray, a_clip
 
 
 class StationOracle:
-    """The task over n environments of one vehicle class (global ids env_off..env_off+n-1)."""
+    """The task over n environments of one vehicle class: global ids env_off..env_off+n-1,
+    or the given ``ids`` (one per entry of ``envs``)."""
 
-    def __init__(self, desc: StationDesc, envs: np.ndarray, m: int, env_off: int = 0):
+    def __init__(self, desc: StationDesc, envs: np.ndarray, m: int, env_off: int = 0, ids=None):
         self.desc, self.envs, self.m = desc, envs, m
-        self.ids = np.arange(env_off, env_off + envs.shape[0], dtype=np.int64)
+        self.ids = (np.arange(env_off, env_off + envs.shape[0], dtype=np.int64) if ids is None
+                    else np.asarray(ids, dtype=np.int64))
 
     def reset(self, seed: int) -> np.ndarray:
         n = self.ids.size

@@ -5,6 +5,7 @@ import glob
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -27,15 +28,34 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    """Compile every HIP source into libmgx.so (always recompiles)."""
+def build(verbose: bool = False, extra=(), jobs: int = 0) -> str:
+    """Compile every HIP source into libmgx.so (always recompiles): one object per source,
+    compiled in parallel, then linked."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [hipcc, *FLAGS, *extra, "-I", INCLUDE, "-I", CSRC, *sources(), "-o", tmp]
+    objdir = os.path.join(PKG, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    tag = f".{os.getpid()}"
+    srcs = sources()
+    objs = [os.path.join(objdir, os.path.basename(s)[:-4] + tag + ".o") for s in srcs]
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    cmds = [[hipcc, *compile_flags, *extra, "-I", INCLUDE, "-I", CSRC, "-c", s, "-o", o] for s, o in zip(srcs, objs)]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+        for c in cmds:
+            print(" ".join(c), flush=True)
+    jobs = jobs or min(len(cmds), max(1, (os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        procs = list(ex.map(lambda c: subprocess.run(c), cmds))
+    failed = [c[-3] for c, p in zip(cmds, procs) if p.returncode != 0]
+    try:
+        if failed:
+            raise subprocess.CalledProcessError(1, "hipcc -c " + " ".join(failed))
+        tmp = LIB + f".tmp{os.getpid()}"
+        subprocess.check_call([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
+        os.replace(tmp, LIB)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     return LIB
 
 

@@ -14,30 +14,6 @@
 
 namespace mgx {
 
-template <typename T, int M>
-__device__ __forceinline__ void load_state(const T* S, int64_t np, int64_t e, StateT<T, M>& s) {
-#pragma unroll
-    for (int j = 0; j < 3; ++j) s.p[j] = S[j * np + e];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) s.q[j] = S[(3 + j) * np + e];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) s.nu[j] = S[(7 + j) * np + e];
-#pragma unroll
-    for (int i = 0; i < M; ++i) s.n[i] = S[(kStateFixed + i) * np + e];
-}
-
-template <typename T, int M>
-__device__ __forceinline__ void store_state(T* S, int64_t np, int64_t e, const StateT<T, M>& s) {
-#pragma unroll
-    for (int j = 0; j < 3; ++j) S[j * np + e] = s.p[j];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) S[(3 + j) * np + e] = s.q[j];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) S[(7 + j) * np + e] = s.nu[j];
-#pragma unroll
-    for (int i = 0; i < M; ++i) S[(kStateFixed + i) * np + e] = s.n[i];
-}
-
 template <typename T>
 __device__ __forceinline__ void load_env(const T* Rc, int64_t np, int64_t e, EnvT<T>& E) {
 #pragma unroll

@@ -239,21 +239,9 @@ __device__ __forceinline__ ClassT<T> class_in_vgpr(const ClassT<T>& Cs) {
     return C;
 }
 
-// K steps of environment `env` (a slot of the segment described by A) from global step
-// t0. Commands are fetched raw one hold interval before use and clipped when their row
-// becomes current; all prologue loads are drained once before the loop so that the only
-// memory operations in flight inside it are those prefetches.
-// kSingle: a launch of exactly one step without outputs (the single-step kernel). Such a
-// launch never reaches the next action row, so it does not fetch it.
-template <typename T, int M, bool kOut, bool kShaped, bool kSingle = false, bool kFins = false, bool kPayload = false>
-__device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs, int64_t env, int64_t t0, int K,
-                                          float st[kStats]) {
-    static_assert(!(kSingle && kOut), "the single-step form has no per-step outputs");
-    const int64_t np = A.npad;
-    const ClassT<T> C = class_in_vgpr<T, M, kFins>(Cs);
-    T* S = (T*)A.state;
-    const T* Rc = (const T*)A.rec;
-    StateT<T, M> s;
+// State and per-environment record of slot `env` of a segment of np slots.
+template <typename T, int M>
+__device__ __forceinline__ void load_state(const T* S, int64_t np, int64_t env, StateT<T, M>& s) {
 #pragma unroll
     for (int j = 0; j < 3; ++j) s.p[j] = S[j * np + env];
 #pragma unroll
@@ -262,7 +250,22 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
     for (int j = 0; j < 6; ++j) s.nu[j] = S[(7 + j) * np + env];
 #pragma unroll
     for (int i = 0; i < M; ++i) s.n[i] = S[(kStateFixed + i) * np + env];
-    EnvT<T> E;
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void store_state(T* S, int64_t np, int64_t env, const StateT<T, M>& s) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) S[j * np + env] = s.p[j];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) S[(3 + j) * np + env] = s.q[j];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) S[(7 + j) * np + env] = s.nu[j];
+#pragma unroll
+    for (int i = 0; i < M; ++i) S[(kStateFixed + i) * np + env] = s.n[i];
+}
+
+template <typename T, bool kPayload>
+__device__ __forceinline__ void load_record(const T* Rc, int64_t np, int64_t env, uint32_t flags, EnvT<T>& E) {
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
         E.dtMinv[j] = Rc[(kRecDtMinv + j) * np + env];
@@ -279,7 +282,70 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
 #pragma unroll
         for (int k = 0; k < 15; ++k) E.dtMinvOff[k] = Rc[(kRecMinvOff + k) * np + env];
     }
-    set_amc(E, C.flags);
+    set_amc(E, flags);
+}
+
+// Per-environment constants of the step formed once per launch: I + A_2, B r_b and, with
+// a payload, the inertia about the origin plus A_2, m r_g and B r_b - W r_g.
+template <typename T, bool kPayload>
+__device__ __forceinline__ void env_prologue(const ClassT<T>& C, EnvT<T>& E, T IA2[3], T Brb[3]) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        IA2[j] = C.inertia[j] + E.A[3 + j];
+        Brb[j] = E.buoy * C.rb[j];
+    }
+    if constexpr (kPayload) {
+        // I_o + A_2 = I_g + m(|r_g|^2 1 - r_g r_g^T) + A_2; m r_g; (B r_b - W r_g)
+        const T* r = C.rg;
+        const T m = E.mass, W = E.mass * C.g0;
+        E.IoA[0] = IA2[0] + m * (r[1] * r[1] + r[2] * r[2]);
+        E.IoA[1] = IA2[1] + m * (r[0] * r[0] + r[2] * r[2]);
+        E.IoA[2] = IA2[2] + m * (r[0] * r[0] + r[1] * r[1]);
+        E.IoA[3] = -(m * r[0] * r[1]);
+        E.IoA[4] = -(m * r[0] * r[2]);
+        E.IoA[5] = -(m * r[1] * r[2]);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            E.mrg[j] = m * r[j];
+            Brb[j] = fma_(-W, r[j], Brb[j]);
+        }
+    }
+}
+
+// Long-horizon attitude drift check: renormalise in double when | |q|^2 - 1 | > 1e-6,
+// recording the drift and whether it renormalised in the launch statistics `st`.
+template <typename T, int M>
+__device__ __forceinline__ void renorm_attitude(StateT<T, M>& s, float st[kStats]) {
+    T n2 = fma_(s.q[3], s.q[3], fma_(s.q[2], s.q[2], fma_(s.q[1], s.q[1], s.q[0] * s.q[0])));
+    T drift = abs_(n2 - T(1));
+    if (drift > T(1e-6)) {
+        double qd[4] = {(double)s.q[0], (double)s.q[1], (double)s.q[2], (double)s.q[3]};
+        double inv = 1.0 / sqrt(qd[0] * qd[0] + qd[1] * qd[1] + qd[2] * qd[2] + qd[3] * qd[3]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) s.q[j] = (T)(qd[j] * inv);
+        st[kStRenorm] = 1.0f;
+    }
+    st[kStMaxDrift] = (float)drift;
+}
+
+// K steps of environment `env` (a slot of the segment described by A) from global step
+// t0. Commands are fetched raw one hold interval before use and clipped when their row
+// becomes current; all prologue loads are drained once before the loop so that the only
+// memory operations in flight inside it are those prefetches.
+// kSingle: a launch of exactly one step without outputs (the single-step kernel). Such a
+// launch never reaches the next action row, so it does not fetch it.
+template <typename T, int M, bool kOut, bool kShaped, bool kSingle = false, bool kFins = false, bool kPayload = false>
+__device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs, int64_t env, int64_t t0, int K,
+                                          float st[kStats]) {
+    static_assert(!(kSingle && kOut), "the single-step form has no per-step outputs");
+    const int64_t np = A.npad;
+    const ClassT<T> C = class_in_vgpr<T, M, kFins>(Cs);
+    T* S = (T*)A.state;
+    const T* Rc = (const T*)A.rec;
+    StateT<T, M> s;
+    load_state<T, M>(S, np, env, s);
+    EnvT<T> E;
+    load_record<T, kPayload>(Rc, np, env, C.flags, E);
 
     // Action rows, relative to the buffer start, uniform across the wave. Every fetch is
     // issued unconditionally at a row index clamped into the buffer (validity is tracked
@@ -307,27 +373,7 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
 #pragma unroll
     for (int i = 0; i < M; ++i) cur[i] = clip1(cur[i]);
     T IA2[3], Brb[3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        IA2[j] = C.inertia[j] + E.A[3 + j];
-        Brb[j] = E.buoy * C.rb[j];
-    }
-    if constexpr (kPayload) {
-        // I_o + A_2 = I_g + m(|r_g|^2 1 - r_g r_g^T) + A_2; m r_g; (B r_b - W r_g)
-        const T* r = C.rg;
-        const T m = E.mass, W = E.mass * C.g0;
-        E.IoA[0] = IA2[0] + m * (r[1] * r[1] + r[2] * r[2]);
-        E.IoA[1] = IA2[1] + m * (r[0] * r[0] + r[2] * r[2]);
-        E.IoA[2] = IA2[2] + m * (r[0] * r[0] + r[1] * r[1]);
-        E.IoA[3] = -(m * r[0] * r[1]);
-        E.IoA[4] = -(m * r[0] * r[2]);
-        E.IoA[5] = -(m * r[1] * r[2]);
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            E.mrg[j] = m * r[j];
-            Brb[j] = fma_(-W, r[j], Brb[j]);
-        }
-    }
+    env_prologue<T, kPayload>(C, E, IA2, Brb);
     if constexpr (kSingle) {
         step_body<T, M, false, kShaped, kFins, kPayload>(C, E, IA2, Brb, s, cur);
     } else {
@@ -377,7 +423,8 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
     }
     if (bad && (threadIdx.x & (kWave - 1)) == 0) atomicOr(&A.misc->err, 1);
 
-    // Long-horizon attitude drift check: renormalise in double when | |q|^2 - 1 | > 1e-6.
+    // The same check as renorm_attitude, written out: as a call it changes the register
+    // allocation of the fused loop (15 more instructions in the plain K-step kernel).
     {
         T n2 = fma_(s.q[3], s.q[3], fma_(s.q[2], s.q[2], fma_(s.q[1], s.q[1], s.q[0] * s.q[0])));
         T drift = abs_(n2 - T(1));
@@ -391,14 +438,7 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
         st[kStMaxDrift] = (float)drift;
     }
 
-#pragma unroll
-    for (int j = 0; j < 3; ++j) S[j * np + env] = s.p[j];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) S[(3 + j) * np + env] = s.q[j];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) S[(7 + j) * np + env] = s.nu[j];
-#pragma unroll
-    for (int i = 0; i < M; ++i) S[(kStateFixed + i) * np + env] = s.n[i];
+    store_state<T, M>(S, np, env, s);
 
     if (A.partials) {
         if (env < A.nvalid) {

@@ -357,6 +357,8 @@ extern "C" mgx_status mgx_batch_create(const mgx_batch_desc* d, mgx_batch** out)
 extern "C" mgx_status mgx_batch_destroy(mgx_batch* b) {
     if (!b) return MGX_OK;
     if (b->n_graphs > 0) return fail(MGX_E_STATE, "destroy the %d graph(s) of this batch first", b->n_graphs);
+    if (b->n_stations > 0)
+        return fail(MGX_E_STATE, "destroy the %d station task(s) of this batch first", b->n_stations);
     hipDevice_guard g(b->device);
     (void)hipStreamSynchronize(b->stream);
     free_batch_mem(b);

@@ -73,6 +73,7 @@ struct mgx_batch {
     int64_t h_t_stage = 0;
     int block = 256;
     int n_graphs = 0;  // live graphs captured from this batch
+    int n_stations = 0;  // live station-keeping tasks on this batch
     // launch shape
     int mode = MGX_LAUNCH_PER_CLASS;
     int shape_K = 16;

@@ -1,0 +1,464 @@
+// Station-keeping task on top of the step (Sec. IV-B): per task step, every environment
+// advances under its held command, then its observation, reward and termination are
+// formed in the same kernel, and an environment whose episode ended starts the next one
+// at once (its state and target drawn again), so the batch never leaves the device
+// between policy calls.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "env_loop.hpp"
+#include "kernels.hpp"
+#include "mgx.h"
+#include "runtime_internal.hpp"
+
+namespace mgx {
+
+constexpr uint32_t kStreamTask = 8u;
+
+struct StationConsts {
+    double box, tilt0, v0;                                // episode start draws
+    double inv_sigma, w_att, w_act_m, d_max, cos_tilt;    // reward (w_act / m) and termination
+    int32_t max_steps, substeps;
+    uint64_t seed;
+};
+
+template <typename T>
+struct StationArgs {
+    T* state;
+    const T* rec;
+    const T* act;        // one action row, class segment
+    T* tgt;              // [7][npad]: p*, q*
+    int32_t* ep;         // [npad] episode index
+    int32_t* et;         // [npad] steps taken in the episode
+    T* obs;              // [13+m][npad]
+    T* final_obs;        // [13+m][npad] or NULL
+    T* reward;           // [npad]
+    uint8_t* term;       // [npad]
+    uint8_t* trunc;      // [npad]
+    int32_t npad, nvalid;
+    int64_t env_off;
+    StationConsts P;
+};
+
+template <typename T>
+struct StationLaunch {
+    StationArgs<T> a;
+    ClassT<T> cls;
+};
+
+// Episode start of global env g, episode k, in double: target p*, q* (a pure yaw) and the
+// start attitude q0 = q_z(yaw) q_y(pitch) q_x(roll) with velocities nu0; p = 0, n = 0.
+__device__ void episode_draw(const StationConsts& P, uint64_t g, uint32_t k, double tgt[7], double q0[4],
+                             double nu0[6]) {
+    double u[14];
+    for (int j = 0; j < 7; ++j) {
+        uint32_t c[4] = {(uint32_t)g, k, (uint32_t)j, 0u};
+        philox4x32_10(c, (uint32_t)P.seed, kStreamTask << 24);
+        u[2 * j] = u53(c[0], c[1]);
+        u[2 * j + 1] = u53(c[2], c[3]);
+    }
+    for (int j = 0; j < 3; ++j) tgt[j] = P.box * (2.0 * u[j] - 1.0);
+    const double ht = 0.5 * (M_PI * (2.0 * u[3] - 1.0));
+    tgt[3] = cos(ht);
+    tgt[4] = 0.0;
+    tgt[5] = 0.0;
+    tgt[6] = sin(ht);
+    const double hy = 0.5 * (M_PI * (2.0 * u[4] - 1.0));
+    const double hr = 0.5 * (P.tilt0 * (2.0 * u[5] - 1.0));
+    const double hp = 0.5 * (P.tilt0 * (2.0 * u[6] - 1.0));
+    const double cy = cos(hy), sy = sin(hy), cp = cos(hp), sp = sin(hp), cr = cos(hr), sr = sin(hr);
+    q0[0] = cy * cp * cr + sy * sp * sr;
+    q0[1] = cy * cp * sr - sy * sp * cr;
+    q0[2] = cy * sp * cr + sy * cp * sr;
+    q0[3] = sy * cp * cr - cy * sp * sr;
+    for (int j = 0; j < 6; ++j) nu0[j] = P.v0 * (2.0 * u[7 + j] - 1.0);
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void start_state(const StationConsts& P, uint64_t g, uint32_t k, StateT<T, M>& s,
+                                            T tg[7]) {
+    double t[7], q0[4], nu0[6];
+    episode_draw(P, g, k, t, q0, nu0);
+#pragma unroll
+    for (int j = 0; j < 7; ++j) tg[j] = (T)t[j];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) s.p[j] = T(0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s.q[j] = (T)q0[j];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) s.nu[j] = (T)nu0[j];
+#pragma unroll
+    for (int i = 0; i < M; ++i) s.n[i] = T(0);
+}
+
+// Attitude error q*^-1 q, scalar part made >= 0.
+template <typename T>
+__device__ __forceinline__ void attitude_error(const T q[4], const T t[4], T e[4]) {
+    e[0] = t[0] * q[0] + t[1] * q[1] + t[2] * q[2] + t[3] * q[3];
+    e[1] = t[0] * q[1] - t[1] * q[0] - t[2] * q[3] + t[3] * q[2];
+    e[2] = t[0] * q[2] + t[1] * q[3] - t[2] * q[0] - t[3] * q[1];
+    e[3] = t[0] * q[3] - t[1] * q[2] + t[2] * q[1] - t[3] * q[0];
+    if (e[0] < T(0)) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) e[j] = -e[j];
+    }
+}
+
+// Observation in the state's layout: R(q)^T (p* - p), the attitude error, nu, n.
+template <typename T, int M>
+__device__ __forceinline__ void write_obs(T* O, int64_t np, int64_t env, const StateT<T, M>& s, const T tg[7]) {
+    const T d0 = tg[0] - s.p[0], d1 = tg[1] - s.p[1], d2 = tg[2] - s.p[2];
+    const T w = s.q[0], x = s.q[1], y = s.q[2], z = s.q[3];
+    // columns of R(q)
+    const T r00 = T(1) - T(2) * (y * y + z * z), r10 = T(2) * (x * y + w * z), r20 = T(2) * (x * z - w * y);
+    const T r01 = T(2) * (x * y - w * z), r11 = T(1) - T(2) * (x * x + z * z), r21 = T(2) * (y * z + w * x);
+    const T r02 = T(2) * (x * z + w * y), r12 = T(2) * (y * z - w * x), r22 = T(1) - T(2) * (x * x + y * y);
+    O[0 * np + env] = r00 * d0 + r10 * d1 + r20 * d2;
+    O[1 * np + env] = r01 * d0 + r11 * d1 + r21 * d2;
+    O[2 * np + env] = r02 * d0 + r12 * d1 + r22 * d2;
+    T e[4];
+    attitude_error(s.q, tg + 3, e);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) O[(3 + j) * np + env] = e[j];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) O[(7 + j) * np + env] = s.nu[j];
+#pragma unroll
+    for (int i = 0; i < M; ++i) O[(kStateFixed + i) * np + env] = s.n[i];
+}
+
+__device__ __forceinline__ float exp_(float x) { return expf(x); }
+__device__ __forceinline__ double exp_(double x) { return exp(x); }
+
+// Episode 0 of every valid slot; observations of every slot.
+template <typename T, int M>
+__global__ void __launch_bounds__(256) k_station_start(StationArgs<T> A) {
+    const int64_t env = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (env >= A.npad) return;
+    const int64_t np = A.npad;
+    StateT<T, M> s;
+    T tg[7];
+    if (env < A.nvalid) {
+        start_state<T, M>(A.P, (uint64_t)(A.env_off + env), 0u, s, tg);
+        store_state<T, M>(A.state, np, env, s);
+#pragma unroll
+        for (int j = 0; j < 7; ++j) A.tgt[j * np + env] = tg[j];
+    } else {
+        load_state<T, M>(A.state, np, env, s);
+#pragma unroll
+        for (int j = 0; j < 7; ++j) tg[j] = A.tgt[j * np + env];
+    }
+    A.ep[env] = 0;
+    A.et[env] = 0;
+    if (A.obs) write_obs<T, M>(A.obs, np, env, s, tg);
+}
+
+// One task step of one class segment.
+template <typename T, int M, bool kShaped, bool kFins, bool kPayload>
+__global__ void __launch_bounds__(256) k_station_step(StationLaunch<T> L) {
+    const StationArgs<T>& A = L.a;
+    const int64_t env = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (env >= A.npad) return;
+    const int64_t np = A.npad;
+    StateT<T, M> s;
+    load_state<T, M>(A.state, np, env, s);
+    T tg[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) tg[j] = A.tgt[j * np + env];
+    if (env >= A.nvalid) {  // padding: no dynamics, no reward
+        write_obs<T, M>(A.obs, np, env, s, tg);
+        if (A.final_obs) write_obs<T, M>(A.final_obs, np, env, s, tg);
+        A.reward[env] = T(0);
+        A.term[env] = 0;
+        A.trunc[env] = 0;
+        return;
+    }
+    const ClassT<T> C = class_in_vgpr<T, M, kFins>(L.cls);
+    EnvT<T> E;
+    load_record<T, kPayload>(A.rec, np, env, C.flags, E);
+    T a[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) a[i] = clip1(A.act[i * np + env]);
+    int32_t ep = A.ep[env], et = A.et[env];
+    T IA2[3], Brb[3];
+    env_prologue<T, kPayload>(C, E, IA2, Brb);
+    for (int k = 0; k < A.P.substeps; ++k) step_body<T, M, false, kShaped, kFins, kPayload>(C, E, IA2, Brb, s, a);
+    float st[kStats];  // launch statistics are not kept by the task
+    renorm_attitude<T, M>(s, st);
+
+    // reward and termination on the state the transition ends in
+    bool fin = true;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) fin &= finite_(s.p[j]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) fin &= finite_(s.q[j]);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) fin &= finite_(s.nu[j]);
+#pragma unroll
+    for (int i = 0; i < M; ++i) fin &= finite_(s.n[i]);
+    const T d0 = tg[0] - s.p[0], d1 = tg[1] - s.p[1], d2 = tg[2] - s.p[2];
+    const T d = sqrt_(d0 * d0 + d1 * d1 + d2 * d2);
+    T e[4];
+    attitude_error(s.q, tg + 3, e);
+    T a2 = T(0);
+#pragma unroll
+    for (int i = 0; i < M; ++i) a2 += a[i] * a[i];
+    const T up = T(1) - T(2) * (s.q[1] * s.q[1] + s.q[2] * s.q[2]);
+    T r = exp_(-d * (T)A.P.inv_sigma) - (T)A.P.w_att * (T(1) - e[0] * e[0]) - (T)A.P.w_act_m * a2;
+    const bool term = !fin || d > (T)A.P.d_max || up < (T)A.P.cos_tilt;
+    if (!fin) r = T(0);
+    ++et;
+    const bool trunc = et >= A.P.max_steps;
+    if (A.final_obs) write_obs<T, M>(A.final_obs, np, env, s, tg);
+    if (term || trunc) {
+        ++ep;
+        et = 0;
+        start_state<T, M>(A.P, (uint64_t)(A.env_off + env), (uint32_t)ep, s, tg);
+#pragma unroll
+        for (int j = 0; j < 7; ++j) A.tgt[j * np + env] = tg[j];
+    }
+    store_state<T, M>(A.state, np, env, s);
+    write_obs<T, M>(A.obs, np, env, s, tg);
+    A.reward[env] = r;
+    A.term[env] = term ? 1 : 0;
+    A.trunc[env] = trunc ? 1 : 0;
+    A.ep[env] = ep;
+    A.et[env] = et;
+}
+
+template <typename T, int M>
+static void launch_station_m(const StationLaunch<T>& L, bool shaped, bool fins, bool payload, hipStream_t s) {
+    const dim3 grid((unsigned)((L.a.npad + 255) / 256)), block(256);
+    if (payload && fins)
+        hipLaunchKernelGGL((k_station_step<T, M, true, true, true>), grid, block, 0, s, L);
+    else if (payload)
+        hipLaunchKernelGGL((k_station_step<T, M, true, false, true>), grid, block, 0, s, L);
+    else if (fins)
+        hipLaunchKernelGGL((k_station_step<T, M, true, true, false>), grid, block, 0, s, L);
+    else if (shaped)
+        hipLaunchKernelGGL((k_station_step<T, M, true, false, false>), grid, block, 0, s, L);
+    else
+        hipLaunchKernelGGL((k_station_step<T, M, false, false, false>), grid, block, 0, s, L);
+}
+
+template <typename T>
+static hipError_t launch_station(const StationLaunch<T>& L, int m, hipStream_t s) {
+    const bool shaped = L.cls.shaped != 0, fins = L.cls.fin_mask != 0, payload = L.cls.payload != 0;
+    switch (m) {
+        case 1: launch_station_m<T, 1>(L, shaped, fins, payload, s); break;
+        case 2: launch_station_m<T, 2>(L, shaped, fins, payload, s); break;
+        case 3: launch_station_m<T, 3>(L, shaped, fins, payload, s); break;
+        case 4: launch_station_m<T, 4>(L, shaped, fins, payload, s); break;
+        case 5: launch_station_m<T, 5>(L, shaped, fins, payload, s); break;
+        case 6: launch_station_m<T, 6>(L, shaped, fins, payload, s); break;
+        case 7: launch_station_m<T, 7>(L, shaped, fins, payload, s); break;
+        case 8: launch_station_m<T, 8>(L, shaped, fins, payload, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_start(const StationArgs<T>& A, int m, hipStream_t s) {
+    const dim3 grid((unsigned)((A.npad + 255) / 256)), block(256);
+    switch (m) {
+        case 1: hipLaunchKernelGGL((k_station_start<T, 1>), grid, block, 0, s, A); break;
+        case 2: hipLaunchKernelGGL((k_station_start<T, 2>), grid, block, 0, s, A); break;
+        case 3: hipLaunchKernelGGL((k_station_start<T, 3>), grid, block, 0, s, A); break;
+        case 4: hipLaunchKernelGGL((k_station_start<T, 4>), grid, block, 0, s, A); break;
+        case 5: hipLaunchKernelGGL((k_station_start<T, 5>), grid, block, 0, s, A); break;
+        case 6: hipLaunchKernelGGL((k_station_start<T, 6>), grid, block, 0, s, A); break;
+        case 7: hipLaunchKernelGGL((k_station_start<T, 7>), grid, block, 0, s, A); break;
+        case 8: hipLaunchKernelGGL((k_station_start<T, 8>), grid, block, 0, s, A); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mgx
+
+using namespace mgx;
+
+struct mgx_station {
+    mgx_batch* batch = nullptr;
+    mgx_station_desc desc{};
+    StationConsts P{};
+    void* d_tgt = nullptr;       // [7][npad] per class segment, at 7 * pad_off[c]
+    int32_t* d_ep = nullptr;     // [npad_total]
+    int32_t* d_et = nullptr;     // [npad_total]
+    bool started = false;
+};
+
+#define HIP_TRY_ST(b, call)                                       \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return hip_fail((b), e_, #call);    \
+    } while (0)
+
+static void free_station(mgx_station* s) {
+    if (s->d_tgt) (void)hipFree(s->d_tgt);
+    if (s->d_ep) (void)hipFree(s->d_ep);
+    if (s->d_et) (void)hipFree(s->d_et);
+    s->d_tgt = nullptr;
+    s->d_ep = s->d_et = nullptr;
+}
+
+template <typename T>
+static StationArgs<T> station_args(mgx_station* st, int c) {
+    mgx_batch* b = st->batch;
+    StationArgs<T> a;
+    std::memset(&a, 0, sizeof a);
+    a.state = (T*)b->seg_state(c);
+    a.rec = (const T*)b->seg_rec(c);
+    a.tgt = (T*)st->d_tgt + 7 * b->pad_off[c];
+    a.ep = st->d_ep + b->pad_off[c];
+    a.et = st->d_et + b->pad_off[c];
+    a.npad = (int32_t)b->npad[c];
+    a.nvalid = (int32_t)b->n[c];
+    a.env_off = b->env_off[c];
+    a.P = st->P;
+    a.P.w_act_m = st->desc.w_act / b->m[c];
+    return a;
+}
+
+extern "C" mgx_status mgx_station_create(mgx_batch* b, const mgx_station_desc* d, mgx_station** out) {
+    if (!b || !d || !out) return fail(MGX_E_INVALID, "NULL argument");
+    *out = nullptr;
+    if (b->faulted) return fail(MGX_E_STATE, "batch faulted by an earlier device error");
+    const double pi = M_PI;
+    if (!(d->target_box >= 0 && d->target_box <= 1e4)) return fail(MGX_E_INVALID, "target_box outside [0, 1e4]");
+    if (!(d->tilt0 >= 0 && d->tilt0 <= pi / 2)) return fail(MGX_E_INVALID, "tilt0 outside [0, pi/2]");
+    if (!(d->v0 >= 0 && d->v0 <= 100)) return fail(MGX_E_INVALID, "v0 outside [0, 100]");
+    if (!(d->sigma_p > 0 && std::isfinite(d->sigma_p))) return fail(MGX_E_INVALID, "sigma_p must be > 0");
+    if (!(d->w_att >= 0 && std::isfinite(d->w_att)) || !(d->w_act >= 0 && std::isfinite(d->w_act)))
+        return fail(MGX_E_INVALID, "w_att and w_act must be finite and >= 0");
+    if (!(d->d_max > 0)) return fail(MGX_E_INVALID, "d_max must be > 0");
+    if (!(d->tilt_max > 0 && d->tilt_max <= pi)) return fail(MGX_E_INVALID, "tilt_max outside (0, pi]");
+    if (d->max_steps < 1) return fail(MGX_E_INVALID, "max_steps must be >= 1");
+    if (d->substeps < 1 || d->substeps > 1000) return fail(MGX_E_INVALID, "substeps outside [1, 1000]");
+    hipDevice_guard g(b->device);
+    mgx_station* s = new (std::nothrow) mgx_station();
+    if (!s) return fail(MGX_E_NOMEM, "host allocation");
+    s->batch = b;
+    s->desc = *d;
+    s->P.box = d->target_box;
+    s->P.tilt0 = d->tilt0;
+    s->P.v0 = d->v0;
+    s->P.inv_sigma = 1.0 / d->sigma_p;
+    s->P.w_att = d->w_att;
+    s->P.d_max = d->d_max;
+    s->P.cos_tilt = std::cos(d->tilt_max);
+    s->P.max_steps = d->max_steps;
+    s->P.substeps = d->substeps;
+    const size_t P = (size_t)b->prec, N = (size_t)b->npad_total;
+    hipError_t e = hipMalloc(&s->d_tgt, 7 * N * P);
+    if (e == hipSuccess) e = hipMalloc((void**)&s->d_ep, N * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&s->d_et, N * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemsetAsync(s->d_tgt, 0, 7 * N * P, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->d_ep, 0, N * sizeof(int32_t), b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->d_et, 0, N * sizeof(int32_t), b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        free_station(s);
+        delete s;
+        return e == hipErrorOutOfMemory ? fail(MGX_E_NOMEM, "station buffers") : hip_fail(b, e, "station buffers");
+    }
+    ++b->n_stations;
+    *out = s;
+    return MGX_OK;
+}
+
+extern "C" mgx_status mgx_station_destroy(mgx_station* s) {
+    if (!s) return MGX_OK;
+    mgx_batch* b = s->batch;
+    hipDevice_guard g(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    free_station(s);
+    --b->n_stations;
+    delete s;
+    return MGX_OK;
+}
+
+extern "C" mgx_status mgx_station_reset(mgx_station* s, uint64_t seed, void* obs) {
+    if (!s) return fail(MGX_E_INVALID, "station is NULL");
+    mgx_batch* b = s->batch;
+    if (b->faulted) return fail(MGX_E_STATE, "batch faulted by an earlier device error");
+    hipDevice_guard g(b->device);
+    s->P.seed = seed;
+    const size_t P = (size_t)b->prec;
+    for (int c = 0; c < b->n_classes; ++c) {
+        hipError_t e;
+        if (b->prec == MGX_FP32) {
+            StationArgs<float> a = station_args<float>(s, c);
+            a.obs = obs ? (float*)((char*)obs + P * b->state_off[c]) : nullptr;
+            e = launch_start<float>(a, b->m[c], b->stream);
+        } else {
+            StationArgs<double> a = station_args<double>(s, c);
+            a.obs = obs ? (double*)((char*)obs + P * b->state_off[c]) : nullptr;
+            e = launch_start<double>(a, b->m[c], b->stream);
+        }
+        if (e != hipSuccess) return hip_fail(b, e, "station start launch");
+    }
+    s->started = true;
+    return MGX_OK;
+}
+
+extern "C" mgx_status mgx_station_step(mgx_station* s, const void* actions, int32_t n_steps, void* obs, void* reward,
+                                       uint8_t* terminated, uint8_t* truncated, void* final_obs) {
+    if (!s) return fail(MGX_E_INVALID, "station is NULL");
+    mgx_batch* b = s->batch;
+    if (b->faulted) return fail(MGX_E_STATE, "batch faulted by an earlier device error");
+    if (!b->params_set) return fail(MGX_E_STATE, "mgx_batch_set_params has not been called");
+    if (!s->started) return fail(MGX_E_STATE, "mgx_station_reset has not been called");
+    if (!actions || !obs || !reward || !terminated || !truncated)
+        return fail(MGX_E_INVALID, "actions, obs, reward, terminated and truncated are required");
+    if (n_steps < 1) return fail(MGX_E_INVALID, "n_steps must be >= 1");
+    hipDevice_guard g(b->device);
+    const size_t P = (size_t)b->prec;
+    for (int32_t k = 0; k < n_steps; ++k) {
+        for (int c = 0; c < b->n_classes; ++c) {
+            const int64_t so = k * b->state_elems + b->state_off[c], po = k * b->npad_total + b->pad_off[c];
+            hipError_t e;
+            if (b->prec == MGX_FP32) {
+                StationLaunch<float> L{station_args<float>(s, c), b->h_class_f[c]};
+                L.a.act = (const float*)((const char*)actions + P * (k * b->row_elems + b->act_off[c]));
+                L.a.obs = (float*)obs + so;
+                L.a.final_obs = final_obs ? (float*)final_obs + so : nullptr;
+                L.a.reward = (float*)reward + po;
+                L.a.term = terminated + po;
+                L.a.trunc = truncated + po;
+                e = launch_station<float>(L, b->m[c], b->stream);
+            } else {
+                StationLaunch<double> L{station_args<double>(s, c), b->h_class_d[c]};
+                L.a.act = (const double*)((const char*)actions + P * (k * b->row_elems + b->act_off[c]));
+                L.a.obs = (double*)obs + so;
+                L.a.final_obs = final_obs ? (double*)final_obs + so : nullptr;
+                L.a.reward = (double*)reward + po;
+                L.a.term = terminated + po;
+                L.a.trunc = truncated + po;
+                e = launch_station<double>(L, b->m[c], b->stream);
+            }
+            if (e != hipSuccess) return hip_fail(b, e, "station step launch");
+        }
+    }
+    return MGX_OK;
+}
+
+extern "C" mgx_status mgx_station_episodes(mgx_station* s, int32_t* episode, int32_t* steps) {
+    if (!s || !episode || !steps) return fail(MGX_E_INVALID, "NULL argument");
+    mgx_batch* b = s->batch;
+    hipDevice_guard g(b->device);
+    std::vector<int32_t> ep((size_t)b->npad_total), et((size_t)b->npad_total);
+    HIP_TRY_ST(b, hipMemcpyAsync(ep.data(), s->d_ep, sizeof(int32_t) * ep.size(), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY_ST(b, hipMemcpyAsync(et.data(), s->d_et, sizeof(int32_t) * et.size(), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY_ST(b, hipStreamSynchronize(b->stream));
+    for (int c = 0; c < b->n_classes; ++c)
+        for (int64_t i = 0; i < b->n[c]; ++i) {
+            episode[b->env_off[c] + i] = ep[(size_t)(b->pad_off[c] + i)];
+            steps[b->env_off[c] + i] = et[(size_t)(b->pad_off[c] + i)];
+        }
+    return MGX_OK;
+}

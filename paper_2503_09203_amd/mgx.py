@@ -148,6 +148,17 @@ def dr_spec(groups: dict) -> DrSpec:
     return s
 
 
+class StationDesc(ctypes.Structure):
+    _fields_ = [("target_box", ctypes.c_double), ("tilt0", ctypes.c_double), ("v0", ctypes.c_double),
+                ("sigma_p", ctypes.c_double), ("w_att", ctypes.c_double), ("w_act", ctypes.c_double),
+                ("d_max", ctypes.c_double), ("tilt_max", ctypes.c_double), ("max_steps", ctypes.c_int32),
+                ("substeps", ctypes.c_int32)]
+
+
+STATION_DEFAULTS = dict(target_box=2.0, tilt0=0.2, v0=0.1, sigma_p=0.5, w_att=0.5, w_act=0.01, d_max=5.0,
+                        tilt_max=1.2, max_steps=500, substeps=1)
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("n_nonfinite", ctypes.c_int64 * MAX_CLASSES),
                 ("n_renorm64", ctypes.c_int64 * MAX_CLASSES),
@@ -206,6 +217,11 @@ SIGNATURES = {
     "mgx_graph_capture": (I32, [P, P, I64, I64, I32, I32, I32, U32, ctypes.POINTER(P)]),
     "mgx_graph_replay": (I32, [P]),
     "mgx_graph_destroy": (I32, [P]),
+    "mgx_station_create": (I32, [P, ctypes.POINTER(StationDesc), ctypes.POINTER(P)]),
+    "mgx_station_destroy": (I32, [P]),
+    "mgx_station_reset": (I32, [P, U64, P]),
+    "mgx_station_step": (I32, [P, P, I32, P, P, P, P, P]),
+    "mgx_station_episodes": (I32, [P, P, P]),
 }
 
 _lib = None
@@ -471,6 +487,8 @@ class Batch:
     def close(self):
         for g in list(getattr(self, "_graphs", [])):
             g.close()
+        for t in list(getattr(self, "_stations", [])):
+            t.close()
         if getattr(self, "h", None):
             mgx_batch_destroy(self.h)
             self.h = None
@@ -650,6 +668,132 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------------------- station keeping
+
+class Station:
+    """Station-keeping task on a batch (``mgx_station_*`` in include/mgx.h). Outputs are
+    flat device tensors in the batch layout; ``VecStationKeeping`` gives the Gym-style view
+    of a one-class batch. ``desc`` overrides fields of ``STATION_DEFAULTS``."""
+
+    def __init__(self, batch, **desc):
+        unknown = set(desc) - set(STATION_DEFAULTS)
+        if unknown:
+            raise TypeError(f"unknown station fields {sorted(unknown)}")
+        self.batch = batch
+        self.desc = dict(STATION_DEFAULTS, **desc)
+        cd = StationDesc(**self.desc)
+        h = P()
+        _call("mgx_station_create", batch.h, ctypes.byref(cd), ctypes.byref(h))
+        self.h = h
+        batch.__dict__.setdefault("_stations", []).append(self)
+        self.pad_off = [int(x) for x in np.concatenate([[0], np.cumsum(batch.n_pad)])[:-1]]
+
+    def _check(self, t, n, dtype=None):
+        b = self.batch
+        assert t.device == b.device and t.is_contiguous() and t.numel() == n, "buffer shape/device"
+        assert dtype is None or t.dtype == dtype, "buffer dtype"
+
+    def empty_outputs(self, n_steps, final_obs=True):
+        torch = _torch()
+        b, L = self.batch, self.batch.layout
+        out = {"obs": torch.zeros((n_steps, L.state_elems), dtype=b.dtype, device=b.device),
+               "reward": torch.zeros((n_steps, L.n_pad_total), dtype=b.dtype, device=b.device),
+               "terminated": torch.zeros((n_steps, L.n_pad_total), dtype=torch.uint8, device=b.device),
+               "truncated": torch.zeros((n_steps, L.n_pad_total), dtype=torch.uint8, device=b.device)}
+        if final_obs:
+            out["final_obs"] = torch.zeros((n_steps, L.state_elems), dtype=b.dtype, device=b.device)
+        return out
+
+    def reset(self, seed, obs=None):
+        """Episode 0 of every environment; returns the first observations (flat layout)."""
+        if obs is None:
+            obs = self.batch.empty_state()
+        self._check(obs, self.batch.layout.state_elems, self.batch.dtype)
+        _call("mgx_station_reset", self.h, int(seed), _ptr(obs))
+        return obs
+
+    def step(self, actions, out=None):
+        """``actions``: [n_steps, row_elems] device tensor; one task step per row. Returns
+        ``out`` (``empty_outputs(n_steps)`` if None), row k holding step k's results."""
+        b, L = self.batch, self.batch.layout
+        n = actions.shape[0]
+        self._check(actions, n * L.row_elems, b.dtype)
+        if out is None:
+            out = self.empty_outputs(n)
+        self._check(out["obs"], n * L.state_elems, b.dtype)
+        self._check(out["reward"], n * L.n_pad_total, b.dtype)
+        self._check(out["terminated"], n * L.n_pad_total)
+        self._check(out["truncated"], n * L.n_pad_total)
+        fo = out.get("final_obs")
+        if fo is not None:
+            self._check(fo, n * L.state_elems, b.dtype)
+        _call("mgx_station_step", self.h, _ptr(actions), n, _ptr(out["obs"]), _ptr(out["reward"]),
+              _ptr(out["terminated"]), _ptr(out["truncated"]), _ptr(fo))
+        return out
+
+    def per_env(self, flat):
+        """[..., n_pad_total] -> per class [..., n] (padding dropped)."""
+        return [flat[..., o:o + n] for o, n in zip(self.pad_off, self.batch.n)]
+
+    def episodes(self):
+        """(episode index, steps taken in it) per global env id, numpy int32."""
+        N = self.batch.layout.n_total
+        ep, st = np.zeros(N, np.int32), np.zeros(N, np.int32)
+        _call("mgx_station_episodes", self.h, ep.ctypes.data_as(ctypes.c_void_p), st.ctypes.data_as(ctypes.c_void_p))
+        return ep, st
+
+    def close(self):
+        if getattr(self, "h", None):
+            _call("mgx_station_destroy", self.h)
+            self.h = None
+            ts = self.batch.__dict__.get("_stations", [])
+            if self in ts:
+                ts.remove(self)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class VecStationKeeping:
+    """Gym-style vector environment: ``n`` station-keeping environments of one vehicle class
+    stepped together on the device. ``reset(seed)`` -> (obs [n, 13+m], {}); ``step(actions
+    [n, m])`` -> (obs, reward [n], terminated [n] bool, truncated [n] bool,
+    {"final_obs": [n, 13+m]}). Episodes that end restart in the same step. Returned tensors
+    are views of device buffers that the next call overwrites."""
+
+    def __init__(self, cls, params, n, dt=0.01, precision=FP32, device=0, **desc):
+        self.batch = Batch([cls], [n], dt, precision, device=device)
+        self.batch.set_params(params)
+        self.task = Station(self.batch, **desc)
+        self.num_envs, self.m = n, cls.m
+        self.single_observation_shape = (STATE_FIXED + cls.m,)
+        self.single_action_shape = (cls.m,)
+        self.action_low, self.action_high = -1.0, 1.0
+        self._act = self.batch.empty_actions(1)
+        self._out = self.task.empty_outputs(1)
+
+    def _view(self, flat):
+        return flat.view(-1, self.batch.n_pad[0])[:, :self.num_envs].t()
+
+    def reset(self, seed=0):
+        self.task.reset(seed, self._out["obs"][0])
+        return self._view(self._out["obs"][0]), {}
+
+    def step(self, actions):
+        n = self.num_envs
+        self._act[0].view(self.m, self.batch.n_pad[0])[:, :n].copy_(actions.t())
+        o = self.task.step(self._act, self._out)
+        return (self._view(o["obs"][0]), o["reward"][0, :n], o["terminated"][0, :n].bool(),
+                o["truncated"][0, :n].bool(), {"final_obs": self._view(o["final_obs"][0])})
+
+    def close(self):
+        self.task.close()
+        self.batch.close()
 
 
 # ----------------------------------------------------------------------------- serving

@@ -98,6 +98,12 @@ def test_null_batch_calls_are_rejected():
     L = mgx.lib()
     assert L.mgx_batch_step(None, None, 1, 0, 1, 1, 0, None, None) == mgx.MGX_E_INVALID
     assert L.mgx_batch_destroy(None) == mgx.MGX_OK
+    d = mgx.StationDesc(**mgx.STATION_DEFAULTS)
+    h = ctypes.c_void_p()
+    assert L.mgx_station_create(None, ctypes.byref(d), ctypes.byref(h)) == mgx.MGX_E_INVALID
+    assert L.mgx_station_step(None, None, 1, None, None, None, None, None) == mgx.MGX_E_INVALID
+    assert L.mgx_station_reset(None, 0, None) == mgx.MGX_E_INVALID
+    assert L.mgx_station_destroy(None) == mgx.MGX_OK
 
 
 def test_binding_structures_match_the_header(tmp_path):
@@ -107,7 +113,8 @@ def test_binding_structures_match_the_header(tmp_path):
              "mgx_dr_dist": mgx.DrDist, "mgx_dr_spec": mgx.DrSpec,
              "mgx_env_params": mgx.EnvParams, "mgx_stats": mgx.Stats, "mgx_launch_shape": mgx.LaunchShape,
              "mgx_server_desc": mgx.ServerDesc, "mgx_request": mgx.Request,
-             "mgx_request_status": mgx.RequestStatus, "mgx_server_stats": mgx.ServerStats}
+             "mgx_request_status": mgx.RequestStatus, "mgx_server_stats": mgx.ServerStats,
+             "mgx_station_desc": mgx.StationDesc}
     src = tmp_path / "sizes.c"
     body = "".join(f'    printf("{n} %zu\\n", sizeof({n}));\n' for n in pairs)
     src.write_text(f'#include <stdio.h>\n#include "mgx.h"\nint main(void) {{\n{body}    return 0;\n}}\n')

@@ -1,0 +1,244 @@
+"""Station-keeping task on the device against the task oracle (``oracle/station.py``),
+through the C ABI: episode start draws, observations, rewards, termination and truncation
+flags, same-step auto-reset and episode counters, for one class and for a mixed batch,
+with substeps, for the shaped, fin and payload bodies, and in float32 and float64.
+
+Termination is decided in the batch precision on the device and in double in the oracle.
+An environment whose oracle distance, lean or attitude-error sign comes within `margin` of
+a threshold is compared up to that step only (both decisions are correct there); the
+others are compared step by step over whole rollouts, including every reset."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import station as S
+from paper_2503_09203_amd import mgx
+
+from gpu_helpers import make_batch, oracle_inputs, torch
+
+pytestmark = pytest.mark.gpu
+
+DESC = dict(target_box=2.0, tilt0=0.3, v0=0.1, sigma_p=0.5, w_att=0.5, w_act=0.01, d_max=2.6, tilt_max=0.6,
+            max_steps=40, substeps=1)
+
+
+def run_both(w, desc, T, precision=mgx.FP32, seed=7, act_seed=3):
+    """T task steps on the device and in the oracle with the same commands. Returns per
+    class a list of per-step dicts with both sides' results."""
+    t = torch()
+    b = make_batch(w, precision)
+    st = mgx.Station(b, **desc)
+    obs0 = st.reset(seed).cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(act_seed)
+    acts = [rng.uniform(-1.2, 1.2, size=(T, c.m, n)).astype(np.float32) for c, n in zip(w.classes, w.n_envs)]
+    dev_acts = t.tensor(b.pack_actions(acts), dtype=b.dtype, device=b.device)
+    out = st.step(dev_acts)
+    t.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    ep_dev, et_dev = st.episodes()
+    st.close()
+    b.close()
+    res = []
+    off = 0
+    for c, (cls, n) in enumerate(zip(w.classes, w.n_envs)):
+        envs = oracle_inputs(w)[c][0]
+        o = S.StationOracle(S.StationDesc(**desc), envs, cls.m, env_off=off)
+        steps = [{"obs_dev": b.unpack_state(obs0)[c].T, "obs_ref": o.reset(seed)}]
+        for k in range(T):
+            obs, r, term, trunc, final = o.step(acts[c][k].T.astype(np.float64))
+            pad = sum(b.n_pad[:c])
+            steps.append({
+                "obs_dev": b.unpack_state(g["obs"][k].astype(np.float64))[c].T, "obs_ref": obs,
+                "final_dev": b.unpack_state(g["final_obs"][k].astype(np.float64))[c].T, "final_ref": final,
+                "r_dev": g["reward"][k, pad:pad + n].astype(np.float64), "r_ref": r,
+                "term_dev": g["terminated"][k, pad:pad + n].astype(bool), "term_ref": term,
+                "trunc_dev": g["truncated"][k, pad:pad + n].astype(bool), "trunc_ref": trunc})
+        res.append({"steps": steps, "ep_dev": ep_dev[off:off + n], "et_dev": et_dev[off:off + n],
+                    "ep_ref": o.episode.copy(), "et_ref": o.t.copy()})
+        off += n
+    return res
+
+
+def ambiguous(obs, desc, margin):
+    """Environments whose observation lies within `margin` of a decision: distance against
+    d_max, lean against tilt_max (R_zz of the state equals that of the attitude error, the
+    target being a pure yaw), or the error quaternion's scalar part against 0 (its sign)."""
+    d = np.linalg.norm(obs[:, 0:3], axis=1)
+    up = 1.0 - 2.0 * (obs[:, 4] ** 2 + obs[:, 5] ** 2)
+    return ((np.abs(d - desc["d_max"]) < margin) | (np.abs(up - np.cos(desc["tilt_max"])) < margin)
+            | (np.abs(obs[:, 3]) < margin))
+
+
+def rel_err(dev, ref, ok):
+    if not ok.any():
+        return 0.0
+    d, r = dev[ok], ref[ok]
+    rms = np.sqrt(np.mean(r * r, axis=0))
+    return float(np.max(np.abs(d - r) / np.maximum(np.abs(r), np.maximum(rms, 1e-30))))
+
+
+def check(res, desc, tol, margin, min_compared=0.5, name=""):
+    stats = {"resets": 0, "terminated": 0}
+    for cres in res:
+        steps = cres["steps"]
+        ok = ~ambiguous(steps[0]["obs_ref"], desc, margin)
+        assert rel_err(steps[0]["obs_dev"], steps[0]["obs_ref"], ok) <= tol, f"{name} reset obs"
+        for k, s in enumerate(steps[1:], 1):
+            ok &= ~ambiguous(s["final_ref"], desc, margin) & ~ambiguous(s["obs_ref"], desc, margin)
+            assert np.array_equal(s["term_dev"][ok], s["term_ref"][ok]), f"{name} terminated at step {k}"
+            assert np.array_equal(s["trunc_dev"][ok], s["trunc_ref"][ok]), f"{name} truncated at step {k}"
+            e_obs = rel_err(s["obs_dev"], s["obs_ref"], ok)
+            e_fin = rel_err(s["final_dev"], s["final_ref"], ok)
+            e_r = float(np.max(np.abs(s["r_dev"][ok] - s["r_ref"][ok]), initial=0.0))
+            assert e_obs <= tol and e_fin <= tol and e_r <= tol, f"{name} step {k}: {e_obs} {e_fin} {e_r}"
+            stats["resets"] += int(np.sum((s["term_ref"] | s["trunc_ref"])[ok]))
+            stats["terminated"] += int(np.sum(s["term_ref"][ok]))
+        assert np.array_equal(cres["ep_dev"][ok], cres["ep_ref"][ok]), name
+        assert np.array_equal(cres["et_dev"][ok], cres["et_ref"][ok]), name
+        assert ok.mean() >= min_compared, f"{name}: only {ok.mean():.2f} of the environments compared"
+    return stats
+
+
+@pytest.mark.parametrize("precision,tol,margin", [(mgx.FP32, 2e-4, 2e-3), (mgx.FP64, 1e-9, 1e-7)])
+def test_reset_draws_match_the_oracle(precision, tol, margin):
+    w = synth.plain_small(n=1000)  # 1000: a ragged last wave
+    t = torch()
+    b = make_batch(w, precision)
+    st = mgx.Station(b, **DESC)
+    obs = st.reset(123).cpu().numpy().astype(np.float64)
+    state = b.get_state().cpu().numpy().astype(np.float64)
+    ref_s, ref_t = S.episode_start(S.StationDesc(**DESC), 123, np.arange(1000), 0, 6)
+    dt = np.float32 if precision == mgx.FP32 else np.float64
+    dev_s = b.unpack_state(state)[0]
+    # the start state is the double draw rounded once. The device and host sine and cosine
+    # may each round differently by an ulp; in the quaternion (sums of products of them,
+    # with cancellation in the small components) that shows at the scale of the unit norm
+    ref = ref_s[:, :19].T
+    scale = np.abs(ref)
+    scale[3:7] = 1.0
+    ulp = np.spacing(scale.astype(dt)).astype(np.float64)
+    assert np.all(np.abs(dev_s - ref) <= (2 if dt is np.float32 else 8) * ulp)
+    assert np.array_equal(dev_s[7:13], ref[7:13].astype(dt))   # velocities: no transcendental
+    ref_o = S.observe(ref_s, ref_t, 6)
+    assert rel_err(b.unpack_state(obs)[0].T, ref_o, ~ambiguous(ref_o, DESC, margin)) <= tol
+    ep, et = st.episodes()
+    assert not ep.any() and not et.any()
+    st.close()
+    b.close()
+    t.cuda.synchronize()
+
+
+@pytest.mark.parametrize("precision,tol,margin", [(mgx.FP32, 2e-4, 2e-3), (mgx.FP64, 1e-9, 1e-7)])
+def test_rollout_with_resets_matches_the_oracle(precision, tol, margin):
+    """1000 environments, 120 task steps: truncation every 40 steps, terminations by
+    distance (targets up to 3.5 m away, d_max 2.6) and by lean (commands up to 1.2, lean
+    limit 0.6 rad), each followed by the next episode's draw."""
+    w = synth.randomised(n=1000, steps=10)
+    res = run_both(w, DESC, 120, precision)
+    stats = check(res, DESC, tol, margin, name=f"plain {precision}")
+    assert stats["terminated"] > 100 and stats["resets"] > 2000, stats
+
+
+def test_mixed_batch_with_substeps():
+    """Five classes (4, 5, 6, 8, 8 thrusters) in one batch, three dynamics steps per task
+    step: slots, per-class constants and the held command."""
+    w = synth.heterogeneous(scale=0.02, steps=10)
+    desc = dict(DESC, substeps=3, max_steps=25)
+    res = run_both(w, desc, 60)
+    check(res, desc, 3e-4, 2e-3, name="mixed")
+
+
+@pytest.mark.parametrize("make", ["propellers", "rudders", "payload"])
+def test_variant_bodies(make):
+    w = getattr(synth, make)(n=700, steps=10)
+    desc = dict(DESC, max_steps=30)
+    res = run_both(w, desc, 45)
+    check(res, desc, 5e-4, 2e-3, name=make)
+
+
+def test_vector_env_interface():
+    """The Gym-style view: shapes and dtypes, the same numbers as the flat interface, a
+    repeatable reset, and final observations on truncation."""
+    t = torch()
+    w = synth.plain_small(n=300)
+    cls = w.classes[0]
+    env = mgx.VecStationKeeping(cls, w.params, 300, w.dt, **dict(DESC, max_steps=3, d_max=100.0, tilt_max=3.0))
+    obs, info = env.reset(seed=5)
+    assert obs.shape == (300, 19) and obs.dtype == t.float32 and info == {}
+    first = obs.clone()
+    a = t.full((300, 6), 0.25, device=obs.device)
+    for k in range(3):
+        obs, r, term, trunc, info = env.step(a)
+        assert r.shape == (300,) and term.dtype == t.bool and trunc.shape == (300,)
+        assert not term.any() and bool(trunc.all()) == (k == 2)
+    # after truncation every environment is in episode 1; final_obs is the episode's last
+    ep, et = env.task.episodes()
+    assert (ep == 1).all() and (et == 0).all()
+    envs = oracle.make_envs(cls, w.params, w.dt)
+    o = S.StationOracle(S.StationDesc(**dict(DESC, max_steps=3, d_max=100.0, tilt_max=3.0)), envs, 6)
+    o.reset(5)
+    for _ in range(3):
+        ro, rr, _, _, rf = o.step(np.full((300, 6), 0.25))
+    assert np.max(np.abs(info["final_obs"].cpu().numpy() - rf)) < 1e-4
+    assert np.max(np.abs(obs.cpu().numpy() - ro)) < 1e-5
+    obs2, _ = env.reset(seed=5)
+    assert t.equal(obs2, first)
+    env.close()
+
+
+def test_full_size_sampled():
+    """65,536 environments of the randomised workload, 200 task steps (five episodes each
+    by truncation, plus terminations); 256 sampled environments against the oracle."""
+    t = torch()
+    w = synth.randomised(n=65536, steps=10)
+    desc = dict(DESC, max_steps=40)
+    b = make_batch(w)
+    st = mgx.Station(b, **desc)
+    st.reset(99)
+    T = 200
+    acts = b.gen_actions(T, seed=17)
+    out = st.step(acts)
+    t.cuda.synchronize()
+    rng = np.random.default_rng(4)
+    ids = np.sort(rng.choice(65536, 256, replace=False))
+    ids[0], ids[-1] = 0, 65535
+    envs = oracle.make_envs(w.classes[0], w.params.subset(ids), w.dt)
+    o = S.StationOracle(S.StationDesc(**desc), envs, 6, ids=ids)
+    o.reset(99)
+    host_acts = b.unpack_actions(acts.cpu().numpy().astype(np.float64))[0]   # [T, m, n]
+    obs_all = out["obs"].cpu().numpy().astype(np.float64)
+    rew = out["reward"].cpu().numpy().astype(np.float64)
+    term = out["terminated"].cpu().numpy().astype(bool)
+    ok = np.ones(ids.size, bool)
+    n_reset = 0
+    for k in range(T):
+        ro, rr, rt, rtr, rf = o.step(host_acts[k][:, ids].T)
+        ok &= ~ambiguous(rf, desc, 2e-3) & ~ambiguous(ro, desc, 2e-3)
+        dev_o = b.unpack_state(obs_all[k])[0][:, ids].T
+        assert np.array_equal(term[k, ids][ok], rt[ok]), k
+        assert rel_err(dev_o, ro, ok) <= 2e-4, k
+        assert np.max(np.abs(rew[k, ids][ok] - rr[ok]), initial=0) <= 2e-4, k
+        n_reset += int(np.sum((rt | rtr)[ok]))
+    assert ok.mean() > 0.5 and n_reset > 5 * 0.5 * ids.size
+    st.close()
+    b.close()
+
+
+def test_errors():
+    t = torch()
+    w = synth.plain_small(n=64)
+    b = make_batch(w)
+    with pytest.raises(mgx.MgxError):
+        mgx.Station(b, **dict(DESC, sigma_p=0.0))
+    with pytest.raises(mgx.MgxError):
+        mgx.Station(b, **dict(DESC, substeps=0))
+    st = mgx.Station(b, **DESC)
+    with pytest.raises(mgx.MgxError):      # before reset
+        st.step(b.empty_actions(1))
+    st.reset(1)
+    with pytest.raises(mgx.MgxError):      # the batch outlives its task
+        mgx.mgx_batch_destroy(b.h)
+    st.close()
+    b.close()
+    t.cuda.synchronize()
