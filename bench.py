@@ -656,9 +656,10 @@ def station(args):
     elapsed = e0.elapsed_time(e1) * 1e-3
     per_launch = elapsed / (reps * CH)
     m, P = c.m, 4
-    # state read and written, record, target, command, observation and pre-reset observation,
-    # reward, two flag bytes, episode index and step count read and written
-    bytes_es = P * (2 * (13 + m) + 30 + 7 + m + 2 * (13 + m) + 1) + 2 + 4 * 4
+    # state read and written, record, target, command, observation, reward, two flag bytes,
+    # episode index and step count read and written (the pre-reset observation and the new
+    # target of an ended episode are written for the few environments that end)
+    bytes_es = P * (2 * (13 + m) + 30 + 7 + m + (13 + m) + 1) + 2 + 4 * 4
     ep, _ = st.episodes()
 
     # parity: 256 sampled environments over one call of 100 task steps from a fresh reset

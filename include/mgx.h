@@ -430,7 +430,7 @@ mgx_status mgx_graph_destroy(mgx_graph* g);
  *   tilt_max from the world z axis. truncated: the episode has taken max_steps task steps.
  *   An episode that ends restarts as episode k + 1 in the same step: obs is then the new
  *   episode's first observation; final_obs holds the observation of the state the
- *   transition ended in. */
+ *   transition ended in, for the environments whose episode ended. */
 typedef struct mgx_station mgx_station;
 
 typedef struct {
@@ -460,7 +460,8 @@ mgx_status mgx_station_reset(mgx_station* s, uint64_t seed, void* obs);
 /* n_steps >= 1 task steps (n_steps launches per class; a Gym step is n_steps = 1). Step k
  * reads command row k of `actions` (device, n_steps rows of row_elems, the batch's action
  * layout and precision) and writes row k of every output, all device memory:
- *   obs, final_obs: [n_steps][state_elems], the batch's state layout (final_obs may be NULL);
+ *   obs, final_obs: [n_steps][state_elems], the batch's state layout (final_obs may be NULL;
+ *   only the entries of environments whose episode ended at that step are written);
  *   reward: [n_steps][n_pad_total], batch precision; terminated, truncated:
  *   [n_steps][n_pad_total] bytes (0 / 1). Environment e of class c sits at slot
  *   sum_{c' < c} n_pad[c'] + e; padded slots get reward 0 and flags 0.

@@ -35,7 +35,7 @@ struct StationArgs {
     int32_t* ep;         // [npad] episode index
     int32_t* et;         // [npad] steps taken in the episode
     T* obs;              // [13+m][npad]
-    T* final_obs;        // [13+m][npad] or NULL
+    T* final_obs;        // [13+m][npad] or NULL; written for lanes whose episode ended
     T* reward;           // [npad]
     uint8_t* term;       // [npad]
     uint8_t* trunc;      // [npad]
@@ -156,77 +156,145 @@ __global__ void __launch_bounds__(256) k_station_start(StationArgs<T> A) {
     if (A.obs) write_obs<T, M>(A.obs, np, env, s, tg);
 }
 
+// Restarts of the lanes in `need` (a mask over the wave), one lane at a time with its draw
+// spread over the wave: lane j < 7 runs generator call j, lanes 1..4 each take one sine and
+// cosine, and lane shuffles bring the values to the restarting lane. The arithmetic is
+// that of episode_draw, value for value. A step ends few episodes per wave, and each then
+// costs a few hundred instructions of the wave instead of the draw's serial chain of about
+// a thousand (seven generator calls, eight double-precision sines and cosines), which
+// would hold the whole wave, and so the launch, at one wave per SIMD.
+constexpr int kSpreadRestarts = 3;
+
+template <typename T, int M>
+__device__ __forceinline__ void restart_spread(const StationConsts& P, uint64_t need, uint32_t g, uint32_t k,
+                                               StateT<T, M>& s, T tg[7]) {
+    const int lane = __lane_id();
+    while (need) {
+        const int src = __ffsll((unsigned long long)need) - 1;
+        need &= need - 1;
+        uint32_t c[4] = {__shfl(g, src), __shfl(k, src), (uint32_t)(lane < 7 ? lane : 0), 0u};
+        philox4x32_10(c, (uint32_t)P.seed, kStreamTask << 24);
+        const double a = 2.0 * u53(c[0], c[1]) - 1.0;  // 2 u[2j] - 1 on lane j
+        const double b = 2.0 * u53(c[2], c[3]) - 1.0;  // 2 u[2j+1] - 1
+        const double b2 = __shfl(b, 2);
+        // half-angles: target yaw (u3), yaw (u4), pitch (u6), roll (u5)
+        const double ang = lane == 1   ? 0.5 * (M_PI * b)
+                           : lane == 2 ? 0.5 * (M_PI * a)
+                           : lane == 3 ? 0.5 * (P.tilt0 * a)
+                                       : 0.5 * (P.tilt0 * b2);
+        const double cs = cos(ang), sn = sin(ang);
+        const double scale = lane < 2 ? P.box : P.v0;  // target position on lanes 0-1, velocities on 3-6
+        const double xa = scale * a, xb = scale * b;
+        const double px = __shfl(xa, 0), py = __shfl(xb, 0), pz = __shfl(xa, 1);
+        const double ct = __shfl(cs, 1), st = __shfl(sn, 1);
+        const double cy = __shfl(cs, 2), sy = __shfl(sn, 2), cp = __shfl(cs, 3), sp = __shfl(sn, 3);
+        const double cr = __shfl(cs, 4), sr = __shfl(sn, 4);
+        const double v[6] = {__shfl(xb, 3), __shfl(xa, 4), __shfl(xb, 4), __shfl(xa, 5), __shfl(xb, 5), __shfl(xa, 6)};
+        if (lane == src) {
+            tg[0] = (T)px;
+            tg[1] = (T)py;
+            tg[2] = (T)pz;
+            tg[3] = (T)ct;
+            tg[4] = T(0);
+            tg[5] = T(0);
+            tg[6] = (T)st;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) s.p[j] = T(0);
+            s.q[0] = (T)(cy * cp * cr + sy * sp * sr);
+            s.q[1] = (T)(cy * cp * sr - sy * sp * cr);
+            s.q[2] = (T)(cy * sp * cr + sy * cp * sr);
+            s.q[3] = (T)(sy * cp * cr - cy * sp * sr);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) s.nu[j] = (T)v[j];
+#pragma unroll
+            for (int i = 0; i < M; ++i) s.n[i] = T(0);
+        }
+    }
+}
+
 // One task step of one class segment.
 template <typename T, int M, bool kShaped, bool kFins, bool kPayload>
 __global__ void __launch_bounds__(256) k_station_step(StationLaunch<T> L) {
     const StationArgs<T>& A = L.a;
     const int64_t env = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (env >= A.npad) return;
+    if (env >= A.npad) return;  // whole waves: a segment holds a multiple of the wave size
     const int64_t np = A.npad;
     StateT<T, M> s;
     load_state<T, M>(A.state, np, env, s);
     T tg[7];
 #pragma unroll
     for (int j = 0; j < 7; ++j) tg[j] = A.tgt[j * np + env];
-    if (env >= A.nvalid) {  // padding: no dynamics, no reward
-        write_obs<T, M>(A.obs, np, env, s, tg);
-        if (A.final_obs) write_obs<T, M>(A.final_obs, np, env, s, tg);
-        A.reward[env] = T(0);
-        A.term[env] = 0;
-        A.trunc[env] = 0;
-        return;
-    }
-    const ClassT<T> C = class_in_vgpr<T, M, kFins>(L.cls);
-    EnvT<T> E;
-    load_record<T, kPayload>(A.rec, np, env, C.flags, E);
-    T a[M];
+    // padding lanes take no step and report nothing, but stay in the wave for the restarts
+    const bool valid = env < A.nvalid;
+    T r = T(0);
+    bool term = false, trunc = false;
+    int32_t ep = 0, et = 0;
+    if (valid) {
+        const ClassT<T> C = class_in_vgpr<T, M, kFins>(L.cls);
+        EnvT<T> E;
+        load_record<T, kPayload>(A.rec, np, env, C.flags, E);
+        T a[M];
 #pragma unroll
-    for (int i = 0; i < M; ++i) a[i] = clip1(A.act[i * np + env]);
-    int32_t ep = A.ep[env], et = A.et[env];
-    T IA2[3], Brb[3];
-    env_prologue<T, kPayload>(C, E, IA2, Brb);
-    for (int k = 0; k < A.P.substeps; ++k) step_body<T, M, false, kShaped, kFins, kPayload>(C, E, IA2, Brb, s, a);
-    float st[kStats];  // launch statistics are not kept by the task
-    renorm_attitude<T, M>(s, st);
+        for (int i = 0; i < M; ++i) a[i] = clip1(A.act[i * np + env]);
+        ep = A.ep[env];
+        et = A.et[env];
+        T IA2[3], Brb[3];
+        env_prologue<T, kPayload>(C, E, IA2, Brb);
+        for (int k = 0; k < A.P.substeps; ++k)
+            step_body<T, M, false, kShaped, kFins, kPayload>(C, E, IA2, Brb, s, a);
+        float st[kStats];  // launch statistics are not kept by the task
+        renorm_attitude<T, M>(s, st);
 
-    // reward and termination on the state the transition ends in
-    bool fin = true;
+        // reward and termination on the state the transition ends in
+        bool fin = true;
 #pragma unroll
-    for (int j = 0; j < 3; ++j) fin &= finite_(s.p[j]);
+        for (int j = 0; j < 3; ++j) fin &= finite_(s.p[j]);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) fin &= finite_(s.q[j]);
+        for (int j = 0; j < 4; ++j) fin &= finite_(s.q[j]);
 #pragma unroll
-    for (int j = 0; j < 6; ++j) fin &= finite_(s.nu[j]);
+        for (int j = 0; j < 6; ++j) fin &= finite_(s.nu[j]);
 #pragma unroll
-    for (int i = 0; i < M; ++i) fin &= finite_(s.n[i]);
-    const T d0 = tg[0] - s.p[0], d1 = tg[1] - s.p[1], d2 = tg[2] - s.p[2];
-    const T d = sqrt_(d0 * d0 + d1 * d1 + d2 * d2);
-    T e[4];
-    attitude_error(s.q, tg + 3, e);
-    T a2 = T(0);
+        for (int i = 0; i < M; ++i) fin &= finite_(s.n[i]);
+        const T d0 = tg[0] - s.p[0], d1 = tg[1] - s.p[1], d2 = tg[2] - s.p[2];
+        const T d = sqrt_(d0 * d0 + d1 * d1 + d2 * d2);
+        T e[4];
+        attitude_error(s.q, tg + 3, e);
+        T a2 = T(0);
 #pragma unroll
-    for (int i = 0; i < M; ++i) a2 += a[i] * a[i];
-    const T up = T(1) - T(2) * (s.q[1] * s.q[1] + s.q[2] * s.q[2]);
-    T r = exp_(-d * (T)A.P.inv_sigma) - (T)A.P.w_att * (T(1) - e[0] * e[0]) - (T)A.P.w_act_m * a2;
-    const bool term = !fin || d > (T)A.P.d_max || up < (T)A.P.cos_tilt;
-    if (!fin) r = T(0);
-    ++et;
-    const bool trunc = et >= A.P.max_steps;
-    if (A.final_obs) write_obs<T, M>(A.final_obs, np, env, s, tg);
-    if (term || trunc) {
+        for (int i = 0; i < M; ++i) a2 += a[i] * a[i];
+        const T up = T(1) - T(2) * (s.q[1] * s.q[1] + s.q[2] * s.q[2]);
+        r = exp_(-d * (T)A.P.inv_sigma) - (T)A.P.w_att * (T(1) - e[0] * e[0]) - (T)A.P.w_act_m * a2;
+        term = !fin || d > (T)A.P.d_max || up < (T)A.P.cos_tilt;
+        if (!fin) r = T(0);
+        ++et;
+        trunc = et >= A.P.max_steps;
+    }
+    const bool done = term || trunc;
+    if (done) {
+        if (A.final_obs) write_obs<T, M>(A.final_obs, np, env, s, tg);
         ++ep;
         et = 0;
-        start_state<T, M>(A.P, (uint64_t)(A.env_off + env), (uint32_t)ep, s, tg);
-#pragma unroll
-        for (int j = 0; j < 7; ++j) A.tgt[j * np + env] = tg[j];
     }
-    store_state<T, M>(A.state, np, env, s);
+    const uint64_t need = __ballot(done);
+    if (need) {
+        if (__popcll(need) <= kSpreadRestarts)
+            restart_spread<T, M>(A.P, need, (uint32_t)(A.env_off + env), (uint32_t)ep, s, tg);
+        else if (done)
+            start_state<T, M>(A.P, (uint64_t)(A.env_off + env), (uint32_t)ep, s, tg);
+        if (done) {
+#pragma unroll
+            for (int j = 0; j < 7; ++j) A.tgt[j * np + env] = tg[j];
+        }
+    }
     write_obs<T, M>(A.obs, np, env, s, tg);
     A.reward[env] = r;
     A.term[env] = term ? 1 : 0;
     A.trunc[env] = trunc ? 1 : 0;
-    A.ep[env] = ep;
-    A.et[env] = et;
+    if (valid) {
+        store_state<T, M>(A.state, np, env, s);
+        A.ep[env] = ep;
+        A.et[env] = et;
+    }
 }
 
 template <typename T, int M>

@@ -763,8 +763,9 @@ class VecStationKeeping:
     """Gym-style vector environment: ``n`` station-keeping environments of one vehicle class
     stepped together on the device. ``reset(seed)`` -> (obs [n, 13+m], {}); ``step(actions
     [n, m])`` -> (obs, reward [n], terminated [n] bool, truncated [n] bool,
-    {"final_obs": [n, 13+m]}). Episodes that end restart in the same step. Returned tensors
-    are views of device buffers that the next call overwrites."""
+    {"final_obs": [n, 13+m]}). Episodes that end restart in the same step; final_obs rows
+    are meaningful where terminated or truncated is set (the pre-reset observation). Returned
+    tensors are views of device buffers that the next call overwrites."""
 
     def __init__(self, cls, params, n, dt=0.01, precision=FP32, device=0, **desc):
         self.batch = Batch([cls], [n], dt, precision, device=device)

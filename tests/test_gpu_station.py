@@ -89,7 +89,9 @@ def check(res, desc, tol, margin, min_compared=0.5, name=""):
             assert np.array_equal(s["term_dev"][ok], s["term_ref"][ok]), f"{name} terminated at step {k}"
             assert np.array_equal(s["trunc_dev"][ok], s["trunc_ref"][ok]), f"{name} truncated at step {k}"
             e_obs = rel_err(s["obs_dev"], s["obs_ref"], ok)
-            e_fin = rel_err(s["final_dev"], s["final_ref"], ok)
+            # the pre-reset observation is written for the environments that ended
+            ended = ok & (s["term_ref"] | s["trunc_ref"])
+            e_fin = rel_err(s["final_dev"], s["final_ref"], ended)
             e_r = float(np.max(np.abs(s["r_dev"][ok] - s["r_ref"][ok]), initial=0.0))
             assert e_obs <= tol and e_fin <= tol and e_r <= tol, f"{name} step {k}: {e_obs} {e_fin} {e_r}"
             stats["resets"] += int(np.sum((s["term_ref"] | s["trunc_ref"])[ok]))
@@ -138,6 +140,17 @@ def test_rollout_with_resets_matches_the_oracle(precision, tol, margin):
     res = run_both(w, DESC, 120, precision)
     stats = check(res, DESC, tol, margin, name=f"plain {precision}")
     assert stats["terminated"] > 100 and stats["resets"] > 2000, stats
+
+
+def test_every_step_restarts():
+    """Episodes of one step: every lane restarts at every step, so whole waves take the
+    per-lane draw (the rollout tests take the wave-spread draw for scattered terminations
+    and the per-lane one at the synchronised truncations)."""
+    w = synth.randomised(n=1000, steps=10)
+    desc = dict(DESC, max_steps=1)
+    res = run_both(w, desc, 6)
+    stats = check(res, desc, 2e-4, 2e-3, name="one-step episodes")
+    assert stats["resets"] >= 0.9 * 6 * 1000
 
 
 def test_mixed_batch_with_substeps():
