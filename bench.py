@@ -730,14 +730,19 @@ def station(args):
 
 def counter_launches(args):
     """Six plain launches of the step kernel (no graph) for counter passes: K = 16 four
-    times, then K = 1000 twice, at N environments of the randomised workload."""
+    times, then K = 1000 twice, at N environments of the chosen single-class workload
+    (the randomised one by default)."""
     import torch
 
     import synth
     from paper_2503_09203_amd import mgx
 
     N, HOLD = args.n, 10
-    w = synth.randomised(n=N, steps=1000)
+    make = {"dr": synth.randomised, "propellers": synth.propellers, "rudders": synth.rudders,
+            "payload": synth.payload}.get(args.workload)
+    if make is None:
+        raise SystemExit("--counter-launches takes the dr, propellers, rudders or payload workload")
+    w = make(n=N, steps=1000)
     b = mgx.Batch(w.classes, [N], w.dt)
     b.set_params(w.params)
     init = torch.tensor(b.pack_state([w.state[0].stacked()]), dtype=torch.float32, device="cuda:0")
