@@ -283,10 +283,18 @@ def main():
         cpu_elapsed = time.perf_counter() - tc
         ref = oracle.unpack_state(st_s, cls.m)
         err = parity_errors(final_state[:, idx], ref)
-        out["cpu_baseline"] = {"value": n_s * T / cpu_elapsed, "unit": "env-steps/s", "cores": oracle.get_threads(),
-                               "kind": "oracle",
+        # the same oracle on one thread, over the first 256 of the sample
+        threads = oracle.get_threads()
+        oracle.set_threads(1)
+        t1 = time.perf_counter()
+        oracle.rollout(envs_all[idx[:256]], full_state[idx[:256]].copy(), oracle.pack_actions(a_host[:, :, idx[:256]]),
+                       HOLD, T)
+        rate_1 = 256 * T / (time.perf_counter() - t1)
+        oracle.set_threads(threads)
+        out["cpu_baseline"] = {"value": n_s * T / cpu_elapsed, "unit": "env-steps/s", "cores": threads,
+                               "kind": "oracle", "value_one_thread": rate_1,
                                "sample": f"{n_s} of {N} environments (evenly spaced ids) x {T} steps, FP64 C oracle, "
-                                         f"OpenMP over environments, {cpu_elapsed:.1f} s"}
+                                         f"OpenMP over environments, {cpu_elapsed:.1f} s; one thread: 256 of them"}
         # The rudder class's attitude dynamics amplify rounding about 20x more than the propeller
         # classes' (the FP64 oracle with its state rounded to FP32 after every step already
         # differs by 5.9e-4 after 1000 steps, against 2.9e-5 for the randomised workload), so its

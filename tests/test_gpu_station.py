@@ -153,6 +153,27 @@ def test_every_step_restarts():
     assert stats["resets"] >= 0.9 * 6 * 1000
 
 
+@pytest.mark.parametrize("n", [1, 65])
+def test_ragged_segments(n):
+    """One environment (63 padding lanes in its wave) and 65 (a second wave with one valid
+    lane): the padding lanes stay in the wave for the spread restarts and report nothing."""
+    t = torch()
+    w = synth.randomised(n=n, steps=10)
+    desc = dict(DESC, max_steps=7)
+    res = run_both(w, desc, 30)
+    check(res, desc, 2e-4, 2e-3, min_compared=0.0, name=f"n={n}")
+    b = make_batch(w)
+    st = mgx.Station(b, **desc)
+    st.reset(7)
+    out = st.step(b.gen_actions(3, seed=2))
+    rew = out["reward"].cpu().numpy()
+    flags = out["terminated"].cpu().numpy() | out["truncated"].cpu().numpy()
+    assert not rew[:, n:].any() and not flags[:, n:].any()
+    st.close()
+    b.close()
+    t.cuda.synchronize()
+
+
 def test_mixed_batch_with_substeps():
     """Five classes (4, 5, 6, 8, 8 thrusters) in one batch, three dynamics steps per task
     step: slots, per-class constants and the held command."""
