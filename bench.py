@@ -627,10 +627,11 @@ def resample(args):
 
 def station(args):
     """Station-keeping task steps of the randomised workload's 65,536 environments: each
-    launch advances every environment one step under its command, then writes its
-    observation (and the pre-reset one), reward and flags and restarts ended episodes.
-    Timed with HIP events on the batch stream over `steps` calls of 100 task steps each,
-    with every output kept per step; parity on 256 sampled environments over one call."""
+    task step advances every environment one step under its command, then writes its
+    observation, reward and flags and restarts ended episodes. Timed with HIP events on the
+    batch stream over `steps` calls of 100 task steps each (one launch per call, the state
+    in registers across its steps, every output kept per step), and separately as Gym steps
+    (one task step per call from Python); parity on 256 sampled environments over one call."""
     import time
 
     import torch
@@ -664,11 +665,26 @@ def station(args):
     elapsed = e0.elapsed_time(e1) * 1e-3
     per_launch = elapsed / (reps * CH)
     m, P = c.m, 4
-    # state read and written, record, target, command, observation, reward, two flag bytes,
-    # episode index and step count read and written (the pre-reset observation and the new
-    # target of an ended episode are written for the few environments that end)
-    bytes_es = P * (2 * (13 + m) + 30 + 7 + m + (13 + m) + 1) + 2 + 4 * 4
+    # per task step: command, observation, reward, two flag bytes (the pre-reset observation
+    # and new target of the few environments that end an episode on top); once per call:
+    # state and episode counters read and written, record and target read
+    bytes_es = P * (m + (13 + m) + 1) + 2 + (P * (2 * (13 + m) + 30 + 7) + 2 * 8) / CH
     ep, _ = st.episodes()
+
+    # Gym steps: one task step per call, Python and the library call included
+    act1 = acts[:1].clone()
+    out1 = st.empty_outputs(1)
+    for _ in range(20):
+        st.step(act1, out1)
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n_gym = 500
+    torch.cuda.synchronize()
+    g0.record(s)
+    for _ in range(n_gym):
+        st.step(act1, out1)
+    g1.record(s)
+    torch.cuda.synchronize()
+    gym_step = g0.elapsed_time(g1) * 1e-3 / n_gym
 
     # parity: 256 sampled environments over one call of 100 task steps from a fresh reset
     st.reset(99)
@@ -721,12 +737,15 @@ def station(args):
         "ms_per_step": elapsed / reps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"station_{N}", "n_envs": N, "task_steps_per_call": CH, "thrusters": m,
-                   "station": desc, "path": "station step: one launch per task step, all outputs kept per step"},
+                   "station": desc, "path": "station step: one launch per call of 100 task steps, all outputs "
+                                            "kept per step"},
         "roofline": {"bound": "hbm", "achieved": N * bytes_es / per_launch / 1e9, "peak": PEAK_HBM / 1e9,
                      "unit": "GB/s", "frac": N * bytes_es / per_launch / PEAK_HBM, "traffic": None,
-                     "kernel": f"k_station_step<float,{m},false,false,false>", "launch_us_mean": per_launch * 1e6,
+                     "kernel": f"k_station_step<float,{m},false,false,false,true>", "launch_us_mean": per_launch * 1e6,
                      "bytes_per_env_step": bytes_es},
         "episodes_started_per_env": float(np.mean(ep)),
+        "gym_step": {"env_steps_per_s": N / gym_step, "us_per_step": gym_step * 1e6,
+                     "note": "one task step per Python call (Station.step with one command row)"},
         "cpu_baseline": cpu,
         "parity": {"metric": "max over sampled envs and steps of obs relative error and reward abs error",
                    "max_err": worst, "tolerance": 2e-4, "flags_equal": flags_ok, "pass": worst <= 2e-4 and flags_ok,

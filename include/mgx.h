@@ -457,7 +457,8 @@ mgx_status mgx_station_destroy(mgx_station* s);   /* synchronises the batch's st
  * precision), the first observations. Does not move the batch step counter. Asynchronous. */
 mgx_status mgx_station_reset(mgx_station* s, uint64_t seed, void* obs);
 
-/* n_steps >= 1 task steps (n_steps launches per class; a Gym step is n_steps = 1). Step k
+/* n_steps >= 1 task steps in one launch per class, the state held in registers between
+ * them (a Gym step is n_steps = 1). Step k
  * reads command row k of `actions` (device, n_steps rows of row_elems, the batch's action
  * layout and precision) and writes row k of every output, all device memory:
  *   obs, final_obs: [n_steps][state_elems], the batch's state layout (final_obs may be NULL;

@@ -30,15 +30,17 @@ template <typename T>
 struct StationArgs {
     T* state;
     const T* rec;
-    const T* act;        // one action row, class segment
+    const T* act;        // command rows, class segment: row k at act + k * act_stride
     T* tgt;              // [7][npad]: p*, q*
     int32_t* ep;         // [npad] episode index
     int32_t* et;         // [npad] steps taken in the episode
-    T* obs;              // [13+m][npad]
-    T* final_obs;        // [13+m][npad] or NULL; written for lanes whose episode ended
-    T* reward;           // [npad]
-    uint8_t* term;       // [npad]
-    uint8_t* trunc;      // [npad]
+    T* obs;              // per step [13+m][npad], row k at obs + k * obs_stride
+    T* final_obs;        // the same or NULL; written for lanes whose episode ended
+    T* reward;           // per step [npad], row k at reward + k * flag_stride
+    uint8_t* term;       // per step [npad], likewise
+    uint8_t* trunc;      // per step [npad], likewise
+    int64_t act_stride, obs_stride, flag_stride;
+    int32_t n_steps;     // task steps in this launch
     int32_t npad, nvalid;
     int64_t env_off;
     StationConsts P;
@@ -212,8 +214,11 @@ __device__ __forceinline__ void restart_spread(const StationConsts& P, uint64_t 
     }
 }
 
-// One task step of one class segment.
-template <typename T, int M, bool kShaped, bool kFins, bool kPayload>
+// n_steps task steps of one class segment in one launch: the state, record and target stay
+// in registers from step to step, the next command row is fetched during the current step,
+// and each step's observation, reward and flags go to their own output row. kMulti = false
+// is the one-step form (a Gym step), compiled without the loop.
+template <typename T, int M, bool kShaped, bool kFins, bool kPayload, bool kMulti>
 __global__ void __launch_bounds__(256) k_station_step(StationLaunch<T> L) {
     const StationArgs<T>& A = L.a;
     const int64_t env = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -226,90 +231,116 @@ __global__ void __launch_bounds__(256) k_station_step(StationLaunch<T> L) {
     for (int j = 0; j < 7; ++j) tg[j] = A.tgt[j * np + env];
     // padding lanes take no step and report nothing, but stay in the wave for the restarts
     const bool valid = env < A.nvalid;
-    T r = T(0);
-    bool term = false, trunc = false;
+    const ClassT<T> C = class_in_vgpr<T, M, kFins>(L.cls);
+    EnvT<T> E;
+    T IA2[3], Brb[3];
     int32_t ep = 0, et = 0;
+    bool restarted = false;
+    T nxt[M];
     if (valid) {
-        const ClassT<T> C = class_in_vgpr<T, M, kFins>(L.cls);
-        EnvT<T> E;
         load_record<T, kPayload>(A.rec, np, env, C.flags, E);
-        T a[M];
-#pragma unroll
-        for (int i = 0; i < M; ++i) a[i] = clip1(A.act[i * np + env]);
         ep = A.ep[env];
         et = A.et[env];
-        T IA2[3], Brb[3];
+#pragma unroll
+        for (int i = 0; i < M; ++i) nxt[i] = A.act[i * np + env];
         env_prologue<T, kPayload>(C, E, IA2, Brb);
-        for (int k = 0; k < A.P.substeps; ++k)
-            step_body<T, M, false, kShaped, kFins, kPayload>(C, E, IA2, Brb, s, a);
-        float st[kStats];  // launch statistics are not kept by the task
-        renorm_attitude<T, M>(s, st);
+    }
+    const int32_t n_steps = kMulti ? A.n_steps : 1;
+    for (int32_t k = 0; k < n_steps; ++k) {
+        T r = T(0);
+        bool term = false, trunc = false;
+        if (valid) {
+            T a[M];
+#pragma unroll
+            for (int i = 0; i < M; ++i) a[i] = clip1(nxt[i]);
+            if constexpr (kMulti) {
+                // the next row, clamped to the last (a load guarded per step would make the
+                // compiler wait for it before the step)
+                const T* an = A.act + (int64_t)(k + 1 < n_steps ? k + 1 : k) * A.act_stride + env;
+#pragma unroll
+                for (int i = 0; i < M; ++i) nxt[i] = an[i * np];
+            }
+            for (int j = 0; j < A.P.substeps; ++j)
+                step_body<T, M, false, kShaped, kFins, kPayload>(C, E, IA2, Brb, s, a);
+            float st[kStats];  // launch statistics are not kept by the task
+            renorm_attitude<T, M>(s, st);
 
-        // reward and termination on the state the transition ends in
-        bool fin = true;
+            // reward and termination on the state the transition ends in
+            bool fin = true;
 #pragma unroll
-        for (int j = 0; j < 3; ++j) fin &= finite_(s.p[j]);
+            for (int j = 0; j < 3; ++j) fin &= finite_(s.p[j]);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) fin &= finite_(s.q[j]);
+            for (int j = 0; j < 4; ++j) fin &= finite_(s.q[j]);
 #pragma unroll
-        for (int j = 0; j < 6; ++j) fin &= finite_(s.nu[j]);
+            for (int j = 0; j < 6; ++j) fin &= finite_(s.nu[j]);
 #pragma unroll
-        for (int i = 0; i < M; ++i) fin &= finite_(s.n[i]);
-        const T d0 = tg[0] - s.p[0], d1 = tg[1] - s.p[1], d2 = tg[2] - s.p[2];
-        const T d = sqrt_(d0 * d0 + d1 * d1 + d2 * d2);
-        T e[4];
-        attitude_error(s.q, tg + 3, e);
-        T a2 = T(0);
+            for (int i = 0; i < M; ++i) fin &= finite_(s.n[i]);
+            const T d0 = tg[0] - s.p[0], d1 = tg[1] - s.p[1], d2 = tg[2] - s.p[2];
+            const T d = sqrt_(d0 * d0 + d1 * d1 + d2 * d2);
+            T e[4];
+            attitude_error(s.q, tg + 3, e);
+            T a2 = T(0);
 #pragma unroll
-        for (int i = 0; i < M; ++i) a2 += a[i] * a[i];
-        const T up = T(1) - T(2) * (s.q[1] * s.q[1] + s.q[2] * s.q[2]);
-        r = exp_(-d * (T)A.P.inv_sigma) - (T)A.P.w_att * (T(1) - e[0] * e[0]) - (T)A.P.w_act_m * a2;
-        term = !fin || d > (T)A.P.d_max || up < (T)A.P.cos_tilt;
-        if (!fin) r = T(0);
-        ++et;
-        trunc = et >= A.P.max_steps;
-    }
-    const bool done = term || trunc;
-    if (done) {
-        if (A.final_obs) write_obs<T, M>(A.final_obs, np, env, s, tg);
-        ++ep;
-        et = 0;
-    }
-    const uint64_t need = __ballot(done);
-    if (need) {
-        if (__popcll(need) <= kSpreadRestarts)
-            restart_spread<T, M>(A.P, need, (uint32_t)(A.env_off + env), (uint32_t)ep, s, tg);
-        else if (done)
-            start_state<T, M>(A.P, (uint64_t)(A.env_off + env), (uint32_t)ep, s, tg);
+            for (int i = 0; i < M; ++i) a2 += a[i] * a[i];
+            const T up = T(1) - T(2) * (s.q[1] * s.q[1] + s.q[2] * s.q[2]);
+            r = exp_(-d * (T)A.P.inv_sigma) - (T)A.P.w_att * (T(1) - e[0] * e[0]) - (T)A.P.w_act_m * a2;
+            term = !fin || d > (T)A.P.d_max || up < (T)A.P.cos_tilt;
+            if (!fin) r = T(0);
+            ++et;
+            trunc = et >= A.P.max_steps;
+        }
+        const bool done = term || trunc;
         if (done) {
+            if (A.final_obs) write_obs<T, M>(A.final_obs + (int64_t)k * A.obs_stride, np, env, s, tg);
+            ++ep;
+            et = 0;
+            restarted = true;
+        }
+        const uint64_t need = __ballot(done);
+        if (need) {
+            if (__popcll(need) <= kSpreadRestarts)
+                restart_spread<T, M>(A.P, need, (uint32_t)(A.env_off + env), (uint32_t)ep, s, tg);
+            else if (done)
+                start_state<T, M>(A.P, (uint64_t)(A.env_off + env), (uint32_t)ep, s, tg);
+        }
+        write_obs<T, M>(A.obs + (int64_t)k * A.obs_stride, np, env, s, tg);
+        const int64_t fo = (int64_t)k * A.flag_stride + env;
+        A.reward[fo] = r;
+        A.term[fo] = term ? 1 : 0;
+        A.trunc[fo] = trunc ? 1 : 0;
+    }
+    if (valid) {
+        store_state<T, M>(A.state, np, env, s);
+        if (restarted) {
 #pragma unroll
             for (int j = 0; j < 7; ++j) A.tgt[j * np + env] = tg[j];
         }
-    }
-    write_obs<T, M>(A.obs, np, env, s, tg);
-    A.reward[env] = r;
-    A.term[env] = term ? 1 : 0;
-    A.trunc[env] = trunc ? 1 : 0;
-    if (valid) {
-        store_state<T, M>(A.state, np, env, s);
         A.ep[env] = ep;
         A.et[env] = et;
     }
 }
 
-template <typename T, int M>
-static void launch_station_m(const StationLaunch<T>& L, bool shaped, bool fins, bool payload, hipStream_t s) {
+template <typename T, int M, bool kMulti>
+static void launch_station_body(const StationLaunch<T>& L, bool shaped, bool fins, bool payload, hipStream_t s) {
     const dim3 grid((unsigned)((L.a.npad + 255) / 256)), block(256);
     if (payload && fins)
-        hipLaunchKernelGGL((k_station_step<T, M, true, true, true>), grid, block, 0, s, L);
+        hipLaunchKernelGGL((k_station_step<T, M, true, true, true, kMulti>), grid, block, 0, s, L);
     else if (payload)
-        hipLaunchKernelGGL((k_station_step<T, M, true, false, true>), grid, block, 0, s, L);
+        hipLaunchKernelGGL((k_station_step<T, M, true, false, true, kMulti>), grid, block, 0, s, L);
     else if (fins)
-        hipLaunchKernelGGL((k_station_step<T, M, true, true, false>), grid, block, 0, s, L);
+        hipLaunchKernelGGL((k_station_step<T, M, true, true, false, kMulti>), grid, block, 0, s, L);
     else if (shaped)
-        hipLaunchKernelGGL((k_station_step<T, M, true, false, false>), grid, block, 0, s, L);
+        hipLaunchKernelGGL((k_station_step<T, M, true, false, false, kMulti>), grid, block, 0, s, L);
     else
-        hipLaunchKernelGGL((k_station_step<T, M, false, false, false>), grid, block, 0, s, L);
+        hipLaunchKernelGGL((k_station_step<T, M, false, false, false, kMulti>), grid, block, 0, s, L);
+}
+
+template <typename T, int M>
+static void launch_station_m(const StationLaunch<T>& L, bool shaped, bool fins, bool payload, hipStream_t s) {
+    if (L.a.n_steps > 1)
+        launch_station_body<T, M, true>(L, shaped, fins, payload, s);
+    else
+        launch_station_body<T, M, false>(L, shaped, fins, payload, s);
 }
 
 template <typename T>
@@ -486,31 +517,37 @@ extern "C" mgx_status mgx_station_step(mgx_station* s, const void* actions, int3
     if (n_steps < 1) return fail(MGX_E_INVALID, "n_steps must be >= 1");
     hipDevice_guard g(b->device);
     const size_t P = (size_t)b->prec;
-    for (int32_t k = 0; k < n_steps; ++k) {
-        for (int c = 0; c < b->n_classes; ++c) {
-            const int64_t so = k * b->state_elems + b->state_off[c], po = k * b->npad_total + b->pad_off[c];
-            hipError_t e;
-            if (b->prec == MGX_FP32) {
-                StationLaunch<float> L{station_args<float>(s, c), b->h_class_f[c]};
-                L.a.act = (const float*)((const char*)actions + P * (k * b->row_elems + b->act_off[c]));
-                L.a.obs = (float*)obs + so;
-                L.a.final_obs = final_obs ? (float*)final_obs + so : nullptr;
-                L.a.reward = (float*)reward + po;
-                L.a.term = terminated + po;
-                L.a.trunc = truncated + po;
-                e = launch_station<float>(L, b->m[c], b->stream);
-            } else {
-                StationLaunch<double> L{station_args<double>(s, c), b->h_class_d[c]};
-                L.a.act = (const double*)((const char*)actions + P * (k * b->row_elems + b->act_off[c]));
-                L.a.obs = (double*)obs + so;
-                L.a.final_obs = final_obs ? (double*)final_obs + so : nullptr;
-                L.a.reward = (double*)reward + po;
-                L.a.term = terminated + po;
-                L.a.trunc = truncated + po;
-                e = launch_station<double>(L, b->m[c], b->stream);
-            }
-            if (e != hipSuccess) return hip_fail(b, e, "station step launch");
+    for (int c = 0; c < b->n_classes; ++c) {
+        const int64_t so = b->state_off[c], po = b->pad_off[c];
+        hipError_t e;
+        if (b->prec == MGX_FP32) {
+            StationLaunch<float> L{station_args<float>(s, c), b->h_class_f[c]};
+            L.a.act = (const float*)((const char*)actions + P * b->act_off[c]);
+            L.a.obs = (float*)obs + so;
+            L.a.final_obs = final_obs ? (float*)final_obs + so : nullptr;
+            L.a.reward = (float*)reward + po;
+            L.a.term = terminated + po;
+            L.a.trunc = truncated + po;
+            L.a.act_stride = b->row_elems;
+            L.a.obs_stride = b->state_elems;
+            L.a.flag_stride = b->npad_total;
+            L.a.n_steps = n_steps;
+            e = launch_station<float>(L, b->m[c], b->stream);
+        } else {
+            StationLaunch<double> L{station_args<double>(s, c), b->h_class_d[c]};
+            L.a.act = (const double*)((const char*)actions + P * b->act_off[c]);
+            L.a.obs = (double*)obs + so;
+            L.a.final_obs = final_obs ? (double*)final_obs + so : nullptr;
+            L.a.reward = (double*)reward + po;
+            L.a.term = terminated + po;
+            L.a.trunc = truncated + po;
+            L.a.act_stride = b->row_elems;
+            L.a.obs_stride = b->state_elems;
+            L.a.flag_stride = b->npad_total;
+            L.a.n_steps = n_steps;
+            e = launch_station<double>(L, b->m[c], b->stream);
         }
+        if (e != hipSuccess) return hip_fail(b, e, "station step launch");
     }
     return MGX_OK;
 }
