@@ -70,6 +70,28 @@ def test_episode_start_is_zyx_euler_of_the_draws():
     assert np.array_equal(s4[0], s[3])
 
 
+def test_start_draw_distributions():
+    """Over 20,000 draws: target coordinates and start velocities uniform on [-b, b] and
+    [-v0, v0] (mean 0, variance b^2/3), target and start yaw uniform on the circle (mean
+    resultant length near 0), roll and pitch within +-t0 with variance t0^2/3."""
+    d = S.StationDesc(target_box=1.5, tilt0=0.3, v0=0.2)
+    n = 20000
+    s, tg = S.episode_start(d, 5, np.arange(n), 2, 6)
+    se = lambda var: 4 * np.sqrt(var / n)   # four standard errors of a mean
+    for x, h in ((tg[:, 0:3], 1.5), (s[:, 7:13], 0.2)):
+        assert np.all(np.abs(x.mean(axis=0)) < se(h * h / 3))
+        assert np.allclose(x.var(axis=0), h * h / 3, rtol=0.05)
+    yaw_t = 2 * np.arctan2(tg[:, 6], tg[:, 3])
+    R = S.rot(s[:, 3:7])
+    yaw0 = np.arctan2(R[:, 1, 0], R[:, 0, 0])
+    for a in (yaw_t, yaw0):
+        assert abs(np.mean(np.exp(1j * a))) < 4 / np.sqrt(n)
+        assert np.allclose(np.var(np.mod(a + np.pi, 2 * np.pi) - np.pi), np.pi ** 2 / 3, rtol=0.05)
+    pitch, roll = -np.arcsin(R[:, 2, 0]), np.arctan2(R[:, 2, 1], R[:, 2, 2])
+    for a in (pitch, roll):
+        assert np.all(np.abs(a) <= 0.3 + 1e-12) and np.allclose(a.var(), 0.09 / 3, rtol=0.05)
+
+
 def test_start_uniforms_use_the_published_generator():
     # counter (g, k, j, 0) at key (seed, 8 << 24); word pairs (w0, w1), (w2, w3) as 53-bit uniforms
     u = S.start_uniforms(7, [12], [3])
