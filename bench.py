@@ -86,7 +86,7 @@ def main():
     ap.add_argument("--n", type=int, default=65536, help="environments")
     ap.add_argument("--rollout", type=int, default=1000, help="steps per rollout")
     ap.add_argument("--chunk", type=int, default=16, help="steps per fused launch (K)")
-    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--block", type=int, default=256, help="threads per block of the step launches (64, 128 or 256)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="dr",
@@ -169,6 +169,8 @@ def main():
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream(dev)
     b = mgx.Batch([cls], [N], w.dt, mgx.FP32)
+    if args.block != 256:
+        b.set_shape(mgx.LAUNCH_PER_CLASS, K, block=args.block)
     b.set_params(w.params, on_device=True)
     param_ptrs = {k: v.data_ptr() for k, v in b._param_tensors.items()}
     init = torch.tensor(b.pack_state([w.state[0].stacked()]), dtype=torch.float32, device=dev)
