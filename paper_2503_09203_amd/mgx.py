@@ -724,8 +724,9 @@ class Station:
             out = self.empty_outputs(n)
         self._check(out["obs"], n * L.state_elems, b.dtype)
         self._check(out["reward"], n * L.n_pad_total, b.dtype)
-        self._check(out["terminated"], n * L.n_pad_total)
-        self._check(out["truncated"], n * L.n_pad_total)
+        for k in ("terminated", "truncated"):
+            self._check(out[k], n * L.n_pad_total)
+            assert out[k].element_size() == 1, f"{k}: one byte per environment (uint8 or bool)"
         fo = out.get("final_obs")
         if fo is not None:
             self._check(fo, n * L.state_elems, b.dtype)
