@@ -475,6 +475,17 @@ mgx_status mgx_station_step(mgx_station* s, const void* actions, int32_t n_steps
  * n_total). Synchronises the stream. */
 mgx_status mgx_station_episodes(mgx_station* s, int32_t* episode, int32_t* steps);
 
+/* Domain randomisation at episode start (Sec. III-C: parameters resampled for the
+ * environments that reset): redraws, on the device, the parameters of every environment
+ * whose episode started in the last mgx_station_reset or mgx_station_step call, exactly as
+ * mgx_batch_resample(spec, nominal, those ids, seed, epoch) would with epoch = the
+ * environment's current episode index, so each episode's parameters are a function of
+ * (seed, env id, episode). Call it between task calls; an episode that starts and ends
+ * within one call of several steps runs with the parameters it started with. spec and
+ * nominal as for mgx_batch_resample (host memory). MGX_E_STATE before mgx_station_reset or
+ * before the batch has parameters. Asynchronous. */
+mgx_status mgx_station_resample(mgx_station* s, const mgx_dr_spec* spec, const double* nominal, uint64_t seed);
+
 /* ------------------------------------------------------------------ serving */
 
 /* Continuous-batching server. A scheduler thread owns a device arena of budget_bytes

@@ -58,13 +58,17 @@ __device__ void dr_group(const mgx_dr_dist& d, const double* nom, const double* 
     }
 }
 
+// Environments `ids[t]` (or t), or, with `mask`, the environments e < n_ids whose mask byte
+// is set; the epoch is `epoch`, or epochs[e] when `epochs` is given.
 template <typename T>
 __global__ void k_dr_resample(mgx_dr_spec spec, DrNominal nom, const ClassDesc64* cls, int ci, double dt, T* rec,
                               int64_t npad, int64_t env_off, const int64_t* ids, int64_t n_ids, uint64_t seed,
-                              uint64_t epoch) {
+                              uint64_t epoch, const uint8_t* mask, const int32_t* epochs) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_ids) return;
     const int64_t e = ids ? ids[t] : t;
+    if (mask && !mask[e]) return;
+    if (epochs) epoch = (uint32_t)epochs[e];
     const uint64_t g = (uint64_t)(env_off + e);
     double u[46];
     for (int j = 0; j < 23; ++j) {
@@ -132,13 +136,9 @@ using namespace mgx;
         if (e_ != hipSuccess) return hip_fail((b), e_, #call);    \
     } while (0)
 
-extern "C" mgx_status mgx_batch_resample(mgx_batch* b, const mgx_dr_spec* spec, const double* nominal,
-                                         const int64_t* env_ids, int64_t n, uint64_t seed, uint64_t epoch) {
-    if (!b) return fail(MGX_E_INVALID, "batch is NULL");
-    if (b->faulted) return fail(MGX_E_STATE, "batch faulted by an earlier device error");
-    if (!spec || !nominal) return fail(MGX_E_INVALID, "spec / nominal is NULL");
-    if (env_ids && !b->params_set) return fail(MGX_E_STATE, "resample every environment (env_ids = NULL) first");
-    if (env_ids && (n < 0 || n > b->n_total)) return fail(MGX_E_INVALID, "n outside [0, n_total]");
+namespace mgx {
+
+static mgx_status check_spec(const mgx_batch* b, const mgx_dr_spec* spec, const double* nominal) {
     for (int c = 0; c < b->n_classes; ++c)
         for (int j = 0; j < 23; ++j) {
             const double v = nominal[23 * c + j];
@@ -152,6 +152,49 @@ extern "C" mgx_status mgx_batch_resample(mgx_batch* b, const mgx_dr_spec* spec, 
     if ((s = check_dist(spec->dquad, "dquad", 6, nominal, b->n_classes, 13, false, false)) != MGX_OK) return s;
     if ((s = check_dist(spec->buoy, "buoy", 1, nominal, b->n_classes, 19, false, false)) != MGX_OK) return s;
     if ((s = check_dist(spec->current, "current", 3, nominal, b->n_classes, 20, false, true)) != MGX_OK) return s;
+    return MGX_OK;
+}
+
+template <typename T>
+static void launch_resample(mgx_batch* b, const mgx_dr_spec& spec, const double* nominal, int c, const int64_t* ids,
+                            int64_t nid, uint64_t seed, uint64_t epoch, const uint8_t* mask, const int32_t* epochs) {
+    DrNominal nom;
+    for (int j = 0; j < 23; ++j) nom.v[j] = nominal[23 * c + j];
+    const unsigned grid = (unsigned)((nid + 127) / 128);
+    hipLaunchKernelGGL(k_dr_resample<T>, dim3(grid), dim3(128), 0, b->stream, spec, nom, b->d_classdesc, c, b->dt,
+                       (T*)b->seg_rec(c), b->npad[c], b->env_off[c], ids, nid, seed, epoch, mask, epochs);
+}
+
+mgx_status resample_masked(mgx_batch* b, const mgx_dr_spec* spec, const double* nominal, const uint8_t* mask,
+                           const int32_t* epochs, uint64_t seed) {
+    if (!spec || !nominal) return fail(MGX_E_INVALID, "spec / nominal is NULL");
+    if (!b->params_set) return fail(MGX_E_STATE, "mgx_batch_set_params or a full resample first");
+    mgx_status st = check_spec(b, spec, nominal);
+    if (st != MGX_OK) return st;
+    hipDevice_guard g(b->device);
+    for (int c = 0; c < b->n_classes; ++c) {
+        if (b->prec == MGX_FP32)
+            launch_resample<float>(b, *spec, nominal, c, nullptr, b->n[c], seed, 0, mask + b->pad_off[c],
+                                   epochs + b->pad_off[c]);
+        else
+            launch_resample<double>(b, *spec, nominal, c, nullptr, b->n[c], seed, 0, mask + b->pad_off[c],
+                                    epochs + b->pad_off[c]);
+        HIP_TRY_DR(b, hipGetLastError());
+    }
+    return MGX_OK;
+}
+
+}  // namespace mgx
+
+extern "C" mgx_status mgx_batch_resample(mgx_batch* b, const mgx_dr_spec* spec, const double* nominal,
+                                         const int64_t* env_ids, int64_t n, uint64_t seed, uint64_t epoch) {
+    if (!b) return fail(MGX_E_INVALID, "batch is NULL");
+    if (b->faulted) return fail(MGX_E_STATE, "batch faulted by an earlier device error");
+    if (!spec || !nominal) return fail(MGX_E_INVALID, "spec / nominal is NULL");
+    if (env_ids && !b->params_set) return fail(MGX_E_STATE, "resample every environment (env_ids = NULL) first");
+    if (env_ids && (n < 0 || n > b->n_total)) return fail(MGX_E_INVALID, "n outside [0, n_total]");
+    mgx_status s = check_spec(b, spec, nominal);
+    if (s != MGX_OK) return s;
     hipDevice_guard g(b->device);
     std::vector<int64_t> local;
     std::vector<int64_t> cnt(b->n_classes, 0), start(b->n_classes, 0);
@@ -175,15 +218,10 @@ extern "C" mgx_status mgx_batch_resample(mgx_batch* b, const mgx_dr_spec* spec, 
         const int64_t* ids = env_ids ? b->d_ids + start[c] : nullptr;
         const int64_t nid = env_ids ? cnt[c] : b->n[c];
         if (nid == 0) continue;
-        DrNominal nom;
-        for (int j = 0; j < 23; ++j) nom.v[j] = nominal[23 * c + j];
-        const unsigned grid = (unsigned)((nid + 127) / 128);
         if (b->prec == MGX_FP32)
-            hipLaunchKernelGGL(k_dr_resample<float>, dim3(grid), dim3(128), 0, b->stream, *spec, nom, b->d_classdesc, c,
-                               b->dt, (float*)b->seg_rec(c), b->npad[c], b->env_off[c], ids, nid, seed, epoch);
+            launch_resample<float>(b, *spec, nominal, c, ids, nid, seed, epoch, nullptr, nullptr);
         else
-            hipLaunchKernelGGL(k_dr_resample<double>, dim3(grid), dim3(128), 0, b->stream, *spec, nom, b->d_classdesc,
-                               c, b->dt, (double*)b->seg_rec(c), b->npad[c], b->env_off[c], ids, nid, seed, epoch);
+            launch_resample<double>(b, *spec, nominal, c, ids, nid, seed, epoch, nullptr, nullptr);
         HIP_TRY_DR(b, hipGetLastError());
     }
     if (!env_ids) b->params_set = true;

@@ -116,4 +116,9 @@ ClassDesc64 to_desc64(const mgx_class_desc& c);
 mgx_status enqueue_step(mgx_batch* b, const void* actions, int64_t n_rows, int64_t row0, int32_t hold, int32_t K,
                         bool stats, void* traj, void* forces, int block);
 mgx_status validate_rows(const mgx_batch* b, int64_t t0, int64_t n_rows, int64_t row0, int32_t hold, int64_t K);
+// Redraws the parameters of the environments whose byte in `mask` is set, with epochs[e] as
+// the draw's epoch (both device arrays of n_pad_total, environment e of class c at
+// pad_off[c] + e), as mgx_batch_resample does for listed environments.
+mgx_status resample_masked(mgx_batch* b, const mgx_dr_spec* spec, const double* nominal, const uint8_t* mask,
+                           const int32_t* epochs, uint64_t seed);
 }  // namespace mgx

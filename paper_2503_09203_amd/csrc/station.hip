@@ -34,6 +34,7 @@ struct StationArgs {
     T* tgt;              // [7][npad]: p*, q*
     int32_t* ep;         // [npad] episode index
     int32_t* et;         // [npad] steps taken in the episode
+    uint8_t* restart;    // [npad] 1 where an episode started during the launch
     T* obs;              // per step [13+m][npad], row k at obs + k * obs_stride
     T* final_obs;        // the same or NULL; written for lanes whose episode ended
     T* reward;           // per step [npad], row k at reward + k * flag_stride
@@ -155,6 +156,7 @@ __global__ void __launch_bounds__(256) k_station_start(StationArgs<T> A) {
     }
     A.ep[env] = 0;
     A.et[env] = 0;
+    A.restart[env] = env < A.nvalid ? 1 : 0;
     if (A.obs) write_obs<T, M>(A.obs, np, env, s, tg);
 }
 
@@ -318,6 +320,7 @@ __global__ void __launch_bounds__(256) k_station_step(StationLaunch<T> L) {
         A.ep[env] = ep;
         A.et[env] = et;
     }
+    A.restart[env] = restarted ? 1 : 0;
 }
 
 template <typename T, int M, bool kMulti>
@@ -388,6 +391,7 @@ struct mgx_station {
     void* d_tgt = nullptr;       // [7][npad] per class segment, at 7 * pad_off[c]
     int32_t* d_ep = nullptr;     // [npad_total]
     int32_t* d_et = nullptr;     // [npad_total]
+    uint8_t* d_restart = nullptr;  // [npad_total]: an episode started in the last reset or step call
     bool started = false;
 };
 
@@ -401,8 +405,10 @@ static void free_station(mgx_station* s) {
     if (s->d_tgt) (void)hipFree(s->d_tgt);
     if (s->d_ep) (void)hipFree(s->d_ep);
     if (s->d_et) (void)hipFree(s->d_et);
+    if (s->d_restart) (void)hipFree(s->d_restart);
     s->d_tgt = nullptr;
     s->d_ep = s->d_et = nullptr;
+    s->d_restart = nullptr;
 }
 
 template <typename T>
@@ -415,6 +421,7 @@ static StationArgs<T> station_args(mgx_station* st, int c) {
     a.tgt = (T*)st->d_tgt + 7 * b->pad_off[c];
     a.ep = st->d_ep + b->pad_off[c];
     a.et = st->d_et + b->pad_off[c];
+    a.restart = st->d_restart + b->pad_off[c];
     a.npad = (int32_t)b->npad[c];
     a.nvalid = (int32_t)b->n[c];
     a.env_off = b->env_off[c];
@@ -456,6 +463,8 @@ extern "C" mgx_status mgx_station_create(mgx_batch* b, const mgx_station_desc* d
     hipError_t e = hipMalloc(&s->d_tgt, 7 * N * P);
     if (e == hipSuccess) e = hipMalloc((void**)&s->d_ep, N * sizeof(int32_t));
     if (e == hipSuccess) e = hipMalloc((void**)&s->d_et, N * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&s->d_restart, N);
+    if (e == hipSuccess) e = hipMemsetAsync(s->d_restart, 0, N, b->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->d_tgt, 0, 7 * N * P, b->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->d_ep, 0, N * sizeof(int32_t), b->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->d_et, 0, N * sizeof(int32_t), b->stream);
@@ -566,4 +575,13 @@ extern "C" mgx_status mgx_station_episodes(mgx_station* s, int32_t* episode, int
             steps[b->env_off[c] + i] = et[(size_t)(b->pad_off[c] + i)];
         }
     return MGX_OK;
+}
+
+extern "C" mgx_status mgx_station_resample(mgx_station* s, const mgx_dr_spec* spec, const double* nominal,
+                                           uint64_t seed) {
+    if (!s) return fail(MGX_E_INVALID, "station is NULL");
+    mgx_batch* b = s->batch;
+    if (b->faulted) return fail(MGX_E_STATE, "batch faulted by an earlier device error");
+    if (!s->started) return fail(MGX_E_STATE, "mgx_station_reset has not been called");
+    return resample_masked(b, spec, nominal, s->d_restart, s->d_ep, seed);
 }

@@ -222,6 +222,7 @@ SIGNATURES = {
     "mgx_station_reset": (I32, [P, U64, P]),
     "mgx_station_step": (I32, [P, P, I32, P, P, P, P, P]),
     "mgx_station_episodes": (I32, [P, P, P]),
+    "mgx_station_resample": (I32, [P, ctypes.POINTER(DrSpec), P, U64]),
 }
 
 _lib = None
@@ -733,6 +734,14 @@ class Station:
         _call("mgx_station_step", self.h, _ptr(actions), n, _ptr(out["obs"]), _ptr(out["reward"]),
               _ptr(out["terminated"]), _ptr(out["truncated"]), _ptr(fo))
         return out
+
+    def resample(self, groups: dict, nominal, seed=0):
+        """Redraw the parameters of the environments whose episode started in the last reset or
+        step call, epoch = their episode index (``groups`` as for ``dr_spec``; ``nominal``:
+        [n_classes, 23] float64)."""
+        spec = dr_spec(groups)
+        nom = np.ascontiguousarray(nominal, dtype=np.float64).reshape(-1)
+        _call("mgx_station_resample", self.h, ctypes.byref(spec), nom.ctypes.data_as(ctypes.c_void_p), int(seed))
 
     def per_env(self, flat):
         """[..., n_pad_total] -> per class [..., n] (padding dropped)."""

@@ -259,6 +259,43 @@ def test_full_size_sampled():
     b.close()
 
 
+def test_parameters_redrawn_at_episode_start():
+    """Domain randomisation at episode start: after the reset every environment holds the
+    parameters of its episode 0; after task steps with scattered terminations, exactly the
+    environments that restarted hold those of their new episode (the oracle sampler at
+    epoch = episode index), and the others keep theirs."""
+    import test_gpu_dr as G
+    from oracle import dr_sampler as D
+    t = torch()
+    w = synth.randomised(n=700, steps=10)
+    b = make_batch(w)
+    st = mgx.Station(b, **DESC)
+    nominal = np.stack([G.nominal_of(c) for c in w.classes])
+    st.reset(7)
+    st.resample(G.SPEC, nominal, seed=21)
+    p0 = b.get_params()
+    G.compare(p0, G.oracle_params(w.classes, w.n_envs, G.SPEC, 21, 0), mgx.FP32)
+    out = st.step(b.gen_actions(4, seed=5))
+    st.resample(G.SPEC, nominal, seed=21)
+    p1 = b.get_params()
+    t.cuda.synchronize()
+    ended = (out["terminated"] | out["truncated"]).cpu().numpy().any(axis=0)[:700].astype(bool)
+    ep, _ = st.episodes()
+    assert 0 < ended.sum() < 700 and np.array_equal(ep > 0, ended)
+    for k in ("mass", "added", "dlin", "dquad", "buoy", "current"):
+        assert np.array_equal(p1[k][..., ~ended], p0[k][..., ~ended]), k
+    ids = np.where(ended)[0]
+    ref = {k: np.zeros_like(p1[k][..., ids]) for k in p1}
+    for e in np.unique(ep[ids]):
+        sel = ep[ids] == e
+        r = D.sample(G.SPEC, nominal[0], ids[sel], 21, int(e))
+        for k in ref:
+            ref[k][..., sel] = r[k]
+    G.compare(p1, ref, mgx.FP32, cols=ids)
+    st.close()
+    b.close()
+
+
 def test_errors():
     t = torch()
     w = synth.plain_small(n=64)
