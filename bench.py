@@ -100,6 +100,9 @@ def main():
                          "resample: on-device domain randomisation of every environment's parameters; "
                          "station: the station-keeping task step (step, observation, reward, termination and "
                          "auto-reset in one kernel)")
+    ap.add_argument("--station-class", default="dr", choices=["dr", "heavy8"],
+                    help="station: the randomised workload's 6-thruster class, or an 8-thruster class (the "
+                         "paper's station-keeping speed test uses an 8-thruster vehicle)")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: requests per second")
     ap.add_argument("--sweep-rates", default="", help="serve: extra comma-separated rates, 5 s each")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: trace length (s)")
@@ -645,10 +648,15 @@ def station(args):
 
     N, CH = args.n, 100
     desc = dict(mgx.STATION_DEFAULTS)
-    w = synth.randomised(n=N, steps=8)
-    c = w.classes[0]
-    b = mgx.Batch([c], [N], w.dt, mgx.FP32)
-    b.set_params(w.params)
+    if args.station_class == "heavy8":
+        # the first 8-thruster class of the heterogeneous set, randomised like the dr workload
+        c = synth.hetero_classes()[3]
+        params, dt = synth.randomised_params(c, N), 0.01
+    else:
+        w = synth.randomised(n=N, steps=8)
+        c, params, dt = w.classes[0], w.params, w.dt
+    b = mgx.Batch([c], [N], dt, mgx.FP32)
+    b.set_params(params)
     st = mgx.Station(b, **desc)
     acts = b.gen_actions(CH, seed=17)
     out = st.empty_outputs(CH)
@@ -695,7 +703,7 @@ def station(args):
     rng = np.random.default_rng(4)
     ids = np.sort(rng.choice(N, 256, replace=False))
     sd = S.StationDesc(**desc)
-    envs = oracle.make_envs(c, w.params.subset(ids), w.dt)
+    envs = oracle.make_envs(c, params.subset(ids), dt)
     o = S.StationOracle(sd, envs, m, ids=ids)
     o.reset(99)
     host_acts = b.unpack_actions(acts.cpu().numpy().astype(np.float64))[0]
@@ -723,7 +731,7 @@ def station(args):
     if not args.no_cpu_baseline:
         n_cpu = 4096
         cids = np.arange(0, N, N // n_cpu)[:n_cpu]
-        oc = S.StationOracle(sd, oracle.make_envs(c, w.params.subset(cids), w.dt), m, ids=cids)
+        oc = S.StationOracle(sd, oracle.make_envs(c, params.subset(cids), dt), m, ids=cids)
         oc.reset(99)
         a_cpu = host_acts[:, :, cids]
         t0 = time.perf_counter()
@@ -738,7 +746,7 @@ def station(args):
         "value": N / per_launch, "unit": "env-steps/s", "n_gpus": 1, "steps": reps, "warmup": args.warmup,
         "ms_per_step": elapsed / reps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"station_{N}", "n_envs": N, "task_steps_per_call": CH, "thrusters": m,
+        "config": {"workload": f"station_{'heavy8_' if args.station_class == 'heavy8' else ''}{N}", "n_envs": N, "task_steps_per_call": CH, "thrusters": m,
                    "station": desc, "path": "station step: one launch per call of 100 task steps, all outputs "
                                             "kept per step"},
         "roofline": {"bound": "hbm", "achieved": N * bytes_es / per_launch / 1e9, "peak": PEAK_HBM / 1e9,
