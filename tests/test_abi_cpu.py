@@ -104,6 +104,7 @@ def test_null_batch_calls_are_rejected():
     assert L.mgx_station_step(None, None, 1, None, None, None, None, None) == mgx.MGX_E_INVALID
     assert L.mgx_station_reset(None, 0, None) == mgx.MGX_E_INVALID
     assert L.mgx_station_destroy(None) == mgx.MGX_OK
+    assert L.mgx_station_resample(None, None, None, 0) == mgx.MGX_E_INVALID
 
 
 def test_binding_structures_match_the_header(tmp_path):

@@ -184,11 +184,12 @@ def test_mixed_batch_with_substeps():
 
 
 @pytest.mark.parametrize("make", ["propellers", "rudders", "payload"])
-def test_variant_bodies(make):
+@pytest.mark.parametrize("precision,tol,margin", [(mgx.FP32, 5e-4, 2e-3), (mgx.FP64, 1e-9, 1e-7)])
+def test_variant_bodies(make, precision, tol, margin):
     w = getattr(synth, make)(n=700, steps=10)
     desc = dict(DESC, max_steps=30)
-    res = run_both(w, desc, 45)
-    check(res, desc, 5e-4, 2e-3, name=make)
+    res = run_both(w, desc, 45, precision)
+    check(res, desc, tol, margin, name=f"{make} {precision}")
 
 
 def test_vector_env_interface():
