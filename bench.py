@@ -620,12 +620,34 @@ def resample(args):
     z.record(s)
     torch.cuda.synchronize()
     per = a.elapsed_time(z) * 1e-3 / reps
+    # the redraw at episode start: one-step station-keeping calls with scattered restarts
+    # (targets up to 3.5 m away, distance limit 2.6 m), each followed by the masked redraw
+    b.set_params(w.params)
+    st = mgx.Station(b, d_max=2.6)
+    st.reset(1)
+    act1 = b.gen_actions(1, seed=3)
+    out1 = st.empty_outputs(1)
+    t_rs, n_rs = [], []
+    for k in range(40):
+        st.step(act1, out1)
+        r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        r0.record(s)
+        st.resample(spec, nominal, seed=5)
+        r1.record(s)
+        torch.cuda.synchronize()
+        if k >= 5:
+            t_rs.append(r0.elapsed_time(r1) * 1e3)
+            n_rs.append(int((out1["terminated"] | out1["truncated"]).sum()))
+    st.close()
     rec_bytes = 30 * 4
     out = {"metric": METRIC, "workload": f"resample_{N}", "unit": "envs/s", "value": N / per,
            "launch_us_mean": per * 1e6, "n_envs": N,
            "roofline": {"bound": "hbm (record writes)", "achieved": N * rec_bytes / per / 1e9, "peak": PEAK_HBM / 1e9,
                         "unit": "GB/s", "frac": N * rec_bytes / per / PEAK_HBM, "bytes_per_env": rec_bytes},
-           "note": "46 Philox uniforms, 10 Box-Muller draws in double and the record rebuild per environment"}
+           "note": "46 Philox uniforms, 10 Box-Muller draws in double and the record rebuild per environment",
+           "restart_redraw": {"us_median": float(np.median(t_rs)), "restarts_per_call": float(np.mean(n_rs)),
+                              "note": "mgx_station_resample after each one-step task call (HIP events around the "
+                                      "call, host side included)"}}
     b.close()
     print(json.dumps(out), flush=True)
 

@@ -58,17 +58,10 @@ __device__ void dr_group(const mgx_dr_dist& d, const double* nom, const double* 
     }
 }
 
-// Environments `ids[t]` (or t), or, with `mask`, the environments e < n_ids whose mask byte
-// is set; the epoch is `epoch`, or epochs[e] when `epochs` is given.
+// The per-lane draw of environment e (its 23 generator calls in sequence) and its record.
 template <typename T>
-__global__ void k_dr_resample(mgx_dr_spec spec, DrNominal nom, const ClassDesc64* cls, int ci, double dt, T* rec,
-                              int64_t npad, int64_t env_off, const int64_t* ids, int64_t n_ids, uint64_t seed,
-                              uint64_t epoch, const uint8_t* mask, const int32_t* epochs) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_ids) return;
-    const int64_t e = ids ? ids[t] : t;
-    if (mask && !mask[e]) return;
-    if (epochs) epoch = (uint32_t)epochs[e];
+__device__ void dr_resample_one(const mgx_dr_spec& spec, const DrNominal& nom, const ClassDesc64& cls, double dt,
+                                T* rec, int64_t npad, int64_t env_off, int64_t e, uint64_t seed, uint64_t epoch) {
     const uint64_t g = (uint64_t)(env_off + e);
     double u[46];
     for (int j = 0; j < 23; ++j) {
@@ -84,7 +77,85 @@ __global__ void k_dr_resample(mgx_dr_spec spec, DrNominal nom, const ClassDesc64
     dr_group(spec.dquad, nom.v + 13, u, 26, 6, dquad);
     dr_group(spec.buoy, nom.v + 19, u, 38, 1, &buoy);
     dr_group(spec.current, nom.v + 20, u, 40, 3, cur);
-    write_record<T>(cls[ci].inertia, cls[ci].g0, dt, mass, added, dlin, dquad, buoy, cur, rec, npad, e, cls[ci].rg);
+    write_record<T>(cls.inertia, cls.g0, dt, mass, added, dlin, dquad, buoy, cur, rec, npad, e, cls.rg);
+}
+
+// Masked redraw: the environments e < n whose mask byte is set, epoch epochs[e]. Few lanes
+// of a wave are set (episodes that just restarted), so each one's draw is spread over the
+// wave: parameter j (mass; added mass 1-6; linear damping 7-12; quadratic damping 13-18;
+// buoyancy 19; current 20-22) is drawn on lane j from generator call j, the call whose
+// uniform pair the per-lane path gives that parameter (a shared group uses its first
+// entry's pair, taken by a lane shuffle), and the restarting lane gathers the 23 values and
+// rebuilds its record. The values are those of the per-lane path; the wave spends about
+// one parameter's draw per restart instead of the 23 in sequence. A wave with more than
+// kSpreadDraws set lanes (all of them after a reset) takes the per-lane path instead.
+constexpr int kSpreadDraws = 8;
+
+template <typename T>
+__device__ void dr_resample_spread(const mgx_dr_spec& spec, const DrNominal& nom, const ClassDesc64& cls, double dt,
+                                   T* rec, int64_t npad, int64_t env_off, int64_t n, uint64_t seed,
+                                   const uint8_t* mask, const int32_t* epochs) {
+    __shared__ mgx_dr_dist sd[6];
+    __shared__ double snom[23];
+    if (threadIdx.x == 0) {
+        sd[0] = spec.mass;
+        sd[1] = spec.added;
+        sd[2] = spec.dlin;
+        sd[3] = spec.dquad;
+        sd[4] = spec.buoy;
+        sd[5] = spec.current;
+        for (int j = 0; j < 23; ++j) snom[j] = nom.v[j];
+    }
+    __syncthreads();
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool want = t < n && mask[t];
+    const int32_t ep_own = want ? epochs[t] : 0;
+    const int lane = __lane_id();
+    const int j = lane < 23 ? lane : 0;
+    const int grp = j == 0 ? 0 : j < 7 ? 1 : j < 13 ? 2 : j < 19 ? 3 : j == 19 ? 4 : 5;
+    const int first = grp == 0 ? 0 : grp == 1 ? 1 : grp == 2 ? 7 : grp == 3 ? 13 : grp == 4 ? 19 : 20;
+    const mgx_dr_dist& d = sd[grp];
+    uint64_t need = __ballot(want);
+    if (__popcll(need) > kSpreadDraws) {
+        if (want) dr_resample_one<T>(spec, nom, cls, dt, rec, npad, env_off, t, seed, (uint32_t)ep_own);
+        return;
+    }
+    while (need) {
+        const int src = __ffsll((unsigned long long)need) - 1;
+        need &= need - 1;
+        const int64_t e = __shfl(t, src);
+        uint32_t c[4] = {(uint32_t)(env_off + e), (uint32_t)__shfl(ep_own, src), (uint32_t)j, 0u};
+        philox4x32_10(c, (uint32_t)seed, kStreamDr << 24);
+        const double u1 = u53(c[0], c[1]), u2 = u53(c[2], c[3]);
+        const int from = d.shared ? first : j;
+        const double v1 = __shfl(u1, from), v2 = __shfl(u2, from);
+        double val = snom[j];
+        if (d.kind != MGX_DR_FIXED) {
+            const double x = dr_draw(d, v1, v2);
+            val = d.relative ? snom[j] * x : x;
+        }
+        double p[23];
+#pragma unroll
+        for (int i = 0; i < 23; ++i) p[i] = __shfl(val, i);
+        if (lane == src)
+            write_record<T>(cls.inertia, cls.g0, dt, p[0], p + 1, p + 7, p + 13, p[19], p + 20, rec, npad, e, cls.rg);
+    }
+}
+
+// Environments `ids[t]` (or t) at epoch `epoch`; or, with `mask`, the environments e < n_ids
+// whose mask byte is set, at epochs[e] (spread over the wave, above).
+template <typename T>
+__global__ void k_dr_resample(mgx_dr_spec spec, DrNominal nom, const ClassDesc64* cls, int ci, double dt, T* rec,
+                              int64_t npad, int64_t env_off, const int64_t* ids, int64_t n_ids, uint64_t seed,
+                              uint64_t epoch, const uint8_t* mask, const int32_t* epochs) {
+    if (mask) {
+        dr_resample_spread<T>(spec, nom, cls[ci], dt, rec, npad, env_off, n_ids, seed, mask, epochs);
+        return;
+    }
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_ids) return;
+    const int64_t e = ids ? ids[t] : t;
+    dr_resample_one<T>(spec, nom, cls[ci], dt, rec, npad, env_off, e, seed, epoch);
 }
 
 // Smallest value a distribution can produce (for validation).
