@@ -531,10 +531,10 @@ class Batch:
         mgx_batch_reset(self.h, None if ids is None else ids.ctypes.data_as(ctypes.c_void_p), n,
                         _ptr(init_state), seed)
 
-    def resample(self, groups: dict, nominal, env_ids=None, seed=0, epoch=0):
-        """Redraw parameters on the device (``groups`` as for ``dr_spec``; ``nominal``:
-        [n_classes, 23] float64)."""
-        spec = dr_spec(groups)
+    def resample(self, groups, nominal, env_ids=None, seed=0, epoch=0):
+        """Redraw parameters on the device (``groups`` as for ``dr_spec``, or a ``DrSpec`` it
+        built; ``nominal``: [n_classes, 23] float64)."""
+        spec = groups if isinstance(groups, DrSpec) else dr_spec(groups)
         nom = np.ascontiguousarray(nominal, dtype=np.float64).reshape(-1)
         ids = None if env_ids is None else np.ascontiguousarray(env_ids, dtype=np.int64)
         _call("mgx_batch_resample", self.h, ctypes.byref(spec), nom.ctypes.data_as(ctypes.c_void_p),
@@ -735,11 +735,11 @@ class Station:
               _ptr(out["terminated"]), _ptr(out["truncated"]), _ptr(fo))
         return out
 
-    def resample(self, groups: dict, nominal, seed=0):
+    def resample(self, groups, nominal, seed=0):
         """Redraw the parameters of the environments whose episode started in the last reset or
-        step call, epoch = their episode index (``groups`` as for ``dr_spec``; ``nominal``:
-        [n_classes, 23] float64)."""
-        spec = dr_spec(groups)
+        step call, epoch = their episode index (``groups`` as for ``dr_spec``, or a ``DrSpec``
+        it built, which saves rebuilding it every step; ``nominal``: [n_classes, 23] float64)."""
+        spec = groups if isinstance(groups, DrSpec) else dr_spec(groups)
         nom = np.ascontiguousarray(nominal, dtype=np.float64).reshape(-1)
         _call("mgx_station_resample", self.h, ctypes.byref(spec), nom.ctypes.data_as(ctypes.c_void_p), int(seed))
 
