@@ -297,6 +297,30 @@ def test_parameters_redrawn_at_episode_start():
     b.close()
 
 
+def test_redraw_without_restarts_changes_nothing():
+    """A call in which no episode ends leaves every parameter as it was, and a prebuilt
+    DrSpec draws what its dictionary draws."""
+    import test_gpu_dr as G
+    t = torch()
+    w = synth.randomised(n=300, steps=10)
+    b = make_batch(w)
+    st = mgx.Station(b, **dict(DESC, d_max=1e6, tilt_max=3.1, max_steps=1000))
+    nominal = np.stack([G.nominal_of(c) for c in w.classes])
+    st.reset(3)
+    st.resample(mgx.dr_spec(G.SPEC), nominal, seed=8)
+    p0 = b.get_params()
+    G.compare(p0, G.oracle_params(w.classes, w.n_envs, G.SPEC, 8, 0), mgx.FP32)
+    out = st.step(b.gen_actions(3, seed=1))
+    assert not (out["terminated"] | out["truncated"]).any()
+    st.resample(G.SPEC, nominal, seed=8)
+    p1 = b.get_params()
+    for k in p0:
+        assert np.array_equal(p0[k], p1[k]), k
+    st.close()
+    b.close()
+    t.cuda.synchronize()
+
+
 def test_errors():
     t = torch()
     w = synth.plain_small(n=64)
