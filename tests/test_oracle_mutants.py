@@ -68,6 +68,17 @@ MUTANTS = {
                         "nl[i] = env->tau[i] > 0.0 ? s->n[i] + orc_lag_factor(env, i) * (a[i] - s->n[i]) : c;"),
     "thrust_from_old_rotor": ("orc_terms_eval(env, s->q, s->nu, nl, &t);", "orc_terms_eval(env, s->q, s->nu, s->n, &t);"),
     "quat_product_sign": ("out[1 + j] = a[0] * bv[j] + b[0] * av[j] + c[j];", "out[1 + j] = a[0] * bv[j] + b[0] * av[j] - c[j];"),
+    "loss_position_before_step": ("orc_step(&envs[e], &s, a, 0);\n            double d0 = s.p[0] - w[0], d1 = s.p[1] - w[1], d2 = s.p[2] - w[2];",
+                                  "double d0 = s.p[0] - w[0], d1 = s.p[1] - w[1], d2 = s.p[2] - w[2];\n            orc_step(&envs[e], &s, a, 0);"),
+    "loss_drops_last_step": ("for (int32_t k = 0; k < horizon; ++k) {\n            const double* a = actions + (e * horizon + k)",
+                             "for (int32_t k = 0; k < horizon - 1; ++k) {\n            const double* a = actions + (e * horizon + k)"),
+    "loss_waypoint_axis": ("d1 = s.p[1] - w[1]", "d1 = s.p[1] - w[0]"),
+    "loss_penalty_all_rows": ("for (int i = 0; i < envs[e].m; ++i) aa += a[i] * a[i];",
+                              "for (int i = 0; i < ORC_MAX_THR; ++i) aa += a[i] * a[i];"),
+    "loss_penalty_clipped": ("for (int i = 0; i < envs[e].m; ++i) aa += a[i] * a[i];",
+                             "for (int i = 0; i < envs[e].m; ++i) aa += fmin(a[i] * a[i], 1.0);"),
+    "loss_action_row_shift": ("const double* a = actions + (e * horizon + k) * ORC_MAX_THR;",
+                              "const double* a = actions + (e * horizon + (k + 1) % horizon) * ORC_MAX_THR;"),
 }
 
 

@@ -766,3 +766,109 @@ def test_action_row_indexing():
     assert np.array_equal(got, expect)
     with pytest.raises(IndexError):
         oracle.rollout(env, state1(), acts, hold=3, n_steps=15, t0=7, row0=2)
+
+
+# ----------------------------------------------------------------------------- P13 rollout loss
+
+def _loss(env, s0, acts, wp, weight=1e-3):
+    """Per-environment loss of one environment; acts [H, 8], wp [3]."""
+    H = acts.shape[0]
+    return oracle.rollout_loss(env, s0, acts[None], H, np.asarray(wp, float)[None], weight)[0]
+
+
+def test_p13_loss_static_equilibrium_is_horizon_times_distance():
+    """A neutral vehicle at rest with its CoB above the CoG and zero commands stays at the
+    origin (pin P6(ii)), so every one of the H terms is |w|^2 and the loss is H |w|^2."""
+    env = env1(m=2)
+    wp = [0.7, -1.3, 2.1]
+    for H in (1, 7, 256):
+        L = _loss(env, state1(), np.zeros((H, oracle.MAX_THR)), wp)
+        assert L == pytest.approx(H * (0.49 + 1.69 + 4.41), rel=1e-13, abs=0)  # summation order only
+
+
+def _surge_closed_form(u0, dl, M, dt, H):
+    """Positions after steps 1..H under pure linear surge damping (no thrust): the
+    velocity after step j is u0 r^j, r = 1 - dt d_L / M, and the semi-implicit position is
+    p_k = dt sum_{j=1..k} u_j = dt u0 r (1 - r^k) / (1 - r)."""
+    r = 1.0 - dt * dl / M
+    k = np.arange(1, H + 1)
+    return dt * u0 * r * (1.0 - r ** k) / (1.0 - r), r
+
+
+def test_p13_loss_surge_decay_closed_form():
+    """Surge-only linear damping: the loss sums the distance from the waypoint of the
+    position AFTER each of the steps 1..H. A loss that scores the position before the
+    step (k = 0..H-1), drops the last step or mixes the waypoint axes fails here."""
+    env = _surge_env(dl=7.0)
+    H, u0, wp = 200, 0.5, np.array([0.9, -0.4, 0.25])
+    p, _ = _surge_closed_form(u0, 7.0, 15.0, 0.01, H)
+    expect = np.sum((p - wp[0]) ** 2) + H * (wp[1] ** 2 + wp[2] ** 2)
+    L = _loss(env, state1(nu=[u0, 0, 0, 0, 0, 0]), np.zeros((H, oracle.MAX_THR)), wp)
+    assert abs(L - expect) / expect < 1e-13
+    before = np.sum((np.concatenate([[0.0], p[:-1]]) - wp[0]) ** 2) + H * (wp[1] ** 2 + wp[2] ** 2)
+    assert abs(before - expect) / expect > 1e-3   # the two readings are far apart here
+
+
+def test_p13_damping_derivative_closed_form_against_finite_differences():
+    """P13's closed form: under pure linear surge damping du_k/dd_L = -k (dt/M) u0 r^(k-1),
+    so dp_k/dd_L = dt sum_{j<=k} du_j/dd_L and dL/dd_L = sum_k 2 (p_k - w_x) dp_k/dd_L.
+    Central differences (h = 1e-4) of the oracle's loss and of its velocity agree with it."""
+    dl, dt, M, H, u0 = 7.0, 0.01, 15.0, 256, 0.5
+    wp = np.array([0.9, -0.4, 0.25])
+    p, r = _surge_closed_form(u0, dl, M, dt, H)
+    k = np.arange(1, H + 1)
+    du = -k * (dt / M) * u0 * r ** (k - 1)
+    dp = dt * np.cumsum(du)
+    dL = np.sum(2.0 * (p - wp[0]) * dp)
+    h = 1e-4
+    s0 = state1(nu=[u0, 0, 0, 0, 0, 0])
+    acts = np.zeros((H, oracle.MAX_THR))
+    fd = (_loss(_surge_env(dl=dl + h), s0, acts, wp) - _loss(_surge_env(dl=dl - h), s0, acts, wp)) / (2 * h)
+    assert abs(fd - dL) / abs(dL) < 1e-7, (fd, dL)
+    _, tp = run(_surge_env(dl=dl + h), s0, [0.0], H)
+    _, tm = run(_surge_env(dl=dl - h), s0, [0.0], H)
+    fd_u = (tp[0, :, 7] - tm[0, :, 7]) / (2 * h)
+    assert np.max(np.abs(fd_u - du)) / np.abs(du).max() < 1e-7
+
+
+def test_p13_action_weight_uses_the_raw_commands_of_the_class_thrusters():
+    """With zero thrust gains the commands move nothing, so L = H |w|^2 + lambda sum_k
+    sum_{i<m} a_{k,i}^2: the raw commands (values beyond [-1, 1] are not clipped in the
+    penalty), only the class's m thrusters (the padding of the action rows is ignored)."""
+    rng = np.random.default_rng(3)
+    m, H, lam = 3, 40, 2.5e-3
+    env = env1(m=m, k=np.zeros(8))
+    acts = np.full((H, oracle.MAX_THR), 7.0)       # padding entries must not count
+    acts[:, :m] = rng.uniform(-1.5, 1.5, size=(H, m))
+    wp = [0.3, 0.2, -0.6]
+    L = _loss(env, state1(), acts, wp, weight=lam)
+    expect = H * 0.49 + lam * np.sum(acts[:, :m] ** 2)
+    assert L == pytest.approx(expect, rel=1e-14)
+
+
+def test_p13_step_k_is_driven_by_action_row_k():
+    """Two zero-order thrusters of equal gain at (0, +-0.1, 0) along +x give pure surge
+    (pin P2) from force F_k = 2 g s_k |s_k|, s_k = clip(a_k); with linear surge damping the
+    map is u_{k+1} = r u_k + (dt/M) F_k and p_{k+1} = p_k + dt u_{k+1}, so the loss follows
+    from a scalar recurrence driven by row k at step k (a shifted row fails)."""
+    rng = np.random.default_rng(11)
+    H, dt, g, lam = 60, 0.01, 30.0, 1e-3
+    env = _surge_env(dl=7.0)
+    env["m"] = 2
+    env["k"][0, :2] = g
+    env["tau"][0, :2] = 0.0
+    env["r"][0, 0] = [0.0, 0.1, 0.0]
+    env["r"][0, 1] = [0.0, -0.1, 0.0]
+    cmd = rng.uniform(-1.2, 1.2, size=H)
+    acts = np.zeros((H, oracle.MAX_THR))
+    acts[:, 0] = acts[:, 1] = cmd
+    wp = np.array([0.05, 0.1, -0.2])
+    r = 1.0 - dt * 7.0 / 15.0
+    u, x, L = 0.0, 0.0, 0.0
+    for kk in range(H):
+        s = np.clip(cmd[kk], -1.0, 1.0)
+        u = r * u + dt / 15.0 * 2.0 * g * s * abs(s)
+        x += dt * u
+        L += (x - wp[0]) ** 2 + wp[1] ** 2 + wp[2] ** 2 + lam * 2.0 * cmd[kk] ** 2
+    got = _loss(env, state1(), acts, wp, weight=lam)
+    assert abs(got - L) / L < 1e-12, (got, L)
