@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -202,7 +203,10 @@ __global__ void k_session_init(float* state, float* rec, int m, int64_t n, int64
     if (e >= npad) return;
     if (e < n) {
         const double* p = nominal + 23 * ci;
-        write_record<float>(cls[ci].inertia, cls[ci].g0, dt, p[0], p + 1, p + 7, p + 13, p[19], p + 20, rec, npad, e);
+        // the nominal values are validated at server creation and the server runs no payload
+        // class, so M is diagonal with positive entries and the record is always valid
+        (void)write_record<float>(cls[ci].inertia, cls[ci].g0, dt, p[0], p + 1, p + 7, p + 13, p[19], p + 20, rec,
+                                  npad, e);
         seeded_state<float>((uint64_t)e, seed, m, state, npad, e);
     } else {
         for (int j = 0; j < kStateFixed + m; ++j) state[j * npad + e] = (j == 3) ? 1.0f : 0.0f;
@@ -279,6 +283,7 @@ struct Session {
     int32_t hold = 1;
     bool keep = false;
     bool busy = false;     // a request is attached
+    int readers = 0;       // host copies of the state in progress: no request is admitted meanwhile
 };
 
 struct Req {
@@ -382,7 +387,7 @@ void mgx_server::admit_locked() {
                 done_cv.notify_all();
                 continue;
             }
-            if (s->second.busy) {
+            if (s->second.busy || s->second.readers > 0) {
                 if (fifo) break;
                 ++it;
                 continue;
@@ -605,7 +610,11 @@ extern "C" mgx_status mgx_server_create(const mgx_server_desc* d, mgx_server** o
             return fail(MGX_E_INVALID, "class %d has a payload: the server runs classes without one", c);
         d64[c] = to_desc64(cd);
         const double* p = d->nominal + 23 * c;
-        if (!(p[0] > 0)) return fail(MGX_E_INVALID, "nominal mass of class %d must be > 0", c);
+        if (!(p[0] > 0) || !std::isfinite(p[0])) return fail(MGX_E_INVALID, "nominal mass of class %d must be > 0", c);
+        for (int j = 1; j < 23; ++j)
+            if (!std::isfinite(p[j]) || (j < 20 && !(p[j] >= 0)))
+                return fail(MGX_E_INVALID, "nominal value %d of class %d must be finite%s", j, c,
+                            j < 20 ? " and >= 0" : "");
     }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(MGX_E_DEVICE, "no HIP device visible");
@@ -773,14 +782,29 @@ extern "C" mgx_status mgx_server_read_state(mgx_server* s, int64_t session, floa
         if (it == s->sessions.end()) return fail(MGX_E_INVALID, "session %lld is not resident", (long long)session);
         if (it->second.busy) return fail(MGX_E_STATE, "session %lld has a request in progress", (long long)session);
         S = it->second;
+        if (capacity < (int64_t)(kStateFixed + S.m) * S.n)
+            return fail(MGX_E_INVALID, "capacity %lld < %lld", (long long)capacity,
+                        (long long)((kStateFixed + S.m) * S.n));
+        // Not busy: no work on this session is in flight. Marking it read keeps the
+        // scheduler from admitting a queued request for it until the copy is done.
+        ++it->second.readers;
     }
     const int rows = kStateFixed + S.m;
-    if (capacity < rows * S.n) return fail(MGX_E_INVALID, "capacity %lld < %lld", (long long)capacity, (long long)(rows * S.n));
-    hipDevice_guard g(s->device);
-    std::vector<float> tmp((size_t)rows * S.npad);
-    hipError_t e = hipMemcpy(tmp.data(), (char*)s->arena_mem + S.off, sizeof(float) * tmp.size(), hipMemcpyDeviceToHost);
+    hipError_t e = hipSuccess;
+    {
+        hipDevice_guard g(s->device);
+        std::vector<float> tmp((size_t)rows * S.npad);
+        e = hipMemcpy(tmp.data(), (char*)s->arena_mem + S.off, sizeof(float) * tmp.size(), hipMemcpyDeviceToHost);
+        if (e == hipSuccess)
+            for (int j = 0; j < rows; ++j)
+                std::memcpy(out + j * S.n, tmp.data() + (size_t)j * S.npad, sizeof(float) * S.n);
+    }
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        --s->sessions[session].readers;
+        s->cv.notify_all();
+    }
     if (e != hipSuccess) return hip_fail(nullptr, e, "hipMemcpy(session state)");
-    for (int j = 0; j < rows; ++j) std::memcpy(out + j * S.n, tmp.data() + (size_t)j * S.npad, sizeof(float) * S.n);
     return MGX_OK;
 }
 
@@ -789,7 +813,8 @@ extern "C" mgx_status mgx_server_release(mgx_server* s, int64_t session) {
     std::lock_guard<std::mutex> lk(s->mu);
     auto it = s->sessions.find(session);
     if (it == s->sessions.end()) return fail(MGX_E_INVALID, "session %lld is not resident", (long long)session);
-    if (it->second.busy) return fail(MGX_E_STATE, "session %lld has a request in progress", (long long)session);
+    if (it->second.busy || it->second.readers > 0)
+        return fail(MGX_E_STATE, "session %lld has a request or a read in progress", (long long)session);
     s->free_session_locked(session);
     return MGX_OK;
 }

@@ -100,6 +100,32 @@ def test_session_continuation_equals_one_long_request():
     assert np.array_equal(cont, one)
 
 
+def test_state_read_never_mixes_steps():
+    """Reads of a session's state issued right after a continuing request is submitted
+    either find the request admitted (MGX_E_STATE) or hold it back until the copy is done:
+    every read returns the state before the request or after it, never a mix."""
+    s = server(chunk_steps=8)
+    r1 = s.submit(class_index=2, n_envs=16384, horizon=50, seed=31, keep=True)
+    sid = s.wait(r1).session
+    before = s.read_state(sid, 2, 16384)
+    r2 = s.submit(class_index=2, n_envs=16384, horizon=200, seed=0, keep=True, session=sid)
+    reads, refused = [], 0
+    for _ in range(40):
+        try:
+            reads.append(s.read_state(sid, 2, 16384))
+        except mgx.MgxError as e:
+            assert e.status == mgx.MGX_E_STATE
+            refused += 1
+    s.wait(r2)
+    after = s.read_state(sid, 2, 16384)
+    s.release(sid)
+    s.close()
+    assert not np.array_equal(before, after)
+    for x in reads:
+        assert np.array_equal(x, before) or np.array_equal(x, after)
+    print(f"reads {len(reads)}, refused while running {refused}", flush=True)
+
+
 def test_admission_waits_for_memory():
     """A budget of three 1024-environment sessions and nine requests: at no admission are
     more than two other sessions resident, and with 2000-step horizons the first three are
