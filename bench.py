@@ -300,11 +300,7 @@ def main():
                                "kind": "oracle", "value_one_thread": rate_1,
                                "sample": f"{n_s} of {N} environments (evenly spaced ids) x {T} steps, FP64 C oracle, "
                                          f"OpenMP over environments, {cpu_elapsed:.1f} s; one thread: 256 of them"}
-        # The rudder class's attitude dynamics amplify rounding about 20x more than the propeller
-        # classes' (the FP64 oracle with its state rounded to FP32 after every step already
-        # differs by 5.9e-4 after 1000 steps, against 2.9e-5 for the randomised workload), so its
-        # bar is 5e-3 rather than the 1e-3 of the propeller workloads.
-        tol = 5e-3 if variant == "rudders" else 1e-3
+        tol = 1e-3
         out["parity"] = {"metric": "max over envs |gpu - oracle| / max(|oracle|, rms), per state component",
                          "step": T, "max_err": float(err.max()), "tolerance": tol, "pass": bool(err.max() <= tol),
                          "envs_checked": n_s}

@@ -40,6 +40,7 @@ typedef int32_t mgx_status;
 #define MGX_E_INVALID (-1)   /* bad argument; nothing changed */
 #define MGX_E_NOMEM (-2)     /* device or host allocation failed */
 #define MGX_E_DEVICE (-3)    /* no usable GPU, or a HIP call failed (see mgx_last_hip_error) */
+#define MGX_E_NOT_SPD (-4)   /* M_RB + M_A of some environment is not positive definite */
 #define MGX_E_NONFINITE (-5) /* mgx_batch_check: some environment holds a non-finite value */
 #define MGX_E_BUDGET (-6)    /* serving: request larger than the memory budget */
 #define MGX_E_STATE (-7)     /* batch faulted earlier, or called in the wrong order */
@@ -71,6 +72,11 @@ size_t mgx_last_error(char* buf, size_t len);
 int32_t mgx_last_hip_error(void);
 /* Library version as major*10000 + minor*100 + patch. */
 int32_t mgx_version(void);
+/* Digest of the sources the library was compiled from (16 hex digits of SHA-256 over the
+ * kernel sources and this header, by relative path and content; "unknown" when built
+ * without it). A loader compares it with the digest of the sources beside it and refuses a
+ * library built from other sources. Static string, never freed. */
+const char* mgx_build_hash(void);
 /* Number of visible HIP devices (MGX_E_DEVICE if the runtime reports none). */
 mgx_status mgx_device_count(int32_t* count);
 
@@ -147,6 +153,12 @@ mgx_status mgx_class_step_cost(int32_t class_id, uint32_t batch_flags, double* f
 
 typedef struct mgx_batch mgx_batch;
 
+/* Device allocator of a batch: alloc returns `bytes` of device memory on the batch's
+ * device (NULL on failure, which the calling function reports as MGX_E_NOMEM); free
+ * releases what alloc returned. Called only from inside library calls on the batch. */
+typedef void* (*mgx_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*mgx_free_fn)(void* ptr, void* ctx);
+
 typedef struct {
     int32_t n_classes;          /* 1..MGX_MAX_CLASSES */
     int32_t precision;          /* MGX_FP32 or MGX_FP64 */
@@ -156,6 +168,19 @@ typedef struct {
     uint32_t flags;             /* MGX_FLAG_* */
     int32_t device;             /* HIP device ordinal; -1 = the calling thread's current device */
     void* stream;               /* hipStream_t for every call on the batch; NULL = null stream */
+    /* Optional caller-owned device buffers (e.g. torch tensors), adopted: the batch works
+     * in them in place and never frees them, so they must outlive it. Sizes and layout from
+     * mgx_batch_plan (state_elems, record_elems elements of the batch precision). NULL: the
+     * library allocates. At creation an adopted state keeps its valid slots as they are and
+     * only its padded slots are set to rest. */
+    void* state;
+    void* record;
+    /* Optional allocator for every device buffer the library allocates for this batch
+     * (state and record unless adopted, bookkeeping, rollout checkpoints, autotuner
+     * snapshots); both or neither. NULL: hipMalloc / hipFree. */
+    mgx_alloc_fn alloc;
+    mgx_free_fn free;
+    void* alloc_ctx;
 } mgx_batch_desc;
 
 /* Memory layout of a batch. Environments are numbered globally 0..n_total-1, class by
@@ -176,11 +201,20 @@ typedef struct {
     int64_t n[MGX_MAX_CLASSES], n_pad[MGX_MAX_CLASSES];
     int64_t env_off[MGX_MAX_CLASSES];     /* first global env id of the class */
     int64_t state_off[MGX_MAX_CLASSES], action_off[MGX_MAX_CLASSES], force_off[MGX_MAX_CLASSES];
+    int64_t record_elems;                 /* parameter record: record_off[c] + row * n_pad[c] + env */
+    int64_t record_off[MGX_MAX_CLASSES];
 } mgx_layout;
 
-/* Creates a batch on the given device and stream and allocates its state, parameter
- * record and bookkeeping (hipMalloc). Synchronous. The step counter starts at 0.
- * MGX_E_INVALID on bad fields; MGX_E_DEVICE if no GPU is usable; MGX_E_NOMEM. */
+/* The layout a batch created from desc would have (sizes of the state and record buffers a
+ * caller may pass in desc->state / desc->record). Host only, no device needed.
+ * MGX_E_INVALID on bad fields. */
+mgx_status mgx_batch_plan(const mgx_batch_desc* desc, mgx_layout* out);
+
+/* A batch of environments, each the vehicle model of Sec. III-B (Eqs. (1)-(3)) with the
+ * actuators of Sec. III-D, sharing the class constants of its segment. Creates it on the
+ * given device and stream and allocates its state, parameter record (unless adopted) and
+ * bookkeeping. Synchronous. The step counter starts at 0. MGX_E_INVALID on bad fields;
+ * MGX_E_DEVICE if no GPU is usable; MGX_E_NOMEM (also when a caller's allocator fails). */
 mgx_status mgx_batch_create(const mgx_batch_desc* desc, mgx_batch** out);
 mgx_status mgx_batch_destroy(mgx_batch* b);   /* synchronises its stream, frees; NULL is OK */
 mgx_status mgx_batch_layout(const mgx_batch* b, mgx_layout* out);
@@ -188,7 +222,8 @@ mgx_status mgx_batch_layout(const mgx_batch* b, mgx_layout* out);
 /* Per-environment parameters, each an array over the global env id (n_total entries per
  * row), always double precision. Rows of 6 are DOF-major: element (j, env) at j*n_total+env.
  *   mass  [n]   rigid-body mass (kg), > 0
- *   added [6][n] added-mass diagonal (positive; Fossen's -X_udot, ...), >= 0
+ *   added [6][n] added-mass diagonal (Fossen's -X_udot, ...; usually positive), finite, with
+ *               M_RB + M_A positive definite
  *   dlin  [6][n] linear damping, >= 0;  dquad [6][n] quadratic damping, >= 0
  *   buoy  [n]   buoyancy force (N), >= 0
  *   current [3][n] constant world-frame water velocity (m/s)  (Sec. III-B, ocean currents) */
@@ -204,9 +239,12 @@ typedef struct {
 /* Per-parameter-set setup (Eq. (1)-(2): M = M_RB + M_A with M_RB = diag(m, m, m, I)):
  * computes dt*M^-1, W - B, lag factors and the thruster layout in double precision on the
  * device, rounds once to the batch precision. on_device = 1: the arrays are device
- * pointers; 0: host pointers (copied, then the call returns; the device work stays async).
- * Host arrays are validated (finite, ranges above); device arrays are not.
- * Must be called before the first step (MGX_E_STATE otherwise). */
+ * pointers; 0: host pointers (copied before the call returns). Every environment's values
+ * are checked on the device before any record is written, and the call waits for that
+ * check: MGX_E_INVALID for a non-finite or out-of-range value (ranges above), MGX_E_NOT_SPD
+ * when some M_RB + M_A is not positive definite (a diagonal entry <= 0, or a Cholesky
+ * pivot <= 0 with a payload); the batch is then unchanged. The record build itself stays
+ * asynchronous. Must be called before the first step (MGX_E_STATE otherwise). */
 mgx_status mgx_batch_set_params(mgx_batch* b, const mgx_env_params* p, int32_t on_device);
 
 /* ------------------------------------------------------------------ domain randomisation */
@@ -256,7 +294,8 @@ mgx_status mgx_batch_resample(mgx_batch* b, const mgx_dr_spec* spec, const doubl
 mgx_status mgx_batch_get_params(const mgx_batch* b, double* mass, double* added, double* dlin, double* dquad,
                                 double* buoy, double* current);
 
-/* Resets environments. env_ids: host array of n global env ids, or NULL for all.
+/* Resets environments (an episode start, Sec. III-C: environments restart independently).
+ * env_ids: host array of n global env ids, or NULL for all.
  * init_state: device pointer to a full state buffer in this batch's layout and precision;
  * the listed environments are copied from it. NULL: seeded state — p = 0, q uniform on
  * the unit 3-sphere (normalised Gaussian), nu ~ N(0, 0.2^2) per component, n = 0 — drawn
@@ -265,7 +304,8 @@ mgx_status mgx_batch_get_params(const mgx_batch* b, double* mass, double* added,
 mgx_status mgx_batch_reset(mgx_batch* b, const int64_t* env_ids, int64_t n, const void* init_state,
                            uint64_t seed);
 
-/* Advances every environment by K >= 1 steps of dt (K = 0: the launch-shape K), fused in
+/* The step of Sec. III-B (Eqs. (1)-(3)) with the rotor and thrust models of Sec. III-D:
+ * advances every environment by K >= 1 steps of dt (K = 0: the launch-shape K), fused in
  * one launch (MGX_STEP_UNFUSED: K launches of one step). Step k of the call (global step
  * t = t0 + k, t0 = the batch step counter) uses row floor(t / hold) - row0 of `actions`
  * (device pointer, n_rows rows in the layout above, batch precision). Commands are
@@ -281,13 +321,15 @@ mgx_status mgx_batch_step(mgx_batch* b, const void* actions, int64_t n_rows, int
 mgx_status mgx_batch_get_step(const mgx_batch* b, int64_t* t);
 mgx_status mgx_batch_set_step(mgx_batch* b, int64_t t);
 
-/* Copies the whole state (state_elems elements) out / in. to_host/from_host = 1: host
+/* The vehicle state of Sec. III-B (position, attitude, body velocity nu) and the rotor
+ * states of Sec. III-D. Copies the whole state (state_elems elements) out / in. to_host/from_host = 1: host
  * memory, and the call synchronises the stream; 0: device memory, asynchronous. */
 mgx_status mgx_batch_get_state(mgx_batch* b, void* out, int32_t to_host);
 mgx_status mgx_batch_set_state(mgx_batch* b, const void* in, int32_t from_host);
 
 /* Batch statistics of the last call that passed MGX_STEP_STATS (synchronises the stream):
- * per class, over its valid environments, wavefront-reduced on the device. */
+ * per class, over its valid environments, wavefront-reduced on the device. mean_kinetic is
+ * the kinetic energy of Eq. (1)'s mass matrix M_RB + M_A (the full one with a payload). */
 typedef struct {
     int64_t step;                                  /* step counter at that call's end */
     int64_t n_nonfinite[MGX_MAX_CLASSES];          /* envs with any non-finite state value */
@@ -300,12 +342,17 @@ typedef struct {
 mgx_status mgx_batch_get_stats(mgx_batch* b, mgx_stats* out);
 
 /* Synchronises the stream and reports the device-side error word and non-finite count
- * (of the last MGX_STEP_STATS call): MGX_OK, MGX_E_NONFINITE (count in *n_nonfinite), or
- * MGX_E_INVALID if a kernel met an action row outside its buffer. */
+ * (of the last MGX_STEP_STATS call). In order of precedence: MGX_E_NOT_SPD if a parameter
+ * record (mgx_batch_resample, mgx_station_resample) was built from a mass matrix that is
+ * not positive definite; MGX_E_INVALID if a record was built from an invalid value or a
+ * kernel met an action row outside its buffer (both sticky until destroy); MGX_E_NONFINITE
+ * (count in *n_nonfinite); MGX_OK. An invalid record holds NaN in its dt M^-1 rows, so its
+ * environment also turns non-finite at its next step. */
 mgx_status mgx_batch_check(mgx_batch* b, int64_t* n_nonfinite);
 mgx_status mgx_batch_sync(mgx_batch* b);
 
-/* Action stream generator on the device: fills `out` (device, rows x row_elems, batch
+/* Action stream generator on the device (the synthetic command streams of the benchmark
+ * workloads; the paper's policies are not part of this library): fills `out` (device, rows x row_elems, batch
  * precision) with a = ((w >> 8) - 2^23) * 2^-23 in [-1, 1), where w is word (i mod 4) of
  * Philox4x32-10 (Salmon et al., SC'11) at key (seed mod 2^32, 4 << 24) and counter
  * (global env id, row_offset + row, i / 4, 0). Padded slots get 0. Asynchronous. */
@@ -349,7 +396,9 @@ mgx_status mgx_autotune_load(const char* path);
 
 /* ------------------------------------------------------------------ differentiable rollout */
 
-/* Forward pass of a differentiable rollout: H steps exactly as mgx_batch_step (same action
+/* Differentiable rollout of the step map of Sec. III-B (the paper trains model-free and
+ * differentiates nothing; this reverse mode is an addition of the library, for losses over
+ * positions and commands). Forward pass: H steps exactly as mgx_batch_step (same action
  * indexing, clip, launch per class; MGX_E_INVALID for a batch with a fin class, whose
  * adjoint is not written), additionally writing the position after every step
  * and the full state every ckpt_every steps into library-owned scratch (allocated on first
@@ -562,9 +611,12 @@ mgx_status mgx_server_wait(mgx_server* s, int64_t request_id, double timeout_s, 
  * iteration; its session is released unless it was kept by an earlier request. */
 mgx_status mgx_server_cancel(mgx_server* s, int64_t request_id);
 /* Copies a resident session's state ([13 + m][n_envs], component-major, float) to host
- * memory (synchronises with the scheduler). MGX_E_INVALID if the session is not resident. */
+ * memory. MGX_E_INVALID if the session is not resident or capacity is short; MGX_E_STATE
+ * while a request on the session is admitted. A request for the session that is queued or
+ * submitted during the copy is admitted only after it, so the copy never mixes steps. */
 mgx_status mgx_server_read_state(mgx_server* s, int64_t session, float* out, int64_t capacity);
-/* Releases a kept session (after its requests finish). */
+/* Releases a kept session (after its requests finish; MGX_E_STATE while one runs or its
+ * state is being read). */
 mgx_status mgx_server_release(mgx_server* s, int64_t session);
 mgx_status mgx_server_stats_get(mgx_server* s, mgx_server_stats* out);
 /* Stops the scheduler after draining in-flight work; frees everything. */

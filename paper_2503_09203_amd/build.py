@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import glob
+import hashlib
 import os
 import subprocess
 import sys
@@ -28,6 +29,23 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
+def source_hash(root: str = ROOT) -> str:
+    """SHA-256 (first 16 hex digits) over the device library's sources under ``root``: every
+    ``*.hip`` and ``*.hpp`` of the package's csrc/ and every ``*.h`` of include/, by relative
+    path and content. Compiled into the library and checked when it is loaded."""
+    h = hashlib.sha256()
+    pkg = os.path.basename(PKG)
+    files = sorted(glob.glob(os.path.join(root, pkg, "csrc", "*.hip")) + glob.glob(os.path.join(root, pkg, "csrc", "*.hpp"))
+                   + glob.glob(os.path.join(root, "include", "*.h")))
+    for f in files:
+        h.update(os.path.relpath(f, root).replace(os.sep, "/").encode())
+        h.update(b"\0")
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+        h.update(b"\0")
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False, extra=(), jobs: int = 0) -> str:
     """Compile every HIP source into libmgx.so (always recompiles): one object per source,
     compiled in parallel, then linked."""
@@ -37,7 +55,7 @@ def build(verbose: bool = False, extra=(), jobs: int = 0) -> str:
     tag = f".{os.getpid()}"
     srcs = sources()
     objs = [os.path.join(objdir, os.path.basename(s)[:-4] + tag + ".o") for s in srcs]
-    compile_flags = [f for f in FLAGS if f != "-shared"]
+    compile_flags = [f for f in FLAGS if f != "-shared"] + [f'-DMGX_BUILD_HASH="{source_hash()}"']
     cmds = [[hipcc, *compile_flags, *extra, "-I", INCLUDE, "-I", CSRC, "-c", s, "-o", o] for s, o in zip(srcs, objs)]
     if verbose:
         for c in cmds:

@@ -340,18 +340,20 @@ extern "C" mgx_status mgx_rollout_forward(mgx_batch* b, const void* actions, int
     const size_t P = (size_t)b->prec;
     const size_t ck_bytes = P * (size_t)nck * b->state_elems, seg_bytes = P * (size_t)2 * ckpt_every * b->state_elems;
     if (ck_bytes > b->ckpt_bytes) {
-        if (b->d_ckpt) (void)hipFree(b->d_ckpt);
+        b->dev_free(b->d_ckpt);
         b->d_ckpt = nullptr;
         b->ckpt_bytes = 0;
-        hipError_t e = hipMalloc(&b->d_ckpt, ck_bytes);
+        hipError_t e;
+        b->d_ckpt = b->dev_alloc(ck_bytes, &e);
         if (e != hipSuccess) return hip_fail(nullptr, e, "hipMalloc(checkpoints)");
         b->ckpt_bytes = ck_bytes;
     }
     if (seg_bytes > b->seg_bytes) {
-        if (b->d_seg) (void)hipFree(b->d_seg);
+        b->dev_free(b->d_seg);
         b->d_seg = nullptr;
         b->seg_bytes = 0;
-        hipError_t e = hipMalloc(&b->d_seg, seg_bytes);
+        hipError_t e;
+        b->d_seg = b->dev_alloc(seg_bytes, &e);
         if (e != hipSuccess) return hip_fail(nullptr, e, "hipMalloc(segment scratch)");
         b->seg_bytes = seg_bytes;
     }

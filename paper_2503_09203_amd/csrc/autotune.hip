@@ -115,7 +115,11 @@ extern "C" mgx_status mgx_autotune(mgx_batch* b, const void* actions, int64_t n_
     hipEvent_t e0 = nullptr, e1 = nullptr;
     mgx_status st = MGX_OK;
     double best_us = 1e30;
-    HIP_TRY_T(hipMalloc(&snap, bytes));
+    {
+        hipError_t ea;
+        snap = b->dev_alloc(bytes, &ea);
+        HIP_TRY_T(ea);
+    }
     HIP_TRY_T(hipEventCreate(&e0));
     HIP_TRY_T(hipEventCreate(&e1));
     HIP_TRY_T(hipMemcpyAsync(snap, b->d_state, bytes, hipMemcpyDeviceToDevice, b->stream));
@@ -155,7 +159,7 @@ done:
     if (st != MGX_OK) apply(b, saved);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    if (snap) (void)hipFree(snap);
+    b->dev_free(snap);
     return st;
 }
 

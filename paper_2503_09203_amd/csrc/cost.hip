@@ -110,12 +110,15 @@ static CostTally measure(uint32_t flags, uint32_t fin_mask = 0, bool payload = f
     for (int j = 0; j < 6; ++j) E.IoA[j] = j < 3 ? 2.0 + j : 0.01;
     for (int j = 0; j < 3; ++j) E.mrg[j] = 0.1 * (j + 1);
     g_tally = CostTally();
+    // classes with fins run the compensated attitude update in float
+    StateLo<Cnt> lo;
+    for (int j = 0; j < 4; ++j) lo.q[j] = 0.0;
     if (payload && fin_mask)
-        step_body<Cnt, M, false, true, true, true>(C, E, IA2, Brb, s, a);
+        step_body<Cnt, M, false, true, true, true, true>(C, E, IA2, Brb, s, a, nullptr, &lo);
     else if (payload)
         step_body<Cnt, M, false, true, false, true>(C, E, IA2, Brb, s, a);
     else if (fin_mask)
-        step_body<Cnt, M, false, true, true>(C, E, IA2, Brb, s, a);
+        step_body<Cnt, M, false, true, true, false, true>(C, E, IA2, Brb, s, a, nullptr, &lo);
     else if (flags & MGX_COST_SHAPED)
         step_body<Cnt, M, false, true>(C, E, IA2, Brb, s, a);
     else

@@ -61,7 +61,8 @@ __device__ void dr_group(const mgx_dr_dist& d, const double* nom, const double* 
 // The per-lane draw of environment e (its 23 generator calls in sequence) and its record.
 template <typename T>
 __device__ void dr_resample_one(const mgx_dr_spec& spec, const DrNominal& nom, const ClassDesc64& cls, double dt,
-                                T* rec, int64_t npad, int64_t env_off, int64_t e, uint64_t seed, uint64_t epoch) {
+                                T* rec, int64_t npad, int64_t env_off, int64_t e, uint64_t seed, uint64_t epoch,
+                                int32_t* err) {
     const uint64_t g = (uint64_t)(env_off + e);
     double u[46];
     for (int j = 0; j < 23; ++j) {
@@ -77,7 +78,8 @@ __device__ void dr_resample_one(const mgx_dr_spec& spec, const DrNominal& nom, c
     dr_group(spec.dquad, nom.v + 13, u, 26, 6, dquad);
     dr_group(spec.buoy, nom.v + 19, u, 38, 1, &buoy);
     dr_group(spec.current, nom.v + 20, u, 40, 3, cur);
-    write_record<T>(cls.inertia, cls.g0, dt, mass, added, dlin, dquad, buoy, cur, rec, npad, e, cls.rg);
+    const int32_t f = write_record<T>(cls.inertia, cls.g0, dt, mass, added, dlin, dquad, buoy, cur, rec, npad, e, cls.rg);
+    if (f) atomicOr(err, f);
 }
 
 // Masked redraw: the environments e < n whose mask byte is set, epoch epochs[e]. Few lanes
@@ -94,7 +96,7 @@ constexpr int kSpreadDraws = 8;
 template <typename T>
 __device__ void dr_resample_spread(const mgx_dr_spec& spec, const DrNominal& nom, const ClassDesc64& cls, double dt,
                                    T* rec, int64_t npad, int64_t env_off, int64_t n, uint64_t seed,
-                                   const uint8_t* mask, const int32_t* epochs) {
+                                   const uint8_t* mask, const int32_t* epochs, int32_t* err) {
     __shared__ mgx_dr_dist sd[6];
     __shared__ double snom[23];
     if (threadIdx.x == 0) {
@@ -117,7 +119,7 @@ __device__ void dr_resample_spread(const mgx_dr_spec& spec, const DrNominal& nom
     const mgx_dr_dist& d = sd[grp];
     uint64_t need = __ballot(want);
     if (__popcll(need) > kSpreadDraws) {
-        if (want) dr_resample_one<T>(spec, nom, cls, dt, rec, npad, env_off, t, seed, (uint32_t)ep_own);
+        if (want) dr_resample_one<T>(spec, nom, cls, dt, rec, npad, env_off, t, seed, (uint32_t)ep_own, err);
         return;
     }
     while (need) {
@@ -137,8 +139,11 @@ __device__ void dr_resample_spread(const mgx_dr_spec& spec, const DrNominal& nom
         double p[23];
 #pragma unroll
         for (int i = 0; i < 23; ++i) p[i] = __shfl(val, i);
-        if (lane == src)
-            write_record<T>(cls.inertia, cls.g0, dt, p[0], p + 1, p + 7, p + 13, p[19], p + 20, rec, npad, e, cls.rg);
+        if (lane == src) {
+            const int32_t f =
+                write_record<T>(cls.inertia, cls.g0, dt, p[0], p + 1, p + 7, p + 13, p[19], p + 20, rec, npad, e, cls.rg);
+            if (f) atomicOr(err, f);
+        }
     }
 }
 
@@ -147,15 +152,15 @@ __device__ void dr_resample_spread(const mgx_dr_spec& spec, const DrNominal& nom
 template <typename T>
 __global__ void k_dr_resample(mgx_dr_spec spec, DrNominal nom, const ClassDesc64* cls, int ci, double dt, T* rec,
                               int64_t npad, int64_t env_off, const int64_t* ids, int64_t n_ids, uint64_t seed,
-                              uint64_t epoch, const uint8_t* mask, const int32_t* epochs) {
+                              uint64_t epoch, const uint8_t* mask, const int32_t* epochs, int32_t* err) {
     if (mask) {
-        dr_resample_spread<T>(spec, nom, cls[ci], dt, rec, npad, env_off, n_ids, seed, mask, epochs);
+        dr_resample_spread<T>(spec, nom, cls[ci], dt, rec, npad, env_off, n_ids, seed, mask, epochs, err);
         return;
     }
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_ids) return;
     const int64_t e = ids ? ids[t] : t;
-    dr_resample_one<T>(spec, nom, cls[ci], dt, rec, npad, env_off, e, seed, epoch);
+    dr_resample_one<T>(spec, nom, cls[ci], dt, rec, npad, env_off, e, seed, epoch, err);
 }
 
 // Smallest value a distribution can produce (for validation).
@@ -233,7 +238,8 @@ static void launch_resample(mgx_batch* b, const mgx_dr_spec& spec, const double*
     for (int j = 0; j < 23; ++j) nom.v[j] = nominal[23 * c + j];
     const unsigned grid = (unsigned)((nid + 127) / 128);
     hipLaunchKernelGGL(k_dr_resample<T>, dim3(grid), dim3(128), 0, b->stream, spec, nom, b->d_classdesc, c, b->dt,
-                       (T*)b->seg_rec(c), b->npad[c], b->env_off[c], ids, nid, seed, epoch, mask, epochs);
+                       (T*)b->seg_rec(c), b->npad[c], b->env_off[c], ids, nid, seed, epoch, mask, epochs,
+                       &b->d_misc->err);
 }
 
 mgx_status resample_masked(mgx_batch* b, const mgx_dr_spec* spec, const double* nominal, const uint8_t* mask,

@@ -37,12 +37,10 @@ __device__ __forceinline__ double u53(uint32_t hi, uint32_t lo) {
 constexpr uint32_t kStreamInit = 3u;
 constexpr uint32_t kStreamAction = 4u;
 
-// dt M^-1 for a class with a payload (centre of gravity at rg from the body origin):
-// M = [m 1 + A_1, -m S(rg); m S(rg), I_o + A_2] with I_o = I_g + m(|rg|^2 1 - rg rg^T),
-// symmetric positive definite; inverted by Cholesky factorisation in double.
-__device__ __forceinline__ void payload_minv(const double inertia[3], const double rg[3], double m,
-                                             const double added[6], double dt, double out[6][6]) {
-    double M[6][6];
+// M = M_RB + M_A of a class with a payload (centre of gravity at rg from the body origin):
+// [m 1 + A_1, -m S(rg); m S(rg), I_o + A_2] with I_o = I_g + m(|rg|^2 1 - rg rg^T).
+__device__ __forceinline__ void payload_mass_matrix(const double inertia[3], const double rg[3], double m,
+                                                    const double added[6], double M[6][6]) {
     const double S[3][3] = {{0.0, -rg[2], rg[1]}, {rg[2], 0.0, -rg[0]}, {-rg[1], rg[0], 0.0}};
     const double r2 = rg[0] * rg[0] + rg[1] * rg[1] + rg[2] * rg[2];
     for (int i = 0; i < 3; ++i)
@@ -53,10 +51,18 @@ __device__ __forceinline__ void payload_minv(const double inertia[3], const doub
             M[3 + i][3 + j] = ((i == j) ? inertia[i] + m * r2 : 0.0) - m * rg[i] * rg[j];
         }
     for (int j = 0; j < 6; ++j) M[j][j] += added[j];
-    double L[6][6] = {};
+}
+
+// Cholesky factor L (M = L L^T) in double; false when a pivot is not positive (M is not
+// positive definite) or not finite.
+__device__ __forceinline__ bool cholesky6(const double M[6][6], double L[6][6]) {
+    bool ok = true;
+    for (int j = 0; j < 6; ++j)
+        for (int i = 0; i < 6; ++i) L[j][i] = 0.0;
     for (int j = 0; j < 6; ++j) {
         double d = M[j][j];
         for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+        ok = ok && d > 0.0 && d <= 1.0e300;
         L[j][j] = sqrt(d);
         for (int i = j + 1; i < 6; ++i) {
             double v = M[i][j];
@@ -64,6 +70,16 @@ __device__ __forceinline__ void payload_minv(const double inertia[3], const doub
             L[i][j] = v / L[j][j];
         }
     }
+    return ok;
+}
+
+// dt M^-1 of a payload class by Cholesky factorisation in double; false (out undefined)
+// when M is not positive definite.
+__device__ __forceinline__ bool payload_minv(const double inertia[3], const double rg[3], double m,
+                                             const double added[6], double dt, double out[6][6]) {
+    double M[6][6], L[6][6];
+    payload_mass_matrix(inertia, rg, m, added, M);
+    if (!cholesky6(M, L)) return false;
     for (int c = 0; c < 6; ++c) {  // column c of M^-1: L y = e_c, then L^T x = y
         double y[6], x[6];
         for (int i = 0; i < 6; ++i) {
@@ -78,21 +94,56 @@ __device__ __forceinline__ void payload_minv(const double inertia[3], const doub
         }
         for (int i = 0; i < 6; ++i) out[i][c] = dt * x[i];
     }
+    return true;
+}
+
+__device__ __forceinline__ bool finite64(double x) { return x - x == 0.0; }
+
+// Validity of one environment's parameters, as a record build needs them: kErrParam when
+// a value is not finite or out of range (mass > 0; added mass, damping, buoyancy >= 0),
+// kErrNotSpd when M = M_RB + M_A is not positive definite (diagonal: every M_jj > 0; with a
+// payload: every Cholesky pivot > 0). 0 when valid.
+__device__ __forceinline__ int32_t params_flags(const double inertia[3], double m, const double added[6],
+                                                const double dlin[6], const double dquad[6], double buoy,
+                                                const double cur[3], const double* rg) {
+    bool ok = finite64(m) && m > 0.0 && finite64(buoy) && buoy >= 0.0;
+    bool spd = true;
+    for (int j = 0; j < 6; ++j) {
+        ok = ok && finite64(added[j]) && finite64(dlin[j]) && dlin[j] >= 0.0 && finite64(dquad[j]) &&
+             dquad[j] >= 0.0;
+        const double Mjj = (j < 3 ? m : inertia[j - 3]) + added[j];
+        spd = spd && Mjj > 0.0;
+    }
+    for (int j = 0; j < 3; ++j) ok = ok && finite64(cur[j]);
+    if (!ok) return kErrParam;
+    if (spd && rg && (rg[0] != 0.0 || rg[1] != 0.0 || rg[2] != 0.0)) {
+        double M[6][6], L[6][6];
+        payload_mass_matrix(inertia, rg, m, added, M);
+        spd = cholesky6(M, L);
+    }
+    return spd ? 0 : kErrNotSpd;
 }
 
 // Per-environment record (dt M^-1, m, M_A, d_L, d_Q, W - B, B, V_c), derived in double
 // (M = M_RB + M_A with M_RB = diag(m, m, m, I)) and rounded once; column i of a segment.
 // With a payload (rg non-null and non-zero) dt M^-1 is the full symmetric inverse: its
 // diagonal in the usual rows, the off-diagonal entries in the 15 rows from kRecMinvOff.
+// Returns params_flags of the inputs; when they are invalid the dt M^-1 rows hold NaN, so
+// the environment's state turns non-finite at its next step instead of running on with an
+// undefined inverse.
 template <typename T>
-__device__ __forceinline__ void write_record(const double inertia[3], double g0, double dt, double m,
-                                             const double added[6], const double dlin[6], const double dquad[6],
-                                             double buoy, const double cur[3], T* rec, int64_t npad, int64_t i,
-                                             const double* rg = nullptr) {
+__device__ __forceinline__ int32_t write_record(const double inertia[3], double g0, double dt, double m,
+                                                const double added[6], const double dlin[6], const double dquad[6],
+                                                double buoy, const double cur[3], T* rec, int64_t npad, int64_t i,
+                                                const double* rg = nullptr) {
+    const int32_t flags = params_flags(inertia, m, added, dlin, dquad, buoy, cur, rg);
     const bool payload = rg && (rg[0] != 0.0 || rg[1] != 0.0 || rg[2] != 0.0);
+    const double nan = __builtin_nan("");
     if (payload) {
         double Mi[6][6];
-        payload_minv(inertia, rg, m, added, dt, Mi);
+        if (flags || !payload_minv(inertia, rg, m, added, dt, Mi))
+            for (int a = 0; a < 6; ++a)
+                for (int b = 0; b < 6; ++b) Mi[a][b] = nan;
         int k = 0;
         for (int a = 0; a < 6; ++a)
             for (int b = a + 1; b < 6; ++b, ++k) rec[(kRecMinvOff + k) * npad + i] = (T)(0.5 * (Mi[a][b] + Mi[b][a]));
@@ -100,7 +151,7 @@ __device__ __forceinline__ void write_record(const double inertia[3], double g0,
     }
     for (int j = 0; j < 6; ++j) {
         const double Mjj = (j < 3 ? m : inertia[j - 3]) + added[j];
-        if (!payload) rec[(kRecDtMinv + j) * npad + i] = (T)(dt / Mjj);
+        if (!payload) rec[(kRecDtMinv + j) * npad + i] = (T)(flags ? nan : dt / Mjj);
         rec[(kRecAdded + j) * npad + i] = (T)added[j];
         rec[(kRecDlin + j) * npad + i] = (T)dlin[j];
         rec[(kRecDquad + j) * npad + i] = (T)dquad[j];
@@ -109,6 +160,7 @@ __device__ __forceinline__ void write_record(const double inertia[3], double g0,
     rec[kRecWmB * npad + i] = (T)(m * g0 - buoy);
     rec[kRecBuoy * npad + i] = (T)buoy;
     for (int j = 0; j < 3; ++j) rec[(kRecCurrent + j) * npad + i] = (T)cur[j];
+    return flags;
 }
 
 // Seeded initial state of global env id g: p = 0, q uniform on S^3 (normalised Gaussian),
@@ -340,6 +392,11 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
     static_assert(!(kSingle && kOut), "the single-step form has no per-step outputs");
     const int64_t np = A.npad;
     const ClassT<T> C = class_in_vgpr<T, M, kFins>(Cs);
+    // classes with fins carry the attitude's low-order words through the launch (float)
+    constexpr bool kComp = kFins && std::is_same<T, float>::value;
+    StateLo<T> lo;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) lo.q[j] = T(0);
     T* S = (T*)A.state;
     const T* Rc = (const T*)A.rec;
     StateT<T, M> s;
@@ -375,7 +432,7 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
     T IA2[3], Brb[3];
     env_prologue<T, kPayload>(C, E, IA2, Brb);
     if constexpr (kSingle) {
-        step_body<T, M, false, kShaped, kFins, kPayload>(C, E, IA2, Brb, s, cur);
+        step_body<T, M, false, kShaped, kFins, kPayload, kComp>(C, E, IA2, Brb, s, cur, nullptr, &lo);
     } else {
 
     // Runs of steps between action-row switches: the inner loop carries only its counter,
@@ -387,7 +444,7 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
         for (int j = 0; j < run; ++j, ++k) {
             if constexpr (kOut) {
                 T f[kForceLen];
-                step_body<T, M, true, kShaped, kFins, kPayload>(C, E, IA2, Brb, s, cur, f);
+                step_body<T, M, true, kShaped, kFins, kPayload, kComp>(C, E, IA2, Brb, s, cur, f, &lo);
                 if (A.forces) {
                     T* fo = (T*)A.forces + k * A.force_stride + env;
 #pragma unroll
@@ -405,7 +462,7 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
                     for (int i = 0; i < M; ++i) to[(kStateFixed + i) * np] = s.n[i];
                 }
             } else {
-                step_body<T, M, false, kShaped, kFins, kPayload>(C, E, IA2, Brb, s, cur);
+                step_body<T, M, false, kShaped, kFins, kPayload, kComp>(C, E, IA2, Brb, s, cur, nullptr, &lo);
             }
         }
         phase += run;
@@ -421,7 +478,7 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
         }
     }
     }
-    if (bad && (threadIdx.x & (kWave - 1)) == 0) atomicOr(&A.misc->err, 1);
+    if (bad && (threadIdx.x & (kWave - 1)) == 0) atomicOr(&A.misc->err, kErrActionRow);
 
     // The same check as renorm_attitude, written out: as a call it changes the register
     // allocation of the fused loop (15 more instructions in the plain K-step kernel).
@@ -454,9 +511,25 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
             if (fin) {
                 float sp = (float)sqrt_(s.nu[0] * s.nu[0] + s.nu[1] * s.nu[1] + s.nu[2] * s.nu[2]);
                 float rt = (float)sqrt_(s.nu[3] * s.nu[3] + s.nu[4] * s.nu[4] + s.nu[5] * s.nu[5]);
+                // nu^T (M_RB + M_A) nu. Diagonal M: (m + A_j) v_j^2 + (I_j + A_{3+j}) w_j^2.
+                // With a payload the full M: m |v|^2 + A_1 v.v - 2 v.(m r_g x w) + w^T (I_o + A_2) w.
+                const T* v = s.nu;
+                const T* w = s.nu + 3;
                 T ke = T(0);
+                if constexpr (kPayload) {
+                    T mrw[3], Iw[3];
+                    cross(E.mrg, w, mrw);
+                    Iw[0] = fma_(E.IoA[4], w[2], fma_(E.IoA[3], w[1], E.IoA[0] * w[0]));
+                    Iw[1] = fma_(E.IoA[5], w[2], fma_(E.IoA[1], w[1], E.IoA[3] * w[0]));
+                    Iw[2] = fma_(E.IoA[2], w[2], fma_(E.IoA[5], w[1], E.IoA[4] * w[0]));
 #pragma unroll
-                for (int j = 0; j < 6; ++j) ke += s.nu[j] * s.nu[j] * (C.dt / E.dtMinv[j]);
+                    for (int j = 0; j < 3; ++j)
+                        ke += v[j] * ((E.mass + E.A[j]) * v[j] - T(2) * mrw[j]) + w[j] * Iw[j];
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+                        ke += (E.mass + E.A[j]) * (v[j] * v[j]) + IA2[j] * (w[j] * w[j]);
+                }
                 st[kStMaxSpeed] = sp;
                 st[kStSumSpeed] = sp;
                 st[kStMaxRate] = rt;

@@ -18,132 +18,50 @@ __global__ void k_class_setup(const ClassDesc64* in, ClassT<float>* outf, ClassT
                               uint32_t flags) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
-    const ClassDesc64& d = in[c];
     ClassT<double> D;
-    const int shaped = shaped_thrust(d) ? 1 : 0;
-    const uint32_t fins = fin_mask_of(d);
-    for (int i = 0; i < kMaxThr; ++i) {
-        for (int j = 0; j < 3; ++j) D.fin_r[i][j] = D.fin_c[i][j] = D.fin_n[i][j] = 0.0;
-        D.fin_max[i] = D.fin_kl[i] = D.fin_kd0[i] = D.fin_kd[i] = 0.0;
-        if (i < d.m && ((fins >> i) & 1u)) {
-            // fin: no layout column; the plane's basis from the span and the chord at zero
-            // deflection (the chord's span component dropped)
-            for (int j = 0; j < 6; ++j) D.Bk[j][i] = 0.0;
-            double sl = sqrt(d.span[i][0] * d.span[i][0] + d.span[i][1] * d.span[i][1] + d.span[i][2] * d.span[i][2]);
-            double s[3] = {d.span[i][0] / sl, d.span[i][1] / sl, d.span[i][2] / sl};
-            double es = d.e[i][0] * s[0] + d.e[i][1] * s[1] + d.e[i][2] * s[2];
-            double c[3] = {d.e[i][0] - es * s[0], d.e[i][1] - es * s[1], d.e[i][2] - es * s[2]};
-            double cl = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
-            for (int j = 0; j < 3; ++j) c[j] /= cl;
-            const double nn[3] = {s[1] * c[2] - s[2] * c[1], s[2] * c[0] - s[0] * c[2], s[0] * c[1] - s[1] * c[0]};
-            for (int j = 0; j < 3; ++j) {
-                D.fin_r[i][j] = d.r[i][j];
-                D.fin_c[i][j] = c[j];
-                D.fin_n[i][j] = nn[j];
-            }
-            D.fin_max[i] = d.fin_max[i];
-            D.fin_kl[i] = d.fin_lift[i];
-            D.fin_kd0[i] = d.fin_drag0[i];
-            D.fin_kd[i] = d.fin_drag[i];
-            double tau = d.tau[i];
-            D.alpha[i] = tau > 0.0 ? ((flags & kFlagLagEuler) ? dt / tau : 1.0 - exp(-dt / tau)) : 1.0;
-            D.dz[i] = 0.0;
-            D.rev[i] = 1.0;
-        } else if (i < d.m) {
-            double len = sqrt(d.e[i][0] * d.e[i][0] + d.e[i][1] * d.e[i][1] + d.e[i][2] * d.e[i][2]);
-            double e[3] = {d.e[i][0] / len, d.e[i][1] / len, d.e[i][2] / len};
-            const double* r = d.r[i];
-            const double k = d.k[i];
-            D.Bk[0][i] = k * e[0];
-            D.Bk[1][i] = k * e[1];
-            D.Bk[2][i] = k * e[2];
-            // moment about the CoG plus the shaft torque c_i about the thrust axis
-            const double c = d.reaction[i];
-            D.Bk[3][i] = k * ((r[1] * e[2] - r[2] * e[1]) + c * e[0]);
-            D.Bk[4][i] = k * ((r[2] * e[0] - r[0] * e[2]) + c * e[1]);
-            D.Bk[5][i] = k * ((r[0] * e[1] - r[1] * e[0]) + c * e[2]);
-            double tau = d.tau[i];
-            D.alpha[i] = tau > 0.0 ? ((flags & kFlagLagEuler) ? dt / tau : 1.0 - exp(-dt / tau)) : 1.0;
-            D.dz[i] = d.dz[i];
-            D.rev[i] = reverse_ratio(d, i);
-        } else {
-            for (int j = 0; j < 6; ++j) D.Bk[j][i] = 0.0;
-            D.alpha[i] = 0.0;
-            D.dz[i] = 0.0;
-            D.rev[i] = 1.0;
-        }
-    }
-    for (int j = 0; j < 3; ++j) {
-        D.inertia[j] = d.inertia[j];
-        D.rb[j] = d.rb[j];
-    }
-    D.g0 = d.g0;
-    D.dt = dt;
-    D.inv_dt = 1.0 / dt;
-    D.half_dt = 0.5 * dt;
-    D.m = d.m;
-    D.flags = flags;
-    D.shaped = shaped;
-    D.pad2 = 0;
-    D.fin_mask = fins;
-    D.pad3 = 0;
-    for (int j = 0; j < 3; ++j) D.rg[j] = d.rg[j];
-    D.payload = has_payload(d) ? 1 : 0;
-    D.pad4 = 0;
     ClassT<float> F;
-    for (int i = 0; i < kMaxThr; ++i) {
-        for (int j = 0; j < 6; ++j) F.Bk[j][i] = (float)D.Bk[j][i];
-        F.alpha[i] = (float)D.alpha[i];
-        F.dz[i] = (float)D.dz[i];
-        F.rev[i] = (float)D.rev[i];
-        for (int j = 0; j < 3; ++j) {
-            F.fin_r[i][j] = (float)D.fin_r[i][j];
-            F.fin_c[i][j] = (float)D.fin_c[i][j];
-            F.fin_n[i][j] = (float)D.fin_n[i][j];
-        }
-        F.fin_max[i] = (float)D.fin_max[i];
-        F.fin_kl[i] = (float)D.fin_kl[i];
-        F.fin_kd0[i] = (float)D.fin_kd0[i];
-        F.fin_kd[i] = (float)D.fin_kd[i];
-    }
-    for (int j = 0; j < 3; ++j) {
-        F.inertia[j] = (float)D.inertia[j];
-        F.rb[j] = (float)D.rb[j];
-    }
-    F.g0 = (float)D.g0;
-    F.dt = (float)D.dt;
-    F.inv_dt = (float)D.inv_dt;
-    F.half_dt = (float)D.half_dt;
-    F.m = D.m;
-    F.flags = flags;
-    F.shaped = shaped;
-    F.pad2 = 0;
-    F.fin_mask = fins;
-    F.pad3 = 0;
-    for (int j = 0; j < 3; ++j) F.rg[j] = (float)D.rg[j];
-    F.payload = D.payload;
-    F.pad4 = 0;
+    class_setup_one(in[c], dt, flags, D, F);
     outd[c] = D;
     outf[c] = F;
 }
 
-// Per-environment record: dt M^-1 (M = M_RB + M_A, diagonal), mass, added mass, damping,
-// W - B, B, current; derived in double, rounded once.
-template <typename T>
-__global__ void k_env_setup(ParamPtrs p, int64_t env_off, int64_t n, int32_t npad, const ClassDesc64* cls,
-                            int ci, double dt, T* rec) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t g = env_off + i, N = p.n_total;
-    double added[6], dlin[6], dquad[6], cur[3];
+// Per-environment parameters of global env g (double arrays over the global env id).
+__device__ __forceinline__ void load_params(const ParamPtrs& p, int64_t g, double added[6], double dlin[6],
+                                            double dquad[6], double cur[3]) {
+    const int64_t N = p.n_total;
     for (int j = 0; j < 6; ++j) {
         added[j] = p.added[j * N + g];
         dlin[j] = p.dlin[j * N + g];
         dquad[j] = p.dquad[j * N + g];
     }
     for (int j = 0; j < 3; ++j) cur[j] = p.current[j * N + g];
-    write_record<T>(cls[ci].inertia, cls[ci].g0, dt, p.mass[g], added, dlin, dquad, p.buoy[g], cur, rec, npad, i,
-                    cls[ci].rg);
+}
+
+// Per-environment record: dt M^-1 (M = M_RB + M_A), mass, added mass, damping, W - B, B,
+// current; derived in double, rounded once. Invalid parameters set bits of *err.
+template <typename T>
+__global__ void k_env_setup(ParamPtrs p, int64_t env_off, int64_t n, int32_t npad, const ClassDesc64* cls,
+                            int ci, double dt, T* rec, int32_t* err) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t g = env_off + i;
+    double added[6], dlin[6], dquad[6], cur[3];
+    load_params(p, g, added, dlin, dquad, cur);
+    const int32_t f = write_record<T>(cls[ci].inertia, cls[ci].g0, dt, p.mass[g], added, dlin, dquad, p.buoy[g], cur,
+                                      rec, npad, i, cls[ci].rg);
+    if (f) atomicOr(err, f);
+}
+
+// The checks of k_env_setup alone, nothing written but the error bits.
+__global__ void k_check_params(ParamPtrs p, int64_t env_off, int64_t n, const ClassDesc64* cls, int ci,
+                               int32_t* err) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t g = env_off + i;
+    double added[6], dlin[6], dquad[6], cur[3];
+    load_params(p, g, added, dlin, dquad, cur);
+    const int32_t f = params_flags(cls[ci].inertia, p.mass[g], added, dlin, dquad, p.buoy[g], cur, cls[ci].rg);
+    if (f) atomicOr(err, f);
 }
 
 // Every slot of a segment to rest at the identity attitude; record zeroed (dt M^-1 = 0
@@ -264,9 +182,24 @@ hipError_t launch_class_setup(const ClassDesc64* d_in, ClassT<float>* d_f, Class
 
 template <typename T>
 hipError_t launch_env_setup(ParamPtrs p, int64_t env_off, int64_t n, int32_t npad, const ClassDesc64* d_cls,
-                            int cls_index, double dt, T* rec_seg, hipStream_t s) {
+                            int cls_index, double dt, T* rec_seg, int32_t* err, hipStream_t s) {
     hipLaunchKernelGGL(k_env_setup<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, env_off, n, npad,
-                       d_cls, cls_index, dt, rec_seg);
+                       d_cls, cls_index, dt, rec_seg, err);
+    return hipGetLastError();
+}
+
+__global__ void k_clear_word(int32_t* w) { *w = 0; }
+
+hipError_t launch_clear_word(int32_t* w, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(1), 0, s, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_params(ParamPtrs p, int64_t env_off, int64_t n, const ClassDesc64* d_cls, int cls_index,
+                               int32_t* err, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_params, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, env_off, n, d_cls,
+                       cls_index, err);
     return hipGetLastError();
 }
 
@@ -366,7 +299,7 @@ hipError_t launch_step(const StepLaunch<T>& L, int m, int block, hipStream_t s) 
 
 #define MGX_INSTANTIATE(T)                                                                                          \
     template hipError_t launch_env_setup<T>(ParamPtrs, int64_t, int64_t, int32_t, const ClassDesc64*, int, double,   \
-                                            T*, hipStream_t);                                                         \
+                                            T*, int32_t*, hipStream_t);                                               \
     template hipError_t launch_init_padding<T>(T*, T*, int, int32_t, int64_t, hipStream_t, int);                    \
     template hipError_t launch_reset_seeded<T>(T*, int, int32_t, int64_t, int64_t, const int64_t*, int64_t, uint64_t, \
                                                hipStream_t);                                                          \

@@ -60,14 +60,128 @@ __host__ __device__ inline uint32_t fin_mask_of(const ClassDesc64& d) {
     return mask;
 }
 
+// Class constants in double, derived from the caller's description, and their single
+// rounding to float: thruster layout columns scaled by the gains (with the shaft torque),
+// lag factors, fin plane bases and gains, inertia, centre of buoyancy and of gravity.
+__host__ __device__ inline void class_setup_one(const ClassDesc64& d, double dt, uint32_t flags, ClassT<double>& D,
+                                                ClassT<float>& F) {
+    const int shaped = shaped_thrust(d) ? 1 : 0;
+    const uint32_t fins = fin_mask_of(d);
+    for (int i = 0; i < kMaxThr; ++i) {
+        for (int j = 0; j < 3; ++j) D.fin_r[i][j] = D.fin_c[i][j] = D.fin_n[i][j] = 0.0;
+        D.fin_max[i] = D.fin_kl[i] = D.fin_kd0[i] = D.fin_kd[i] = 0.0;
+        if (i < d.m && ((fins >> i) & 1u)) {
+            // fin: no layout column; the plane's basis from the span and the chord at zero
+            // deflection (the chord's span component dropped)
+            for (int j = 0; j < 6; ++j) D.Bk[j][i] = 0.0;
+            double sl = sqrt(d.span[i][0] * d.span[i][0] + d.span[i][1] * d.span[i][1] + d.span[i][2] * d.span[i][2]);
+            double s[3] = {d.span[i][0] / sl, d.span[i][1] / sl, d.span[i][2] / sl};
+            double es = d.e[i][0] * s[0] + d.e[i][1] * s[1] + d.e[i][2] * s[2];
+            double c[3] = {d.e[i][0] - es * s[0], d.e[i][1] - es * s[1], d.e[i][2] - es * s[2]};
+            double cl = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+            for (int j = 0; j < 3; ++j) c[j] /= cl;
+            const double nn[3] = {s[1] * c[2] - s[2] * c[1], s[2] * c[0] - s[0] * c[2], s[0] * c[1] - s[1] * c[0]};
+            for (int j = 0; j < 3; ++j) {
+                D.fin_r[i][j] = d.r[i][j];
+                D.fin_c[i][j] = c[j];
+                D.fin_n[i][j] = nn[j];
+            }
+            D.fin_max[i] = d.fin_max[i];
+            D.fin_kl[i] = d.fin_lift[i];
+            D.fin_kd0[i] = d.fin_drag0[i];
+            D.fin_kd[i] = d.fin_drag[i];
+            double tau = d.tau[i];
+            D.alpha[i] = tau > 0.0 ? ((flags & kFlagLagEuler) ? dt / tau : 1.0 - exp(-dt / tau)) : 1.0;
+            D.dz[i] = 0.0;
+            D.rev[i] = 1.0;
+        } else if (i < d.m) {
+            double len = sqrt(d.e[i][0] * d.e[i][0] + d.e[i][1] * d.e[i][1] + d.e[i][2] * d.e[i][2]);
+            double e[3] = {d.e[i][0] / len, d.e[i][1] / len, d.e[i][2] / len};
+            const double* r = d.r[i];
+            const double k = d.k[i];
+            D.Bk[0][i] = k * e[0];
+            D.Bk[1][i] = k * e[1];
+            D.Bk[2][i] = k * e[2];
+            // moment about the CoG plus the shaft torque c_i about the thrust axis
+            const double c = d.reaction[i];
+            D.Bk[3][i] = k * ((r[1] * e[2] - r[2] * e[1]) + c * e[0]);
+            D.Bk[4][i] = k * ((r[2] * e[0] - r[0] * e[2]) + c * e[1]);
+            D.Bk[5][i] = k * ((r[0] * e[1] - r[1] * e[0]) + c * e[2]);
+            double tau = d.tau[i];
+            D.alpha[i] = tau > 0.0 ? ((flags & kFlagLagEuler) ? dt / tau : 1.0 - exp(-dt / tau)) : 1.0;
+            D.dz[i] = d.dz[i];
+            D.rev[i] = reverse_ratio(d, i);
+        } else {
+            for (int j = 0; j < 6; ++j) D.Bk[j][i] = 0.0;
+            D.alpha[i] = 0.0;
+            D.dz[i] = 0.0;
+            D.rev[i] = 1.0;
+        }
+    }
+    for (int j = 0; j < 3; ++j) {
+        D.inertia[j] = d.inertia[j];
+        D.rb[j] = d.rb[j];
+    }
+    D.g0 = d.g0;
+    D.dt = dt;
+    D.inv_dt = 1.0 / dt;
+    D.half_dt = 0.5 * dt;
+    D.m = d.m;
+    D.flags = flags;
+    D.shaped = shaped;
+    D.pad2 = 0;
+    D.fin_mask = fins;
+    D.pad3 = 0;
+    for (int j = 0; j < 3; ++j) D.rg[j] = d.rg[j];
+    D.payload = has_payload(d) ? 1 : 0;
+    D.pad4 = 0;
+    for (int i = 0; i < kMaxThr; ++i) {
+        for (int j = 0; j < 6; ++j) F.Bk[j][i] = (float)D.Bk[j][i];
+        F.alpha[i] = (float)D.alpha[i];
+        F.dz[i] = (float)D.dz[i];
+        F.rev[i] = (float)D.rev[i];
+        for (int j = 0; j < 3; ++j) {
+            F.fin_r[i][j] = (float)D.fin_r[i][j];
+            F.fin_c[i][j] = (float)D.fin_c[i][j];
+            F.fin_n[i][j] = (float)D.fin_n[i][j];
+        }
+        F.fin_max[i] = (float)D.fin_max[i];
+        F.fin_kl[i] = (float)D.fin_kl[i];
+        F.fin_kd0[i] = (float)D.fin_kd0[i];
+        F.fin_kd[i] = (float)D.fin_kd[i];
+    }
+    for (int j = 0; j < 3; ++j) {
+        F.inertia[j] = (float)D.inertia[j];
+        F.rb[j] = (float)D.rb[j];
+    }
+    F.g0 = (float)D.g0;
+    F.dt = (float)D.dt;
+    F.inv_dt = (float)D.inv_dt;
+    F.half_dt = (float)D.half_dt;
+    F.m = D.m;
+    F.flags = flags;
+    F.shaped = shaped;
+    F.pad2 = 0;
+    F.fin_mask = fins;
+    F.pad3 = 0;
+    for (int j = 0; j < 3; ++j) F.rg[j] = (float)D.rg[j];
+    F.payload = D.payload;
+    F.pad4 = 0;
+}
+
+// Bits of DevMisc::err, the batch's device error word (read by mgx_batch_check).
+constexpr int32_t kErrActionRow = 1;  // a step met an action row outside its buffer
+constexpr int32_t kErrParam = 2;      // a record was built from a non-finite or out-of-range value
+constexpr int32_t kErrNotSpd = 4;     // M_RB + M_A of some environment is not positive definite
+
 // Device bookkeeping of a batch. The step counter is double-buffered: a launch reads
 // slot rd and (if it moves the counter) its first block writes slot wr = 1 - rd, so the
 // counter advances with one plain store and no completion handshake. `done` counts
 // finished blocks per class for the statistics reduction only.
 struct DevMisc {
     int64_t t[2];
-    int32_t err;
-    int32_t pad;
+    int32_t err;        // kErr* bits, sticky until the batch is destroyed
+    int32_t check;      // kErr* bits of the last parameter check (mgx_batch_set_params)
     uint32_t done[16];
     uint32_t work[2];   // persistent launches: tiles handed out past the first round (slot rd)
     uint32_t exits[2];  // persistent launch with statistics: waves finished
@@ -162,7 +276,13 @@ struct ParamPtrs {
 
 template <typename T>
 hipError_t launch_env_setup(ParamPtrs p, int64_t env_off, int64_t n, int32_t npad, const ClassDesc64* d_cls,
-                            int cls_index, double dt, T* rec_seg, hipStream_t s);
+                            int cls_index, double dt, T* rec_seg, int32_t* err, hipStream_t s);
+// Sets one device word to 0 (a kernel, not a memset node).
+hipError_t launch_clear_word(int32_t* w, hipStream_t s);
+// Checks the parameters of environments [env_off, env_off + n) as a record build would,
+// without writing a record: ORs kErrParam / kErrNotSpd into *err.
+hipError_t launch_check_params(ParamPtrs p, int64_t env_off, int64_t n, const ClassDesc64* d_cls, int cls_index,
+                               int32_t* err, hipStream_t s);
 template <typename T>
 hipError_t launch_reset_seeded(T* state_seg, int m, int32_t npad, int64_t env_off, int64_t n_local,
                                const int64_t* d_local_ids, int64_t n_ids, uint64_t seed, hipStream_t s);

@@ -93,6 +93,7 @@ extern "C" const char* mgx_status_string(mgx_status s) {
         case MGX_E_INVALID: return "invalid argument";
         case MGX_E_NOMEM: return "out of memory";
         case MGX_E_DEVICE: return "device error";
+        case MGX_E_NOT_SPD: return "mass matrix not positive definite";
         case MGX_E_NONFINITE: return "non-finite state";
         case MGX_E_BUDGET: return "memory budget exceeded";
         case MGX_E_STATE: return "invalid state";
@@ -111,6 +112,11 @@ extern "C" size_t mgx_last_error(char* buf, size_t len) {
 
 extern "C" int32_t mgx_last_hip_error(void) { return g_hip_err; }
 extern "C" int32_t mgx_version(void) { return 100; }
+
+#ifndef MGX_BUILD_HASH
+#define MGX_BUILD_HASH "unknown"
+#endif
+extern "C" const char* mgx_build_hash(void) { return MGX_BUILD_HASH; }
 
 extern "C" mgx_status mgx_device_count(int32_t* count) {
     if (!count) return fail(MGX_E_INVALID, "count is NULL");
@@ -178,52 +184,29 @@ extern "C" mgx_status mgx_class_define(const mgx_class_desc* d, int32_t* class_i
 
 // ----------------------------------------------------------------------------- batches
 
-static void* dalloc(size_t bytes, hipError_t* e) {
-    void* p = nullptr;
-    *e = hipMalloc(&p, bytes ? bytes : 16);
-    return *e == hipSuccess ? p : nullptr;
-}
-
 static void free_batch_mem(mgx_batch* b) {
-    void* ptrs[] = {b->d_state, b->d_rec, b->d_misc, b->d_classdesc, b->d_class_f, b->d_class_d, b->d_partials,
-                    b->d_stats, b->d_ids, b->d_param_stage, b->d_tiles, b->d_segs, b->d_tile_partials,
-                    b->d_ckpt, b->d_seg};
-    for (void* p : ptrs)
-        if (p) (void)hipFree(p);
+    void* ptrs[] = {b->own_state ? b->d_state : nullptr, b->own_rec ? b->d_rec : nullptr, b->d_misc, b->d_classdesc,
+                    b->d_class_f, b->d_class_d, b->d_partials, b->d_stats, b->d_ids, b->d_param_stage, b->d_tiles,
+                    b->d_segs, b->d_tile_partials, b->d_ckpt, b->d_seg};
+    for (void* p : ptrs) b->dev_free(p);
 }
 
-extern "C" mgx_status mgx_batch_create(const mgx_batch_desc* d, mgx_batch** out) {
-    if (!d || !out) return fail(MGX_E_INVALID, "NULL argument");
-    *out = nullptr;
+// Validates a batch description and fills the layout of the batch it describes (no device
+// work). rec_elems receives the parameter-record size in elements.
+static mgx_status plan_batch(const mgx_batch_desc* d, std::vector<mgx_class_desc>* cls_out, mgx_batch* b) {
     if (d->n_classes < 1 || d->n_classes > MGX_MAX_CLASSES)
         return fail(MGX_E_INVALID, "n_classes=%d outside [1,%d]", d->n_classes, MGX_MAX_CLASSES);
     if (d->precision != MGX_FP32 && d->precision != MGX_FP64) return fail(MGX_E_INVALID, "precision must be 4 or 8");
     if (!d->class_ids || !d->n_envs) return fail(MGX_E_INVALID, "class_ids / n_envs NULL");
     if (!(d->dt > 0) || !std::isfinite(d->dt)) return fail(MGX_E_INVALID, "dt must be > 0");
     if (d->flags & ~(MGX_FLAG_NO_AMC | MGX_FLAG_LAG_EULER)) return fail(MGX_E_INVALID, "unknown batch flag");
+    if ((d->alloc == nullptr) != (d->free == nullptr)) return fail(MGX_E_INVALID, "alloc and free: both or neither");
     std::vector<mgx_class_desc> cls(d->n_classes);
     for (int c = 0; c < d->n_classes; ++c) {
         if (!get_class(d->class_ids[c], &cls[c])) return fail(MGX_E_INVALID, "class id %d unknown", d->class_ids[c]);
         if (d->n_envs[c] < 1 || d->n_envs[c] > (int64_t)1 << 30)
             return fail(MGX_E_INVALID, "n_envs[%d]=%lld outside [1, 2^30]", c, (long long)d->n_envs[c]);
     }
-    int ndev = 0;
-    hipError_t e = hipGetDeviceCount(&ndev);
-    if (e != hipSuccess || ndev <= 0) {
-        g_hip_err = (int32_t)e;
-        return fail(MGX_E_DEVICE, "no HIP device visible");
-    }
-    int dev = d->device;
-    if (dev < 0) {
-        e = hipGetDevice(&dev);
-        if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
-    }
-    if (dev >= ndev) return fail(MGX_E_INVALID, "device %d of %d", dev, ndev);
-
-    mgx_batch* b = new (std::nothrow) mgx_batch();
-    if (!b) return fail(MGX_E_NOMEM, "host allocation");
-    b->device = dev;
-    b->stream = (hipStream_t)d->stream;
     b->prec = d->precision;
     b->dt = d->dt;
     b->flags = d->flags;
@@ -258,6 +241,79 @@ extern "C" mgx_status mgx_batch_create(const mgx_batch_desc* d, mgx_batch** out)
     b->row_elems = aoff;
     b->force_row_elems = foff;
     b->max_blocks = max_blocks;
+    if (cls_out) *cls_out = cls;
+    return MGX_OK;
+}
+
+static void fill_layout(const mgx_batch* b, mgx_layout* out) {
+    std::memset(out, 0, sizeof *out);
+    out->n_classes = b->n_classes;
+    out->precision = b->prec;
+    out->n_total = b->n_total;
+    out->n_pad_total = b->npad_total;
+    out->state_elems = b->state_elems;
+    out->row_elems = b->row_elems;
+    out->force_row_elems = b->force_row_elems;
+    out->record_elems = b->rec_elems;
+    for (int c = 0; c < b->n_classes; ++c) {
+        out->m[c] = b->m[c];
+        out->n[c] = b->n[c];
+        out->n_pad[c] = b->npad[c];
+        out->env_off[c] = b->env_off[c];
+        out->state_off[c] = b->state_off[c];
+        out->action_off[c] = b->act_off[c];
+        out->force_off[c] = b->force_off[c];
+        out->record_off[c] = b->rec_off[c];
+    }
+}
+
+extern "C" mgx_status mgx_batch_plan(const mgx_batch_desc* d, mgx_layout* out) {
+    if (!d || !out) return fail(MGX_E_INVALID, "NULL argument");
+    mgx_batch tmp;
+    mgx_status st = plan_batch(d, nullptr, &tmp);
+    if (st != MGX_OK) return st;
+    fill_layout(&tmp, out);
+    return MGX_OK;
+}
+
+extern "C" mgx_status mgx_batch_create(const mgx_batch_desc* d, mgx_batch** out) {
+    if (!d || !out) return fail(MGX_E_INVALID, "NULL argument");
+    *out = nullptr;
+    mgx_batch* b = new (std::nothrow) mgx_batch();
+    if (!b) return fail(MGX_E_NOMEM, "host allocation");
+    std::vector<mgx_class_desc> cls;
+    {
+        mgx_status st = plan_batch(d, &cls, b);
+        if (st != MGX_OK) {
+            delete b;
+            return st;
+        }
+    }
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0) {
+        delete b;
+        g_hip_err = (int32_t)e;
+        return fail(MGX_E_DEVICE, "no HIP device visible");
+    }
+    int dev = d->device;
+    if (dev < 0) {
+        e = hipGetDevice(&dev);
+        if (e != hipSuccess) {
+            delete b;
+            return hip_fail(nullptr, e, "hipGetDevice");
+        }
+    }
+    if (dev >= ndev) {
+        delete b;
+        return fail(MGX_E_INVALID, "device %d of %d", dev, ndev);
+    }
+    b->device = dev;
+    b->stream = (hipStream_t)d->stream;
+    b->alloc_fn = d->alloc;
+    b->free_fn = d->free;
+    b->alloc_ctx = d->alloc_ctx;
+    const int64_t max_blocks = b->max_blocks;
 
     hipDevice_guard g(dev);
     if (!g.ok()) {
@@ -265,19 +321,30 @@ extern "C" mgx_status mgx_batch_create(const mgx_batch_desc* d, mgx_batch** out)
         return hip_fail(nullptr, g.err(), "hipSetDevice");
     }
     const size_t P = (size_t)b->prec;
-    b->d_state = dalloc(P * b->state_elems, &e);
-    if (e == hipSuccess) b->d_rec = dalloc(P * b->rec_elems, &e);
-    if (e == hipSuccess) b->d_misc = (DevMisc*)dalloc(sizeof(DevMisc), &e);
-    if (e == hipSuccess) b->d_classdesc = (ClassDesc64*)dalloc(sizeof(ClassDesc64) * MGX_MAX_CLASSES, &e);
-    if (e == hipSuccess) b->d_class_f = (ClassT<float>*)dalloc(sizeof(ClassT<float>) * MGX_MAX_CLASSES, &e);
-    if (e == hipSuccess) b->d_class_d = (ClassT<double>*)dalloc(sizeof(ClassT<double>) * MGX_MAX_CLASSES, &e);
-    if (e == hipSuccess) b->d_partials = (float*)dalloc(sizeof(float) * kStats * max_blocks, &e);
-    if (e == hipSuccess) b->d_stats = (double*)dalloc(sizeof(double) * kStats * MGX_MAX_CLASSES, &e);
-    if (e == hipSuccess) b->d_ids = (int64_t*)dalloc(sizeof(int64_t) * b->n_total, &e);
+    e = hipSuccess;
+    if (d->state) {
+        b->d_state = d->state;
+        b->own_state = false;
+    } else {
+        b->d_state = b->dev_alloc(P * b->state_elems, &e);
+    }
+    if (e == hipSuccess && d->record) {
+        b->d_rec = d->record;
+        b->own_rec = false;
+    } else if (e == hipSuccess) {
+        b->d_rec = b->dev_alloc(P * b->rec_elems, &e);
+    }
+    if (e == hipSuccess) b->d_misc = (DevMisc*)b->dev_alloc(sizeof(DevMisc), &e);
+    if (e == hipSuccess) b->d_classdesc = (ClassDesc64*)b->dev_alloc(sizeof(ClassDesc64) * MGX_MAX_CLASSES, &e);
+    if (e == hipSuccess) b->d_class_f = (ClassT<float>*)b->dev_alloc(sizeof(ClassT<float>) * MGX_MAX_CLASSES, &e);
+    if (e == hipSuccess) b->d_class_d = (ClassT<double>*)b->dev_alloc(sizeof(ClassT<double>) * MGX_MAX_CLASSES, &e);
+    if (e == hipSuccess) b->d_partials = (float*)b->dev_alloc(sizeof(float) * kStats * max_blocks, &e);
+    if (e == hipSuccess) b->d_stats = (double*)b->dev_alloc(sizeof(double) * kStats * MGX_MAX_CLASSES, &e);
+    if (e == hipSuccess) b->d_ids = (int64_t*)b->dev_alloc(sizeof(int64_t) * b->n_total, &e);
     b->n_tiles = (int32_t)(b->npad_total / kWave);
-    if (e == hipSuccess) b->d_tiles = (int32_t*)dalloc(sizeof(int32_t) * 2 * b->n_tiles, &e);
-    if (e == hipSuccess) b->d_segs = (SegDesc*)dalloc(sizeof(SegDesc) * MGX_MAX_CLASSES, &e);
-    if (e == hipSuccess) b->d_tile_partials = (float*)dalloc(sizeof(float) * kStats * b->n_tiles, &e);
+    if (e == hipSuccess) b->d_tiles = (int32_t*)b->dev_alloc(sizeof(int32_t) * 2 * b->n_tiles, &e);
+    if (e == hipSuccess) b->d_segs = (SegDesc*)b->dev_alloc(sizeof(SegDesc) * MGX_MAX_CLASSES, &e);
+    if (e == hipSuccess) b->d_tile_partials = (float*)b->dev_alloc(sizeof(float) * kStats * b->n_tiles, &e);
     if (e != hipSuccess) {
         free_batch_mem(b);
         delete b;
@@ -334,11 +401,14 @@ extern "C" mgx_status mgx_batch_create(const mgx_batch_desc* d, mgx_batch** out)
         HIP_TRY(b, hipMemsetAsync(b->d_stats, 0, sizeof(double) * kStats * MGX_MAX_CLASSES, b->stream));
         for (int c = 0; c < b->n_classes; ++c) {
             if (b->prec == MGX_FP32) {
+                // an adopted state keeps its valid slots; padded slots are always set to rest
                 HIP_TRY(b, launch_init_padding<float>((float*)b->seg_state(c), (float*)b->seg_rec(c), b->m[c],
-                                                      (int32_t)b->npad[c], 0, b->stream, b->rec_len(c)));
+                                                      (int32_t)b->npad[c], b->own_state ? 0 : b->n[c], b->stream,
+                                                      b->rec_len(c)));
             } else {
                 HIP_TRY(b, launch_init_padding<double>((double*)b->seg_state(c), (double*)b->seg_rec(c), b->m[c],
-                                                       (int32_t)b->npad[c], 0, b->stream, b->rec_len(c)));
+                                                       (int32_t)b->npad[c], b->own_state ? 0 : b->n[c], b->stream,
+                                                       b->rec_len(c)));
             }
         }
         HIP_TRY(b, hipStreamSynchronize(b->stream));
@@ -368,23 +438,7 @@ extern "C" mgx_status mgx_batch_destroy(mgx_batch* b) {
 
 extern "C" mgx_status mgx_batch_layout(const mgx_batch* b, mgx_layout* out) {
     if (!b || !out) return fail(MGX_E_INVALID, "NULL argument");
-    std::memset(out, 0, sizeof *out);
-    out->n_classes = b->n_classes;
-    out->precision = b->prec;
-    out->n_total = b->n_total;
-    out->n_pad_total = b->npad_total;
-    out->state_elems = b->state_elems;
-    out->row_elems = b->row_elems;
-    out->force_row_elems = b->force_row_elems;
-    for (int c = 0; c < b->n_classes; ++c) {
-        out->m[c] = b->m[c];
-        out->n[c] = b->n[c];
-        out->n_pad[c] = b->npad[c];
-        out->env_off[c] = b->env_off[c];
-        out->state_off[c] = b->state_off[c];
-        out->action_off[c] = b->act_off[c];
-        out->force_off[c] = b->force_off[c];
-    }
+    fill_layout(b, out);
     return MGX_OK;
 }
 
@@ -409,15 +463,16 @@ extern "C" mgx_status mgx_batch_set_params(mgx_batch* b, const mgx_env_params* p
             if (!(p->buoy[i] >= 0) || !is_fin(p->buoy[i])) return fail(MGX_E_INVALID, "buoy[%lld] must be >= 0", (long long)i);
             for (int j = 0; j < 6; ++j) {
                 const double a = p->added[j * N + i], l = p->dlin[j * N + i], q = p->dquad[j * N + i];
-                if (!(a >= 0 && l >= 0 && q >= 0) || !is_fin(a) || !is_fin(l) || !is_fin(q))
-                    return fail(MGX_E_INVALID, "added/dlin/dquad[%d][%lld] must be finite and >= 0", j, (long long)i);
+                if (!(l >= 0 && q >= 0) || !is_fin(a) || !is_fin(l) || !is_fin(q))
+                    return fail(MGX_E_INVALID, "added[%d][%lld] must be finite, dlin/dquad finite and >= 0", j,
+                                (long long)i);
             }
             for (int j = 0; j < 3; ++j)
                 if (!is_fin(p->current[j * N + i])) return fail(MGX_E_INVALID, "current must be finite");
         }
         if (!b->d_param_stage) {
             hipError_t e;
-            b->d_param_stage = (double*)dalloc(sizeof(double) * 23 * N, &e);
+            b->d_param_stage = (double*)b->dev_alloc(sizeof(double) * 23 * N, &e);
             if (!b->d_param_stage) return hip_fail(nullptr, e, "hipMalloc(param stage)");
         }
         double* s = b->d_param_stage;
@@ -435,13 +490,25 @@ extern "C" mgx_status mgx_batch_set_params(mgx_batch* b, const mgx_env_params* p
         pp.buoy = s + 19 * N;
         pp.current = s + 20 * N;
     }
+    // Every environment's values and mass matrix are checked on the device before any
+    // record is written, so a refused call leaves the batch unchanged. The check word is
+    // cleared by a one-thread kernel rather than a memset node.
+    HIP_TRY(b, launch_clear_word(&b->d_misc->check, b->stream));
+    for (int c = 0; c < b->n_classes; ++c)
+        HIP_TRY(b, launch_check_params(pp, b->env_off[c], b->n[c], b->d_classdesc, c, &b->d_misc->check, b->stream));
+    int32_t chk = 0;
+    HIP_TRY(b, hipMemcpyAsync(&chk, &b->d_misc->check, sizeof chk, hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(b, hipStreamSynchronize(b->stream));
+    if (chk & kErrParam)
+        return fail(MGX_E_INVALID, "a device parameter is not finite or out of range (mass > 0; damping, buoyancy >= 0)");
+    if (chk & kErrNotSpd) return fail(MGX_E_NOT_SPD, "M_RB + M_A of some environment is not positive definite");
     for (int c = 0; c < b->n_classes; ++c) {
         if (b->prec == MGX_FP32) {
             HIP_TRY(b, launch_env_setup<float>(pp, b->env_off[c], b->n[c], (int32_t)b->npad[c], b->d_classdesc, c, b->dt,
-                                               (float*)b->seg_rec(c), b->stream));
+                                               (float*)b->seg_rec(c), &b->d_misc->err, b->stream));
         } else {
             HIP_TRY(b, launch_env_setup<double>(pp, b->env_off[c], b->n[c], (int32_t)b->npad[c], b->d_classdesc, c,
-                                                b->dt, (double*)b->seg_rec(c), b->stream));
+                                                b->dt, (double*)b->seg_rec(c), &b->d_misc->err, b->stream));
         }
     }
     b->params_set = true;
@@ -702,6 +769,9 @@ extern "C" mgx_status mgx_batch_check(mgx_batch* b, int64_t* n_nonfinite) {
     int64_t nf = 0;
     for (int c = 0; c < b->n_classes; ++c) nf += (int64_t)h[kStats * c + kStNonFinite];
     if (n_nonfinite) *n_nonfinite = nf;
+    if (m.err & kErrNotSpd)
+        return fail(MGX_E_NOT_SPD, "a parameter record was built from a mass matrix that is not positive definite");
+    if (m.err & kErrParam) return fail(MGX_E_INVALID, "a parameter record was built from an invalid value");
     if (m.err) return fail(MGX_E_INVALID, "a kernel met an action row outside its buffer (err=%d)", m.err);
     if (nf) return fail(MGX_E_NONFINITE, "%lld environments hold non-finite values", (long long)nf);
     return MGX_OK;

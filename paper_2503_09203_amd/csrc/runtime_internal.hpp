@@ -54,6 +54,11 @@ struct mgx_batch {
 
     void* d_state = nullptr;
     void* d_rec = nullptr;
+    bool own_state = true, own_rec = true;  // false: adopted from the caller, never freed
+    // Device allocator of every buffer the batch allocates (default hipMalloc / hipFree).
+    void* (*alloc_fn)(size_t, void*) = nullptr;
+    void (*free_fn)(void*, void*) = nullptr;
+    void* alloc_ctx = nullptr;
     mgx::DevMisc* d_misc = nullptr;
     mgx::ClassDesc64* d_classdesc = nullptr;
     mgx::ClassT<float>* d_class_f = nullptr;
@@ -93,6 +98,27 @@ struct mgx_batch {
     int64_t ro_n_rows = 0, ro_row0 = 0, ro_t0 = 0;
     int32_t ro_hold = 1, ro_H = 0, ro_ckpt = 32;
     bool ro_valid = false;
+
+    // Allocation through the batch's allocator; *e = hipErrorOutOfMemory when a caller's
+    // allocator returns NULL.
+    void* dev_alloc(size_t bytes, hipError_t* e) {
+        void* p = nullptr;
+        if (!bytes) bytes = 16;
+        if (alloc_fn) {
+            p = alloc_fn(bytes, alloc_ctx);
+            *e = p ? hipSuccess : hipErrorOutOfMemory;
+        } else {
+            *e = hipMalloc(&p, bytes);
+        }
+        return *e == hipSuccess ? p : nullptr;
+    }
+    void dev_free(void* p) {
+        if (!p) return;
+        if (free_fn)
+            free_fn(p, alloc_ctx);
+        else
+            (void)hipFree(p);
+    }
 
     void* seg_state(int c) const { return (char*)d_state + (size_t)prec * state_off[c]; }
     void* seg_rec(int c) const { return (char*)d_rec + (size_t)prec * rec_off[c]; }

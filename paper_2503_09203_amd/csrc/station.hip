@@ -228,6 +228,11 @@ __global__ void __launch_bounds__(256) k_station_step(StationLaunch<T> L) {
     const int64_t np = A.npad;
     StateT<T, M> s;
     load_state<T, M>(A.state, np, env, s);
+    // classes with fins carry the attitude's low-order words through the launch (float)
+    constexpr bool kComp = kFins && std::is_same<T, float>::value;
+    StateLo<T> lo;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) lo.q[j] = T(0);
     T tg[7];
 #pragma unroll
     for (int j = 0; j < 7; ++j) tg[j] = A.tgt[j * np + env];
@@ -263,7 +268,7 @@ __global__ void __launch_bounds__(256) k_station_step(StationLaunch<T> L) {
                 for (int i = 0; i < M; ++i) nxt[i] = an[i * np];
             }
             for (int j = 0; j < A.P.substeps; ++j)
-                step_body<T, M, false, kShaped, kFins, kPayload>(C, E, IA2, Brb, s, a);
+                step_body<T, M, false, kShaped, kFins, kPayload, kComp>(C, E, IA2, Brb, s, a, nullptr, &lo);
             float st[kStats];  // launch statistics are not kept by the task
             renorm_attitude<T, M>(s, st);
 
@@ -297,6 +302,8 @@ __global__ void __launch_bounds__(256) k_station_step(StationLaunch<T> L) {
             ++ep;
             et = 0;
             restarted = true;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) lo.q[j] = T(0);
         }
         const uint64_t need = __ballot(done);
         if (need) {

@@ -114,6 +114,27 @@ struct StateT {
     T n[M];
 };
 
+// Low-order words of the attitude for the compensated update: the quaternion is then the
+// unevaluated sum hi + lo of each component, with |lo| <= ulp(hi) / 2. Rounding the
+// attitude to float every step turns its direction by about 2^-24 rad per step; on
+// trajectories that amplify attitude errors (classes with fins) those turns dominate the
+// error after many steps, and carrying the low words through a launch removes them.
+template <typename T>
+struct StateLo {
+    T q[4];
+};
+
+// hi + lo += x as an error-free transformation (Knuth's TwoSum of hi and x + lo): the new
+// hi is the rounded sum, lo what the rounding dropped.
+template <typename T>
+__host__ __device__ __forceinline__ void two_sum_acc(T& hi, T& lo, T x) {
+    const T y = x + lo;
+    const T t = hi + y;
+    const T bb = t - hi;
+    lo = (hi - (t - bb)) + (y - bb);
+    hi = t;
+}
+
 // ----------------------------------------------------------------------------- arithmetic
 
 __host__ __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -271,6 +292,39 @@ __host__ __device__ __forceinline__ void quat_increment(T h, const T w[3], T& c,
     }
 }
 
+// The same increment with its scalar part given as c - 1 = -2 sin^2(phi / 2), free of the
+// cancellation in 1 - cos(phi), for the compensated attitude update.
+template <typename T>
+__host__ __device__ __forceinline__ void quat_increment_cm1(T h, const T w[3], T& cm1, T& s) {
+    T w2 = fma_(w[2], w[2], fma_(w[1], w[1], w[0] * w[0]));
+    if constexpr (std::is_same<T, double>::value) {
+        T wn = sqrt_(w2);
+        T phi = h * wn;
+        T sh = sin(0.5 * phi);
+        cm1 = -2.0 * sh * sh;
+        s = wn > 0.0 ? sin(phi) / wn : h;
+    } else {
+        T phi2 = (h * h) * w2;
+        cm1 = fma_(phi2, T(1.0f / 24.0f), T(-0.5f)) * phi2;
+        s = h * fma_(fma_(phi2, T(1.0f / 120.0f), T(-1.0f / 6.0f)), phi2, T(1.0f));
+        const bool big = !(phi2 <= T(0.0025f));
+        if (any_lane(big)) {
+            T phi = sqrt_(phi2);
+            T sn, cs;
+            if constexpr (std::is_same<T, float>::value) {
+                sincosf(T(0.5f) * phi, &sn, &cs);
+            } else {
+                sn = sin(T(0.5f) * phi);
+                cs = cos(T(0.5f) * phi);
+            }
+            const T ce = T(-2.0f) * (sn * sn);
+            const T se = (T(2.0f) * (sn * cs)) * h / phi;
+            cm1 = big ? ce : cm1;
+            s = big ? se : s;
+        }
+    }
+}
+
 // dnu = (dt M^-1) F with the symmetric dt M^-1 of a payload class: diagonal entries in
 // dtMinv, the others (0,1), (0,2), ..., (4,5) in dtMinvOff.
 template <typename T>
@@ -291,10 +345,11 @@ __host__ __device__ __forceinline__ void payload_solve(const EnvT<T>& E, const T
 // are per-environment constants hoisted out of the step loop by the caller. `forces`
 // (optional, 12 values) receives the actuator wrench and the hydrodynamic wrench of
 // Eq. (3) with d(nu)/dt the solved acceleration.
-template <typename T, int M, bool kForces = false, bool kShaped = false, bool kFins = false, bool kPayload = false>
+template <typename T, int M, bool kForces = false, bool kShaped = false, bool kFins = false, bool kPayload = false,
+          bool kComp = false>
 __host__ __device__ __forceinline__ void step_body(const ClassT<T>& C, const EnvT<T>& E, const T IA2[3],
                                                    const T Brb[3], StateT<T, M>& s, const T a[M],
-                                                   T* forces = nullptr) {
+                                                   T* forces = nullptr, StateLo<T>* lo = nullptr) {
     // 1. rotor lag (first-order hold; alpha = 1 is the zero-order rotor)
     T nl[M];
 #pragma unroll
@@ -461,6 +516,30 @@ __host__ __device__ __forceinline__ void step_body(const ClassT<T>& C, const Env
         s.p[j] = fma_(C.dt, rv, s.p[j]);
     }
     // attitude: body-frame increment on the right
+    if constexpr (kComp) {
+        // compensated: q (x) dq - q = q (c - 1) + q (x) (0, d) added to q_hi + q_lo, then
+        // the Newton step toward |q| = 1 applied as q_hi += q_hi (g - 1)
+        T cm1, sh;
+        quat_increment_cm1(C.half_dt, s.nu + 3, cm1, sh);
+        const T dx = sh * s.nu[3], dy = sh * s.nu[4], dz = sh * s.nu[5];
+        const T d0 = fma_(qw, cm1, -fma_(qx, dx, fma_(qy, dy, qz * dz)));
+        const T d1 = fma_(qw, dx, fma_(qx, cm1, fma_(qy, dz, -(qz * dy))));
+        const T d2 = fma_(qw, dy, fma_(qy, cm1, fma_(qz, dx, -(qx * dz))));
+        const T d3 = fma_(qw, dz, fma_(qz, cm1, fma_(qx, dy, -(qy * dx))));
+        two_sum_acc(s.q[0], lo->q[0], d0);
+        two_sum_acc(s.q[1], lo->q[1], d1);
+        two_sum_acc(s.q[2], lo->q[2], d2);
+        two_sum_acc(s.q[3], lo->q[3], d3);
+        // |q|^2 - 1 with the low words' first-order part
+        T n2m1 = fma_(s.q[3], s.q[3], fma_(s.q[2], s.q[2], fma_(s.q[1], s.q[1], fma_(s.q[0], s.q[0], T(-1)))));
+        T cr = fma_(s.q[3], lo->q[3], fma_(s.q[2], lo->q[2], fma_(s.q[1], lo->q[1], s.q[0] * lo->q[0])));
+        const T gm1 = T(-0.5) * fma_(T(2), cr, n2m1);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) two_sum_acc(s.q[j], lo->q[j], s.q[j] * gm1);
+#pragma unroll
+        for (int i = 0; i < M; ++i) s.n[i] = nl[i];
+        return;
+    }
     T c, sh;
     quat_increment(C.half_dt, s.nu + 3, c, sh);
     const T dx = sh * s.nu[3], dy = sh * s.nu[4], dz = sh * s.nu[5];

@@ -19,6 +19,7 @@ MGX_OK = 0
 MGX_E_INVALID = -1
 MGX_E_NOMEM = -2
 MGX_E_DEVICE = -3
+MGX_E_NOT_SPD = -4
 MGX_E_NONFINITE = -5
 MGX_E_BUDGET = -6
 MGX_E_STATE = -7
@@ -61,11 +62,16 @@ class ClassDesc(ctypes.Structure):
                 ("rg", ctypes.c_double * 3)]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class BatchDesc(ctypes.Structure):
     _fields_ = [("n_classes", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("class_ids", ctypes.POINTER(ctypes.c_int32)), ("n_envs", ctypes.POINTER(ctypes.c_int64)),
                 ("dt", ctypes.c_double), ("flags", ctypes.c_uint32), ("device", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("state", ctypes.c_void_p), ("record", ctypes.c_void_p),
+                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p)]
 
 
 class Layout(ctypes.Structure):
@@ -76,7 +82,8 @@ class Layout(ctypes.Structure):
                 ("m", ctypes.c_int32 * MAX_CLASSES), ("n", ctypes.c_int64 * MAX_CLASSES),
                 ("n_pad", ctypes.c_int64 * MAX_CLASSES), ("env_off", ctypes.c_int64 * MAX_CLASSES),
                 ("state_off", ctypes.c_int64 * MAX_CLASSES), ("action_off", ctypes.c_int64 * MAX_CLASSES),
-                ("force_off", ctypes.c_int64 * MAX_CLASSES)]
+                ("force_off", ctypes.c_int64 * MAX_CLASSES), ("record_elems", ctypes.c_int64),
+                ("record_off", ctypes.c_int64 * MAX_CLASSES)]
 
 
 class LaunchShape(ctypes.Structure):
@@ -172,6 +179,7 @@ I32, I64, U32, U64, F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctype
 
 # name -> (restype, argtypes)
 SIGNATURES = {
+    "mgx_build_hash": (ctypes.c_char_p, []),
     "mgx_status_string": (ctypes.c_char_p, [I32]),
     "mgx_last_error": (ctypes.c_size_t, [ctypes.c_char_p, ctypes.c_size_t]),
     "mgx_last_hip_error": (I32, []),
@@ -181,6 +189,7 @@ SIGNATURES = {
     "mgx_class_step_cost": (I32, [I32, U32, ctypes.POINTER(F64), ctypes.POINTER(F64)]),
     "mgx_class_define": (I32, [ctypes.POINTER(ClassDesc), ctypes.POINTER(I32)]),
     "mgx_batch_create": (I32, [ctypes.POINTER(BatchDesc), ctypes.POINTER(P)]),
+    "mgx_batch_plan": (I32, [ctypes.POINTER(BatchDesc), ctypes.POINTER(Layout)]),
     "mgx_batch_destroy": (I32, [P]),
     "mgx_batch_layout": (I32, [P, ctypes.POINTER(Layout)]),
     "mgx_batch_set_params": (I32, [P, ctypes.POINTER(EnvParams), I32]),
@@ -228,13 +237,28 @@ SIGNATURES = {
 _lib = None
 
 
+def check_build(L, root=None):
+    """Raise ImportError unless the loaded library ``L`` was compiled from the sources under
+    ``root`` (default: this tree), compared by ``mgx_build_hash``."""
+    from . import build as _build
+    want = _build.source_hash(root or _build.ROOT)
+    got = L.mgx_build_hash().decode()
+    if got != want:
+        raise ImportError(f"{LIB_PATH} was built from other sources (library {got}, tree {want}): "
+                          "rebuild it with paper_2503_09203_amd.build.build()")
+
+
 def lib():
-    """Load libmgx.so (built in-tree by ``build()``); raise if it is missing."""
+    """Load libmgx.so (built in-tree by ``build()``); raise if it is missing or was built
+    from sources other than the ones beside it."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_2503_09203_amd.build.build()")
         L = ctypes.CDLL(LIB_PATH)
+        L.mgx_build_hash.restype = ctypes.c_char_p
+        L.mgx_build_hash.argtypes = []
+        check_build(L)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
             fn.restype = res
@@ -263,6 +287,10 @@ def _call(name, *args):
 
 def mgx_version():
     return lib().mgx_version()
+
+
+def mgx_build_hash() -> str:
+    return lib().mgx_build_hash().decode()
 
 
 def mgx_device_count():
@@ -319,11 +347,51 @@ def mgx_class_define(cls) -> int:
     return cid.value
 
 
-def mgx_batch_create(class_ids, n_envs, dt, precision=FP32, flags=0, device=-1, stream=0):
+class TorchAllocator:
+    """Device allocator of a batch backed by torch's caching allocator on one stream; keeps
+    the C callbacks alive for as long as the object lives (the batch's lifetime at least)."""
+
+    def __init__(self, device, stream):
+        self.device, self.stream = device, stream
+        self.live = {}
+
+        def _alloc(nbytes, ctx):
+            try:
+                ptr = _torch().cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            except Exception:
+                return None
+            self.live[int(ptr)] = int(nbytes)
+            return int(ptr)
+
+        def _free(ptr, ctx):
+            if ptr and self.live.pop(int(ptr), None) is not None:
+                _torch().cuda.caching_allocator_delete(int(ptr))
+
+        self.alloc_fn = ALLOC_FN(_alloc)
+        self.free_fn = FREE_FN(_free)
+
+
+def _batch_desc(class_ids, n_envs, dt, precision, flags, device, stream, state=0, record=0, allocator=None):
     n = len(class_ids)
     ids = (I32 * n)(*class_ids)
     ns = (I64 * n)(*n_envs)
-    d = BatchDesc(n, precision, ids, ns, float(dt), int(flags), int(device), ctypes.c_void_p(int(stream)))
+    d = BatchDesc(n, precision, ids, ns, float(dt), int(flags), int(device), ctypes.c_void_p(int(stream)),
+                  ctypes.c_void_p(int(state)), ctypes.c_void_p(int(record)),
+                  allocator.alloc_fn if allocator else ALLOC_FN(), allocator.free_fn if allocator else FREE_FN(),
+                  None)
+    return d, (ids, ns)
+
+
+def mgx_batch_plan(class_ids, n_envs, dt, precision=FP32, flags=0) -> Layout:
+    d, keep = _batch_desc(class_ids, n_envs, dt, precision, flags, -1, 0)
+    L = Layout()
+    _call("mgx_batch_plan", ctypes.byref(d), ctypes.byref(L))
+    return L
+
+
+def mgx_batch_create(class_ids, n_envs, dt, precision=FP32, flags=0, device=-1, stream=0, state=0, record=0,
+                     allocator=None):
+    d, keep = _batch_desc(class_ids, n_envs, dt, precision, flags, device, stream, state, record, allocator)
     h = P()
     _call("mgx_batch_create", ctypes.byref(d), ctypes.byref(h))
     return h
@@ -468,7 +536,12 @@ class Batch:
     """Owns one batch. Device buffers are torch tensors on the batch's device; every call
     goes to the library on torch's current stream at creation (or the one given)."""
 
-    def __init__(self, classes, n_envs, dt=0.01, precision=FP32, flags=0, device=0, stream=None):
+    def __init__(self, classes, n_envs, dt=0.01, precision=FP32, flags=0, device=0, stream=None, state=None,
+                 record=None, torch_allocator=False):
+        """``state`` / ``record``: optional contiguous tensors of the batch precision on its
+        device, adopted in place (sizes from ``mgx_batch_plan``; they must outlive the batch).
+        ``torch_allocator``: take every buffer the library allocates from torch's caching
+        allocator instead of hipMalloc."""
         torch = _torch()
         self.device = torch.device("cuda", device)
         if stream is None:
@@ -477,8 +550,17 @@ class Batch:
         self.class_ids = [mgx_class_define(c) for c in classes]
         self.precision = precision
         self.dtype = torch.float32 if precision == FP32 else torch.float64
+        plan = mgx_batch_plan(self.class_ids, list(n_envs), dt, precision, flags)
+        for name, t, need in (("state", state, plan.state_elems), ("record", record, plan.record_elems)):
+            if t is not None and (t.dtype != self.dtype or t.device != self.device or not t.is_contiguous()
+                                  or t.numel() < need):
+                raise ValueError(f"{name}: need a contiguous {self.dtype} tensor of >= {need} elements on "
+                                 f"{self.device}")
+        self._adopted = (state, record)
+        self._allocator = TorchAllocator(self.device, stream) if torch_allocator else None
         self.h = mgx_batch_create(self.class_ids, list(n_envs), dt, precision, flags, device,
-                                  stream.cuda_stream)
+                                  stream.cuda_stream, 0 if state is None else state.data_ptr(),
+                                  0 if record is None else record.data_ptr(), self._allocator)
         self.layout = mgx_batch_layout(self.h)
         self.m = [self.layout.m[c] for c in range(len(classes))]
         self.n = [self.layout.n[c] for c in range(len(classes))]

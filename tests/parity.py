@@ -16,3 +16,9 @@ def geodesic(qa, qb):
     """Rotation angle between quaternion columns [4, N] (sign-insensitive)."""
     d = np.abs(np.sum(np.asarray(qa, dtype=np.float64) * np.asarray(qb, dtype=np.float64), axis=0))
     return 2 * np.arccos(np.clip(d, 0, 1))
+
+
+# Rudder-workload environments (of 65,536) whose trajectories amplify rounding the most:
+# the ten largest drifts of the FP64 oracle with its state rounded to float32 after every
+# step, against itself, after 1000 steps (recomputed by tests/test_conditioning.py).
+RUDDER_SENSITIVE = np.array([39754, 26752, 49185, 13584, 29825, 21597, 5733, 64156, 26187, 14274])

@@ -34,6 +34,24 @@ def test_binding_covers_every_declared_symbol():
     assert set(declared_functions()) <= set(mgx.SIGNATURES)
 
 
+def test_loader_refuses_a_library_built_from_other_sources(tmp_path):
+    """The library carries the digest of the sources it was compiled from; the loader
+    accepts it against an identical copy of the sources and refuses it once one byte of a
+    kernel source differs."""
+    import shutil
+    from paper_2503_09203_amd import build as B
+    L = mgx.lib()
+    assert mgx.mgx_build_hash() == B.source_hash() != "unknown"
+    pkg = os.path.basename(B.PKG)
+    shutil.copytree(os.path.join(ROOT, "include"), tmp_path / "include")
+    shutil.copytree(os.path.join(B.PKG, "csrc"), tmp_path / pkg / "csrc")
+    mgx.check_build(L, str(tmp_path))
+    f = tmp_path / pkg / "csrc" / "step.hpp"
+    f.write_text(f.read_text() + "\n")
+    with pytest.raises(ImportError, match="other sources"):
+        mgx.check_build(L, str(tmp_path))
+
+
 def test_version_and_status_strings():
     assert mgx.mgx_version() >= 100
     assert mgx.lib().mgx_status_string(mgx.MGX_E_INVALID) == b"invalid argument"
