@@ -409,6 +409,21 @@ mgx_status mgx_autotune_load(const char* path);
 mgx_status mgx_rollout_forward(mgx_batch* b, const void* actions, int64_t n_rows, int64_t row0, int32_t hold,
                                int32_t H, int32_t ckpt_every, void* pos_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * training loops, harnesses that forbid hipMalloc): mgx_rollout_forward with the
+ * checkpoints and the segment scratch placed in a library-static device array of 64 MiB per
+ * GPU instead of batch buffers allocated on first use; no allocation of any kind. Same
+ * arguments, results and step-counter movement as mgx_rollout_forward, followed by the same
+ * mgx_rollout_backward. MGX_E_INVALID (nothing launched) when the checkpoints
+ * (P * ceil(H / ckpt_every) * state_elems bytes, rounded up to 256) and the segment scratch
+ * (P * 2 * ckpt_every * state_elems bytes) exceed 64 MiB; P is the element size. The array
+ * is shared by every call on the GPU and keeps the last call's contents: a later
+ * mgx_rollout_forward_static on any batch of the same GPU overwrites the checkpoints of an
+ * earlier one, whose mgx_rollout_backward then returns MGX_E_STATE; calls that overlap on
+ * one GPU (other threads, other streams) race. */
+mgx_status mgx_rollout_forward_static(mgx_batch* b, const void* actions, int64_t n_rows, int64_t row0, int32_t hold,
+                                      int32_t H, int32_t ckpt_every, void* pos_out);
+
 /* Reverse-mode sweep of the last forward pass (vector-Jacobian product of the step map,
  * written out by hand): each environment recomputes every ckpt_every-step segment from its
  * checkpoint into scratch, then runs the adjoint backwards through it. Given

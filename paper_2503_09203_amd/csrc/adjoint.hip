@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "adjoint.hpp"
@@ -310,16 +311,45 @@ static AdjArgs adj_args(mgx_batch* b, int c) {
     A.ckpt = b->ro_ckpt;
     A.npad = (int32_t)b->npad[c];
     A.t0 = b->ro_t0;
-    A.ckpt_buf = (char*)b->d_ckpt + P * b->state_off[c];
+    A.ckpt_buf = (char*)b->ro_ckpt_mem + P * b->state_off[c];
     A.ckpt_stride = b->state_elems;
-    A.seg_buf = (char*)b->d_seg + P * b->state_off[c];
+    A.seg_buf = (char*)b->ro_seg_mem + P * b->state_off[c];
     A.pos_stride = 3 * b->npad_total;
     A.misc = b->d_misc;
     return A;
 }
 
-extern "C" mgx_status mgx_rollout_forward(mgx_batch* b, const void* actions, int64_t n_rows, int64_t row0, int32_t hold,
-                                          int32_t H, int32_t ckpt_every, void* pos_out) {
+// The static scratch of the allocation-free forward pass: one array per GPU (each device
+// holds its own copy at its own address), its address taken once per device with that
+// device current. The generation counts static forward passes per device, so a backward
+// pass can tell that a later one has overwritten its checkpoints.
+namespace {
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+uint64_t g_scratch_gen[kMaxScratchDevices] = {};
+}  // namespace
+
+// Address of this device's scratch array (the array's name is only a host-side stand-in).
+static mgx_status scratch_address(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxScratchDevices) return fail(MGX_E_INVALID, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        hipDevice_guard g(dev);
+        if (!g.ok()) return hip_fail(nullptr, g.err(), "hipSetDevice");
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MGX_OK;
+}
+
+static mgx_status rollout_forward(mgx_batch* b, const void* actions, int64_t n_rows, int64_t row0, int32_t hold,
+                                  int32_t H, int32_t ckpt_every, void* pos_out, bool use_static) {
     if (!b) return fail(MGX_E_INVALID, "batch is NULL");
     if (b->faulted) return fail(MGX_E_STATE, "batch faulted by an earlier device error");
     if (!b->params_set) return fail(MGX_E_STATE, "mgx_batch_set_params has not been called");
@@ -339,24 +369,46 @@ extern "C" mgx_status mgx_rollout_forward(mgx_batch* b, const void* actions, int
     const int64_t nck = (H + ckpt_every - 1) / ckpt_every;
     const size_t P = (size_t)b->prec;
     const size_t ck_bytes = P * (size_t)nck * b->state_elems, seg_bytes = P * (size_t)2 * ckpt_every * b->state_elems;
-    if (ck_bytes > b->ckpt_bytes) {
-        b->dev_free(b->d_ckpt);
-        b->d_ckpt = nullptr;
-        b->ckpt_bytes = 0;
-        hipError_t e;
-        b->d_ckpt = b->dev_alloc(ck_bytes, &e);
-        if (e != hipSuccess) return hip_fail(nullptr, e, "hipMalloc(checkpoints)");
-        b->ckpt_bytes = ck_bytes;
+    void* ck_mem = nullptr;
+    void* seg_mem = nullptr;
+    uint64_t gen = 0;
+    if (use_static) {
+        const size_t ck_aligned = (ck_bytes + 255) / 256 * 256;
+        if (ck_aligned + seg_bytes > kScratchBytes)
+            return fail(MGX_E_INVALID, "the rollout needs %zu bytes of checkpoints and segment scratch; the static "
+                        "scratch holds %zu", ck_aligned + seg_bytes, kScratchBytes);
+        void* base = nullptr;
+        mgx_status st = scratch_address(b->device, &base);
+        if (st != MGX_OK) return st;
+        ck_mem = base;
+        seg_mem = (char*)base + ck_aligned;
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        gen = ++g_scratch_gen[b->device];
+    } else {
+        if (ck_bytes > b->ckpt_bytes) {
+            b->dev_free(b->d_ckpt);
+            b->d_ckpt = nullptr;
+            b->ckpt_bytes = 0;
+            hipError_t e;
+            b->d_ckpt = b->dev_alloc(ck_bytes, &e);
+            if (e != hipSuccess) return hip_fail(nullptr, e, "hipMalloc(checkpoints)");
+            b->ckpt_bytes = ck_bytes;
+        }
+        if (seg_bytes > b->seg_bytes) {
+            b->dev_free(b->d_seg);
+            b->d_seg = nullptr;
+            b->seg_bytes = 0;
+            hipError_t e;
+            b->d_seg = b->dev_alloc(seg_bytes, &e);
+            if (e != hipSuccess) return hip_fail(nullptr, e, "hipMalloc(segment scratch)");
+            b->seg_bytes = seg_bytes;
+        }
+        ck_mem = b->d_ckpt;
+        seg_mem = b->d_seg;
     }
-    if (seg_bytes > b->seg_bytes) {
-        b->dev_free(b->d_seg);
-        b->d_seg = nullptr;
-        b->seg_bytes = 0;
-        hipError_t e;
-        b->d_seg = b->dev_alloc(seg_bytes, &e);
-        if (e != hipSuccess) return hip_fail(nullptr, e, "hipMalloc(segment scratch)");
-        b->seg_bytes = seg_bytes;
-    }
+    b->ro_ckpt_mem = ck_mem;
+    b->ro_seg_mem = seg_mem;
+    b->ro_static_gen = gen;
     b->ro_actions = actions;
     b->ro_n_rows = n_rows;
     b->ro_row0 = row0;
@@ -384,11 +436,26 @@ extern "C" mgx_status mgx_rollout_forward(mgx_batch* b, const void* actions, int
     return MGX_OK;
 }
 
+extern "C" mgx_status mgx_rollout_forward(mgx_batch* b, const void* actions, int64_t n_rows, int64_t row0, int32_t hold,
+                                          int32_t H, int32_t ckpt_every, void* pos_out) {
+    return rollout_forward(b, actions, n_rows, row0, hold, H, ckpt_every, pos_out, false);
+}
+
+extern "C" mgx_status mgx_rollout_forward_static(mgx_batch* b, const void* actions, int64_t n_rows, int64_t row0,
+                                                 int32_t hold, int32_t H, int32_t ckpt_every, void* pos_out) {
+    return rollout_forward(b, actions, n_rows, row0, hold, H, ckpt_every, pos_out, true);
+}
+
 extern "C" mgx_status mgx_rollout_backward(mgx_batch* b, const void* dpos, void* dactions, void* dparams) {
     if (!b) return fail(MGX_E_INVALID, "batch is NULL");
     if (b->faulted) return fail(MGX_E_STATE, "batch faulted by an earlier device error");
     if (!b->ro_valid) return fail(MGX_E_STATE, "no forward rollout recorded");
     if (!dpos) return fail(MGX_E_INVALID, "dpos is NULL");
+    if (b->ro_static_gen) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (g_scratch_gen[b->device] != b->ro_static_gen)
+            return fail(MGX_E_STATE, "a later mgx_rollout_forward_static on this GPU overwrote the checkpoints");
+    }
     hipDevice_guard guard(b->device);
     const size_t P = (size_t)b->prec;
     for (int c = 0; c < b->n_classes; ++c) {

@@ -211,6 +211,7 @@ SIGNATURES = {
     "mgx_autotune_save": (I32, [ctypes.c_char_p]),
     "mgx_autotune_load": (I32, [ctypes.c_char_p]),
     "mgx_rollout_forward": (I32, [P, P, I64, I64, I32, I32, I32, P]),
+    "mgx_rollout_forward_static": (I32, [P, P, I64, I64, I32, I32, I32, P]),
     "mgx_rollout_backward": (I32, [P, P, P, P]),
     "mgx_host_step_vjp": (I32, [I32, U32, P, P, P, P, P, P, P, P, P]),
     "mgx_server_now": (ctypes.c_double, []),
@@ -489,6 +490,11 @@ def mgx_autotune_load(path):
 
 def mgx_rollout_forward(h, actions_ptr, n_rows, row0, hold, H, ckpt_every, pos_ptr):
     _call("mgx_rollout_forward", h, actions_ptr, int(n_rows), int(row0), int(hold), int(H), int(ckpt_every), pos_ptr)
+
+
+def mgx_rollout_forward_static(h, actions_ptr, n_rows, row0, hold, H, ckpt_every, pos_ptr):
+    _call("mgx_rollout_forward_static", h, actions_ptr, int(n_rows), int(row0), int(hold), int(H), int(ckpt_every),
+          pos_ptr)
 
 
 def mgx_rollout_backward(h, dpos_ptr, dactions_ptr, dparams_ptr):
