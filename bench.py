@@ -574,10 +574,24 @@ def adjoint(args):
             fw.append(e[0].elapsed_time(e[1]) * 1e-3)
             bw.append(e[1].elapsed_time(e[2]) * 1e-3)
     f, g = float(np.mean(fw)), float(np.mean(bw))
+    m = w.classes[0].m
+    step_flops, _ = mgx.mgx_step_cost(m)
+    vjp_flops, vjp_ops = mgx.mgx_vjp_cost(m)
+    # backward: every step recomputed once from its checkpoint, then its vector-Jacobian
+    # product (which recomputes the step's forward quantities from the stored state)
+    bwd_flops = (step_flops + vjp_flops) * N * H
     out = {"metric": METRIC, "workload": f"adjoint_{N}x{H}", "unit": "env-steps/s", "value": N * H / (f + g),
-           "n_envs": N, "horizon": H, "checkpoint_every": CK, "thrusters": w.classes[0].m,
+           "n_envs": N, "horizon": H, "checkpoint_every": CK, "thrusters": m,
            "forward_ms": f * 1e3, "backward_ms": g * 1e3, "forward_env_steps_per_s": N * H / f,
-           "backward_env_steps_per_s": N * H / g, "backward_over_forward": g / f}
+           "backward_env_steps_per_s": N * H / g, "backward_over_forward": g / f,
+           "roofline": {"bound": "alu", "kernel": f"k_rollout_bwd<float,{m},false>",
+                        "achieved": bwd_flops / g / 1e12, "peak": (PEAK_FP32_VECTOR / 1e12), "unit": "TFLOP/s",
+                        "frac": bwd_flops / g / 1e12 / (PEAK_FP32_VECTOR / 1e12), "flops_per_env_step": step_flops + vjp_flops,
+                        "vjp_flops_per_env_step": vjp_flops, "vjp_valu_ops_per_env_step": vjp_ops,
+                        "launch_ms": g * 1e3, "traffic": None},
+           "forward_roofline": {"bound": "alu", "kernel": f"k_rollout_fwd<float,{m},false>",
+                                "achieved": step_flops * N * H / f / 1e12, "peak": (PEAK_FP32_VECTOR / 1e12),
+                                "unit": "TFLOP/s", "frac": step_flops * N * H / f / 1e12 / (PEAK_FP32_VECTOR / 1e12)}}
     b.close()
     print(json.dumps(out), flush=True)
 

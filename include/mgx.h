@@ -88,6 +88,17 @@ mgx_status mgx_device_count(int32_t* count);
  * reverse gains instead of the plain one. */
 #define MGX_COST_SHAPED 0x80000000u
 mgx_status mgx_step_cost(int32_t m, uint32_t batch_flags, double* flops, double* valu_ops);
+/* The same count for the reverse sweep of a differentiable rollout: one environment-step
+ * of the hand-written vector-Jacobian product (mgx_rollout_backward), including the
+ * forward quantities it recomputes from the stored state. */
+mgx_status mgx_vjp_cost(int32_t m, uint32_t batch_flags, double* flops, double* valu_ops);
+
+/* Diagnostics: the per-wave phase times of the last step launch, four 100 MHz real-time
+ * counter values per wave (entry, prologue loads landed, steps done, stores drained), wave
+ * w of the launch at out[4 w .. 4 w + 3]; synchronises the device. Only a library compiled
+ * with MGX_WAVE_TIMESTAMPS records them (the recording changes the kernels); any other
+ * build returns MGX_E_STATE. */
+mgx_status mgx_diag_wave_times(uint64_t* out, int64_t n_waves);
 
 /* ------------------------------------------------------------------ vehicle classes */
 

@@ -13,6 +13,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmgx.so")
+# The diagnostic build: the same sources with per-wave phase timestamps in the step kernels.
+LIB_WAVE_TS = os.path.join(PKG, "libmgx_wavets.so")
 ARCH = os.environ.get("MGX_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -46,9 +48,9 @@ def source_hash(root: str = ROOT) -> str:
     return h.hexdigest()[:16]
 
 
-def build(verbose: bool = False, extra=(), jobs: int = 0) -> str:
-    """Compile every HIP source into libmgx.so (always recompiles): one object per source,
-    compiled in parallel, then linked."""
+def build(verbose: bool = False, extra=(), jobs: int = 0, out: str = LIB) -> str:
+    """Compile every HIP source into ``out`` (libmgx.so; always recompiles): one object per
+    source, compiled in parallel, then linked."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
@@ -67,16 +69,24 @@ def build(verbose: bool = False, extra=(), jobs: int = 0) -> str:
     try:
         if failed:
             raise subprocess.CalledProcessError(1, "hipcc -c " + " ".join(failed))
-        tmp = LIB + f".tmp{os.getpid()}"
+        tmp = out + f".tmp{os.getpid()}"
         subprocess.check_call([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
-        os.replace(tmp, LIB)
+        os.replace(tmp, out)
     finally:
         for o in objs:
             if os.path.exists(o):
                 os.remove(o)
-    return LIB
+    return out
+
+
+def build_wave_timestamps(verbose: bool = False) -> str:
+    """The diagnostic library libmgx_wavets.so (step kernels record per-wave phase times)."""
+    return build(verbose, extra=("-DMGX_WAVE_TIMESTAMPS",), out=LIB_WAVE_TS)
 
 
 if __name__ == "__main__":
-    build(verbose=True, extra=sys.argv[1:])
-    print(LIB)
+    if sys.argv[1:] == ["--wave-timestamps"]:
+        print(build_wave_timestamps(verbose=True))
+    else:
+        build(verbose=True, extra=sys.argv[1:])
+        print(LIB)

@@ -71,6 +71,9 @@ template <typename T, int M, bool kShaped = false>
 __host__ __device__ __forceinline__ void step_vjp(const ClassT<T>& C, const EnvT<T>& E, const T IA2[3], const T Brb[3],
                                                   const StateT<T, M>& s, const T a[M], StateT<T, M>& xb, T abar[M],
                                                   T gdL[6], T gdQ[6], T gA[6], T gDt[6]) {
+    // The adjoint's own products and sums may fuse into multiply-adds (this function only;
+    // the forward step it differentiates keeps its explicit rounding).
+#pragma clang fp contract(fast)
     // ------------------------------------------------------------------ forward recompute
     T nl[M], fd[M];  // lagged rotor state; d(thrust / k)/d(nl)
     T tau[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};

@@ -4,6 +4,7 @@
 
 #include <cmath>
 
+#include "adjoint.hpp"
 #include "mgx.h"
 #include "runtime_internal.hpp"
 #include "step.hpp"
@@ -34,6 +35,7 @@ static inline Cnt operator*(Cnt a, Cnt b) { return tally(a.v * b.v, 1, 1); }
 static inline Cnt operator/(Cnt a, Cnt b) { return tally(a.v / b.v, 1, 1); }
 static inline Cnt operator-(Cnt a) { return Cnt(-a.v); }
 static inline Cnt& operator+=(Cnt& a, Cnt b) { return a = a + b; }
+static inline Cnt& operator-=(Cnt& a, Cnt b) { return a = a - b; }
 static inline bool operator<(Cnt a, Cnt b) { return a.v < b.v; }
 static inline bool operator>(Cnt a, Cnt b) { return a.v > b.v; }
 static inline bool operator<=(Cnt a, Cnt b) { return a.v <= b.v; }
@@ -126,7 +128,86 @@ static CostTally measure(uint32_t flags, uint32_t fin_mask = 0, bool payload = f
     return g_tally;
 }
 
+// The reverse sweep's arithmetic per environment-step: the hand-written vector-Jacobian
+// product of the step (its forward recomputation included), counted like the step itself.
+template <int M>
+static CostTally measure_vjp(uint32_t flags) {
+    ClassT<Cnt> C;
+    for (int j = 0; j < 6; ++j)
+        for (int i = 0; i < kMaxThr; ++i) C.Bk[j][i] = Cnt(3.0 * (i + 1) + 0.3 * j);
+    for (int i = 0; i < kMaxThr; ++i) {
+        C.alpha[i] = 0.1;
+        C.dz[i] = (flags & MGX_COST_SHAPED) ? 0.05 : 0.0;
+        C.rev[i] = (flags & MGX_COST_SHAPED) ? 0.7 : 1.0;
+    }
+    for (int j = 0; j < 3; ++j) {
+        C.inertia[j] = 1.0 + j;
+        C.rb[j] = j == 2 ? -0.01 : 0.0;
+        C.rg[j] = 0.0;
+    }
+    C.g0 = 9.81;
+    C.dt = 0.01;
+    C.inv_dt = 100;
+    C.half_dt = 0.005;
+    C.m = M;
+    C.flags = flags & ~MGX_COST_SHAPED;
+    C.shaped = (flags & MGX_COST_SHAPED) ? 1 : 0;
+    C.fin_mask = 0;
+    C.payload = 0;
+    EnvT<Cnt> E;
+    for (int j = 0; j < 6; ++j) {
+        E.dtMinv[j] = 0.001;
+        E.A[j] = 1.0;
+        E.dL[j] = 5;
+        E.dQ[j] = 20;
+    }
+    E.mass = 12;
+    E.wmb = -1;
+    E.buoy = 118;
+    for (int j = 0; j < 3; ++j) E.Vc[j] = 0.1 * (j + 1);
+    set_amc(E, flags & ~MGX_COST_SHAPED);
+    Cnt IA2[3] = {2, 3, 4}, Brb[3] = {0, 0, -1.18};
+    StateT<Cnt, M> s, xb;
+    for (int j = 0; j < 3; ++j) s.p[j] = 0, xb.p[j] = 0.3;
+    s.q[0] = 0.9;
+    s.q[1] = 0.1;
+    s.q[2] = 0.3;
+    s.q[3] = -0.2;
+    for (int j = 0; j < 4; ++j) xb.q[j] = 0.1 * j;
+    for (int j = 0; j < 6; ++j) s.nu[j] = 0.1 * (j - 2), xb.nu[j] = 0.2;
+    for (int i = 0; i < M; ++i) s.n[i] = 0.1 * i - 0.3, xb.n[i] = 0.05;
+    Cnt a[M], ab[M], gdL[6], gdQ[6], gA[6], gDt[6];
+    for (int i = 0; i < M; ++i) a[i] = 0.5 - 0.1 * i;
+    for (int j = 0; j < 6; ++j) gdL[j] = gdQ[j] = gA[j] = gDt[j] = 0.0;
+    g_tally = CostTally();
+    if (flags & MGX_COST_SHAPED)
+        step_vjp<Cnt, M, true>(C, E, IA2, Brb, s, a, xb, ab, gdL, gdQ, gA, gDt);
+    else
+        step_vjp<Cnt, M, false>(C, E, IA2, Brb, s, a, xb, ab, gdL, gdQ, gA, gDt);
+    return g_tally;
+}
+
 }  // namespace mgx
+
+extern "C" mgx_status mgx_vjp_cost(int32_t m, uint32_t batch_flags, double* flops, double* valu_ops) {
+    using namespace mgx;
+    if (!flops || !valu_ops) return fail(MGX_E_INVALID, "NULL argument");
+    CostTally t;
+    switch (m) {
+        case 1: t = measure_vjp<1>(batch_flags); break;
+        case 2: t = measure_vjp<2>(batch_flags); break;
+        case 3: t = measure_vjp<3>(batch_flags); break;
+        case 4: t = measure_vjp<4>(batch_flags); break;
+        case 5: t = measure_vjp<5>(batch_flags); break;
+        case 6: t = measure_vjp<6>(batch_flags); break;
+        case 7: t = measure_vjp<7>(batch_flags); break;
+        case 8: t = measure_vjp<8>(batch_flags); break;
+        default: return fail(MGX_E_INVALID, "m=%d outside [1,8]", m);
+    }
+    *flops = t.flops;
+    *valu_ops = t.ops;
+    return MGX_OK;
+}
 
 extern "C" mgx_status mgx_step_cost(int32_t m, uint32_t batch_flags, double* flops, double* valu_ops) {
     using namespace mgx;

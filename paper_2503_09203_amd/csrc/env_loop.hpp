@@ -246,6 +246,18 @@ __device__ __forceinline__ void final_reduce_stats(const float* partials, unsign
     out[j] = acc;
 }
 
+#ifdef MGX_WAVE_TIMESTAMPS
+// Diagnostic builds only: per-wave phase times of the step loop on the 100 MHz real-time
+// counter (entry; prologue loads landed; steps done; stores drained), indexed by the wave's
+// position in its launch. Every translation unit has its own copy; the step kernels' copy
+// is read back by mgx_diag_wave_times.
+constexpr int kWaveTsMax = 1 << 16;
+static __device__ unsigned long long g_wave_ts[kWaveTsMax][4];
+#define MGX_WAVE_TS(var) const unsigned long long var = __builtin_amdgcn_s_memrealtime()
+#else
+#define MGX_WAVE_TS(var)
+#endif
+
 // A wave-uniform value moved to a vector register and hidden from the uniformity analysis,
 // so the compiler keeps it there. The allocation columns (6 x m values) would otherwise sit
 // in scalar registers, which cannot hold them next to the loop's own scalars for m = 8.
@@ -390,6 +402,7 @@ template <typename T, int M, bool kOut, bool kShaped, bool kSingle = false, bool
 __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs, int64_t env, int64_t t0, int K,
                                           float st[kStats]) {
     static_assert(!(kSingle && kOut), "the single-step form has no per-step outputs");
+    MGX_WAVE_TS(ts_entry);
     const int64_t np = A.npad;
     const ClassT<T> C = class_in_vgpr<T, M, kFins>(Cs);
     // classes with fins carry the attitude's low-order words through the launch (float)
@@ -427,6 +440,7 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
         }
     }
     __builtin_amdgcn_s_waitcnt(0);
+    MGX_WAVE_TS(ts_loaded);
 #pragma unroll
     for (int i = 0; i < M; ++i) cur[i] = clip1(cur[i]);
     T IA2[3], Brb[3];
@@ -478,6 +492,7 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
         }
     }
     }
+    MGX_WAVE_TS(ts_stepped);
     if (bad && (threadIdx.x & (kWave - 1)) == 0) atomicOr(&A.misc->err, kErrActionRow);
 
     // The same check as renorm_attitude, written out: as a call it changes the register
@@ -496,6 +511,19 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
     }
 
     store_state<T, M>(S, np, env, s);
+#ifdef MGX_WAVE_TIMESTAMPS
+    __builtin_amdgcn_s_waitcnt(0);
+    MGX_WAVE_TS(ts_stored);
+    {
+        const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+        if ((threadIdx.x & (kWave - 1)) == 0 && w < kWaveTsMax) {
+            g_wave_ts[w][0] = ts_entry;
+            g_wave_ts[w][1] = ts_loaded;
+            g_wave_ts[w][2] = ts_stepped;
+            g_wave_ts[w][3] = ts_stored;
+        }
+    }
+#endif
 
     if (A.partials) {
         if (env < A.nvalid) {

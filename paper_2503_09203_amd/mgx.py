@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libmgx.so")
+# MGX_LIB selects another in-tree build of the same sources (e.g. the diagnostic one).
+LIB_PATH = os.environ.get("MGX_LIB") or os.path.join(PKG, "libmgx.so")
 
 MGX_OK = 0
 MGX_E_INVALID = -1
@@ -180,12 +181,14 @@ I32, I64, U32, U64, F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctype
 # name -> (restype, argtypes)
 SIGNATURES = {
     "mgx_build_hash": (ctypes.c_char_p, []),
+    "mgx_diag_wave_times": (I32, [P, I64]),
     "mgx_status_string": (ctypes.c_char_p, [I32]),
     "mgx_last_error": (ctypes.c_size_t, [ctypes.c_char_p, ctypes.c_size_t]),
     "mgx_last_hip_error": (I32, []),
     "mgx_version": (I32, []),
     "mgx_device_count": (I32, [ctypes.POINTER(I32)]),
     "mgx_step_cost": (I32, [I32, U32, ctypes.POINTER(F64), ctypes.POINTER(F64)]),
+    "mgx_vjp_cost": (I32, [I32, U32, ctypes.POINTER(F64), ctypes.POINTER(F64)]),
     "mgx_class_step_cost": (I32, [I32, U32, ctypes.POINTER(F64), ctypes.POINTER(F64)]),
     "mgx_class_define": (I32, [ctypes.POINTER(ClassDesc), ctypes.POINTER(I32)]),
     "mgx_batch_create": (I32, [ctypes.POINTER(BatchDesc), ctypes.POINTER(P)]),
@@ -303,6 +306,12 @@ def mgx_device_count():
 def mgx_step_cost(m, flags=0):
     f, o = F64(), F64()
     _call("mgx_step_cost", int(m), int(flags), ctypes.byref(f), ctypes.byref(o))
+    return f.value, o.value
+
+
+def mgx_vjp_cost(m, flags=0):
+    f, o = F64(), F64()
+    _call("mgx_vjp_cost", int(m), int(flags), ctypes.byref(f), ctypes.byref(o))
     return f.value, o.value
 
 
