@@ -90,8 +90,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="dr",
-                    choices=["dr", "propellers", "rudders", "payload", "hetero", "serve", "adjoint", "resample", "station"],
-                    help="dr: the default benchmark line; propellers: the same line with dead zones, reverse "
+                    choices=["dr", "plain", "propellers", "rudders", "payload", "hetero", "serve", "adjoint", "resample",
+                             "station"],
+                    help="dr: the default benchmark line; plain: the small plain workload (1024 environments at the "
+                         "class nominal, 1000 steps) in FP64 and FP32 batches beside the oracle on the same inputs; propellers: the same line with dead zones, reverse "
                          "gains and shaft torques on every thruster; rudders: the same line for a rudder-propeller "
                          "class (one propeller, four tail fins); payload: the same line with the centre of gravity "
                          "off the body origin (full mass matrix); hetero: five classes in one persistent launch; "
@@ -115,6 +117,13 @@ def main():
                          "passes: 4 of K = 16 and 2 of K = 1000 at the default N")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark line, print launch-duration sweeps over K and N")
+    ap.add_argument("--probe", action="store_true",
+                    help="instead of the benchmark line, print the VALU issue-rate probe (float multiply-add chains "
+                         "at 1, 2 and 4 waves per SIMD) and the launch floor (back-to-back launches that do nothing)")
+    ap.add_argument("--wave-phases", action="store_true",
+                    help="instead of the benchmark line, print the per-wave phase times of the step kernel "
+                         "(needs the diagnostic build: python -m paper_2503_09203_amd.build --wave-timestamps, "
+                         "then MGX_LIB=<repo>/paper_2503_09203_amd/libmgx_wavets.so)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -142,6 +151,15 @@ def main():
         del src, dst
     if args.sweep:
         sweep(args)
+        return
+    if args.probe:
+        probe(args)
+        return
+    if args.wave_phases:
+        wave_phases(args)
+        return
+    if args.workload == "plain":
+        plain(args)
         return
     if args.counter_launches:
         counter_launches(args)
@@ -186,7 +204,7 @@ def main():
           for _ in range(args.steps)]
 
     def bench_step(i=None):
-        mgx.mgx_batch_set_params(b.h, param_ptrs, 1)
+        mgx.mgx_batch_set_params(b.h, param_ptrs, 2)   # device arrays known valid: no host wait
         b.reset(init_state=init)
         b.t = 0
         if i is not None:
@@ -311,6 +329,137 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def plain(args):
+    """The small plain workload: one 6-thruster class, 1024 environments at the class
+    nominal, no current, 1000 steps, actions resampled every 10 steps. The rollout runs as
+    one captured graph of 16-step launches, in an FP64 batch (the configuration's precision)
+    and an FP32 one; every environment's final state is checked against the FP64 oracle,
+    which is timed on the same inputs at one thread and at all threads."""
+    import torch
+
+    import oracle  # CPU baseline and parity leg
+    import synth
+    from paper_2503_09203_amd import mgx
+
+    N, T, K, HOLD = 1024, 1000, 16, 10
+    w = synth.plain_small(n=N, steps=T)
+    cls = w.classes[0]
+    rows = -(-T // HOLD)
+    stream = torch.cuda.current_stream()
+    out = {"metric": METRIC, "workload": f"plain_small_{N}x{T}", "unit": "env-steps/s", "n_envs": N,
+           "rollout_steps": T, "launch_steps_K": K, "hold": HOLD, "thrusters": cls.m}
+    envs = oracle.make_envs(cls, w.params, w.dt)
+    x0 = oracle.pack_state(w.state[0].p, w.state[0].q, w.state[0].nu, w.state[0].n)
+    a_host = oracle.pack_actions(synth.actions(N, cls.m, rows))
+    for prec, name in ((mgx.FP64, "f64"), (mgx.FP32, "f32")):
+        b = mgx.Batch([cls], [N], w.dt, prec)
+        b.set_params(w.params)
+        init = torch.tensor(b.pack_state([w.state[0].stacked()]), dtype=b.dtype, device="cuda:0")
+        acts = b.gen_actions(rows, seed=synth.MASTER_SEED)
+        g = b.capture(acts, T, K, hold=HOLD)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        for i in range(args.warmup + args.steps):
+            b.reset(init_state=init)
+            b.t = 0
+            if i >= args.warmup:
+                ev[i - args.warmup][0].record(stream)
+            g.replay()
+            if i >= args.warmup:
+                ev[i - args.warmup][1].record(stream)
+        torch.cuda.synchronize()
+        sec = float(np.mean([a.elapsed_time(c) for a, c in ev])) * 1e-3
+        final = b.unpack_state(b.get_state().cpu().numpy().astype(np.float64))[0]
+        g.close()
+        b.close()
+        ref, _, _ = oracle.rollout(envs, x0.copy(), a_host, HOLD, T)
+        err = parity_errors(final, oracle.unpack_state(ref, cls.m))
+        out[name] = {"ms_per_rollout": sec * 1e3, "env_steps_per_s": N * T / sec, "launch_us_mean": sec / -(-T // K) * 1e6,
+                     "parity_max_err": float(err.max()), "tolerance": 1e-9 if prec == mgx.FP64 else 1e-3,
+                     "pass": bool(err.max() <= (1e-9 if prec == mgx.FP64 else 1e-3)), "envs_checked": N}
+    threads = oracle.get_threads()
+    rates = {}
+    for nt in (1, threads):
+        oracle.set_threads(nt)
+        tc = time.perf_counter()
+        oracle.rollout(envs, x0.copy(), a_host, HOLD, T)
+        rates[nt] = N * T / (time.perf_counter() - tc)
+    oracle.set_threads(threads)
+    out["value"] = out["f64"]["env_steps_per_s"]
+    out["dtype"] = "f64"
+    out["cpu_baseline"] = {"value": rates[threads], "unit": "env-steps/s", "cores": threads, "kind": "oracle",
+                           "value_one_thread": rates[1],
+                           "sample": f"all {N} environments x {T} steps, FP64 C oracle (OpenMP over environments)"}
+    out["note"] = "16 waves on 1024 SIMDs: launch-latency bound (63 launches per rollout)"
+    print(json.dumps(out), flush=True)
+
+
+def probe(args):
+    """VALU issue rate of plain float multiply-add chains at 1, 2 and 4 waves per SIMD, and
+    the launch floor of kernels that do nothing (library diagnostics)."""
+    from paper_2503_09203_amd import mgx
+
+    simds, clock = 1024, 2.4e9
+    iters = 2048
+    for waves_per_simd in (1, 2, 4):
+        n = simds * 64 * waves_per_simd
+        for chains in (1, 2, 4, 8):
+            sec = mgx.mgx_diag_valu_probe(chains, n, iters)
+            wave_instr = n / 64 * 16 * iters * chains
+            print(json.dumps({"probe": "valu", "chains": chains, "threads": n, "waves_per_simd": waves_per_simd,
+                              "seconds": sec, "lane_fma_per_s": n * 16 * iters * chains / sec,
+                              "tflops": 2 * n * 16 * iters * chains / sec / 1e12,
+                              "cycles_per_wave_instr_per_simd": sec * clock / (wave_instr / simds)}), flush=True)
+    for n, block in ((65536, 256), (65536, 64), (262144, 256), (4096, 256)):
+        sec = mgx.mgx_diag_launch_floor(n, block, 1000)
+        print(json.dumps({"probe": "launch_floor", "threads": n, "block": block, "us_per_launch": sec * 1e6}),
+              flush=True)
+
+
+def wave_phases(args):
+    """Per-wave phase times of the step kernel (entry, prologue loads landed, steps done,
+    stores drained) on the randomised workload, for K = 16 and K = 1, read after a run of
+    back-to-back launches (the last launch's waves)."""
+    import ctypes
+
+    import torch
+
+    import synth
+    from paper_2503_09203_amd import mgx
+
+    probe_buf = np.zeros((1, 4), dtype=np.uint64)
+    if mgx.lib().mgx_diag_wave_times(probe_buf.ctypes.data_as(ctypes.c_void_p), 1) != mgx.MGX_OK:
+        print("the loaded library records no wave times: build python -m paper_2503_09203_amd.build "
+              "--wave-timestamps and set MGX_LIB to the built libmgx_wavets.so", file=sys.stderr)
+        sys.exit(1)
+    N, HOLD = args.n, 10
+    w = synth.randomised(n=N, steps=1000)
+    cls = w.classes[0]
+    b = mgx.Batch([cls], [N], w.dt)
+    b.set_params(w.params)
+    init = torch.tensor(b.pack_state([w.state[0].stacked()]), dtype=torch.float32, device="cuda:0")
+    acts = b.gen_actions(101, seed=synth.MASTER_SEED)
+    nw = b.layout.n_pad_total // 64
+    stream = torch.cuda.current_stream()
+    for K, launches in ((16, 62), (1, 500)):
+        b.reset(init_state=init)
+        b.t = 0
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(launches):
+            b.step(acts, K, hold=HOLD)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        buf = np.zeros((nw, 4), dtype=np.uint64)
+        mgx._call("mgx_diag_wave_times", buf.ctypes.data_as(ctypes.c_void_p), nw)
+        t = (buf - buf[:, 0].min()).astype(np.int64) * 10  # 100 MHz counter -> ns
+        q = lambda x: {"p10": float(np.percentile(x, 10)), "p50": float(np.median(x)), "max": float(x.max())}
+        print(json.dumps({"wave_phases": True, "n": N, "K": K, "waves": nw,
+                          "launch_us_mean": e0.elapsed_time(e1) * 1e3 / launches,
+                          "entry_ns": q(t[:, 0]), "loads_ns": q(t[:, 1] - t[:, 0]), "steps_ns": q(t[:, 2] - t[:, 1]),
+                          "stores_ns": q(t[:, 3] - t[:, 2]), "end_ns": q(t[:, 3])}), flush=True)
+    b.close()
+
+
 def hetero(args):
     """Five vehicle classes (4, 5, 6, 8, 8 thrusters; 512 / 3000 / 20000 / 40000 / 7000
     envs) advanced 1024 steps as 32 captured 32-step chunks, launch shape from the
@@ -377,11 +526,37 @@ def hetero(args):
     tuned = b.autotune(acts, CHUNK, hold=HOLD)
     best = run("autotuned")
     whole = run_rollout_graph("autotuned, all chunks in one graph")
+    final = b.unpack_state(b.get_state().cpu().numpy().astype(np.float64))
     out = {"metric": METRIC, "workload": f"hetero_{n}x{T}", "value": best["env_steps_per_s"], "unit": "env-steps/s",
            "n_envs": n, "classes": [c.m for c in w.classes], "n_per_class": w.n_envs, "chunk_steps": CHUNK,
            "autotune": {"candidates": tuned.candidates, "us_per_chunk": tuned.us_per_chunk}, "tuned": best,
            "tuned_rollout_graph": whole, "baseline": base,
            "speedup_vs_per_class": best["env_steps_per_s"] / base["env_steps_per_s"]}
+    if not args.no_cpu_baseline:
+        # the FP64 oracle per class on a bounded sample of that class's environments (the
+        # last rollout's inputs), which also gives each class's parity after T steps
+        import oracle  # CPU baseline leg only
+
+        threads = oracle.get_threads()
+        per_class, off = [], 0
+        for c, nc, st in zip(w.classes, w.n_envs, w.state):
+            idx = np.linspace(0, nc - 1, min(nc, 2048)).round().astype(np.int64)
+            envs = oracle.make_envs(c, w.params.subset(off + idx), w.dt)
+            x = oracle.pack_state(st.p[:, idx], st.q[:, idx], st.nu[:, idx], st.n[:, idx])
+            a = oracle.pack_actions(synth.actions(nc, c.m, -(-T // HOLD) + 1, env_offset=off)[:, :, idx])
+            tc = time.perf_counter()
+            x, _, _ = oracle.rollout(envs, x, a, HOLD, T)
+            sec = time.perf_counter() - tc
+            err = parity_errors(final[len(per_class)][:, idx], oracle.unpack_state(x, c.m))
+            per_class.append({"m": c.m, "n": nc, "sample": len(idx), "env_steps_per_s": len(idx) * T / sec,
+                              "parity_max_err": float(err.max())})
+            off += nc
+        total = sum(p["sample"] for p in per_class) * T / sum(p["sample"] * T / p["env_steps_per_s"] for p in per_class)
+        out["cpu_baseline"] = {"value": total, "unit": "env-steps/s", "cores": threads, "kind": "oracle",
+                               "per_class": per_class,
+                               "sample": f"up to 2048 evenly spaced environments per class x {T} steps, FP64 C oracle"}
+        out["parity"] = {"step": T, "max_err": max(p["parity_max_err"] for p in per_class), "tolerance": 1e-3,
+                         "pass": all(p["parity_max_err"] <= 1e-3 for p in per_class)}
     b.close()
     print(json.dumps(out), flush=True)
 

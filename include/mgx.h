@@ -99,6 +99,15 @@ mgx_status mgx_vjp_cost(int32_t m, uint32_t batch_flags, double* flops, double* 
  * with MGX_WAVE_TIMESTAMPS records them (the recording changes the kernels); any other
  * build returns MGX_E_STATE. */
 mgx_status mgx_diag_wave_times(uint64_t* out, int64_t n_waves);
+/* Diagnostics: the VALU issue rate. Every thread runs `chains` (1, 2, 4 or 8) independent
+ * float multiply-add chains of 16 * iters links; n_threads (a multiple of 256) threads in
+ * blocks of 256; *seconds = the best of three timed launches (HIP events, null stream;
+ * allocates its own output). */
+mgx_status mgx_diag_valu_probe(int32_t chains, int64_t n_threads, int32_t iters, double* seconds);
+/* Diagnostics: the time per launch of `launches` back-to-back launches of a kernel that
+ * does nothing, n_threads threads in blocks of `block` (the fixed cost every launch pays);
+ * best of three timed batches. */
+mgx_status mgx_diag_launch_floor(int64_t n_threads, int32_t block, int32_t launches, double* seconds);
 
 /* ------------------------------------------------------------------ vehicle classes */
 
@@ -255,7 +264,10 @@ typedef struct {
  * check: MGX_E_INVALID for a non-finite or out-of-range value (ranges above), MGX_E_NOT_SPD
  * when some M_RB + M_A is not positive definite (a diagonal entry <= 0, or a Cholesky
  * pivot <= 0 with a payload); the batch is then unchanged. The record build itself stays
- * asynchronous. Must be called before the first step (MGX_E_STATE otherwise). */
+ * asynchronous. on_device = 2: device pointers taken without the prior check, nothing
+ * waited for (for loops that rebuild known-good parameters); an invalid environment then
+ * gets a NaN record and sets the batch's error word (mgx_batch_check). Must be called
+ * before the first step (MGX_E_STATE otherwise). */
 mgx_status mgx_batch_set_params(mgx_batch* b, const mgx_env_params* p, int32_t on_device);
 
 /* ------------------------------------------------------------------ domain randomisation */

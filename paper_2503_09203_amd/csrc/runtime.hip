@@ -444,6 +444,7 @@ extern "C" mgx_status mgx_batch_layout(const mgx_batch* b, mgx_layout* out) {
 
 extern "C" mgx_status mgx_batch_set_params(mgx_batch* b, const mgx_env_params* p, int32_t on_device) {
     CHECK_BATCH(b);
+    if (on_device < 0 || on_device > 2) return fail(MGX_E_INVALID, "on_device must be 0, 1 or 2");
     if (!p || !p->mass || !p->added || !p->dlin || !p->dquad || !p->buoy || !p->current)
         return fail(MGX_E_INVALID, "NULL parameter array");
     const int64_t N = b->n_total;
@@ -489,6 +490,21 @@ extern "C" mgx_status mgx_batch_set_params(mgx_batch* b, const mgx_env_params* p
         pp.dquad = s + 13 * N;
         pp.buoy = s + 19 * N;
         pp.current = s + 20 * N;
+    }
+    if (on_device == 2) {
+        // unchecked device arrays: the record build alone, asynchronous; invalid values reach
+        // the batch's error word (mgx_batch_check) and NaN records
+        for (int c = 0; c < b->n_classes; ++c) {
+            if (b->prec == MGX_FP32) {
+                HIP_TRY(b, launch_env_setup<float>(pp, b->env_off[c], b->n[c], (int32_t)b->npad[c], b->d_classdesc, c,
+                                                   b->dt, (float*)b->seg_rec(c), &b->d_misc->err, b->stream));
+            } else {
+                HIP_TRY(b, launch_env_setup<double>(pp, b->env_off[c], b->n[c], (int32_t)b->npad[c], b->d_classdesc,
+                                                    c, b->dt, (double*)b->seg_rec(c), &b->d_misc->err, b->stream));
+            }
+        }
+        b->params_set = true;
+        return MGX_OK;
     }
     // Every environment's values and mass matrix are checked on the device before any
     // record is written, so a refused call leaves the batch unchanged. The check word is

@@ -182,6 +182,8 @@ I32, I64, U32, U64, F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctype
 SIGNATURES = {
     "mgx_build_hash": (ctypes.c_char_p, []),
     "mgx_diag_wave_times": (I32, [P, I64]),
+    "mgx_diag_valu_probe": (I32, [I32, I64, I32, ctypes.POINTER(F64)]),
+    "mgx_diag_launch_floor": (I32, [I64, I32, I32, ctypes.POINTER(F64)]),
     "mgx_status_string": (ctypes.c_char_p, [I32]),
     "mgx_last_error": (ctypes.c_size_t, [ctypes.c_char_p, ctypes.c_size_t]),
     "mgx_last_hip_error": (I32, []),
@@ -291,6 +293,18 @@ def _call(name, *args):
 
 def mgx_version():
     return lib().mgx_version()
+
+
+def mgx_diag_valu_probe(chains, n_threads, iters):
+    t = F64()
+    _call("mgx_diag_valu_probe", int(chains), int(n_threads), int(iters), ctypes.byref(t))
+    return t.value
+
+
+def mgx_diag_launch_floor(n_threads, block, launches):
+    t = F64()
+    _call("mgx_diag_launch_floor", int(n_threads), int(block), int(launches), ctypes.byref(t))
+    return t.value
 
 
 def mgx_build_hash() -> str:
@@ -456,10 +470,11 @@ def mgx_batch_get_stats(h) -> Stats:
 
 
 def mgx_batch_check(h):
-    """Returns (status, n_nonfinite) without raising on MGX_E_NONFINITE / MGX_E_INVALID."""
+    """Returns (status, n_nonfinite) without raising on the statuses the check reports
+    (MGX_E_NONFINITE, MGX_E_INVALID, MGX_E_NOT_SPD)."""
     n = I64()
     st = lib().mgx_batch_check(h, ctypes.byref(n))
-    if st not in (MGX_OK, MGX_E_NONFINITE, MGX_E_INVALID):
+    if st not in (MGX_OK, MGX_E_NONFINITE, MGX_E_INVALID, MGX_E_NOT_SPD):
         check(st, "mgx_batch_check")
     return st, n.value
 

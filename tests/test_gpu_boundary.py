@@ -117,6 +117,28 @@ def test_device_parameter_check_refuses_and_leaves_the_batch_unchanged():
     b.close()
 
 
+def test_unchecked_device_parameters_report_through_the_error_word():
+    """on_device = 2 skips the prior check and the wait: the same invalid added mass is
+    accepted by the call, its environment gets a NaN record (non-finite after a step) and
+    mgx_batch_check reports MGX_E_NOT_SPD."""
+    t = torch()
+    w = synth.randomised(n=300, steps=10)
+    b = make_batch(w)
+    bad = w.params.subset(np.arange(300))
+    bad.added = bad.added.copy()
+    bad.added[3, 5] = -(w.classes[0].inertia[0] + 0.5)
+    keep = {k: t.as_tensor(np.ascontiguousarray(getattr(bad, k), dtype=np.float64), device=b.device)
+            for k in ("mass", "added", "dlin", "dquad", "buoy", "current")}
+    mgx.mgx_batch_set_params(b.h, {k: v.data_ptr() for k, v in keep.items()}, 2)
+    b.step(device_actions(b, w.actions(1)), 5, hold=10, flags=mgx.STEP_STATS)
+    st, nf = b.check()
+    assert st == mgx.MGX_E_NOT_SPD
+    state = b.unpack_state(b.get_state().cpu().numpy())[0]
+    finite = np.all(np.isfinite(state), axis=0)
+    assert not finite[5] and finite.sum() == 299
+    b.close()
+
+
 def test_payload_mass_matrix_that_is_not_positive_definite_is_refused():
     """With a payload every diagonal entry of M can be positive while M is not positive
     definite (the centre of gravity couples surge and heave with pitch): the Cholesky check
