@@ -1001,8 +1001,11 @@ def counter_launches(args):
 
 
 def sweep(args):
-    """Per-launch durations (HIP events on the batch stream) over K at the default N, and
-    over N for K = 1 and K = 16. One JSON line per point."""
+    """Per-launch durations over K at the default N, and over N for K = 1 and K = 16: L
+    launches back to back between two HIP events on the batch stream (L x K steps from one
+    resident state, the action buffer sized for them), so the numbers carry the launch floor
+    as a rollout does. One JSON line per point, with the bytes the batch's state, record and
+    one step's actions occupy."""
     import torch
 
     import synth
@@ -1012,39 +1015,40 @@ def sweep(args):
     cls = synth.plain_class()
     flops_es, _ = mgx.mgx_step_cost(cls.m)
 
-    def measure(N, K, reps):
+    def measure(N, K):
+        steps = int(min(4096, max(K, 1e9 * HOLD / (N * cls.m * 4)))) // K * K   # actions <= ~1 GB
+        L = max(1, steps // K)
         p = synth.randomised_params(cls, N)
         st = synth.initial_state(N, cls.m)
         b = mgx.Batch([cls], [N], 0.01)
         b.set_params(p)
         init = torch.tensor(b.pack_state([st.stacked()]), dtype=torch.float32, device="cuda:0")
-        rows = -(-(K * 2) // HOLD) + 1
-        acts = b.gen_actions(rows)
+        acts = b.gen_actions(-(-L * K // HOLD) + 1)
         stream = torch.cuda.current_stream()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-        for i in range(reps + 2):
+        best = None
+        for rep in range(4):
             b.reset(init_state=init)
             b.t = 0
-            if i >= 2:
-                ev[i - 2][0].record(stream)
-            b.step(acts, K, hold=HOLD)
-            if i >= 2:
-                ev[i - 2][1].record(stream)
-        torch.cuda.synchronize()
-        d = np.array([a.elapsed_time(c) for a, c in ev]) * 1e-3
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(L):
+                b.step(acts, K, hold=HOLD)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if rep:
+                t = e0.elapsed_time(e1) * 1e-3 / L
+                best = t if best is None else min(best, t)
         b.close()
-        mean = float(d.mean())
-        return {"n": N, "K": K, "launch_us_mean": mean * 1e6, "launch_us_min": float(d.min()) * 1e6,
-                "env_steps_per_s": N * K / mean, "tflops": flops_es * N * K / mean / 1e12,
-                "gbps": bytes_per_env_step(cls.m, K, HOLD) * N * K / mean / 1e9}
+        resident = N * ((13 + cls.m) * 4 + 30 * 4 + cls.m * 4)
+        return {"n": N, "K": K, "launches": L, "launch_us": best * 1e6, "env_steps_per_s": N * K / best,
+                "tflops": flops_es * N * K / best / 1e12,
+                "gbps": bytes_per_env_step(cls.m, K, HOLD) * N * K / best / 1e9, "resident_mb": resident / 1e6}
 
     for K in (1, 2, 4, 8, 16, 32, 64, 128, 256, 1000):
-        print(json.dumps({"sweep": "K", **measure(args.n, K, 20 if K < 256 else 5)}), flush=True)
+        print(json.dumps({"sweep": "K", **measure(args.n, K)}), flush=True)
     for e in range(12, 23):
-        N = 1 << e
         for K in (1, 16):
-            print(json.dumps({"sweep": "N", **measure(N, K, 20)}), flush=True)
-
+            print(json.dumps({"sweep": "N", **measure(1 << e, K)}), flush=True)
 
 if __name__ == "__main__":
     main()
