@@ -584,8 +584,9 @@ mgx_status mgx_station_resample(mgx_station* s, const mgx_dr_spec* spec, const d
  * requests arriving while others run are launched at once and their work overlaps on the
  * device; chunks of one request are ordered with events. Actions are generated inside the
  * kernel from each session's seed with the generator of mgx_gen_actions (env id local to
- * the session, row floor(t / hold) with t counted from the session's first step). A
- * session's state stays resident between its requests. Results are bitwise the same
+ * the session, row floor(t / hold) with t counted from the session's first step), unless a
+ * request brings its own command rows (mgx_request.actions). A session's state stays
+ * resident between its requests. Results are bitwise the same
  * whatever else runs. */
 
 typedef struct mgx_server mgx_server;
@@ -615,6 +616,14 @@ typedef struct {
     int64_t session;            /* -1: new session; else an id returned by an earlier request */
     uint64_t seed;              /* action stream (and initial state) seed of a new session */
     double arrival;             /* caller's timestamp (s, steady clock of mgx_server_now); 0 = now */
+    /* Optional commands (e.g. a policy's), device float [action_rows][m][n_envs of the
+     * session], clipped to [-1, 1] when used; NULL: generated from the session's seed. Row r
+     * is applied to the request's steps in hold interval floor(t0 / hold) + r, t0 the
+     * session's step count when the request is admitted (0 for a new session). A request
+     * whose rows do not cover its horizon fails at admission (state 4). The buffer must
+     * stay valid until the request is done. */
+    const float* actions;
+    int64_t action_rows;
 } mgx_request;
 
 typedef struct {

@@ -29,8 +29,10 @@ struct ServeTile {
     const float* rec;    // [30][npad]
     int64_t t0;          // session step at the start of this iteration
     uint64_t seed;       // the session's action stream
+    const float* act;    // the request's commands [rows][m][nvalid], or null (generated from seed)
+    int64_t act_row0;    // hold interval of the request's row 0
     int32_t npad, env0, steps, hold;
-    int32_t cls, pad0, pad1, pad2;
+    int32_t cls, nvalid, pad0, pad1;
 };
 
 struct ServeArgs {
@@ -52,6 +54,20 @@ __device__ __forceinline__ void session_actions(uint64_t seed, int64_t e, int64_
 #pragma unroll
         for (int w = 0; w < 4; ++w)
             if (b + w < M) a[b + w] = action_from_word(c[w]);
+    }
+}
+
+// Commands of hold interval `row`: the request's own (clipped to [-1, 1]; padded lanes 0),
+// or the session's generated stream.
+template <int M>
+__device__ __forceinline__ void tile_actions(const ServeTile& T, int64_t e, int64_t row, float a[M]) {
+    if (T.act) {
+        const int64_t n = T.nvalid;
+        const float* src = T.act + (row - T.act_row0) * M * n + e;
+#pragma unroll
+        for (int i = 0; i < M; ++i) a[i] = e < n ? clip1(src[i * n]) : 0.0f;
+    } else {
+        session_actions<M>(T.seed, e, row, a);
     }
 }
 
@@ -94,13 +110,13 @@ __device__ __forceinline__ void serve_env(const ServeTile& T, const ClassT<float
     int64_t row = T.t0 / hold;
     int phase = (int)(T.t0 - row * hold);
     float a[M];
-    session_actions<M>(T.seed, e, row, a);
+    tile_actions<M>(T, e, row, a);
     for (int k = 0; k < T.steps; ++k) {
         step_body<float, M, false, kShaped>(C, E, IA2, Brb, s, a);
         if (++phase == hold) {
             phase = 0;
             ++row;
-            session_actions<M>(T.seed, e, row, a);
+            if (k + 1 < T.steps) tile_actions<M>(T, e, row, a);   // no row past the last step
         }
     }
     {
@@ -294,6 +310,7 @@ struct Req {
     double t_arr = 0, t_admit = 0, t_done = 0;
     bool cancel = false;
     bool needs_init = false;      // new session: record and state still to be written
+    int64_t act_row0 = 0;         // caller commands: hold interval of their row 0
     hipEvent_t last_ev = nullptr;  // event of the iteration holding this request's latest chunk
 };
 
@@ -379,12 +396,16 @@ void mgx_server::admit_locked() {
             continue;
         }
         int64_t sid = q.r.session;
+        auto fail_request = [&]() {
+            q.state = 4;
+            q.t_done = now_s();
+            it = pending.erase(it);
+            done_cv.notify_all();
+        };
         if (sid >= 0) {
             auto s = sessions.find(sid);
             if (s == sessions.end()) {
-                q.state = 4;
-                it = pending.erase(it);
-                done_cv.notify_all();
+                fail_request();
                 continue;
             }
             if (s->second.busy || s->second.readers > 0) {
@@ -392,8 +413,19 @@ void mgx_server::admit_locked() {
                 ++it;
                 continue;
             }
-            s->second.busy = true;
-            s->second.keep = s->second.keep || q.r.keep;
+        }
+        // caller commands must cover every hold interval the request's steps touch, from the
+        // session's current step on
+        const int64_t t_start = sid >= 0 ? sessions[sid].t_sched : 0;
+        const int64_t hold = sid >= 0 ? sessions[sid].hold : q.r.hold;
+        if (q.r.actions && (t_start + q.r.horizon - 1) / hold - t_start / hold + 1 > q.r.action_rows) {
+            fail_request();
+            continue;
+        }
+        if (sid >= 0) {
+            Session& S = sessions[sid];
+            S.busy = true;
+            S.keep = S.keep || q.r.keep;
         } else {
             const size_t bytes = session_bytes(q.r.class_index, q.r.n_envs);
             size_t off = 0;
@@ -417,6 +449,7 @@ void mgx_server::admit_locked() {
             q.needs_init = true;
             sessions[sid] = S;
         }
+        q.act_row0 = t_start / hold;
         q.session = sid;
         q.state = 1;
         q.t_admit = now_s();
@@ -468,12 +501,15 @@ bool mgx_server::launch_locked() {
             T.rec = rec;
             T.t0 = S.t_sched;
             T.seed = S.seed;
+            T.act = q.r.actions;
+            T.act_row0 = q.act_row0;
             T.npad = (int32_t)S.npad;
             T.env0 = t * kWave;
             T.steps = steps;
             T.hold = S.hold;
             T.cls = S.cls;
-            T.pad0 = T.pad1 = T.pad2 = 0;
+            T.nvalid = (int32_t)S.n;
+            T.pad0 = T.pad1 = 0;
         }
         S.t_sched += steps;
         q.steps_sched += steps;
@@ -703,6 +739,7 @@ extern "C" mgx_status mgx_server_submit(mgx_server* s, const mgx_request* r, int
     if (!s || !r || !request_id) return fail(MGX_E_INVALID, "NULL argument");
     if (r->class_index < 0 || r->class_index >= s->d.n_classes) return fail(MGX_E_INVALID, "class_index out of range");
     if (r->horizon < 1 || r->hold < 1) return fail(MGX_E_INVALID, "horizon and hold must be >= 1");
+    if (r->actions && r->action_rows < 1) return fail(MGX_E_INVALID, "action_rows must be >= 1 with actions");
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return fail(MGX_E_STATE, "server is stopping");
     if (r->session < 0) {

@@ -104,7 +104,8 @@ class ServerDesc(ctypes.Structure):
 class Request(ctypes.Structure):
     _fields_ = [("class_index", ctypes.c_int32), ("hold", ctypes.c_int32), ("n_envs", ctypes.c_int64),
                 ("horizon", ctypes.c_int32), ("keep", ctypes.c_int32), ("session", ctypes.c_int64),
-                ("seed", ctypes.c_uint64), ("arrival", ctypes.c_double)]
+                ("seed", ctypes.c_uint64), ("arrival", ctypes.c_double), ("actions", ctypes.c_void_p),
+                ("action_rows", ctypes.c_int64)]
 
 
 class RequestStatus(ctypes.Structure):
@@ -946,9 +947,13 @@ class Server:
         _call("mgx_server_create", ctypes.byref(d), ctypes.byref(h))
         self.h = h
 
-    def submit(self, class_index, n_envs, horizon, seed, hold=10, keep=False, session=-1, arrival=0.0):
+    def submit(self, class_index, n_envs, horizon, seed, hold=10, keep=False, session=-1, arrival=0.0,
+               actions=None):
+        """``actions``: optional float32 device tensor [rows][m][n_envs] of commands (kept
+        alive by the caller until the request is done)."""
         r = Request(int(class_index), int(hold), int(n_envs), int(horizon), 1 if keep else 0, int(session), int(seed),
-                    float(arrival))
+                    float(arrival), ctypes.c_void_p(actions.data_ptr() if actions is not None else 0),
+                    int(actions.shape[0]) if actions is not None else 0)
         rid = I64()
         _call("mgx_server_submit", self.h, ctypes.byref(r), ctypes.byref(rid))
         return rid.value

@@ -126,6 +126,48 @@ def test_state_read_never_mixes_steps():
     print(f"reads {len(reads)}, refused while running {refused}", flush=True)
 
 
+def test_caller_commands_drive_a_session():
+    """A request may bring its own command rows. The generator's own rows given as caller
+    commands reproduce the seed-driven result bit for bit; a continuing request with other
+    commands (clipped) matches the oracle over both requests; rows that do not cover the
+    horizon fail the request at admission."""
+    import torch as t
+    c, n, seed = 3, 700, 41
+    m = classes()[c].m
+    gen = synth.actions(n, m, 10, seed)                            # [rows, m, n]
+    s = server(chunk_steps=16)
+    r1 = s.submit(class_index=c, n_envs=n, horizon=90, seed=seed, keep=True)
+    own = s.read_state(s.wait(r1).session, c, n)
+    dev = t.tensor(gen, dtype=t.float32, device="cuda:0").contiguous()
+    r2 = s.submit(class_index=c, n_envs=n, horizon=90, seed=seed, keep=True, actions=dev)
+    sid = s.wait(r2).session
+    given = s.read_state(sid, c, n)
+    assert np.array_equal(own, given)
+    # continue the second session at step 90 with other commands: hold intervals 9..14
+    rng = np.random.default_rng(8)
+    other = rng.uniform(-1.3, 1.3, size=(6, m, n)).astype(np.float32)
+    dev2 = t.tensor(other, device="cuda:0").contiguous()
+    r3 = s.submit(class_index=c, n_envs=n, horizon=55, seed=0, keep=True, session=sid, actions=dev2)
+    s.wait(r3)
+    got = s.read_state(sid, c, n)
+    short = t.zeros((2, m, n), dtype=t.float32, device="cuda:0")
+    r4 = s.submit(class_index=c, n_envs=n, horizon=55, seed=0, keep=True, session=sid, actions=short)
+    with pytest.raises(mgx.MgxError):
+        s.wait(r4)
+    assert s.poll(r4).state == mgx.REQ_FAILED
+    assert np.array_equal(s.read_state(sid, c, n), got)             # the failed request moved nothing
+    s.release(sid)
+    s.close()
+    cl = classes()[c]
+    st = synth.initial_state(n, m, seed)
+    x = oracle.pack_state(st.p, st.q, st.nu, st.n)
+    envs = oracle.make_envs(cl, synth.nominal_params(cl, n), 0.01)
+    x, _, _ = oracle.rollout(envs, x, oracle.pack_actions(gen), 10, 90)
+    x, _, _ = oracle.rollout(envs, x, oracle.pack_actions(other.astype(np.float64)), 10, 55, t0=90, row0=9)
+    ref = oracle.unpack_state(x, m)
+    assert component_errors(got.astype(np.float64), ref).max() <= 5e-4
+
+
 def test_admission_waits_for_memory():
     """A budget of three 1024-environment sessions and nine requests: at no admission are
     more than two other sessions resident, and with 2000-step horizons the first three are

@@ -3,10 +3,13 @@ through the C ABI: episode start draws, observations, rewards, termination and t
 flags, same-step auto-reset and episode counters, for one class and for a mixed batch,
 with substeps, for the shaped, fin and payload bodies, and in float32 and float64.
 
-Termination is decided in the batch precision on the device and in double in the oracle.
-An environment whose oracle distance, lean or attitude-error sign comes within `margin` of
-a threshold is compared up to that step only (both decisions are correct there); the
-others are compared step by step over whole rollouts, including every reset."""
+Termination is decided in the batch precision on the device and in double in the oracle,
+so where the oracle's distance or lean lies within `margin` of its threshold both decisions
+are correct. Every environment is compared step by step over whole rollouts, including
+every reset; one leaves the comparison only at a step where the two sides decide
+differently, which must be such a near-threshold step (their episodes then part). The
+attitude error's scalar part is kept non-negative, so near zero the two sides may hold the
+same rotation with opposite vector parts: those are compared up to that sign."""
 import numpy as np
 import pytest
 
@@ -61,33 +64,53 @@ def run_both(w, desc, T, precision=mgx.FP32, seed=7, act_seed=3):
 
 
 def ambiguous(obs, desc, margin):
-    """Environments whose observation lies within `margin` of a decision: distance against
-    d_max, lean against tilt_max (R_zz of the state equals that of the attitude error, the
-    target being a pure yaw), or the error quaternion's scalar part against 0 (its sign)."""
+    """Environments whose observation lies within `margin` of a termination decision:
+    distance against d_max, or lean against tilt_max (R_zz of the state equals that of the
+    attitude error, the target being a pure yaw)."""
     d = np.linalg.norm(obs[:, 0:3], axis=1)
     up = 1.0 - 2.0 * (obs[:, 4] ** 2 + obs[:, 5] ** 2)
-    return ((np.abs(d - desc["d_max"]) < margin) | (np.abs(up - np.cos(desc["tilt_max"])) < margin)
-            | (np.abs(obs[:, 3]) < margin))
+    return (np.abs(d - desc["d_max"]) < margin) | (np.abs(up - np.cos(desc["tilt_max"])) < margin)
+
+
+def align_sign(dev, ref):
+    """The device observations with the attitude error's vector part (columns 4-6) turned to
+    the oracle's sign. Both sides keep the scalar part (column 3) non-negative; where it is
+    near zero they may hold the same rotation as q and -q, which then differ in the sign of
+    the vector part only."""
+    out = dev.copy()
+    s = np.sign(np.sum(dev[:, 4:7] * ref[:, 4:7], axis=1))
+    out[:, 4:7] *= np.where(s == 0, 1.0, s)[:, None]
+    return out
 
 
 def rel_err(dev, ref, ok):
+    """max over the selected environments of |dev - ref| / max(|ref|, rms), per component,
+    the rms taken over the whole batch's reference (as the parity metric does)."""
     if not ok.any():
         return 0.0
-    d, r = dev[ok], ref[ok]
-    rms = np.sqrt(np.mean(r * r, axis=0))
+    rms = np.sqrt(np.mean(ref * ref, axis=0))
+    d, r = align_sign(dev, ref)[ok], ref[ok]
     return float(np.max(np.abs(d - r) / np.maximum(np.abs(r), np.maximum(rms, 1e-30))))
 
 
-def check(res, desc, tol, margin, min_compared=0.5, name=""):
-    stats = {"resets": 0, "terminated": 0}
+def decide(alive, term_dev, term_ref, trunc_dev, trunc_ref, obs_ref, desc, margin, where):
+    """Environments still compared after this step: a differing decision must lie within
+    the margin of its threshold, and takes the environment out of the comparison."""
+    differ = (term_dev != term_ref) | (trunc_dev != trunc_ref)
+    bad = alive & differ & ~ambiguous(obs_ref, desc, margin)
+    assert not bad.any(), f"{where}: decisions differ away from a threshold at {np.flatnonzero(bad)[:8]}"
+    return alive & ~differ
+
+
+def check(res, desc, tol, margin, min_compared=0.99, name=""):
+    stats = {"resets": 0, "terminated": 0, "parted": 0}
     for cres in res:
         steps = cres["steps"]
-        ok = ~ambiguous(steps[0]["obs_ref"], desc, margin)
+        ok = np.ones(steps[0]["obs_ref"].shape[0], bool)
         assert rel_err(steps[0]["obs_dev"], steps[0]["obs_ref"], ok) <= tol, f"{name} reset obs"
         for k, s in enumerate(steps[1:], 1):
-            ok &= ~ambiguous(s["final_ref"], desc, margin) & ~ambiguous(s["obs_ref"], desc, margin)
-            assert np.array_equal(s["term_dev"][ok], s["term_ref"][ok]), f"{name} terminated at step {k}"
-            assert np.array_equal(s["trunc_dev"][ok], s["trunc_ref"][ok]), f"{name} truncated at step {k}"
+            ok = decide(ok, s["term_dev"], s["term_ref"], s["trunc_dev"], s["trunc_ref"], s["final_ref"], desc,
+                        margin, f"{name} step {k}")
             e_obs = rel_err(s["obs_dev"], s["obs_ref"], ok)
             # the pre-reset observation is written for the environments that ended
             ended = ok & (s["term_ref"] | s["trunc_ref"])
@@ -98,7 +121,9 @@ def check(res, desc, tol, margin, min_compared=0.5, name=""):
             stats["terminated"] += int(np.sum(s["term_ref"][ok]))
         assert np.array_equal(cres["ep_dev"][ok], cres["ep_ref"][ok]), name
         assert np.array_equal(cres["et_dev"][ok], cres["et_ref"][ok]), name
-        assert ok.mean() >= min_compared, f"{name}: only {ok.mean():.2f} of the environments compared"
+        stats["parted"] += int((~ok).sum())
+        assert ok.mean() >= min_compared, f"{name}: only {ok.mean():.3f} of the environments compared"
+    print(name, stats, flush=True)
     return stats
 
 
@@ -123,7 +148,7 @@ def test_reset_draws_match_the_oracle(precision, tol, margin):
     assert np.all(np.abs(dev_s - ref) <= (2 if dt is np.float32 else 8) * ulp)
     assert np.array_equal(dev_s[7:13], ref[7:13].astype(dt))   # velocities: no transcendental
     ref_o = S.observe(ref_s, ref_t, 6)
-    assert rel_err(b.unpack_state(obs)[0].T, ref_o, ~ambiguous(ref_o, DESC, margin)) <= tol
+    assert rel_err(b.unpack_state(obs)[0].T, ref_o, np.ones(ref_o.shape[0], bool)) <= tol
     ep, et = st.episodes()
     assert not ep.any() and not et.any()
     st.close()
@@ -161,7 +186,7 @@ def test_ragged_segments(n):
     w = synth.randomised(n=n, steps=10)
     desc = dict(DESC, max_steps=7)
     res = run_both(w, desc, 30)
-    check(res, desc, 2e-4, 2e-3, min_compared=0.0, name=f"n={n}")
+    check(res, desc, 2e-4, 2e-3, name=f"n={n}")
     b = make_batch(w)
     st = mgx.Station(b, **desc)
     st.reset(7)
@@ -245,17 +270,17 @@ def test_full_size_sampled():
     obs_all = out["obs"].cpu().numpy().astype(np.float64)
     rew = out["reward"].cpu().numpy().astype(np.float64)
     term = out["terminated"].cpu().numpy().astype(bool)
+    trunc = out["truncated"].cpu().numpy().astype(bool)
     ok = np.ones(ids.size, bool)
     n_reset = 0
     for k in range(T):
         ro, rr, rt, rtr, rf = o.step(host_acts[k][:, ids].T)
-        ok &= ~ambiguous(rf, desc, 2e-3) & ~ambiguous(ro, desc, 2e-3)
+        ok = decide(ok, term[k, ids], rt, trunc[k, ids], rtr, rf, desc, 2e-3, f"step {k}")
         dev_o = b.unpack_state(obs_all[k])[0][:, ids].T
-        assert np.array_equal(term[k, ids][ok], rt[ok]), k
         assert rel_err(dev_o, ro, ok) <= 2e-4, k
         assert np.max(np.abs(rew[k, ids][ok] - rr[ok]), initial=0) <= 2e-4, k
         n_reset += int(np.sum((rt | rtr)[ok]))
-    assert ok.mean() > 0.5 and n_reset > 5 * 0.5 * ids.size
+    assert ok.mean() >= 0.99 and n_reset > 5 * 0.99 * ids.size
     st.close()
     b.close()
 
