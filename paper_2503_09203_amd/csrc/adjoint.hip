@@ -59,6 +59,50 @@ struct RowCursor {
     }
 };
 
+// Tape of one step: field f of environment e at row + f * field + e (fields: fd[0..M-1] at
+// 0.., R at kMaxThr, vc, F, c, sh, dc, dsh, nq, g).
+template <typename T, int M>
+__device__ __forceinline__ void store_tape(T* row, int64_t field, int64_t e, const VjpTape<T>& tp) {
+    T* o = row + e;
+#pragma unroll
+    for (int i = 0; i < M; ++i) o[i * field] = tp.fd[i];
+    o += kMaxThr * field;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) o[j * field] = tp.R[j];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) o[(9 + j) * field] = tp.vc[j];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) o[(12 + j) * field] = tp.F[j];
+    o[18 * field] = tp.c;
+    o[19 * field] = tp.sh;
+    o[20 * field] = tp.dc;
+    o[21 * field] = tp.dsh;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[(22 + j) * field] = tp.nq[j];
+    o[26 * field] = tp.g;
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void load_tape(const T* row, int64_t field, int64_t e, VjpTape<T>& tp) {
+    const T* o = row + e;
+#pragma unroll
+    for (int i = 0; i < M; ++i) tp.fd[i] = o[i * field];
+    o += kMaxThr * field;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) tp.R[j] = o[j * field];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) tp.vc[j] = o[(9 + j) * field];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) tp.F[j] = o[(12 + j) * field];
+    tp.c = o[18 * field];
+    tp.sh = o[19 * field];
+    tp.dc = o[20 * field];
+    tp.dsh = o[21 * field];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) tp.nq[j] = o[(22 + j) * field];
+    tp.g = o[26 * field];
+}
+
 template <typename T, int M>
 __device__ __forceinline__ void load_action(const AdjArgs& A, int64_t row, int64_t e, T raw[M]) {
     const T* src = (const T*)A.actions + row * A.row_stride + e;
@@ -129,10 +173,14 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
     }
     const T* ck = (const T*)A.ckpt_buf;
     T* sg = (T*)A.seg_buf;
+    T* tb = (T*)A.tape_buf;
     const int nseg = (A.H + A.ckpt - 1) / A.ckpt;
     auto seg_row = [&](int seg, int k) { return sg + ((int64_t)(seg & 1) * A.ckpt + (k - seg * A.ckpt)) * A.ckpt_stride; };
+    auto tape_row = [&](int seg, int k) { return tb + ((int64_t)(seg & 1) * A.ckpt + (k - seg * A.ckpt)) * A.tape_stride; };
+    const int64_t tf = A.tape_field;
 
-    // recompute one segment's states into its half of the buffer (actions one step ahead)
+    // recompute one segment's states into its half of the buffer, with the forward
+    // quantities each step's reverse pass needs (actions one step ahead)
     auto recompute = [&](int seg) {
         const int k0 = seg * A.ckpt;
         const int k1 = (k0 + A.ckpt < A.H) ? k0 + A.ckpt : A.H;
@@ -147,7 +195,9 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
             load_action<T, M>(A, k + 1 < k1 ? rc.next_row() : rc.row, e, nxt);
             rc.advance();
             store_state<T, M>(seg_row(seg, k), np, e, s);
-            step_body<T, M, false, kShaped>(C, E, IA2, Brb, s, a);
+            VjpTape<T> tp;
+            step_body<T, M, false, kShaped, false, false, false, true>(C, E, IA2, Brb, s, a, nullptr, nullptr, &tp);
+            store_tape<T, M>(tape_row(seg, k), tf, e, tp);
         }
     };
 
@@ -187,9 +237,11 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
         // the stored state, position adjoint and action of step k - 1 are fetched while
         // step k runs (at k0 the fetch repeats step k0)
         StateT<T, M> s, sn;
+        VjpTape<T> tp, tpn;
         T dpn[3], rawn[M];
         auto fetch = [&](int k, int64_t row) {
             load_state<T, M>(seg_row(seg, k), np, e, sn);
+            load_tape<T, M>(tape_row(seg, k), tf, e, tpn);
 #pragma unroll
             for (int j = 0; j < 3; ++j) dpn[j] = dpos[(int64_t)k * A.pos_stride + j * np + e];
             load_action<T, M>(A, row, e, rawn);
@@ -198,6 +250,7 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
         fetch(k1 - 1, rb.row);
         for (int k = k1 - 1; k >= k0; --k) {
             s = sn;
+            tp = tpn;
             T raw[M], ac[M], ab[M];
 #pragma unroll
             for (int i = 0; i < M; ++i) raw[i] = rawn[i];
@@ -211,7 +264,7 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
             rb.retreat();
 #pragma unroll
             for (int i = 0; i < M; ++i) ac[i] = clip1(raw[i]);
-            step_vjp<T, M, kShaped>(C, E, IA2, Brb, s, ac, xb, ab, gdL, gdQ, gA, gDt);
+            vjp_reverse<T, M, kShaped>(C, E, IA2, Brb, s, tp, xb, ab, gdL, gdQ, gA, gDt);
             if (r != row_cur) {
                 if (row_cur >= 0 && dact) {
 #pragma unroll
@@ -314,6 +367,9 @@ static AdjArgs adj_args(mgx_batch* b, int c) {
     A.ckpt_buf = (char*)b->ro_ckpt_mem + P * b->state_off[c];
     A.ckpt_stride = b->state_elems;
     A.seg_buf = (char*)b->ro_seg_mem + P * b->state_off[c];
+    A.tape_buf = (char*)b->ro_tape_mem + P * b->pad_off[c];
+    A.tape_stride = (int64_t)kTapeLen * b->npad_total;
+    A.tape_field = b->npad_total;
     A.pos_stride = 3 * b->npad_total;
     A.misc = b->d_misc;
     return A;
@@ -369,19 +425,22 @@ static mgx_status rollout_forward(mgx_batch* b, const void* actions, int64_t n_r
     const int64_t nck = (H + ckpt_every - 1) / ckpt_every;
     const size_t P = (size_t)b->prec;
     const size_t ck_bytes = P * (size_t)nck * b->state_elems, seg_bytes = P * (size_t)2 * ckpt_every * b->state_elems;
+    const size_t tape_bytes = P * (size_t)2 * ckpt_every * kTapeLen * b->npad_total;
     void* ck_mem = nullptr;
     void* seg_mem = nullptr;
+    void* tape_mem = nullptr;
     uint64_t gen = 0;
     if (use_static) {
-        const size_t ck_aligned = (ck_bytes + 255) / 256 * 256;
-        if (ck_aligned + seg_bytes > kScratchBytes)
+        const size_t ck_aligned = (ck_bytes + 255) / 256 * 256, seg_aligned = (seg_bytes + 255) / 256 * 256;
+        if (ck_aligned + seg_aligned + tape_bytes > kScratchBytes)
             return fail(MGX_E_INVALID, "the rollout needs %zu bytes of checkpoints and segment scratch; the static "
-                        "scratch holds %zu", ck_aligned + seg_bytes, kScratchBytes);
+                        "scratch holds %zu", ck_aligned + seg_aligned + tape_bytes, kScratchBytes);
         void* base = nullptr;
         mgx_status st = scratch_address(b->device, &base);
         if (st != MGX_OK) return st;
         ck_mem = base;
         seg_mem = (char*)base + ck_aligned;
+        tape_mem = (char*)base + ck_aligned + seg_aligned;
         std::lock_guard<std::mutex> lk(g_scratch_mu);
         gen = ++g_scratch_gen[b->device];
     } else {
@@ -403,11 +462,22 @@ static mgx_status rollout_forward(mgx_batch* b, const void* actions, int64_t n_r
             if (e != hipSuccess) return hip_fail(nullptr, e, "hipMalloc(segment scratch)");
             b->seg_bytes = seg_bytes;
         }
+        if (tape_bytes > b->tape_bytes) {
+            b->dev_free(b->d_tape);
+            b->d_tape = nullptr;
+            b->tape_bytes = 0;
+            hipError_t e;
+            b->d_tape = b->dev_alloc(tape_bytes, &e);
+            if (e != hipSuccess) return hip_fail(nullptr, e, "hipMalloc(segment tape)");
+            b->tape_bytes = tape_bytes;
+        }
         ck_mem = b->d_ckpt;
         seg_mem = b->d_seg;
+        tape_mem = b->d_tape;
     }
     b->ro_ckpt_mem = ck_mem;
     b->ro_seg_mem = seg_mem;
+    b->ro_tape_mem = tape_mem;
     b->ro_static_gen = gen;
     b->ro_actions = actions;
     b->ro_n_rows = n_rows;

@@ -20,39 +20,6 @@ __host__ __device__ __forceinline__ void qmul(const T a[4], const T b[4], T o[4]
     o[3] = a[0] * b[3] + a[3] * b[0] + a[1] * b[2] - a[2] * b[1];
 }
 
-// d/d(phi^2) of the attitude increment (cos(phi), h sin(phi)/phi), phi^2 = h^2 |w|^2,
-// matching the branches of quat_increment.
-template <typename T>
-__host__ __device__ __forceinline__ void quat_increment_d(T h, T phi2, T& dc, T& ds) {
-    if constexpr (std::is_same<T, double>::value) {
-        if (phi2 < 1e-8) {
-            dc = -0.5 + phi2 / 12.0;
-            ds = h * (-1.0 / 6.0 + phi2 / 60.0);
-        } else {
-            const T phi = sqrt_(phi2);
-            const T sn = sin(phi), cs = cos(phi);
-            dc = -sn / (2.0 * phi);
-            ds = h * (phi * cs - sn) / (2.0 * phi * phi2);
-        }
-    } else {
-        if (phi2 <= T(0.0025f)) {
-            dc = fma_(phi2, T(1.0f / 12.0f), T(-0.5f));
-            ds = h * fma_(phi2, T(1.0f / 60.0f), T(-1.0f / 6.0f));
-        } else {
-            const T phi = sqrt_(phi2);
-            T sn, cs;
-            if constexpr (std::is_same<T, float>::value) {
-                sincosf(phi, &sn, &cs);
-            } else {
-                sn = sin(phi);
-                cs = cos(phi);
-            }
-            dc = -sn / (T(2) * phi);
-            ds = h * (phi * cs - sn) / (T(2) * phi * phi2);
-        }
-    }
-}
-
 template <typename T>
 __host__ __device__ __forceinline__ void cross_bar(const T x[3], const T y[3], const T zb[3], T xb[3], T yb[3]) {
     // z = x cross y:  xb += y cross zb,  yb += zb cross x
@@ -67,28 +34,26 @@ __host__ __device__ __forceinline__ void cross_bar(const T x[3], const T y[3], c
     yb[2] += t[2];
 }
 
+// Forward part of the vector-Jacobian product: the step's quantities from the state before
+// it and the clipped commands.
 template <typename T, int M, bool kShaped = false>
-__host__ __device__ __forceinline__ void step_vjp(const ClassT<T>& C, const EnvT<T>& E, const T IA2[3], const T Brb[3],
-                                                  const StateT<T, M>& s, const T a[M], StateT<T, M>& xb, T abar[M],
-                                                  T gdL[6], T gdQ[6], T gA[6], T gDt[6]) {
-    // The adjoint's own products and sums may fuse into multiply-adds (this function only;
-    // the forward step it differentiates keeps its explicit rounding).
+__host__ __device__ __forceinline__ void vjp_forward(const ClassT<T>& C, const EnvT<T>& E, const T IA2[3],
+                                                     const T Brb[3], const StateT<T, M>& s, const T a[M],
+                                                     VjpTape<T>& tp) {
 #pragma clang fp contract(fast)
-    // ------------------------------------------------------------------ forward recompute
-    T nl[M], fd[M];  // lagged rotor state; d(thrust / k)/d(nl)
     T tau[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-        nl[i] = fma_(C.alpha[i], a[i] - s.n[i], s.n[i]);
+        const T nl = fma_(C.alpha[i], a[i] - s.n[i], s.n[i]);
         T f;
         if constexpr (kShaped) {
-            const T mag = max_(abs_(nl[i]) - C.dz[i], T(0));
-            const T g = select_(nl[i] < T(0), C.rev[i], T(1));
-            f = copysign_(g * (mag * mag), nl[i]);
-            fd[i] = T(2) * g * mag;
+            const T mag = max_(abs_(nl) - C.dz[i], T(0));
+            const T g = select_(nl < T(0), C.rev[i], T(1));
+            f = copysign_(g * (mag * mag), nl);
+            tp.fd[i] = T(2) * g * mag;
         } else {
-            f = nl[i] * abs_(nl[i]);
-            fd[i] = T(2) * abs_(nl[i]);
+            f = nl * abs_(nl);
+            tp.fd[i] = T(2) * abs_(nl);
         }
 #pragma unroll
         for (int j = 0; j < 6; ++j) tau[j] = fma_(C.Bk[j][i], f, tau[j]);
@@ -98,21 +63,22 @@ __host__ __device__ __forceinline__ void step_vjp(const ClassT<T>& C, const EnvT
     const T xx = qx * x2, yy = qy * y2, zz = qz * z2;
     const T xy = qx * y2, xz = qx * z2, yz = qy * z2;
     const T wx = qw * x2, wy = qw * y2, wz = qw * z2;
-    T R[3][3];
-    R[0][0] = T(1) - (yy + zz);
-    R[0][1] = xy - wz;
-    R[0][2] = xz + wy;
-    R[1][0] = xy + wz;
-    R[1][1] = T(1) - (xx + zz);
-    R[1][2] = yz - wx;
-    R[2][0] = xz - wy;
-    R[2][1] = yz + wx;
-    R[2][2] = T(1) - (xx + yy);
-    const T gb[3] = {R[2][0], R[2][1], R[2][2]};
-    T vc[3], vr[3];
+    T* R = tp.R;
+    R[0] = T(1) - (yy + zz);
+    R[1] = xy - wz;
+    R[2] = xz + wy;
+    R[3] = xy + wz;
+    R[4] = T(1) - (xx + zz);
+    R[5] = yz - wx;
+    R[6] = xz - wy;
+    R[7] = yz + wx;
+    R[8] = T(1) - (xx + yy);
+    const T gb[3] = {R[6], R[7], R[8]};
+    T* vc = tp.vc;
+    T vr[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        vc[j] = fma_(R[2][j], E.Vc[2], fma_(R[1][j], E.Vc[1], R[0][j] * E.Vc[0]));
+        vc[j] = fma_(R[6 + j], E.Vc[2], fma_(R[3 + j], E.Vc[1], R[j] * E.Vc[0]));
         vr[j] = s.nu[j] - vc[j];
     }
     const T* v = s.nu;
@@ -131,8 +97,9 @@ __host__ __device__ __forceinline__ void step_vjp(const ClassT<T>& C, const EnvT
 #pragma unroll
     for (int j = 0; j < 3; ++j) cor_ang[j] = cor_ang[j] + t1[j];
     const bool amc = !(C.flags & kFlagNoAmc);
-    T wvc[3] = {T(0), T(0), T(0)}, hA[3] = {T(0), T(0), T(0)};
+    T hA[3] = {T(0), T(0), T(0)};
     if (amc) {
+        T wvc[3];
         cross(w, vc, wvc);
 #pragma unroll
         for (int j = 0; j < 3; ++j) hA[j] = E.A[j] * wvc[j];
@@ -145,39 +112,75 @@ __host__ __device__ __forceinline__ void step_vjp(const ClassT<T>& C, const EnvT
     }
     T rmom[3];
     cross(Brb, gb, rmom);
-    T F[6];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        F[j] = fma_(E.wmb, gb[j], tau[j] - cor_lin[j] - damp[j] - hA[j]);
-        F[3 + j] = tau[3 + j] - cor_ang[j] - damp[3 + j] - rmom[j];
+        tp.F[j] = fma_(E.wmb, gb[j], tau[j] - cor_lin[j] - damp[j] - hA[j]);
+        tp.F[3 + j] = tau[3 + j] - cor_ang[j] - damp[3 + j] - rmom[j];
     }
+    T w1[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) w1[j] = s.nu[3 + j] + E.dtMinv[3 + j] * tp.F[3 + j];
+    const T h = C.half_dt;
+    const T w2 = fma_(w1[2], w1[2], fma_(w1[1], w1[1], w1[0] * w1[0]));
+    quat_increment(h, w1, tp.c, tp.sh);
+    const T phi2 = (h * h) * w2;
+    quat_increment_d(h, phi2, tp.dc, tp.dsh);
+    const T c = tp.c, sh = tp.sh;
+    const T d1 = sh * w1[0], d2 = sh * w1[1], d3 = sh * w1[2];
+    tp.nq[0] = fma_(qw, c, -fma_(qx, d1, fma_(qy, d2, qz * d3)));
+    tp.nq[1] = fma_(qw, d1, fma_(qx, c, fma_(qy, d3, -(qz * d2))));
+    tp.nq[2] = fma_(qw, d2, fma_(qy, c, fma_(qz, d1, -(qx * d3))));
+    tp.nq[3] = fma_(qw, d3, fma_(qz, c, fma_(qx, d2, -(qy * d1))));
+    const T n2 = fma_(tp.nq[3], tp.nq[3], fma_(tp.nq[2], tp.nq[2], fma_(tp.nq[1], tp.nq[1], tp.nq[0] * tp.nq[0])));
+    if constexpr (std::is_same<T, double>::value) {
+        tp.g = 1.0 / sqrt_(n2);
+    } else {
+        tp.g = fma_(T(-0.5f), n2, T(1.5f));
+    }
+}
+
+// Reverse part: given the state before the step, its tape and the adjoint of the state
+// after the step, the adjoint of the state before it and of the commands, accumulating the
+// parameter adjoints. The cheap forward quantities are formed again from the state and the
+// tape.
+template <typename T, int M, bool kShaped = false>
+__host__ __device__ __forceinline__ void vjp_reverse(const ClassT<T>& C, const EnvT<T>& E, const T IA2[3],
+                                                     const T Brb[3], const StateT<T, M>& s, const VjpTape<T>& tp,
+                                                     StateT<T, M>& xb, T abar[M], T gdL[6], T gdQ[6], T gA[6],
+                                                     T gDt[6]) {
+#pragma clang fp contract(fast)
+    const T qw = s.q[0], qx = s.q[1], qy = s.q[2], qz = s.q[3];
+    const T R[3][3] = {{tp.R[0], tp.R[1], tp.R[2]}, {tp.R[3], tp.R[4], tp.R[5]}, {tp.R[6], tp.R[7], tp.R[8]}};
+    const T* vc = tp.vc;
+    const T* F = tp.F;
+    const T* v = s.nu;
+    const T* w = s.nu + 3;
+    T vr[3], A1vr[3], P[3], L[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        vr[j] = v[j] - vc[j];
+        A1vr[j] = E.A[j] * vr[j];
+        P[j] = fma_(E.mass, v[j], A1vr[j]);
+        L[j] = IA2[j] * w[j];
+    }
+    const bool amc = !(C.flags & kFlagNoAmc);
+    T wvc[3] = {T(0), T(0), T(0)};
+    if (amc) cross(w, vc, wvc);
     T nu1[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) nu1[j] = s.nu[j] + E.dtMinv[j] * F[j];
     const T h = C.half_dt;
     const T* w1 = nu1 + 3;
-    const T w2 = fma_(w1[2], w1[2], fma_(w1[1], w1[1], w1[0] * w1[0]));
-    T c, sh;
-    quat_increment(h, w1, c, sh);
-    const T phi2 = (h * h) * w2;
-    T dc, dsh;
-    quat_increment_d(h, phi2, dc, dsh);
+    const T c = tp.c, sh = tp.sh, dc = tp.dc, dsh = tp.dsh;
     const T d[4] = {c, sh * w1[0], sh * w1[1], sh * w1[2]};
-    T nq[4];
-    nq[0] = fma_(qw, c, -fma_(qx, d[1], fma_(qy, d[2], qz * d[3])));
-    nq[1] = fma_(qw, d[1], fma_(qx, c, fma_(qy, d[3], -(qz * d[2]))));
-    nq[2] = fma_(qw, d[2], fma_(qy, c, fma_(qz, d[1], -(qx * d[3]))));
-    nq[3] = fma_(qw, d[3], fma_(qz, c, fma_(qx, d[2], -(qy * d[1]))));
-    const T n2 = fma_(nq[3], nq[3], fma_(nq[2], nq[2], fma_(nq[1], nq[1], nq[0] * nq[0])));
-    T g, dg;  // q+ = g(n2) nq
+    const T* nq = tp.nq;
+    const T g = tp.g;
+    T dg;
     if constexpr (std::is_same<T, double>::value) {
-        g = 1.0 / sqrt_(n2);
         dg = -0.5 * g * g * g;
     } else {
-        g = fma_(T(-0.5f), n2, T(1.5f));
         dg = T(-0.5f);
     }
-
     // ------------------------------------------------------------------ reverse
     // q+ = g nq
     T gbar = T(0);
@@ -307,7 +310,7 @@ __host__ __device__ __forceinline__ void step_vjp(const ClassT<T>& C, const EnvT
         T fb = T(0);
 #pragma unroll
         for (int j = 0; j < 6; ++j) fb = fma_(C.Bk[j][i], taub[j], fb);
-        const T nlb = fb * fd[i] + xb.n[i];
+        const T nlb = fb * tp.fd[i] + xb.n[i];
         abar[i] = C.alpha[i] * nlb;
         xb.n[i] = (T(1) - C.alpha[i]) * nlb;
     }
@@ -319,6 +322,18 @@ __host__ __device__ __forceinline__ void step_vjp(const ClassT<T>& C, const EnvT
         xb.nu[j] = nu1b[j] + vb[j];
         xb.nu[3 + j] = nu1b[3 + j] + wb[j];
     }
+}
+
+
+// The vector-Jacobian product of one step (written out by hand in reverse order of the
+// forward pass): its forward part, then its reverse part.
+template <typename T, int M, bool kShaped = false>
+__host__ __device__ __forceinline__ void step_vjp(const ClassT<T>& C, const EnvT<T>& E, const T IA2[3], const T Brb[3],
+                                                  const StateT<T, M>& s, const T a[M], StateT<T, M>& xb, T abar[M],
+                                                  T gdL[6], T gdQ[6], T gA[6], T gDt[6]) {
+    VjpTape<T> tp;
+    vjp_forward<T, M, kShaped>(C, E, IA2, Brb, s, a, tp);
+    vjp_reverse<T, M, kShaped>(C, E, IA2, Brb, s, tp, xb, abar, gdL, gdQ, gA, gDt);
 }
 
 }  // namespace mgx

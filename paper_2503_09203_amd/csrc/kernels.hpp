@@ -256,6 +256,9 @@ struct AdjArgs {
     void* ckpt_buf;        // class segment within each checkpoint row; row stride ckpt_stride
     int64_t ckpt_stride;   // elements per checkpoint row (state_elems)
     void* seg_buf;         // recompute buffer, same layout, ckpt rows
+    void* tape_buf;        // forward quantities of the recomputed steps (kTapeLen fields), class column
+    int64_t tape_stride;   // elements per step row of the tape (kTapeLen x n_pad_total)
+    int64_t tape_field;    // elements per tape field (n_pad_total)
     void* pos;             // class segment within a position row (3 x npad); row stride pos_stride
     int64_t pos_stride;
     void* dactions;        // class segment within an action row (m x npad), or null

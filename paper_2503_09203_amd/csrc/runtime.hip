@@ -187,7 +187,7 @@ extern "C" mgx_status mgx_class_define(const mgx_class_desc* d, int32_t* class_i
 static void free_batch_mem(mgx_batch* b) {
     void* ptrs[] = {b->own_state ? b->d_state : nullptr, b->own_rec ? b->d_rec : nullptr, b->d_misc, b->d_classdesc,
                     b->d_class_f, b->d_class_d, b->d_partials, b->d_stats, b->d_ids, b->d_param_stage, b->d_tiles,
-                    b->d_segs, b->d_tile_partials, b->d_ckpt, b->d_seg};
+                    b->d_segs, b->d_tile_partials, b->d_ckpt, b->d_seg, b->d_tape};
     for (void* p : ptrs) b->dev_free(p);
 }
 

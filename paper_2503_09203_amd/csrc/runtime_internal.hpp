@@ -93,9 +93,11 @@ struct mgx_batch {
     // differentiable rollout: checkpoints, segment scratch, and the last forward's arguments
     void* d_ckpt = nullptr;
     void* d_seg = nullptr;
-    size_t ckpt_bytes = 0, seg_bytes = 0;
+    void* d_tape = nullptr;
+    size_t ckpt_bytes = 0, seg_bytes = 0, tape_bytes = 0;
     void* ro_ckpt_mem = nullptr;  // checkpoints and segment scratch of the last forward pass:
     void* ro_seg_mem = nullptr;   // the batch's own buffers, or the static scratch array
+    void* ro_tape_mem = nullptr;
     uint64_t ro_static_gen = 0;   // static scratch: the generation the forward pass wrote
     const void* ro_actions = nullptr;
     int64_t ro_n_rows = 0, ro_row0 = 0, ro_t0 = 0;

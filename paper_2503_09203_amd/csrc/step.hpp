@@ -325,6 +325,56 @@ __host__ __device__ __forceinline__ void quat_increment_cm1(T h, const T w[3], T
     }
 }
 
+// d/d(phi^2) of the attitude increment (cos(phi), h sin(phi)/phi), phi^2 = h^2 |w|^2,
+// matching the branches of quat_increment.
+template <typename T>
+__host__ __device__ __forceinline__ void quat_increment_d(T h, T phi2, T& dc, T& ds) {
+    if constexpr (std::is_same<T, double>::value) {
+        if (phi2 < 1e-8) {
+            dc = -0.5 + phi2 / 12.0;
+            ds = h * (-1.0 / 6.0 + phi2 / 60.0);
+        } else {
+            const T phi = sqrt_(phi2);
+            const T sn = sin(phi), cs = cos(phi);
+            dc = -sn / (2.0 * phi);
+            ds = h * (phi * cs - sn) / (2.0 * phi * phi2);
+        }
+    } else {
+        if (phi2 <= T(0.0025f)) {
+            dc = fma_(phi2, T(1.0f / 12.0f), T(-0.5f));
+            ds = h * fma_(phi2, T(1.0f / 60.0f), T(-1.0f / 6.0f));
+        } else {
+            const T phi = sqrt_(phi2);
+            T sn, cs;
+            if constexpr (std::is_same<T, float>::value) {
+                sincosf(phi, &sn, &cs);
+            } else {
+                sn = sin(phi);
+                cs = cos(phi);
+            }
+            dc = -sn / (T(2) * phi);
+            ds = h * (phi * cs - sn) / (T(2) * phi * phi2);
+        }
+    }
+}
+
+// The forward quantities of one step that its reverse pass needs and that cost more to
+// recompute than to keep: thrust derivatives, the rotation, the relative velocity, the
+// force, the attitude increment and its derivatives, the unnormalised attitude and its
+// renormalisation factor. kTapeLen values per environment and step (fd padded to 8).
+constexpr int kTapeLen = kMaxThr + 9 + 3 + 6 + 4 + 4 + 1;
+
+template <typename T>
+struct VjpTape {
+    T fd[kMaxThr];  // d(thrust / k)/d(lagged rotor state)
+    T R[9];         // R(q), row-major
+    T vc[3];        // R^T V_c
+    T F[6];         // right-hand side of M dnu/dt = F
+    T c, sh, dc, dsh;
+    T nq[4];        // q (x) dq before renormalisation
+    T g;            // renormalisation factor
+};
+
 // dnu = (dt M^-1) F with the symmetric dt M^-1 of a payload class: diagonal entries in
 // dtMinv, the others (0,1), (0,2), ..., (4,5) in dtMinvOff.
 template <typename T>
@@ -346,10 +396,12 @@ __host__ __device__ __forceinline__ void payload_solve(const EnvT<T>& E, const T
 // (optional, 12 values) receives the actuator wrench and the hydrodynamic wrench of
 // Eq. (3) with d(nu)/dt the solved acceleration.
 template <typename T, int M, bool kForces = false, bool kShaped = false, bool kFins = false, bool kPayload = false,
-          bool kComp = false>
+          bool kComp = false, bool kTape = false>
 __host__ __device__ __forceinline__ void step_body(const ClassT<T>& C, const EnvT<T>& E, const T IA2[3],
                                                    const T Brb[3], StateT<T, M>& s, const T a[M],
-                                                   T* forces = nullptr, StateLo<T>* lo = nullptr) {
+                                                   T* forces = nullptr, StateLo<T>* lo = nullptr,
+                                                   VjpTape<T>* tape = nullptr) {
+    static_assert(!(kTape && (kFins || kPayload || kComp)), "the tape covers the diagonal propeller body");
     // 1. rotor lag (first-order hold; alpha = 1 is the zero-order rotor)
     T nl[M];
 #pragma unroll
@@ -368,8 +420,10 @@ __host__ __device__ __forceinline__ void step_body(const ClassT<T>& C, const Env
             T mag = max_(abs_(nl[i]) - C.dz[i], T(0));
             const T g = select_(nl[i] < T(0), C.rev[i], T(1));
             f = copysign_(g * (mag * mag), nl[i]);
+            if constexpr (kTape) tape->fd[i] = T(2) * g * mag;
         } else {
             f = nl[i] * abs_(nl[i]);
+            if constexpr (kTape) tape->fd[i] = T(2) * abs_(nl[i]);
         }
 #pragma unroll
         for (int j = 0; j < 6; ++j) tau[j] = fma_(C.Bk[j][i], f, tau[j]);
@@ -397,6 +451,14 @@ __host__ __device__ __forceinline__ void step_body(const ClassT<T>& C, const Env
     for (int j = 0; j < 3; ++j) {
         vc[j] = fma_(R[2][j], E.Vc[2], fma_(R[1][j], E.Vc[1], R[0][j] * E.Vc[0]));
         vr[j] = s.nu[j] - vc[j];
+    }
+    if constexpr (kTape) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            tape->vc[i] = vc[i];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) tape->R[3 * i + j] = R[i][j];
+        }
     }
     const T* v = s.nu;
     const T* w = s.nu + 3;
@@ -493,6 +555,14 @@ __host__ __device__ __forceinline__ void step_body(const ClassT<T>& C, const Env
         }
     }
 
+    if constexpr (kTape) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            tape->F[j] = Fl[j];
+            tape->F[3 + j] = Fa[j];
+        }
+    }
+
     // 5. acceleration solve and velocity update: diagonal M, or the full symmetric
     // dt M^-1 of a class with a payload
     if constexpr (kPayload) {
@@ -553,6 +623,19 @@ __host__ __device__ __forceinline__ void step_body(const ClassT<T>& C, const Env
         g = 1.0 / sqrt_(n2);
     } else {
         g = fma_(T(-0.5f), n2, T(1.5f));  // one Newton step toward 1/|q|
+    }
+    if constexpr (kTape) {
+        const T* w1 = s.nu + 3;
+        const T h = C.half_dt;
+        const T phi2 = (h * h) * fma_(w1[2], w1[2], fma_(w1[1], w1[1], w1[0] * w1[0]));
+        quat_increment_d(h, phi2, tape->dc, tape->dsh);
+        tape->c = c;
+        tape->sh = sh;
+        tape->nq[0] = nq0;
+        tape->nq[1] = nq1;
+        tape->nq[2] = nq2;
+        tape->nq[3] = nq3;
+        tape->g = g;
     }
     s.q[0] = nq0 * g;
     s.q[1] = nq1 * g;
