@@ -232,7 +232,11 @@ def main():
     fused_launch = float(graph_s.mean()) / n_launch
     fused_flops_per_launch = flops_es * N * T / n_launch
 
-    # The same rollout as T single-step launches (graph-captured), timed the same way.
+    # The same rollout as T single-step launches (graph-captured), timed the same way. The
+    # capture is taken at step 0, the step every replay starts from, so each launch's
+    # expected action row is the right one (replays from other steps fetch it after the
+    # device counter instead).
+    b.t = 0
     g1 = b.capture(acts, T, 1, hold=HOLD, flags=mgx.STEP_UNFUSED)
     reps1 = max(3, args.steps // 10)
     ev1 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps1 + 1)]

@@ -131,7 +131,8 @@ extern "C" mgx_status mgx_autotune(mgx_batch* b, const void* actions, int64_t n_
             HIP_TRY_T(launch_set_counter(b->d_misc, b->slot, t_start, b->stream));
             HIP_TRY_T(hipEventRecord(e0, b->stream));
             for (int32_t done = 0; done < chunk; done += c.K) {
-                st = enqueue_step(b, actions, n_rows, row0, hold, c.K, false, nullptr, nullptr, c.block);
+                st = enqueue_step(b, actions, n_rows, row0, hold, c.K, false, nullptr, nullptr, c.block,
+                                  t_start + done);
                 if (st != MGX_OK) goto done;
             }
             HIP_TRY_T(hipEventRecord(e1, b->stream));

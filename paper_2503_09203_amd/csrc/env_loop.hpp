@@ -269,6 +269,17 @@ __device__ __forceinline__ double in_vgpr(double x) {
     asm("" : "+v"(x));
     return x;
 }
+__device__ __forceinline__ int32_t in_vgpr(int32_t x) {
+    asm("" : "+v"(x));
+    return x;
+}
+
+// 64-bit wave-uniform value of lane 0 (the value is the same in every lane)
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 
 // A copy of the class constants for the step loop. With more than six thrusters, or with
 // fins, the per-actuator arrays (k-scaled layout columns, lag factors, fin geometry and
@@ -397,56 +408,92 @@ __device__ __forceinline__ void renorm_attitude(StateT<T, M>& s, float st[kStats
 // becomes current; all prologue loads are drained once before the loop so that the only
 // memory operations in flight inside it are those prefetches.
 // kSingle: a launch of exactly one step without outputs (the single-step kernel). Such a
-// launch never reaches the next action row, so it does not fetch it.
+// launch never reaches the next action row, so it does not fetch it. Every lane of its grid
+// calls this (env may be past the segment: such a lane works on the last slot and stores
+// nothing). It reads the step counter itself and returns it in *t_single (t0 is not used):
+// the state and record are loaded first, then the action row the host expected
+// (A.row_hint, for step A.t_hint), and the counter last, per lane, so that waiting for the
+// earlier loads does not wait for it (vector loads complete in order; a scalar load would
+// be waited for with every other scalar load). The step runs on the expected row, and the
+// counter is compared only afterwards; a launch that runs at another step (a graph
+// replayed from another step) runs the step again from the loaded state on the row the
+// counter names. Reading the counter first and the row after it cost a dependent memory
+// round trip of about half a microsecond per launch.
 template <typename T, int M, bool kOut, bool kShaped, bool kSingle = false, bool kFins = false, bool kPayload = false>
 __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs, int64_t env, int64_t t0, int K,
-                                          float st[kStats]) {
+                                          float st[kStats], int64_t* t_single = nullptr) {
     static_assert(!(kSingle && kOut), "the single-step form has no per-step outputs");
     MGX_WAVE_TS(ts_entry);
     const int64_t np = A.npad;
+    const int64_t envl = (kSingle && env >= np) ? np - 1 : env;  // the slot this lane reads
+    T* S = (T*)A.state;
+    const T* Rc = (const T*)A.rec;
+    StateT<T, M> s;
+    load_state<T, M>(S, np, envl, s);
+    EnvT<T> E;
+    load_record<T, kPayload>(Rc, np, envl, Cs.flags, E);
     const ClassT<T> C = class_in_vgpr<T, M, kFins>(Cs);
     // classes with fins carry the attitude's low-order words through the launch (float)
     constexpr bool kComp = kFins && std::is_same<T, float>::value;
     StateLo<T> lo;
 #pragma unroll
     for (int j = 0; j < 4; ++j) lo.q[j] = T(0);
-    T* S = (T*)A.state;
-    const T* Rc = (const T*)A.rec;
-    StateT<T, M> s;
-    load_state<T, M>(S, np, env, s);
-    EnvT<T> E;
-    load_record<T, kPayload>(Rc, np, env, C.flags, E);
 
     // Action rows, relative to the buffer start, uniform across the wave. Every fetch is
     // issued unconditionally at a row index clamped into the buffer (validity is tracked
     // separately), so each prefetch has a single definition and no copy forces an early wait.
     const int64_t hold = A.hold, nrows = A.n_rows, rstride = A.row_stride;
-    const int64_t rowa = floor_div(t0, hold);
-    int phase = (int)(t0 - rowa * hold);
-    int64_t r = rowa - A.row0;
-    const T* abase = (const T*)A.actions + env;
+    const T* abase = (const T*)A.actions + envl;
     auto clamp_row = [nrows](int64_t x) { return x < 0 ? (int64_t)0 : (x >= nrows ? nrows - 1 : x); };
-    bool bad = (r < 0 || r >= nrows);
     T cur[M], nxt[M];
-    {
+    bool bad;
+    int phase = 0;
+    int64_t r = 0;
+    int64_t t_lane = 0;
+    if constexpr (kSingle) {
+        const T* ph = abase + A.row_hint * rstride;   // inside the buffer (host-checked)
+#pragma unroll
+        for (int i = 0; i < M; ++i) cur[i] = ph[i * np];
+        bad = false;
+        t_lane = A.misc->t[A.rd + in_vgpr(0)];         // a vector load, issued last
+    } else {
+        const int64_t rowa = floor_div(t0, hold);
+        phase = (int)(t0 - rowa * hold);
+        r = rowa - A.row0;
+        bad = (r < 0 || r >= nrows);
         const T* p0 = abase + clamp_row(r) * rstride;
 #pragma unroll
         for (int i = 0; i < M; ++i) cur[i] = p0[i * np];
-        if constexpr (!kSingle) {
-            const T* p1 = abase + clamp_row(r + 1) * rstride;
+        const T* p1 = abase + clamp_row(r + 1) * rstride;
 #pragma unroll
-            for (int i = 0; i < M; ++i) nxt[i] = p1[i * np];
-            if (hold - phase < K && r + 1 >= nrows) bad = true;
-        }
+        for (int i = 0; i < M; ++i) nxt[i] = p1[i * np];
+        if (hold - phase < K && r + 1 >= nrows) bad = true;
     }
-    __builtin_amdgcn_s_waitcnt(0);
+    if constexpr (!kSingle) __builtin_amdgcn_s_waitcnt(0);
     MGX_WAVE_TS(ts_loaded);
 #pragma unroll
     for (int i = 0; i < M; ++i) cur[i] = clip1(cur[i]);
     T IA2[3], Brb[3];
     env_prologue<T, kPayload>(C, E, IA2, Brb);
     if constexpr (kSingle) {
+        const StateT<T, M> s_in = s;
         step_body<T, M, false, kShaped, kFins, kPayload, kComp>(C, E, IA2, Brb, s, cur, nullptr, &lo);
+        const int64_t tc = uniform64(t_lane);
+        if (tc != A.t_hint) {
+            // not the step the host expected: the row the counter names, through volatile
+            // loads (the compiler would otherwise merge them with the expected row's fetch
+            // into one fetch placed after the counter's)
+            r = floor_div(tc, hold) - A.row0;
+            bad = (r < 0 || r >= nrows);
+            const volatile T* p0 = abase + clamp_row(r) * rstride;
+#pragma unroll
+            for (int i = 0; i < M; ++i) cur[i] = clip1((T)p0[i * np]);
+            s = s_in;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) lo.q[j] = T(0);
+            step_body<T, M, false, kShaped, kFins, kPayload, kComp>(C, E, IA2, Brb, s, cur, nullptr, &lo);
+        }
+        *t_single = tc;
     } else {
 
     // Runs of steps between action-row switches: the inner loop carries only its counter,
@@ -510,7 +557,7 @@ __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs
         st[kStMaxDrift] = (float)drift;
     }
 
-    store_state<T, M>(S, np, env, s);
+    if (!kSingle || env < np) store_state<T, M>(S, np, env, s);
 #ifdef MGX_WAVE_TIMESTAMPS
     __builtin_amdgcn_s_waitcnt(0);
     MGX_WAVE_TS(ts_stored);

@@ -66,8 +66,9 @@ extern "C" mgx_status mgx_graph_capture(mgx_batch* b, const void* actions, int64
         int32_t launches = 0;
         for (int32_t done = 0; done < n_steps && st == MGX_OK;) {
             const int32_t k = (n_steps - done) < per ? (n_steps - done) : per;
+            // the hints name the steps as of capture: replays from the same step confirm them
             st = enqueue_step(b, actions, n_rows, row0, hold, k, stats && done + k == n_steps, nullptr, nullptr,
-                              b->block);
+                              b->block, b->host_t + done);
             done += k;
             ++launches;
         }

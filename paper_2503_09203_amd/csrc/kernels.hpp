@@ -220,17 +220,25 @@ struct PersistArgs {
 };
 
 // Arguments of the step kernel for one class segment.
+// The first 64 bytes hold what the single-step form needs before its loads (one scalar
+// cache line, fetched in the kernel's first batch of argument loads).
 struct StepArgs {
     void* state;          // class segment base, [13+m][npad]
     const void* rec;      // class segment base, [30][npad]
     const void* actions;  // buffer base + class action offset; row r at actions + r*row_stride
-    int64_t row_stride, n_rows, row0;
-    int32_t hold, K;
-    int32_t npad, nvalid;
+    int64_t row_stride;
+    // The step count the host expects the launch to start at (-1: unknown) and the action
+    // row it names, clamped into the buffer. The single-step form fetches that row beside
+    // the state and confirms it against the device counter, so the row's fetch does not
+    // wait for the counter's.
+    int64_t row_hint, t_hint;
     DevMisc* misc;
+    int32_t npad, nvalid;
+    int32_t rd, wr;       // step-counter slots
+    int32_t hold, K;
+    int64_t n_rows, row0;
     int32_t class_index;
     int32_t advance;      // 0, or K: block 0 writes t[wr] = t[rd] + K
-    int32_t rd, wr;       // step-counter slots
     void* traj;           // class segment base within step row 0, or null
     int64_t traj_stride;  // elements per step row
     void* forces;         // class segment base within step row 0, or null

@@ -112,6 +112,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
         A.advance = 0;
         A.rd = P.rd;
         A.wr = P.wr;
+        A.t_hint = -1;
+        A.row_hint = 0;
         A.traj = nullptr;
         A.traj_stride = 0;
         A.forces = nullptr;

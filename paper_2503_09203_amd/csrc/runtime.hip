@@ -589,7 +589,7 @@ static int64_t floor_div_h(int64_t a, int64_t b) {
 namespace mgx {
 // Enqueues K steps of every class; `advance` of the last class launch moves the counter.
 mgx_status enqueue_step(mgx_batch* b, const void* actions, int64_t n_rows, int64_t row0, int32_t hold, int32_t K,
-                        bool stats, void* traj, void* forces, int block) {
+                        bool stats, void* traj, void* forces, int block, int64_t t_hint) {
     const size_t P = (size_t)b->prec;
     bool fins = false;
     for (int c = 0; c < b->n_classes; ++c) fins = fins || b->h_class_f[c].fin_mask != 0 || b->h_class_f[c].payload != 0;
@@ -643,6 +643,12 @@ mgx_status enqueue_step(mgx_batch* b, const void* actions, int64_t n_rows, int64
         a.advance = (c == b->n_classes - 1) ? K : 0;
         a.rd = b->slot;
         a.wr = 1 - b->slot;
+        // a hint whose row lies outside the buffer is dropped: the launch then finds and
+        // reports the row the device counter names
+        const int64_t rh = t_hint >= 0 ? floor_div_h(t_hint, hold) - row0 : -1;
+        const bool hint = t_hint >= 0 && rh >= 0 && rh < n_rows;
+        a.t_hint = hint ? t_hint : -1;
+        a.row_hint = hint ? rh : 0;
         a.traj = traj ? (char*)traj + P * b->state_off[c] : nullptr;
         a.traj_stride = b->state_elems;
         a.forces = forces ? (char*)forces + P * b->force_off[c] : nullptr;
@@ -691,11 +697,12 @@ extern "C" mgx_status mgx_batch_step(mgx_batch* b, const void* actions, int64_t 
         for (int32_t k = 0; k < K; ++k) {
             mgx_status s = enqueue_step(b, actions, n_rows, row0, hold, 1, stats && k == K - 1,
                                         traj ? (char*)traj + P * k * b->state_elems : nullptr,
-                                        forces ? (char*)forces + P * k * b->force_row_elems : nullptr, b->block);
+                                        forces ? (char*)forces + P * k * b->force_row_elems : nullptr, b->block,
+                                        b->host_t + k);
             if (s != MGX_OK) return s;
         }
     } else {
-        mgx_status s = enqueue_step(b, actions, n_rows, row0, hold, K, stats, traj, forces, b->block);
+        mgx_status s = enqueue_step(b, actions, n_rows, row0, hold, K, stats, traj, forces, b->block, b->host_t);
         if (s != MGX_OK) return s;
     }
     b->host_t += K;

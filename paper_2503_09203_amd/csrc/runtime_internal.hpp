@@ -143,9 +143,11 @@ namespace mgx {
 mgx_status hip_fail(mgx_batch* b, hipError_t e, const char* what);
 bool get_class(int32_t id, mgx_class_desc* out);
 ClassDesc64 to_desc64(const mgx_class_desc& c);
-// Enqueues K steps of every class and flips the counter slot.
+// Enqueues K steps of every class and flips the counter slot. t_hint: the step count the
+// launches are expected to start at when they run (-1 if unknown); any value is correct,
+// a matching one saves the single-step launch a dependent memory round trip.
 mgx_status enqueue_step(mgx_batch* b, const void* actions, int64_t n_rows, int64_t row0, int32_t hold, int32_t K,
-                        bool stats, void* traj, void* forces, int block);
+                        bool stats, void* traj, void* forces, int block, int64_t t_hint);
 mgx_status validate_rows(const mgx_batch* b, int64_t t0, int64_t n_rows, int64_t row0, int32_t hold, int64_t K);
 // Redraws the parameters of the environments whose byte in `mask` is set, with epochs[e] as
 // the draw's epoch (both device arrays of n_pad_total, environment e of class c at

@@ -416,10 +416,13 @@ def test_checkpoint_resume_is_bitwise():
     b2.close()
 
 
-@pytest.mark.parametrize("n_steps,K", [(48, 16), (40, 16), (7, 3)])
+@pytest.mark.parametrize("n_steps,K", [(48, 16), (40, 16), (7, 3), (12, 1)])
 def test_graph_replays_equal_eager_steps(n_steps, K):
     """A captured chunk replayed across a rollout-long action buffer gives the same state,
-    bit for bit, as eager calls; odd and even launch counts exercise both counter slots."""
+    bit for bit, as eager calls; odd and even launch counts exercise both counter slots.
+    With K = 1 the launches are single-step ones: the first replay runs at the steps the
+    capture expected, the later ones at other steps, where each launch finds its expected
+    action row wrong and fetches the one the device counter names."""
     t = torch()
     w = synth.randomised(n=700, steps=4 * n_steps)
     acts = w.actions(-(-4 * n_steps // 10) + 1)
