@@ -756,8 +756,8 @@ def adjoint(args):
     m = w.classes[0].m
     step_flops, _ = mgx.mgx_step_cost(m)
     vjp_flops, vjp_ops = mgx.mgx_vjp_cost(m)
-    # backward: every step recomputed once from its checkpoint, then its vector-Jacobian
-    # product (which recomputes the step's forward quantities from the stored state)
+    # backward: every step recomputed once from its checkpoint (storing its forward
+    # quantities), then the reverse part of its vector-Jacobian product
     bwd_flops = (step_flops + vjp_flops) * N * H
     out = {"metric": METRIC, "workload": f"adjoint_{N}x{H}", "unit": "env-steps/s", "value": N * H / (f + g),
            "n_envs": N, "horizon": H, "checkpoint_every": CK, "thrusters": m,
@@ -1005,11 +1005,11 @@ def counter_launches(args):
 
 
 def sweep(args):
-    """Per-launch durations over K at the default N, and over N for K = 1 and K = 16: L
-    launches back to back between two HIP events on the batch stream (L x K steps from one
-    resident state, the action buffer sized for them), so the numbers carry the launch floor
-    as a rollout does. One JSON line per point, with the bytes the batch's state, record and
-    one step's actions occupy."""
+    """Per-launch durations over K at the default N, and over N for K = 1 and K = 16: a
+    graph of L launches replayed between two HIP events on the batch stream (L x K steps
+    from one resident state, the action buffer sized for them), so the numbers carry the
+    launch floor as a rollout does but not the host's launch calls. One JSON line per point,
+    with the bytes the batch's state, record and one step's actions occupy."""
     import torch
 
     import synth
@@ -1029,19 +1029,21 @@ def sweep(args):
         init = torch.tensor(b.pack_state([st.stacked()]), dtype=torch.float32, device="cuda:0")
         acts = b.gen_actions(-(-L * K // HOLD) + 1)
         stream = torch.cuda.current_stream()
+        b.t = 0
+        g = b.capture(acts, L * K, K, hold=HOLD)
         best = None
         for rep in range(4):
             b.reset(init_state=init)
             b.t = 0
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            for _ in range(L):
-                b.step(acts, K, hold=HOLD)
+            g.replay()
             e1.record(stream)
             torch.cuda.synchronize()
             if rep:
                 t = e0.elapsed_time(e1) * 1e-3 / L
                 best = t if best is None else min(best, t)
+        g.close()
         b.close()
         resident = N * ((13 + cls.m) * 4 + 30 * 4 + cls.m * 4)
         return {"n": N, "K": K, "launches": L, "launch_us": best * 1e6, "env_steps_per_s": N * K / best,

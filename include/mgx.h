@@ -89,8 +89,9 @@ mgx_status mgx_device_count(int32_t* count);
 #define MGX_COST_SHAPED 0x80000000u
 mgx_status mgx_step_cost(int32_t m, uint32_t batch_flags, double* flops, double* valu_ops);
 /* The same count for the reverse sweep of a differentiable rollout: one environment-step
- * of the hand-written vector-Jacobian product (mgx_rollout_backward), including the
- * forward quantities it recomputes from the stored state. */
+ * of the hand-written vector-Jacobian product (mgx_rollout_backward) given the step's
+ * forward quantities, which the backward's recomputation of the step stores as it runs
+ * (that recomputation is counted by mgx_step_cost). */
 mgx_status mgx_vjp_cost(int32_t m, uint32_t batch_flags, double* flops, double* valu_ops);
 
 /* Diagnostics: the per-wave phase times of the last step launch, four 100 MHz real-time

@@ -179,11 +179,18 @@ static CostTally measure_vjp(uint32_t flags) {
     Cnt a[M], ab[M], gdL[6], gdQ[6], gA[6], gDt[6];
     for (int i = 0; i < M; ++i) a[i] = 0.5 - 0.1 * i;
     for (int j = 0; j < 6; ++j) gdL[j] = gdQ[j] = gA[j] = gDt[j] = 0.0;
+    // the forward quantities come from the tape the recomputation writes: only the reverse
+    // part is the sweep's own work
+    VjpTape<Cnt> tp;
+    if (flags & MGX_COST_SHAPED)
+        vjp_forward<Cnt, M, true>(C, E, IA2, Brb, s, a, tp);
+    else
+        vjp_forward<Cnt, M, false>(C, E, IA2, Brb, s, a, tp);
     g_tally = CostTally();
     if (flags & MGX_COST_SHAPED)
-        step_vjp<Cnt, M, true>(C, E, IA2, Brb, s, a, xb, ab, gdL, gdQ, gA, gDt);
+        vjp_reverse<Cnt, M, true>(C, E, IA2, Brb, s, tp, xb, ab, gdL, gdQ, gA, gDt);
     else
-        step_vjp<Cnt, M, false>(C, E, IA2, Brb, s, a, xb, ab, gdL, gdQ, gA, gDt);
+        vjp_reverse<Cnt, M, false>(C, E, IA2, Brb, s, tp, xb, ab, gdL, gdQ, gA, gDt);
     return g_tally;
 }
 
