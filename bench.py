@@ -45,7 +45,7 @@ def bytes_per_env_step(m, K, hold, prec=4, rec_len=30):
 # of the step kernel comes from the committed rocprofv3 summary, and only while the kernel
 # sources still hash to the value recorded with those counters (else null).
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_step_dr65536x1000.md")
-KERNEL_SOURCES = ("step.hpp", "env_loop.hpp", "kernels.hip", "kernels.hpp")
+KERNEL_SOURCES = ("step.hpp", "env_loop.hpp", "kernels.hip", "kernels.hpp", "step_kernel.hpp", "step_f32.hip")
 
 
 def kernel_sources_sha256():

@@ -345,6 +345,14 @@ mgx_status mgx_batch_step(mgx_batch* b, const void* actions, int64_t n_rows, int
 mgx_status mgx_batch_get_step(const mgx_batch* b, int64_t* t);
 mgx_status mgx_batch_set_step(mgx_batch* b, int64_t t);
 
+/* Diagnostics: sets the batch's device step counter to t (t >= 0) on its stream without the
+ * host's step count, which mgx_batch_get_step keeps returning. Step launches are enqueued
+ * with the host's count as the step they expect to start at; after this call they find
+ * the counter different, take the action rows the counter names and run their steps again
+ * (the results are those of steps from t). For tests of that check; every other entry
+ * point keeps the two counts equal. */
+mgx_status mgx_diag_set_device_step(mgx_batch* b, int64_t t);
+
 /* The vehicle state of Sec. III-B (position, attitude, body velocity nu) and the rotor
  * states of Sec. III-D. Copies the whole state (state_elems elements) out / in. to_host/from_host = 1: host
  * memory, and the call synchronises the stream; 0: device memory, asynchronous. */

@@ -1,7 +1,12 @@
 // Captured rollout chunks: the step launches of a chunk recorded once into a HIP graph and
 // replayed with one launch call. The step counter lives on the device, so replays need no
-// parameter updates. Because the counter is double-buffered, the chunk is captured twice,
-// once per starting slot, and each replay picks the copy for the batch's current slot.
+// parameter updates. Because the counter is double-buffered, the chunk is captured once per
+// starting slot, and each replay picks the copy for the batch's current slot. Each slot has
+// two copies: one whose launches carry the steps as of capture (a replay from the capture
+// step: each launch fetches its action rows beside its state, without waiting for the
+// counter), and one whose launches carry none (a replay from any other step: the rows
+// follow from the counter). A hint that turned out wrong would cost a launch its steps
+// twice; picking the copy by the replay's step keeps that from happening.
 #include <hip/hip_runtime.h>
 
 #include <new>
@@ -13,8 +18,10 @@ using namespace mgx;
 
 struct mgx_graph {
     mgx_batch* batch = nullptr;
-    hipGraph_t graph[2] = {nullptr, nullptr};
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    // [counter slot][0: launches without step hints, 1: with the capture step's]
+    hipGraph_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    int64_t t_capture = 0;  // host step count when captured
     int64_t n_rows = 0, row0 = 0;
     int32_t hold = 1, n_steps = 0;
     int32_t n_launches = 0;
@@ -22,12 +29,13 @@ struct mgx_graph {
 };
 
 static void release(mgx_graph* g) {
-    for (int p = 0; p < 2; ++p) {
-        if (g->exec[p]) (void)hipGraphExecDestroy(g->exec[p]);
-        if (g->graph[p]) (void)hipGraphDestroy(g->graph[p]);
-        g->exec[p] = nullptr;
-        g->graph[p] = nullptr;
-    }
+    for (int p = 0; p < 2; ++p)
+        for (int h = 0; h < 2; ++h) {
+            if (g->exec[p][h]) (void)hipGraphExecDestroy(g->exec[p][h]);
+            if (g->graph[p][h]) (void)hipGraphDestroy(g->graph[p][h]);
+            g->exec[p][h] = nullptr;
+            g->graph[p][h] = nullptr;
+        }
 }
 
 extern "C" mgx_status mgx_graph_capture(mgx_batch* b, const void* actions, int64_t n_rows, int64_t row0, int32_t hold,
@@ -56,7 +64,8 @@ extern "C" mgx_status mgx_graph_capture(mgx_batch* b, const void* actions, int64
     const bool stats = (flags & MGX_STEP_STATS) != 0;
     mgx_status st = MGX_OK;
     b->stream = cap;
-    for (int p = 0; p < 2 && st == MGX_OK; ++p) {
+    for (int c = 0; c < 4 && st == MGX_OK; ++c) {
+        const int p = c >> 1, h = c & 1;  // counter slot; step hints or none
         b->slot = p;
         e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) {
@@ -66,9 +75,8 @@ extern "C" mgx_status mgx_graph_capture(mgx_batch* b, const void* actions, int64
         int32_t launches = 0;
         for (int32_t done = 0; done < n_steps && st == MGX_OK;) {
             const int32_t k = (n_steps - done) < per ? (n_steps - done) : per;
-            // the hints name the steps as of capture: replays from the same step confirm them
             st = enqueue_step(b, actions, n_rows, row0, hold, k, stats && done + k == n_steps, nullptr, nullptr,
-                              b->block, b->host_t + done);
+                              b->block, h ? b->host_t + done : -1);
             done += k;
             ++launches;
         }
@@ -77,8 +85,8 @@ extern "C" mgx_status mgx_graph_capture(mgx_batch* b, const void* actions, int64
         hipError_t e2 = hipStreamEndCapture(cap, &graph);
         if (st == MGX_OK && e2 != hipSuccess) st = hip_fail(nullptr, e2, "hipStreamEndCapture");
         if (st == MGX_OK) {
-            g->graph[p] = graph;
-            e2 = hipGraphInstantiate(&g->exec[p], graph, nullptr, nullptr, 0);
+            g->graph[p][h] = graph;
+            e2 = hipGraphInstantiate(&g->exec[p][h], graph, nullptr, nullptr, 0);
             if (e2 != hipSuccess) st = hip_fail(nullptr, e2, "hipGraphInstantiate");
         } else if (graph) {
             (void)hipGraphDestroy(graph);
@@ -94,6 +102,7 @@ extern "C" mgx_status mgx_graph_capture(mgx_batch* b, const void* actions, int64
         return st;
     }
     g->batch = b;
+    g->t_capture = b->host_t;
     g->n_rows = n_rows;
     g->row0 = row0;
     g->hold = hold;
@@ -111,7 +120,7 @@ extern "C" mgx_status mgx_graph_replay(mgx_graph* g) {
     mgx_status v = validate_rows(b, b->host_t, g->n_rows, g->row0, g->hold, g->n_steps);
     if (v != MGX_OK) return v;
     hipDevice_guard guard(b->device);
-    hipError_t e = hipGraphLaunch(g->exec[b->slot], b->stream);
+    hipError_t e = hipGraphLaunch(g->exec[b->slot][b->host_t == g->t_capture ? 1 : 0], b->stream);
     if (e != hipSuccess) return hip_fail(b, e, "hipGraphLaunch");
     b->host_t += g->n_steps;
     if (g->n_launches & 1) b->slot = 1 - b->slot;

@@ -643,8 +643,8 @@ mgx_status enqueue_step(mgx_batch* b, const void* actions, int64_t n_rows, int64
         a.advance = (c == b->n_classes - 1) ? K : 0;
         a.rd = b->slot;
         a.wr = 1 - b->slot;
-        // a hint whose row lies outside the buffer is dropped: the launch then finds and
-        // reports the row the device counter names
+        // a hint whose row lies outside the buffer is dropped: the launch then finds (and
+        // reports) the row the device counter names
         const int64_t rh = t_hint >= 0 ? floor_div_h(t_hint, hold) - row0 : -1;
         const bool hint = t_hint >= 0 && rh >= 0 && rh < n_rows;
         a.t_hint = hint ? t_hint : -1;
@@ -713,6 +713,14 @@ extern "C" mgx_status mgx_batch_step(mgx_batch* b, const void* actions, int64_t 
 extern "C" mgx_status mgx_batch_get_step(const mgx_batch* b, int64_t* t) {
     if (!b || !t) return fail(MGX_E_INVALID, "NULL argument");
     *t = b->host_t;
+    return MGX_OK;
+}
+
+extern "C" mgx_status mgx_diag_set_device_step(mgx_batch* b, int64_t t) {
+    CHECK_BATCH(b);
+    if (t < 0) return fail(MGX_E_INVALID, "t must be >= 0");
+    hipDevice_guard g(b->device);
+    HIP_TRY(b, launch_set_counter(b->d_misc, b->slot, t, b->stream));
     return MGX_OK;
 }
 

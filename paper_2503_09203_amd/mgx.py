@@ -205,6 +205,7 @@ SIGNATURES = {
     "mgx_batch_step": (I32, [P, P, I64, I64, I32, I32, U32, P, P]),
     "mgx_batch_get_step": (I32, [P, ctypes.POINTER(I64)]),
     "mgx_batch_set_step": (I32, [P, I64]),
+    "mgx_diag_set_device_step": (I32, [P, I64]),
     "mgx_batch_get_state": (I32, [P, P, I32]),
     "mgx_batch_set_state": (I32, [P, P, I32]),
     "mgx_batch_get_stats": (I32, [P, ctypes.POINTER(Stats)]),
@@ -454,6 +455,10 @@ def mgx_batch_get_step(h):
 
 def mgx_batch_set_step(h, t):
     _call("mgx_batch_set_step", h, int(t))
+
+
+def mgx_diag_set_device_step(h, t):
+    _call("mgx_diag_set_device_step", h, int(t))
 
 
 def mgx_batch_get_state(h, out_ptr, to_host):

@@ -416,6 +416,37 @@ def test_checkpoint_resume_is_bitwise():
     b2.close()
 
 
+@pytest.mark.parametrize("K", [1, 16, 5])
+def test_launch_at_another_step_than_expected_runs_the_counters_rows(K):
+    """Step launches carry the step the host expects them to start at and fetch that step's
+    action rows before the device counter arrives; a launch that finds the counter elsewhere
+    runs its steps again on the rows the counter names. With the device counter moved
+    behind the host's back (a diagnostic call), K steps from step 23 give the same bits as K
+    steps taken at step 23 the ordinary way, and the counter ends at 23 + K."""
+    t = torch()
+    w = synth.randomised(n=700, steps=80)
+    acts = w.actions(9)
+    ref = make_batch(w)
+    a_r = device_actions(ref, acts)
+    ref.t = 23
+    ref.step(a_r, K, hold=10)
+    b = make_batch(w)
+    a_b = device_actions(b, acts)
+    b.t = 0
+    mgx.mgx_diag_set_device_step(b.h, 23)
+    b.step(a_b, K, hold=10)          # enqueued as steps 0..K-1, runs as 23..23+K-1
+    assert t.equal(b.get_state(), ref.get_state())
+    # the device counter moved on from 23: one more step at host step K (device 23 + K)
+    mgx.mgx_batch_set_step(ref.h, 23 + K)
+    ref.step(a_r, 1, hold=10)
+    b.step(a_b, 1, hold=10)
+    assert t.equal(b.get_state(), ref.get_state())
+    st, _ = mgx.mgx_batch_check(b.h)
+    assert st == mgx.MGX_OK
+    ref.close()
+    b.close()
+
+
 @pytest.mark.parametrize("n_steps,K", [(48, 16), (40, 16), (7, 3), (12, 1)])
 def test_graph_replays_equal_eager_steps(n_steps, K):
     """A captured chunk replayed across a rollout-long action buffer gives the same state,
