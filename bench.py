@@ -252,7 +252,9 @@ def main():
         ev1[i][1].record(stream)
     torch.cuda.synchronize()
     single_rate = N * T * reps1 / (time.perf_counter() - t1)
-    single_launch = float(np.mean([a.elapsed_time(c) for a, c in ev1[1:]])) * 1e-3 / T
+    per_replay = np.array([a.elapsed_time(c) for a, c in ev1[1:]]) * 1e-3 / T   # s per launch, per replay
+    single_launch = float(per_replay.mean())
+    single_launch_median = float(np.median(per_replay))
     rec_len = 45 if variant == "payload" else 30
     single_bytes = bytes_per_env_step(cls.m, 1, HOLD, rec_len=rec_len) * N
     traffic = recorded_traffic() if (N, T, HOLD) == (65536, 1000, 10) and not shaped else {}
@@ -282,6 +284,7 @@ def main():
                      "valu_ops_per_env_step": ops_es},
         "single_step": {"env_steps_per_s": single_rate, "kernel": f"k_step<float,{cls.m},false,true,{str(shaped).lower()},{tmpl_tail}> K=1",
                         "launch_us_mean": single_launch * 1e6,
+                        "launch_us_median_of_replays": single_launch_median * 1e6, "replays": int(len(per_replay)),
                         "roofline": {"bound": "hbm", "achieved": single_bytes / single_launch / 1e9,
                                      "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                                      "frac": single_bytes / single_launch / PEAK_HBM,
