@@ -415,10 +415,11 @@ __device__ __forceinline__ void renorm_attitude(StateT<T, M>& s, float st[kStats
 // (A.row_hint, for step A.t_hint), and the counter last, per lane, so that waiting for the
 // earlier loads does not wait for it (vector loads complete in order; a scalar load would
 // be waited for with every other scalar load). The step runs on the expected row, and the
-// counter is compared only afterwards; a launch that runs at another step (a graph
-// replayed from another step) runs the step again from the loaded state on the row the
-// counter names. Reading the counter first and the row after it cost a dependent memory
-// round trip of about half a microsecond per launch.
+// counter is compared only afterwards; a launch that finds another step (which the host's
+// own bookkeeping never produces: graphs replayed from another step than their capture's
+// run one-step launches without a hint, in the K-step instantiation) runs the step again
+// from the loaded state on the row the counter names. Reading the counter first and the
+// row after it cost a dependent memory round trip of about half a microsecond per launch.
 template <typename T, int M, bool kOut, bool kShaped, bool kSingle = false, bool kFins = false, bool kPayload = false>
 __device__ __forceinline__ void env_steps(const StepArgs& A, const ClassT<T>& Cs, int64_t env, int64_t t0, int K,
                                           float st[kStats], int64_t* t_single = nullptr) {
