@@ -6,7 +6,8 @@
 // step: each launch fetches its action rows beside its state, without waiting for the
 // counter), and one whose launches carry none (a replay from any other step: the rows
 // follow from the counter). A hint that turned out wrong would cost a launch its steps
-// twice; picking the copy by the replay's step keeps that from happening.
+// twice; picking the copy by the replay's step keeps that from happening. Only one-step
+// launches use the hints, so a graph without any has the second kind alone.
 #include <hip/hip_runtime.h>
 
 #include <new>
@@ -64,8 +65,12 @@ extern "C" mgx_status mgx_graph_capture(mgx_batch* b, const void* actions, int64
     const bool stats = (flags & MGX_STEP_STATS) != 0;
     mgx_status st = MGX_OK;
     b->stream = cap;
+    // Only one-step launches use the step hints: a graph without any is captured once per
+    // slot, and its hinted copy stays empty.
+    const bool any_single = per == 1 || n_steps % per == 1;
     for (int c = 0; c < 4 && st == MGX_OK; ++c) {
         const int p = c >> 1, h = c & 1;  // counter slot; step hints or none
+        if (h && !any_single) continue;
         b->slot = p;
         e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) {
@@ -120,7 +125,8 @@ extern "C" mgx_status mgx_graph_replay(mgx_graph* g) {
     mgx_status v = validate_rows(b, b->host_t, g->n_rows, g->row0, g->hold, g->n_steps);
     if (v != MGX_OK) return v;
     hipDevice_guard guard(b->device);
-    hipError_t e = hipGraphLaunch(g->exec[b->slot][b->host_t == g->t_capture ? 1 : 0], b->stream);
+    const int h = (g->exec[b->slot][1] && b->host_t == g->t_capture) ? 1 : 0;
+    hipError_t e = hipGraphLaunch(g->exec[b->slot][h], b->stream);
     if (e != hipSuccess) return hip_fail(b, e, "hipGraphLaunch");
     b->host_t += g->n_steps;
     if (g->n_launches & 1) b->slot = 1 - b->slot;
