@@ -227,10 +227,11 @@ struct StepArgs {
     const void* rec;      // class segment base, [30][npad]
     const void* actions;  // buffer base + class action offset; row r at actions + r*row_stride
     int64_t row_stride;
-    // The step count the host expects the launch to start at (-1: unknown) and the action
-    // row it names, clamped into the buffer. The single-step form fetches that row beside
-    // the state and confirms it against the device counter, so the row's fetch does not
-    // wait for the counter's.
+    // The step count the host expects the launch to start at (-1: none) and the action row
+    // it names, which lies in the buffer (the host drops a hint whose row does not). The
+    // single-step form fetches that row beside the state and confirms it against the
+    // device counter afterwards, so the row's fetch does not wait for the counter's; a
+    // one-step launch without a hint runs the K-step form, which reads the counter first.
     int64_t row_hint, t_hint;
     DevMisc* misc;
     int32_t npad, nvalid;
