@@ -234,37 +234,36 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
     for (int seg = nseg - 1; seg >= 0; --seg) {
         const int k0 = seg * A.ckpt;
         const int k1 = (k0 + A.ckpt < A.H) ? k0 + A.ckpt : A.H;
-        // the stored state, position adjoint and action of step k - 1 are fetched while
-        // step k runs (at k0 the fetch repeats step k0)
-        StateT<T, M> s, sn;
-        VjpTape<T> tp, tpn;
-        T dpn[3], rawn[M];
-        auto fetch = [&](int k, int64_t row) {
-            load_state<T, M>(seg_row(seg, k), np, e, sn);
-            load_tape<T, M>(tape_row(seg, k), tf, e, tpn);
+        // The stored state, tape, position adjoint and action of step k - 1 are fetched while
+        // step k runs (at k0 the fetch repeats step k0), into the other of two buffers: the
+        // loop takes two steps per turn, so no step copies its fetched values into the ones
+        // it works on (a copy per value and step when one buffer was refilled).
+        struct Buf {
+            StateT<T, M> s;
+            VjpTape<T> tp;
+            T dp[3], raw[M];
+        };
+        Buf b0, b1;
+        auto fetch = [&](Buf& b, int k, int64_t row) {
+            load_state<T, M>(seg_row(seg, k), np, e, b.s);
+            load_tape<T, M>(tape_row(seg, k), tf, e, b.tp);
 #pragma unroll
-            for (int j = 0; j < 3; ++j) dpn[j] = dpos[(int64_t)k * A.pos_stride + j * np + e];
-            load_action<T, M>(A, row, e, rawn);
+            for (int j = 0; j < 3; ++j) b.dp[j] = dpos[(int64_t)k * A.pos_stride + j * np + e];
+            load_action<T, M>(A, row, e, b.raw);
         };
         RowCursor rb(A, A.t0 + k1 - 1);
-        fetch(k1 - 1, rb.row);
-        for (int k = k1 - 1; k >= k0; --k) {
-            s = sn;
-            tp = tpn;
-            T raw[M], ac[M], ab[M];
+        // step k from buffer `cur`, fetching step k - 1 into `nxt`
+        auto reverse_step = [&](Buf& cur, Buf& nxt, int k) {
+            T ab[M];
 #pragma unroll
-            for (int i = 0; i < M; ++i) raw[i] = rawn[i];
-#pragma unroll
-            for (int j = 0; j < 3; ++j) xb.p[j] += dpn[j];
+            for (int j = 0; j < 3; ++j) xb.p[j] += cur.dp[j];
             const int64_t r = rb.row;
             if (k > k0)
-                fetch(k - 1, rb.prev_row());
+                fetch(nxt, k - 1, rb.prev_row());
             else
-                fetch(k0, r);
+                fetch(nxt, k0, r);
             rb.retreat();
-#pragma unroll
-            for (int i = 0; i < M; ++i) ac[i] = clip1(raw[i]);
-            vjp_reverse<T, M, kShaped>(C, E, IA2, Brb, s, tp, xb, ab, gdL, gdQ, gA, gDt);
+            vjp_reverse<T, M, kShaped>(C, E, IA2, Brb, cur.s, cur.tp, xb, ab, gdL, gdQ, gA, gDt);
             if (r != row_cur) {
                 if (row_cur >= 0 && dact) {
 #pragma unroll
@@ -275,7 +274,14 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
                 for (int i = 0; i < M; ++i) arow[i] = T(0);
             }
 #pragma unroll
-            for (int i = 0; i < M; ++i) arow[i] += (raw[i] > T(-1) && raw[i] < T(1)) ? ab[i] : T(0);
+            for (int i = 0; i < M; ++i) arow[i] += (cur.raw[i] > T(-1) && cur.raw[i] < T(1)) ? ab[i] : T(0);
+        };
+        fetch(b0, k1 - 1, rb.row);
+        for (int k = k1 - 1;;) {
+            reverse_step(b0, b1, k);
+            if (--k < k0) break;
+            reverse_step(b1, b0, k);
+            if (--k < k0) break;
         }
         __syncthreads();
     }
