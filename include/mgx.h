@@ -498,7 +498,10 @@ typedef struct mgx_graph mgx_graph;
 mgx_status mgx_graph_capture(mgx_batch* b, const void* actions, int64_t n_rows, int64_t row0, int32_t hold,
                              int32_t n_steps, int32_t K, uint32_t flags, mgx_graph** out);
 /* MGX_E_INVALID (nothing launched) if the rows needed at the batch's current step fall
- * outside [0, n_rows). Asynchronous. */
+ * outside [0, n_rows). Asynchronous. A replay from the step the graph was captured at is the
+ * fastest for graphs of one-step launches: those launches then fetch their action rows
+ * beside the state instead of after reading the device counter (the graph holds both forms
+ * and the replay picks one; the results are the same). */
 mgx_status mgx_graph_replay(mgx_graph* g);
 mgx_status mgx_graph_destroy(mgx_graph* g);
 
