@@ -27,6 +27,7 @@ struct StationConsts {
 };
 
 template <typename T>
+// The first 64 bytes hold what the step kernel's loads need (one scalar cache line).
 struct StationArgs {
     T* state;
     const T* rec;
@@ -34,6 +35,7 @@ struct StationArgs {
     T* tgt;              // [7][npad]: p*, q*
     int32_t* ep;         // [npad] episode index
     int32_t* et;         // [npad] steps taken in the episode
+    int32_t npad, nvalid;
     uint8_t* restart;    // [npad] 1 where an episode started during the launch
     T* obs;              // per step [13+m][npad], row k at obs + k * obs_stride
     T* final_obs;        // the same or NULL; written for lanes whose episode ended
@@ -42,7 +44,6 @@ struct StationArgs {
     uint8_t* trunc;      // per step [npad], likewise
     int64_t act_stride, obs_stride, flag_stride;
     int32_t n_steps;     // task steps in this launch
-    int32_t npad, nvalid;
     int64_t env_off;
     StationConsts P;
 };
@@ -224,10 +225,19 @@ template <typename T, int M, bool kShaped, bool kFins, bool kPayload, bool kMult
 __global__ void __launch_bounds__(256) k_station_step(StationLaunch<T> L) {
     const StationArgs<T>& A = L.a;
     const int64_t env = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (env >= A.npad) return;  // whole waves: a segment holds a multiple of the wave size
     const int64_t np = A.npad;
+    // Every lane loads everything, with no branch ahead of its loads: lanes past the segment
+    // (whole waves) at its last slot, padding slots as they are (they hold a valid state,
+    // parameter set and command). Behind a branch on the kernel arguments, each group of
+    // loads waited for another argument fetch; a one-step launch took about 8 us.
+    // Every lane also takes the steps (the commands' loads otherwise moved behind the branch
+    // that left padding lanes out): padding lanes store and report nothing and never end an
+    // episode (they stay in the wave for the restarts); lanes past the segment write nothing.
+    const bool live = env < np;
+    const bool valid = env < A.nvalid;
+    const int64_t el = live ? env : np - 1;
     StateT<T, M> s;
-    load_state<T, M>(A.state, np, env, s);
+    load_state<T, M>(A.state, np, el, s);
     // classes with fins carry the attitude's low-order words through the launch (float)
     constexpr bool kComp = kFins && std::is_same<T, float>::value;
     StateLo<T> lo;
@@ -235,40 +245,39 @@ __global__ void __launch_bounds__(256) k_station_step(StationLaunch<T> L) {
     for (int j = 0; j < 4; ++j) lo.q[j] = T(0);
     T tg[7];
 #pragma unroll
-    for (int j = 0; j < 7; ++j) tg[j] = A.tgt[j * np + env];
-    // padding lanes take no step and report nothing, but stay in the wave for the restarts
-    const bool valid = env < A.nvalid;
+    for (int j = 0; j < 7; ++j) tg[j] = A.tgt[j * np + el];
     const ClassT<T> C = class_in_vgpr<T, M, kFins>(L.cls);
     EnvT<T> E;
     T IA2[3], Brb[3];
-    int32_t ep = 0, et = 0;
     bool restarted = false;
     T nxt[M];
-    if (valid) {
-        load_record<T, kPayload>(A.rec, np, env, C.flags, E);
-        ep = A.ep[env];
-        et = A.et[env];
+    load_record<T, kPayload>(A.rec, np, el, C.flags, E);
+    int32_t ep = A.ep[el];
+    int32_t et = A.et[el];
 #pragma unroll
-        for (int i = 0; i < M; ++i) nxt[i] = A.act[i * np + env];
-        env_prologue<T, kPayload>(C, E, IA2, Brb);
-    }
+    for (int i = 0; i < M; ++i) nxt[i] = A.act[i * np + el];
+    env_prologue<T, kPayload>(C, E, IA2, Brb);
     const int32_t n_steps = kMulti ? A.n_steps : 1;
     for (int32_t k = 0; k < n_steps; ++k) {
         T r = T(0);
         bool term = false, trunc = false;
-        if (valid) {
+        {
             T a[M];
 #pragma unroll
             for (int i = 0; i < M; ++i) a[i] = clip1(nxt[i]);
             if constexpr (kMulti) {
                 // the next row, clamped to the last (a load guarded per step would make the
                 // compiler wait for it before the step)
-                const T* an = A.act + (int64_t)(k + 1 < n_steps ? k + 1 : k) * A.act_stride + env;
+                const T* an = A.act + (int64_t)(k + 1 < n_steps ? k + 1 : k) * A.act_stride + el;
 #pragma unroll
                 for (int i = 0; i < M; ++i) nxt[i] = an[i * np];
             }
-            for (int j = 0; j < A.P.substeps; ++j)
+            // substeps >= 1 (checked at creation): the first step is unconditional, so no
+            // branch on the argument stands between the record's loads and their use
+            int j = 0;
+            do {
                 step_body<T, M, false, kShaped, kFins, kPayload, kComp>(C, E, IA2, Brb, s, a, nullptr, &lo);
+            } while (++j < A.P.substeps);
             float st[kStats];  // launch statistics are not kept by the task
             renorm_attitude<T, M>(s, st);
 
@@ -291,10 +300,10 @@ __global__ void __launch_bounds__(256) k_station_step(StationLaunch<T> L) {
             for (int i = 0; i < M; ++i) a2 += a[i] * a[i];
             const T up = T(1) - T(2) * (s.q[1] * s.q[1] + s.q[2] * s.q[2]);
             r = exp_(-d * (T)A.P.inv_sigma) - (T)A.P.w_att * (T(1) - e[0] * e[0]) - (T)A.P.w_act_m * a2;
-            term = !fin || d > (T)A.P.d_max || up < (T)A.P.cos_tilt;
-            if (!fin) r = T(0);
-            ++et;
-            trunc = et >= A.P.max_steps;
+            term = valid && (!fin || d > (T)A.P.d_max || up < (T)A.P.cos_tilt);
+            if (!fin || !valid) r = T(0);
+            et += valid ? 1 : 0;
+            trunc = valid && et >= A.P.max_steps;
         }
         const bool done = term || trunc;
         if (done) {
@@ -312,11 +321,13 @@ __global__ void __launch_bounds__(256) k_station_step(StationLaunch<T> L) {
             else if (done)
                 start_state<T, M>(A.P, (uint64_t)(A.env_off + env), (uint32_t)ep, s, tg);
         }
-        write_obs<T, M>(A.obs + (int64_t)k * A.obs_stride, np, env, s, tg);
-        const int64_t fo = (int64_t)k * A.flag_stride + env;
-        A.reward[fo] = r;
-        A.term[fo] = term ? 1 : 0;
-        A.trunc[fo] = trunc ? 1 : 0;
+        if (live) {
+            write_obs<T, M>(A.obs + (int64_t)k * A.obs_stride, np, env, s, tg);
+            const int64_t fo = (int64_t)k * A.flag_stride + env;
+            A.reward[fo] = r;
+            A.term[fo] = term ? 1 : 0;
+            A.trunc[fo] = trunc ? 1 : 0;
+        }
     }
     if (valid) {
         store_state<T, M>(A.state, np, env, s);
@@ -327,7 +338,7 @@ __global__ void __launch_bounds__(256) k_station_step(StationLaunch<T> L) {
         A.ep[env] = ep;
         A.et[env] = et;
     }
-    A.restart[env] = restarted ? 1 : 0;
+    if (live) A.restart[env] = restarted ? 1 : 0;
 }
 
 template <typename T, int M, bool kMulti>
