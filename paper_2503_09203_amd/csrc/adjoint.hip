@@ -172,12 +172,15 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
         Brb[j] = E.buoy * C.rb[j];
     }
     const T* ck = (const T*)A.ckpt_buf;
-    T* sg = (T*)A.seg_buf;
-    T* tb = (T*)A.tape_buf;
+    // this tile's blocks of the recompute buffer and the tape; within a row, field f of lane l
+    // at f * kWave + l
+    constexpr int kSegRow = (kStateFixed + M) * kWave, kTapeRow = kTapeLen * kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    T* sg = (T*)A.seg_buf + (int64_t)blockIdx.x * 2 * A.ckpt * kSegRow;
+    T* tb = (T*)A.tape_buf + (int64_t)blockIdx.x * 2 * A.ckpt * kTapeRow;
     const int nseg = (A.H + A.ckpt - 1) / A.ckpt;
-    auto seg_row = [&](int seg, int k) { return sg + ((int64_t)(seg & 1) * A.ckpt + (k - seg * A.ckpt)) * A.ckpt_stride; };
-    auto tape_row = [&](int seg, int k) { return tb + ((int64_t)(seg & 1) * A.ckpt + (k - seg * A.ckpt)) * A.tape_stride; };
-    const int64_t tf = A.tape_field;
+    auto seg_row = [&](int seg, int k) { return sg + ((seg & 1) * A.ckpt + (k - seg * A.ckpt)) * kSegRow; };
+    auto tape_row = [&](int seg, int k) { return tb + ((seg & 1) * A.ckpt + (k - seg * A.ckpt)) * kTapeRow; };
 
     // recompute one segment's states into its half of the buffer, with the forward
     // quantities each step's reverse pass needs (actions one step ahead)
@@ -194,10 +197,10 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
             for (int i = 0; i < M; ++i) a[i] = clip1(nxt[i]);
             load_action<T, M>(A, k + 1 < k1 ? rc.next_row() : rc.row, e, nxt);
             rc.advance();
-            store_state<T, M>(seg_row(seg, k), np, e, s);
+            store_state<T, M>(seg_row(seg, k), kWave, lane, s);
             VjpTape<T> tp;
             step_body<T, M, false, kShaped, false, false, false, true>(C, E, IA2, Brb, s, a, nullptr, nullptr, &tp);
-            store_tape<T, M>(tape_row(seg, k), tf, e, tp);
+            store_tape<T, M>(tape_row(seg, k), kWave, lane, tp);
         }
     };
 
@@ -245,8 +248,8 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
         };
         Buf b0, b1;
         auto fetch = [&](Buf& b, int k, int64_t row) {
-            load_state<T, M>(seg_row(seg, k), np, e, b.s);
-            load_tape<T, M>(tape_row(seg, k), tf, e, b.tp);
+            load_state<T, M>(seg_row(seg, k), kWave, lane, b.s);
+            load_tape<T, M>(tape_row(seg, k), kWave, lane, b.tp);
 #pragma unroll
             for (int j = 0; j < 3; ++j) b.dp[j] = dpos[(int64_t)k * A.pos_stride + j * np + e];
             load_action<T, M>(A, row, e, b.raw);
@@ -372,10 +375,9 @@ static AdjArgs adj_args(mgx_batch* b, int c) {
     A.t0 = b->ro_t0;
     A.ckpt_buf = (char*)b->ro_ckpt_mem + P * b->state_off[c];
     A.ckpt_stride = b->state_elems;
-    A.seg_buf = (char*)b->ro_seg_mem + P * b->state_off[c];
-    A.tape_buf = (char*)b->ro_tape_mem + P * b->pad_off[c];
-    A.tape_stride = (int64_t)kTapeLen * b->npad_total;
-    A.tape_field = b->npad_total;
+    // tile-blocked: a class's block follows the blocks of the classes before it
+    A.seg_buf = (char*)b->ro_seg_mem + P * (size_t)2 * b->ro_ckpt * b->state_off[c];
+    A.tape_buf = (char*)b->ro_tape_mem + P * (size_t)2 * b->ro_ckpt * kTapeLen * b->pad_off[c];
     A.pos_stride = 3 * b->npad_total;
     A.misc = b->d_misc;
     return A;

@@ -264,10 +264,12 @@ struct AdjArgs {
     int64_t t0;            // global step at the start of the rollout
     void* ckpt_buf;        // class segment within each checkpoint row; row stride ckpt_stride
     int64_t ckpt_stride;   // elements per checkpoint row (state_elems)
-    void* seg_buf;         // recompute buffer, same layout, ckpt rows
-    void* tape_buf;        // forward quantities of the recomputed steps (kTapeLen fields), class column
-    int64_t tape_stride;   // elements per step row of the tape (kTapeLen x n_pad_total)
-    int64_t tape_field;    // elements per tape field (n_pad_total)
+    // Recompute buffer (states of two segments) and tape (the kTapeLen forward quantities of
+    // their steps), both private to the reverse sweep and blocked by 64-environment tile:
+    // [tile][2 x ckpt rows][field][64 lanes], so the fields of one step of one tile lie 256 B
+    // apart and a wave reaches them from one address with immediate offsets.
+    void* seg_buf;         // class block, (13+m) fields per row
+    void* tape_buf;        // class block, kTapeLen fields per row
     void* pos;             // class segment within a position row (3 x npad); row stride pos_stride
     int64_t pos_stride;
     void* dactions;        // class segment within an action row (m x npad), or null
