@@ -162,3 +162,50 @@ def test_fin_and_payload_classes_are_refused(make, word):
         mgx.mgx_rollout_forward(b.h, acts.data_ptr(), acts.shape[0], 0, 1, 8, 4, pos.data_ptr())
     assert word in str(e.value)
     b.close()
+
+
+def test_classes_in_one_batch_match_each_class_alone():
+    """Two classes in one batch (4 and 8 thrusters; 70 and 200 environments, so ragged
+    tiles; horizon 70, so a short last segment) give, bit for bit in float32, the positions
+    and gradients of each class run in a batch of its own: each class works in its own block
+    of the checkpoint, recompute and tape buffers."""
+    t = torch()
+    from paper_2503_09203_amd.autograd import DiffRollout
+    Hs = 70
+    classes = [synth.draw_class(4, 0), synth.draw_class(8, 4)]
+    ns = [70, 200]
+    w = synth.mixed(classes, ns, steps=Hs, hold=1)
+    acts = w.actions(Hs)
+    wp_all = synth.waypoints(sum(ns))
+
+    def run(cls_idx):
+        cl = [classes[c] for c in cls_idx]
+        b = mgx.Batch(cl, [ns[c] for c in cls_idx], w.dt, mgx.FP32)
+        offs = np.cumsum([0] + ns)
+        idx = np.concatenate([np.arange(offs[c], offs[c + 1]) for c in cls_idx])
+        params = w.params.subset(idx)
+        init = t.tensor(b.pack_state([w.state[c].stacked() for c in cls_idx]), dtype=b.dtype, device=b.device)
+        ro = DiffRollout(b, params, init, Hs, hold=1)
+        a = t.tensor(b.pack_actions([acts[c] for c in cls_idx]), dtype=b.dtype, device=b.device, requires_grad=True)
+        f = lambda x: t.tensor(np.ascontiguousarray(x), dtype=t.float64, device=b.device, requires_grad=True)
+        dl, dq, am = f(params.dlin), f(params.dquad), f(params.added)
+        wp = t.tensor(wp_all[:, idx], dtype=t.float64, device=b.device)
+        pos = ro.positions(ro(a, dl, dq, am))
+        d = pos.to(t.float64) - wp[None]
+        ((d * d).sum() + 1e-3 * (a.to(t.float64) ** 2).sum()).backward()
+        out = dict(pos=pos.detach().cpu().numpy(),
+                   ga=b.unpack_actions(a.grad.detach().cpu().numpy()),
+                   gp=np.concatenate([dl.grad.cpu().numpy(), dq.grad.cpu().numpy(), am.grad.cpu().numpy()]))
+        b.close()
+        return out
+
+    both = run([0, 1])
+    off = 0
+    for c in range(2):
+        alone = run([c])
+        sl = slice(off, off + ns[c])
+        assert np.array_equal(both["pos"][:, :, sl], alone["pos"]), f"positions of class {c}"
+        assert np.array_equal(both["ga"][c], alone["ga"][0]), f"action gradients of class {c}"
+        assert np.array_equal(both["gp"][:, sl], alone["gp"]), f"parameter gradients of class {c}"
+        assert np.abs(alone["gp"]).max() > 0 and np.abs(alone["ga"][0]).max() > 0
+        off += ns[c]
