@@ -449,7 +449,7 @@ mgx_status mgx_rollout_forward(mgx_batch* b, const void* actions, int64_t n_rows
  * mgx_rollout_backward. MGX_E_INVALID (nothing launched) when the checkpoints
  * (P * ceil(H / ckpt_every) * state_elems bytes), the segment scratch
  * (P * 2 * ckpt_every * state_elems bytes), each rounded up to 256, and the segment tape
- * (P * 2 * ckpt_every * 35 * n_pad_total bytes) exceed 64 MiB; P is the element size. The array
+ * (P * 2 * ckpt_every * 36 * n_pad_total bytes) exceed 64 MiB; P is the element size. The array
  * is shared by every call on the GPU and keeps the last call's contents: a later
  * mgx_rollout_forward_static on any batch of the same GPU overwrites the checkpoints of an
  * earlier one, whose mgx_rollout_backward then returns MGX_E_STATE; calls that overlap on

@@ -103,6 +103,11 @@ __device__ __forceinline__ void load_tape(const T* row, int64_t field, int64_t e
     tp.g = o[26 * field];
 }
 
+// Fields of a tape row: the step's forward quantities, then the mask of the actions that the
+// clip to [-1, 1] passes through (bit i for actuator i, held as a value of T): the reverse
+// sweep needs no action values of its own.
+constexpr int kTapeFields = kTapeLen + 1;
+
 template <typename T, int M>
 __device__ __forceinline__ void load_action(const AdjArgs& A, int64_t row, int64_t e, T raw[M]) {
     const T* src = (const T*)A.actions + row * A.row_stride + e;
@@ -174,7 +179,7 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
     const T* ck = (const T*)A.ckpt_buf;
     // this tile's blocks of the recompute buffer and the tape; within a row, field f of lane l
     // at f * kWave + l
-    constexpr int kSegRow = (kStateFixed + M) * kWave, kTapeRow = kTapeLen * kWave;
+    constexpr int kSegRow = (kStateFixed + M) * kWave, kTapeRow = kTapeFields * kWave;
     const int lane = threadIdx.x & (kWave - 1);
     T* sg = (T*)A.seg_buf + (int64_t)blockIdx.x * 2 * A.ckpt * kSegRow;
     T* tb = (T*)A.tape_buf + (int64_t)blockIdx.x * 2 * A.ckpt * kTapeRow;
@@ -193,14 +198,20 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
         T a[M], nxt[M];
         load_action<T, M>(A, rc.row, e, nxt);
         for (int k = k0; k < k1; ++k) {
+            uint32_t pass = 0;
 #pragma unroll
-            for (int i = 0; i < M; ++i) a[i] = clip1(nxt[i]);
+            for (int i = 0; i < M; ++i) {
+                pass |= (nxt[i] > T(-1) && nxt[i] < T(1)) ? 1u << i : 0u;
+                a[i] = clip1(nxt[i]);
+            }
             load_action<T, M>(A, k + 1 < k1 ? rc.next_row() : rc.row, e, nxt);
             rc.advance();
             store_state<T, M>(seg_row(seg, k), kWave, lane, s);
             VjpTape<T> tp;
             step_body<T, M, false, kShaped, false, false, false, true>(C, E, IA2, Brb, s, a, nullptr, nullptr, &tp);
-            store_tape<T, M>(tape_row(seg, k), kWave, lane, tp);
+            T* tr = tape_row(seg, k);
+            store_tape<T, M>(tr, kWave, lane, tp);
+            tr[kTapeLen * kWave + lane] = T(pass);
         }
     };
 
@@ -237,22 +248,23 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
     for (int seg = nseg - 1; seg >= 0; --seg) {
         const int k0 = seg * A.ckpt;
         const int k1 = (k0 + A.ckpt < A.H) ? k0 + A.ckpt : A.H;
-        // The stored state, tape, position adjoint and action of step k - 1 are fetched while
+        // The stored state, tape and position adjoint of step k - 1 are fetched while
         // step k runs (at k0 the fetch repeats step k0), into the other of two buffers: the
         // loop takes two steps per turn, so no step copies its fetched values into the ones
         // it works on (a copy per value and step when one buffer was refilled).
         struct Buf {
             StateT<T, M> s;
             VjpTape<T> tp;
-            T dp[3], raw[M];
+            T dp[3], pass;
         };
         Buf b0, b1;
-        auto fetch = [&](Buf& b, int k, int64_t row) {
+        auto fetch = [&](Buf& b, int k) {
             load_state<T, M>(seg_row(seg, k), kWave, lane, b.s);
-            load_tape<T, M>(tape_row(seg, k), kWave, lane, b.tp);
+            const T* tr = tape_row(seg, k);
+            load_tape<T, M>(tr, kWave, lane, b.tp);
+            b.pass = tr[kTapeLen * kWave + lane];
 #pragma unroll
             for (int j = 0; j < 3; ++j) b.dp[j] = dpos[(int64_t)k * A.pos_stride + j * np + e];
-            load_action<T, M>(A, row, e, b.raw);
         };
         RowCursor rb(A, A.t0 + k1 - 1);
         // step k from buffer `cur`, fetching step k - 1 into `nxt`
@@ -261,10 +273,7 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
 #pragma unroll
             for (int j = 0; j < 3; ++j) xb.p[j] += cur.dp[j];
             const int64_t r = rb.row;
-            if (k > k0)
-                fetch(nxt, k - 1, rb.prev_row());
-            else
-                fetch(nxt, k0, r);
+            fetch(nxt, k > k0 ? k - 1 : k0);
             rb.retreat();
             vjp_reverse<T, M, kShaped>(C, E, IA2, Brb, cur.s, cur.tp, xb, ab, gdL, gdQ, gA, gDt);
             if (r != row_cur) {
@@ -276,10 +285,11 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
 #pragma unroll
                 for (int i = 0; i < M; ++i) arow[i] = T(0);
             }
+            const uint32_t pass = (uint32_t)cur.pass;
 #pragma unroll
-            for (int i = 0; i < M; ++i) arow[i] += (cur.raw[i] > T(-1) && cur.raw[i] < T(1)) ? ab[i] : T(0);
+            for (int i = 0; i < M; ++i) arow[i] += ((pass >> i) & 1u) ? ab[i] : T(0);
         };
-        fetch(b0, k1 - 1, rb.row);
+        fetch(b0, k1 - 1);
         for (int k = k1 - 1;;) {
             reverse_step(b0, b1, k);
             if (--k < k0) break;
@@ -377,7 +387,7 @@ static AdjArgs adj_args(mgx_batch* b, int c) {
     A.ckpt_stride = b->state_elems;
     // tile-blocked: a class's block follows the blocks of the classes before it
     A.seg_buf = (char*)b->ro_seg_mem + P * (size_t)2 * b->ro_ckpt * b->state_off[c];
-    A.tape_buf = (char*)b->ro_tape_mem + P * (size_t)2 * b->ro_ckpt * kTapeLen * b->pad_off[c];
+    A.tape_buf = (char*)b->ro_tape_mem + P * (size_t)2 * b->ro_ckpt * kTapeFields * b->pad_off[c];
     A.pos_stride = 3 * b->npad_total;
     A.misc = b->d_misc;
     return A;
@@ -433,7 +443,7 @@ static mgx_status rollout_forward(mgx_batch* b, const void* actions, int64_t n_r
     const int64_t nck = (H + ckpt_every - 1) / ckpt_every;
     const size_t P = (size_t)b->prec;
     const size_t ck_bytes = P * (size_t)nck * b->state_elems, seg_bytes = P * (size_t)2 * ckpt_every * b->state_elems;
-    const size_t tape_bytes = P * (size_t)2 * ckpt_every * kTapeLen * b->npad_total;
+    const size_t tape_bytes = P * (size_t)2 * ckpt_every * kTapeFields * b->npad_total;
     void* ck_mem = nullptr;
     void* seg_mem = nullptr;
     void* tape_mem = nullptr;

@@ -265,11 +265,12 @@ struct AdjArgs {
     void* ckpt_buf;        // class segment within each checkpoint row; row stride ckpt_stride
     int64_t ckpt_stride;   // elements per checkpoint row (state_elems)
     // Recompute buffer (states of two segments) and tape (the kTapeLen forward quantities of
-    // their steps), both private to the reverse sweep and blocked by 64-environment tile:
+    // their steps and the actions' clip mask), both private to the reverse sweep and blocked
+    // by 64-environment tile:
     // [tile][2 x ckpt rows][field][64 lanes], so the fields of one step of one tile lie 256 B
     // apart and a wave reaches them from one address with immediate offsets.
     void* seg_buf;         // class block, (13+m) fields per row
-    void* tape_buf;        // class block, kTapeLen fields per row
+    void* tape_buf;        // class block, kTapeLen + 1 fields per row
     void* pos;             // class segment within a position row (3 x npad); row stride pos_stride
     int64_t pos_stride;
     void* dactions;        // class segment within an action row (m x npad), or null
