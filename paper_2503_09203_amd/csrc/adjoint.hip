@@ -116,7 +116,7 @@ __device__ __forceinline__ void load_action(const AdjArgs& A, int64_t row, int64
 }
 
 template <typename T, int M, bool kShaped>
-__global__ void __launch_bounds__(256) k_rollout_fwd(AdjArgs A, ClassT<T> Cs) {
+__global__ void __launch_bounds__(64) k_rollout_fwd(AdjArgs A, ClassT<T> Cs) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const ClassT<T> C = class_in_vgpr<T, M>(Cs);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -339,7 +339,10 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
 
 template <typename T>
 hipError_t launch_rollout_fwd(const AdjArgs& A, const ClassT<T>& C, int m, bool shaped, hipStream_t s) {
-    const unsigned grid = (unsigned)((A.npad + 255) / 256), block = 256;
+    // one wave per block: a few thousand environments are a few waves per class, and blocks of
+    // four waves would pack them onto a quarter as many compute units, sharing their issue
+    // and memory pipelines (0.180 -> 0.171 ms at 8192 x 256 with 8 thrusters)
+    const unsigned grid = (unsigned)((A.npad + kWave - 1) / kWave), block = kWave;
 #define KERNEL k_rollout_fwd
     MGX_ADJ_SWITCH
 #undef KERNEL
