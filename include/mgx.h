@@ -409,7 +409,9 @@ typedef struct {
 } mgx_launch_shape;
 
 /* Reads / sets the launch shape of a batch (validated; MGX_LAUNCH_PERSISTENT on a double
- * batch is MGX_E_INVALID). Default: per-class launches, K = 16, block 256. */
+ * batch is MGX_E_INVALID). Default: per-class launches, K = 16, block 64 while the batch
+ * has fewer 64-environment tiles than four per compute unit (a small batch then spreads
+ * over as many compute units), else 256. */
 mgx_status mgx_batch_get_shape(const mgx_batch* b, mgx_launch_shape* out);
 mgx_status mgx_batch_set_shape(mgx_batch* b, const mgx_launch_shape* in);
 

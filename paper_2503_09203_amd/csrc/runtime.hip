@@ -383,6 +383,11 @@ extern "C" mgx_status mgx_batch_create(const mgx_batch_desc* d, mgx_batch** out)
             b->arch = prop.gcnArchName;
         }
     }
+    // Default block: one wave per block while the batch has fewer waves than the device has
+    // SIMDs (four per compute unit), so that a small batch spreads over as many compute units
+    // instead of sharing a quarter as many (1024 environments x 1000 steps in FP64: 1.31 ->
+    // 1.23 ms); blocks of four waves from one wave per SIMD on.
+    b->block = b->npad_total / kWave < 4 * (int64_t)b->n_cu ? kWave : 256;
     mgx_status st = MGX_OK;
     auto run = [&]() -> mgx_status {
         HIP_TRY(b, hipMemcpyAsync(b->d_classdesc, d64.data(), sizeof(ClassDesc64) * MGX_MAX_CLASSES,
