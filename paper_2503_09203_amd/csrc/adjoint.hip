@@ -115,18 +115,71 @@ __device__ __forceinline__ void load_action(const AdjArgs& A, int64_t row, int64
     for (int i = 0; i < M; ++i) raw[i] = src[i * (int64_t)A.npad];
 }
 
+// Row k of segment `seg` in a tile's block of the recompute buffer (states) and of the tape,
+// both [tile][2 x ckpt rows][field][64 lanes]; consecutive segments alternate between the
+// two halves of a block.
+template <typename T, int M>
+__device__ __forceinline__ T* seg_row_of(const AdjArgs& A, int64_t tile, int seg, int k) {
+    constexpr int kRow = (kStateFixed + M) * kWave;
+    return (T*)A.seg_buf + (tile * 2 * A.ckpt + (seg & 1) * A.ckpt + (k - seg * A.ckpt)) * kRow;
+}
+template <typename T>
+__device__ __forceinline__ T* tape_row_of(const AdjArgs& A, int64_t tile, int seg, int k) {
+    constexpr int kRow = kTapeFields * kWave;
+    return (T*)A.tape_buf + (tile * 2 * A.ckpt + (seg & 1) * A.ckpt + (k - seg * A.ckpt)) * kRow;
+}
+
+// Segment `seg` (steps k0 .. k1 - 1) run from its checkpoint the way the reverse sweep needs
+// it: each step's state before the step into the recompute buffer, and its forward
+// quantities and the actions' clip mask into the tape. Used by the forward pass for the last
+// segment and by the backward for the others; the actions of step k + 1 are in flight while
+// step k runs.
 template <typename T, int M, bool kShaped>
-__global__ void __launch_bounds__(64) k_rollout_fwd(AdjArgs A, ClassT<T> Cs) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void recompute_segment(const AdjArgs& A, const ClassT<T>& C, const EnvT<T>& E,
+                                                  const T IA2[3], const T Brb[3], int64_t e, int lane, int seg) {
+    const int k0 = seg * A.ckpt;
+    const int k1 = (k0 + A.ckpt < A.H) ? k0 + A.ckpt : A.H;
+    const int64_t tile = e / kWave;
+    StateT<T, M> s;
+    load_state<T, M>((const T*)A.ckpt_buf + (int64_t)seg * A.ckpt_stride, A.npad, e, s);
+    RowCursor rc(A, A.t0 + k0);
+    T a[M], nxt[M];
+    load_action<T, M>(A, rc.row, e, nxt);
+    for (int k = k0; k < k1; ++k) {
+        uint32_t pass = 0;
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            pass |= (nxt[i] > T(-1) && nxt[i] < T(1)) ? 1u << i : 0u;
+            a[i] = clip1(nxt[i]);
+        }
+        load_action<T, M>(A, k + 1 < k1 ? rc.next_row() : rc.row, e, nxt);
+        rc.advance();
+        store_state<T, M>(seg_row_of<T, M>(A, tile, seg, k), kWave, lane, s);
+        VjpTape<T> tp;
+        step_body<T, M, false, kShaped, false, false, false, true>(C, E, IA2, Brb, s, a, nullptr, nullptr, &tp);
+        T* tr = tape_row_of<T>(A, tile, seg, k);
+        store_tape<T, M>(tr, kWave, lane, tp);
+        tr[kTapeLen * kWave + lane] = T(pass);
+    }
+}
+
+// Forward pass with checkpoints. Two waves per 64-environment tile (block of 128): wave 0
+// runs every step, storing the checkpoints and the positions; once it has stored the last
+// segment's checkpoint (block barrier), wave 1 runs that segment again as the backward's
+// recomputation would, into the recompute buffer and the tape, while wave 0 finishes it. The
+// backward then sweeps the last segment at once instead of first waiting for its
+// recomputation. The grid covers the padded segment exactly, so both waves reach the barrier.
+template <typename T, int M, bool kShaped>
+__global__ void __launch_bounds__(128) k_rollout_fwd(AdjArgs A, ClassT<T> Cs) {
+    const int role = threadIdx.x / kWave;  // 0: the rollout, 1: the last segment's tape
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t e = (int64_t)blockIdx.x * kWave + lane;
     const ClassT<T> C = class_in_vgpr<T, M>(Cs);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (A.advance) A.misc->t[A.wr] = A.t0 + A.advance;
         prepare_next_slot(A.misc, A.wr);
     }
-    if (e >= A.npad) return;
     const int64_t np = A.npad;
-    StateT<T, M> s;
-    load_state<T, M>((const T*)A.state, np, e, s);
     EnvT<T> E;
     load_env<T>((const T*)A.rec, np, e, E);
     set_amc(E, C.flags);
@@ -137,30 +190,45 @@ __global__ void __launch_bounds__(64) k_rollout_fwd(AdjArgs A, ClassT<T> Cs) {
         Brb[j] = E.buoy * C.rb[j];
     }
     T* ck = (T*)A.ckpt_buf;
+    const int seg_last = (A.H - 1) / A.ckpt, k_last = seg_last * A.ckpt;
+    if (role == 1) {
+        __syncthreads();
+        recompute_segment<T, M, kShaped>(A, C, E, IA2, Brb, e, lane, seg_last);
+        return;
+    }
     T* pos = (T*)A.pos;
+    StateT<T, M> s;
+    load_state<T, M>((const T*)A.state, np, e, s);
     // The action row of step k + 1 is in flight while step k runs (with per-step actions a
     // load issued right before its use would leave every step waiting on memory).
     RowCursor rc(A, A.t0);
     T a[M], nxt[M];
     load_action<T, M>(A, rc.row, e, nxt);
-    for (int k = 0; k < A.H; ++k) {
+    auto step = [&](int k) {
 #pragma unroll
         for (int i = 0; i < M; ++i) a[i] = clip1(nxt[i]);
         load_action<T, M>(A, k + 1 < A.H ? rc.next_row() : rc.row, e, nxt);
         rc.advance();
-        if (k % A.ckpt == 0) store_state<T, M>(ck + (int64_t)(k / A.ckpt) * A.ckpt_stride, np, e, s);
         step_body<T, M, false, kShaped>(C, E, IA2, Brb, s, a);
 #pragma unroll
         for (int j = 0; j < 3; ++j) pos[(int64_t)k * A.pos_stride + j * np + e] = s.p[j];
+    };
+    for (int k = 0; k < k_last; ++k) {
+        if (k % A.ckpt == 0) store_state<T, M>(ck + (int64_t)(k / A.ckpt) * A.ckpt_stride, np, e, s);
+        step(k);
     }
+    store_state<T, M>(ck + (int64_t)seg_last * A.ckpt_stride, np, e, s);
+    __syncthreads();
+    for (int k = k_last; k < A.H; ++k) step(k);
     store_state<T, M>((T*)A.state, np, e, s);
 }
 
 // Reverse sweep with per-segment recomputation. Two waves per 64-environment tile (block of
 // 128): wave 1 recomputes segment s - 1 from its checkpoint into one half of the segment
 // buffer while wave 0 sweeps segment s backwards from the other half, so recomputation
-// overlaps the sweep; the block barrier after each segment hands the halves over. The grid
-// covers the padded segment exactly, so both waves reach every barrier.
+// overlaps the sweep; the block barrier after each segment hands the halves over. The last
+// segment is in its half already (the forward pass stored it). The grid covers the padded
+// segment exactly, so both waves reach every barrier.
 template <typename T, int M, bool kShaped>
 __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
     const int role = threadIdx.x / kWave;  // 0: sweep, 1: recompute
@@ -176,9 +244,9 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
         IA2[j] = C.inertia[j] + E.A[3 + j];
         Brb[j] = E.buoy * C.rb[j];
     }
-    const T* ck = (const T*)A.ckpt_buf;
-    // this tile's blocks of the recompute buffer and the tape; within a row, field f of lane l
-    // at f * kWave + l
+    // this tile's blocks of the recompute buffer and the tape (the layout of seg_row_of and
+    // tape_row_of, with the tile's base hoisted); within a row, field f of lane l at
+    // f * kWave + l
     constexpr int kSegRow = (kStateFixed + M) * kWave, kTapeRow = kTapeFields * kWave;
     const int lane = threadIdx.x & (kWave - 1);
     T* sg = (T*)A.seg_buf + (int64_t)blockIdx.x * 2 * A.ckpt * kSegRow;
@@ -187,40 +255,10 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
     auto seg_row = [&](int seg, int k) { return sg + ((seg & 1) * A.ckpt + (k - seg * A.ckpt)) * kSegRow; };
     auto tape_row = [&](int seg, int k) { return tb + ((seg & 1) * A.ckpt + (k - seg * A.ckpt)) * kTapeRow; };
 
-    // recompute one segment's states into its half of the buffer, with the forward
-    // quantities each step's reverse pass needs (actions one step ahead)
-    auto recompute = [&](int seg) {
-        const int k0 = seg * A.ckpt;
-        const int k1 = (k0 + A.ckpt < A.H) ? k0 + A.ckpt : A.H;
-        StateT<T, M> s;
-        load_state<T, M>(ck + (int64_t)seg * A.ckpt_stride, np, e, s);
-        RowCursor rc(A, A.t0 + k0);
-        T a[M], nxt[M];
-        load_action<T, M>(A, rc.row, e, nxt);
-        for (int k = k0; k < k1; ++k) {
-            uint32_t pass = 0;
-#pragma unroll
-            for (int i = 0; i < M; ++i) {
-                pass |= (nxt[i] > T(-1) && nxt[i] < T(1)) ? 1u << i : 0u;
-                a[i] = clip1(nxt[i]);
-            }
-            load_action<T, M>(A, k + 1 < k1 ? rc.next_row() : rc.row, e, nxt);
-            rc.advance();
-            store_state<T, M>(seg_row(seg, k), kWave, lane, s);
-            VjpTape<T> tp;
-            step_body<T, M, false, kShaped, false, false, false, true>(C, E, IA2, Brb, s, a, nullptr, nullptr, &tp);
-            T* tr = tape_row(seg, k);
-            store_tape<T, M>(tr, kWave, lane, tp);
-            tr[kTapeLen * kWave + lane] = T(pass);
-        }
-    };
-
-    if (role == 1) recompute(nseg - 1);
-    __syncthreads();
-
+    // the forward pass stored the last segment's states and tape
     if (role == 1) {
         for (int seg = nseg - 1; seg >= 0; --seg) {
-            if (seg > 0) recompute(seg - 1);
+            if (seg > 0) recompute_segment<T, M, kShaped>(A, C, E, IA2, Brb, e, lane, seg - 1);
             __syncthreads();
         }
         return;
@@ -339,10 +377,12 @@ __global__ void __launch_bounds__(128) k_rollout_bwd(AdjArgs A, ClassT<T> Cs) {
 
 template <typename T>
 hipError_t launch_rollout_fwd(const AdjArgs& A, const ClassT<T>& C, int m, bool shaped, hipStream_t s) {
-    // one wave per block: a few thousand environments are a few waves per class, and blocks of
-    // four waves would pack them onto a quarter as many compute units, sharing their issue
-    // and memory pipelines (0.180 -> 0.171 ms at 8192 x 256 with 8 thrusters)
-    const unsigned grid = (unsigned)((A.npad + kWave - 1) / kWave), block = kWave;
+    // one block of two waves per 64-environment tile (npad is a multiple of 64): a few
+    // thousand environments are a few tiles per class, each on a compute unit of its own
+    // (blocks of several tiles packed them onto fewer units, sharing their issue and memory
+    // pipelines: 0.180 against 0.171 ms at 8192 x 256 with 8 thrusters)
+    if (A.npad % kWave != 0) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)(A.npad / kWave), block = 2 * kWave;
 #define KERNEL k_rollout_fwd
     MGX_ADJ_SWITCH
 #undef KERNEL
