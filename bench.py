@@ -759,21 +759,26 @@ def adjoint(args):
     m = w.classes[0].m
     step_flops, _ = mgx.mgx_step_cost(m)
     vjp_flops, vjp_ops = mgx.mgx_vjp_cost(m)
-    # backward: every step recomputed once from its checkpoint (storing its forward
-    # quantities), then the reverse part of its vector-Jacobian product
-    bwd_flops = (step_flops + vjp_flops) * N * H
+    # backward: every step outside the last segment recomputed once from its checkpoint
+    # (storing its forward quantities; the forward pass stores the last segment's), then the
+    # reverse part of every step's vector-Jacobian product. Forward: every step, plus the last
+    # segment's steps once more with their forward quantities.
+    last = H - (H - 1) // CK * CK
+    bwd_flops = step_flops * N * (H - last) + vjp_flops * N * H
+    fwd_flops = step_flops * N * (H + last)
     out = {"metric": METRIC, "workload": f"adjoint_{N}x{H}", "unit": "env-steps/s", "value": N * H / (f + g),
            "n_envs": N, "horizon": H, "checkpoint_every": CK, "thrusters": m,
            "forward_ms": f * 1e3, "backward_ms": g * 1e3, "forward_env_steps_per_s": N * H / f,
            "backward_env_steps_per_s": N * H / g, "backward_over_forward": g / f,
            "roofline": {"bound": "alu", "kernel": f"k_rollout_bwd<float,{m},false>",
                         "achieved": bwd_flops / g / 1e12, "peak": (PEAK_FP32_VECTOR / 1e12), "unit": "TFLOP/s",
-                        "frac": bwd_flops / g / 1e12 / (PEAK_FP32_VECTOR / 1e12), "flops_per_env_step": step_flops + vjp_flops,
+                        "frac": bwd_flops / g / 1e12 / (PEAK_FP32_VECTOR / 1e12), "flops_per_env_step": bwd_flops / (N * H),
                         "vjp_flops_per_env_step": vjp_flops, "vjp_valu_ops_per_env_step": vjp_ops,
                         "launch_ms": g * 1e3, "traffic": None},
            "forward_roofline": {"bound": "alu", "kernel": f"k_rollout_fwd<float,{m},false>",
-                                "achieved": step_flops * N * H / f / 1e12, "peak": (PEAK_FP32_VECTOR / 1e12),
-                                "unit": "TFLOP/s", "frac": step_flops * N * H / f / 1e12 / (PEAK_FP32_VECTOR / 1e12)}}
+                                "achieved": fwd_flops / f / 1e12, "peak": (PEAK_FP32_VECTOR / 1e12),
+                                "unit": "TFLOP/s", "frac": fwd_flops / f / 1e12 / (PEAK_FP32_VECTOR / 1e12),
+                                "flops_per_env_step": fwd_flops / (N * H)}}
     b.close()
     print(json.dumps(out), flush=True)
 
