@@ -48,11 +48,11 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_step_dr65536x1000.md")
 KERNEL_SOURCES = ("step.hpp", "env_loop.hpp", "kernels.hip", "kernels.hpp", "step_kernel.hpp", "step_f32.hip")
 
 
-def kernel_sources_sha256():
+def kernel_sources_sha256(files=KERNEL_SOURCES):
     import hashlib
 
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, "paper_2503_09203_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -70,6 +70,26 @@ def recorded_traffic():
     if not m or m.group(2) != kernel_sources_sha256():
         return {}
     return {int(k): float(v) for k, v in re.findall(r"K=(\d+) (\d+) B/launch", m.group(1))}
+
+
+# The same for the differentiable rollout's forward and backward kernels.
+ADJOINT_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_rollout_adjoint8192x256.md")
+ADJOINT_SOURCES = ("adjoint.hip", "adjoint.hpp", "step.hpp", "env_loop.hpp", "kernels.hpp")
+
+
+def recorded_adjoint_traffic():
+    """{"fwd": bytes, "bwd": bytes} per launch at 8192 envs x 256 steps from the adjoint
+    profile's 'traffic:' line, if its source hash matches."""
+    import re
+
+    try:
+        text = open(ADJOINT_TRAFFIC_PROFILE).read()
+    except OSError:
+        return {}
+    m = re.search(r"^traffic: (.*); sources sha256 ([0-9a-f]{64})$", text, re.M)
+    if not m or m.group(2) != kernel_sources_sha256(ADJOINT_SOURCES):
+        return {}
+    return {k: float(v) for k, v in re.findall(r"(fwd|bwd) (\d+) B/launch", m.group(1))}
 
 
 def parity_errors(gpu, ref):
@@ -764,6 +784,7 @@ def adjoint(args):
     # reverse part of every step's vector-Jacobian product. Forward: every step, plus the last
     # segment's steps once more with their forward quantities.
     last = H - (H - 1) // CK * CK
+    traffic = recorded_adjoint_traffic()
     bwd_flops = step_flops * N * (H - last) + vjp_flops * N * H
     fwd_flops = step_flops * N * (H + last)
     out = {"metric": METRIC, "workload": f"adjoint_{N}x{H}", "unit": "env-steps/s", "value": N * H / (f + g),
@@ -774,11 +795,12 @@ def adjoint(args):
                         "achieved": bwd_flops / g / 1e12, "peak": (PEAK_FP32_VECTOR / 1e12), "unit": "TFLOP/s",
                         "frac": bwd_flops / g / 1e12 / (PEAK_FP32_VECTOR / 1e12), "flops_per_env_step": bwd_flops / (N * H),
                         "vjp_flops_per_env_step": vjp_flops, "vjp_valu_ops_per_env_step": vjp_ops,
-                        "launch_ms": g * 1e3, "traffic": None},
+                        "launch_ms": g * 1e3, "traffic": traffic.get("bwd"), "traffic_unit": "B/launch"},
            "forward_roofline": {"bound": "alu", "kernel": f"k_rollout_fwd<float,{m},false>",
                                 "achieved": fwd_flops / f / 1e12, "peak": (PEAK_FP32_VECTOR / 1e12),
                                 "unit": "TFLOP/s", "frac": fwd_flops / f / 1e12 / (PEAK_FP32_VECTOR / 1e12),
-                                "flops_per_env_step": fwd_flops / (N * H)}}
+                                "flops_per_env_step": fwd_flops / (N * H), "traffic": traffic.get("fwd"),
+                                "traffic_unit": "B/launch"}}
     b.close()
     print(json.dumps(out), flush=True)
 
