@@ -58,38 +58,53 @@ def kernel_sources_sha256(files=KERNEL_SOURCES):
     return h.hexdigest()
 
 
-def recorded_traffic():
-    """{K: bytes per launch} from the profile's 'traffic:' line, if its source hash matches."""
+def traffic_line(path, files):
+    """The 'traffic:' line of a committed profile (the figures before '; sources'), if the
+    sources it names hash to the value recorded with the counters, else None."""
     import re
 
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(path).read()
     except OSError:
-        return {}
+        return None
     m = re.search(r"^traffic: (.*); sources sha256 ([0-9a-f]{64})$", text, re.M)
-    if not m or m.group(2) != kernel_sources_sha256():
-        return {}
-    return {int(k): float(v) for k, v in re.findall(r"K=(\d+) (\d+) B/launch", m.group(1))}
+    if not m or m.group(2) != kernel_sources_sha256(files):
+        return None
+    return m.group(1)
 
 
-# The same for the differentiable rollout's forward and backward kernels.
+def recorded_traffic():
+    """{K: bytes per launch} from the step profile's 'traffic:' line, if its source hash matches."""
+    import re
+
+    line = traffic_line(TRAFFIC_PROFILE, KERNEL_SOURCES)
+    return {int(k): float(v) for k, v in re.findall(r"K=(\d+) (\d+) B/launch", line or "")}
+
+
+# The same for the differentiable rollout's forward and backward kernels and the
+# station-keeping task's step kernel.
 ADJOINT_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_rollout_adjoint8192x256.md")
 ADJOINT_SOURCES = ("adjoint.hip", "adjoint.hpp", "step.hpp", "env_loop.hpp", "kernels.hpp")
+STATION_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_station_step65536.md")
+STATION_SOURCES = ("station.hip", "step.hpp", "env_loop.hpp", "kernels.hpp")
 
 
 def recorded_adjoint_traffic():
-    """{"fwd": bytes, "bwd": bytes} per launch at 8192 envs x 256 steps from the adjoint
-    profile's 'traffic:' line, if its source hash matches."""
+    """{"fwd": bytes, "bwd": bytes} per launch at 8192 envs x 256 steps, if the adjoint
+    sources hash to the recorded value."""
     import re
 
-    try:
-        text = open(ADJOINT_TRAFFIC_PROFILE).read()
-    except OSError:
-        return {}
-    m = re.search(r"^traffic: (.*); sources sha256 ([0-9a-f]{64})$", text, re.M)
-    if not m or m.group(2) != kernel_sources_sha256(ADJOINT_SOURCES):
-        return {}
-    return {k: float(v) for k, v in re.findall(r"(fwd|bwd) (\d+) B/launch", m.group(1))}
+    line = traffic_line(ADJOINT_TRAFFIC_PROFILE, ADJOINT_SOURCES)
+    return {k: float(v) for k, v in re.findall(r"(fwd|bwd) (\d+) B/launch", line or "")}
+
+
+def recorded_station_traffic():
+    """{K: bytes per launch} of the station step at 65,536 envs for calls of K task steps,
+    if the station sources hash to the recorded value."""
+    import re
+
+    line = traffic_line(STATION_TRAFFIC_PROFILE, STATION_SOURCES)
+    return {int(k): float(v) for k, v in re.findall(r"K=(\d+) (\d+) B/launch", line or "")}
 
 
 def parity_errors(gpu, ref):
@@ -991,7 +1006,9 @@ def station(args):
                    "station": desc, "path": "station step: one launch per call of 100 task steps, all outputs "
                                             "kept per step"},
         "roofline": {"bound": "hbm", "achieved": N * bytes_es / per_launch / 1e9, "peak": PEAK_HBM / 1e9,
-                     "unit": "GB/s", "frac": N * bytes_es / per_launch / PEAK_HBM, "traffic": None,
+                     "unit": "GB/s", "frac": N * bytes_es / per_launch / PEAK_HBM,
+                     "traffic": (recorded_station_traffic().get(CH) if (N, args.station_class) == (65536, "dr")
+                                 else None), "traffic_unit": "B/launch",
                      "kernel": f"k_station_step<float,{m},false,false,false,true>", "launch_us_mean": per_launch * 1e6,
                      "bytes_per_env_step": bytes_es},
         "episodes_started_per_env": float(np.mean(ep)),

@@ -40,3 +40,12 @@ def test_recorded_adjoint_traffic_follows_the_sources():
     line = [l for l in open(os.path.join(ROOT, "profiles", "k_rollout_adjoint8192x256.md")) if l.startswith("traffic:")]
     assert len(line) == 1
     assert (bench.kernel_sources_sha256(bench.ADJOINT_SOURCES) in line[0]) == bool(t)
+
+
+def test_recorded_station_traffic_follows_the_sources():
+    t = bench.recorded_station_traffic()
+    if t:  # recorded for exactly these sources
+        assert set(t) == {1, 100} and all(v > 0 for v in t.values())
+    line = [l for l in open(os.path.join(ROOT, "profiles", "k_station_step65536.md")) if l.startswith("traffic:")]
+    assert len(line) == 1
+    assert (bench.kernel_sources_sha256(bench.STATION_SOURCES) in line[0]) == bool(t)
