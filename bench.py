@@ -574,6 +574,15 @@ def hetero(args):
            "autotune": {"candidates": tuned.candidates, "us_per_chunk": tuned.us_per_chunk}, "tuned": best,
            "tuned_rollout_graph": whole, "baseline": base,
            "speedup_vs_per_class": best["env_steps_per_s"] / base["env_steps_per_s"]}
+    # Launches per chunk of the tuned shape: one persistent launch of K steps, or one launch
+    # per class of K steps, CHUNK / K times.
+    per_chunk = (CHUNK // best["K"]) * (1 if best["mode"] == "persistent" else len(w.classes))
+    launch_us = best["ms_per_rollout"] * 1e3 / (T // CHUNK) / per_chunk
+    out["roofline"] = {"bound": "alu", "kernel": "k_persistent<float>" if best["mode"] == "persistent" else "k_step (per class)",
+                       "achieved": best["tflops"], "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
+                       "frac": best["tflops"] * 1e12 / PEAK_FP32_VECTOR, "traffic": None,
+                       "launches_per_chunk": per_chunk, "us_per_launch_with_gaps": launch_us,
+                       "flops_per_env_step": flops / n}
     if not args.no_cpu_baseline:
         # the FP64 oracle per class on a bounded sample of that class's environments (the
         # last rollout's inputs), which also gives each class's parity after T steps
@@ -1009,7 +1018,7 @@ def station(args):
                      "unit": "GB/s", "frac": N * bytes_es / per_launch / PEAK_HBM,
                      "traffic": (recorded_station_traffic().get(CH) if (N, args.station_class) == (65536, "dr")
                                  else None), "traffic_unit": "B/launch",
-                     "kernel": f"k_station_step<float,{m},false,false,false,true>", "launch_us_mean": per_launch * 1e6,
+                     "kernel": f"k_station_step<float,{m},false,false,false,true>", "launch_us_mean": per_launch * CH * 1e6, "us_per_task_step": per_launch * 1e6,
                      "bytes_per_env_step": bytes_es},
         "episodes_started_per_env": float(np.mean(ep)),
         "gym_step": {"env_steps_per_s": N / gym_step, "us_per_step": gym_step * 1e6,
