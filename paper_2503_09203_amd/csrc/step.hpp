@@ -202,7 +202,7 @@ __host__ __device__ __forceinline__ void sincos_deflection(T x, T& s, T& c) {
                       x2, T(-0.5f)),
                  x2, T(1.0f));
         const bool big = !(abs_(x) <= T(0.7854f));
-        if (any_lane(big)) {
+        if (__builtin_expect(any_lane(big), 0)) {
             T se, ce;
             if constexpr (std::is_same<T, float>::value) {
                 sincosf(x, &se, &ce);
@@ -274,9 +274,10 @@ __host__ __device__ __forceinline__ void quat_increment(T h, const T w[3], T& c,
         s = h * fma_(fma_(phi2, T(1.0f / 120.0f), T(-1.0f / 6.0f)), phi2, T(1.0f));
         // the exact form where the series is not accurate enough: evaluated by the whole
         // wavefront when any lane needs it and selected per lane, so the common case is one
-        // uniform branch with no execution-mask bookkeeping
+        // uniform branch with no execution-mask bookkeeping; marked unlikely, so that the
+        // common path falls through and a step takes no branch here
         const bool big = !(phi2 <= T(0.0025f));
-        if (any_lane(big)) {
+        if (__builtin_expect(any_lane(big), 0)) {
             T phi = sqrt_(phi2);
             T sn, cs;
             if constexpr (std::is_same<T, float>::value) {
@@ -308,7 +309,7 @@ __host__ __device__ __forceinline__ void quat_increment_cm1(T h, const T w[3], T
         cm1 = fma_(phi2, T(1.0f / 24.0f), T(-0.5f)) * phi2;
         s = h * fma_(fma_(phi2, T(1.0f / 120.0f), T(-1.0f / 6.0f)), phi2, T(1.0f));
         const bool big = !(phi2 <= T(0.0025f));
-        if (any_lane(big)) {
+        if (__builtin_expect(any_lane(big), 0)) {
             T phi = sqrt_(phi2);
             T sn, cs;
             if constexpr (std::is_same<T, float>::value) {
