@@ -73,11 +73,21 @@ def traffic_line(path, files):
     return m.group(1)
 
 
-def recorded_traffic():
-    """{K: bytes per launch} from the step profile's 'traffic:' line, if its source hash matches."""
+# Profiles of the other step bodies at the same sizes, by workload.
+VARIANT_TRAFFIC_PROFILES = {
+    "dr": TRAFFIC_PROFILE,
+    "propellers": os.path.join(ROOT, "profiles", "k_step_prop65536x1000.md"),
+    "rudders": os.path.join(ROOT, "profiles", "k_step_rudder65536x1000.md"),
+    "payload": os.path.join(ROOT, "profiles", "k_step_payload65536x1000.md"),
+}
+
+
+def recorded_traffic(workload="dr"):
+    """{K: bytes per launch} from the workload's step profile 'traffic:' line, if its source
+    hash matches."""
     import re
 
-    line = traffic_line(TRAFFIC_PROFILE, KERNEL_SOURCES)
+    line = traffic_line(VARIANT_TRAFFIC_PROFILES[workload], KERNEL_SOURCES)
     return {int(k): float(v) for k, v in re.findall(r"K=(\d+) (\d+) B/launch", line or "")}
 
 
@@ -292,7 +302,7 @@ def main():
     single_launch_median = float(np.median(per_replay))
     rec_len = 45 if variant == "payload" else 30
     single_bytes = bytes_per_env_step(cls.m, 1, HOLD, rec_len=rec_len) * N
-    traffic = recorded_traffic() if (N, T, HOLD) == (65536, 1000, 10) and not shaped else {}
+    traffic = recorded_traffic(variant) if (N, T, HOLD) == (65536, 1000, 10) else {}
 
     out = {
         "metric": METRIC,

@@ -49,3 +49,13 @@ def test_recorded_station_traffic_follows_the_sources():
     line = [l for l in open(os.path.join(ROOT, "profiles", "k_station_step65536.md")) if l.startswith("traffic:")]
     assert len(line) == 1
     assert (bench.kernel_sources_sha256(bench.STATION_SOURCES) in line[0]) == bool(t)
+
+
+def test_recorded_traffic_of_every_step_body_follows_the_sources():
+    for wl, path in bench.VARIANT_TRAFFIC_PROFILES.items():
+        t = bench.recorded_traffic(wl)
+        if t:
+            assert set(t) == {1, 16} and all(v > 0 for v in t.values()), wl
+        line = [l for l in open(path) if l.startswith("traffic:")]
+        assert len(line) == 1, wl
+        assert (bench.kernel_sources_sha256() in line[0]) == bool(t), wl
