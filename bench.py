@@ -99,6 +99,19 @@ STATION_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_station_step65536.md
 STATION_SOURCES = ("station.hip", "step.hpp", "env_loop.hpp", "kernels.hpp")
 
 
+HETERO_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_persistent_hetero70512x1024.md")
+HETERO_SOURCES = ("persistent.hip", "step.hpp", "env_loop.hpp", "kernels.hpp")
+
+
+def recorded_hetero_traffic():
+    """{K: bytes per launch} of the persistent launch over the five-class batch of 70,512
+    environments, if the persistent sources hash to the recorded value."""
+    import re
+
+    line = traffic_line(HETERO_TRAFFIC_PROFILE, HETERO_SOURCES)
+    return {int(k): float(v) for k, v in re.findall(r"K=(\d+) (\d+) B/launch", line or "")}
+
+
 def recorded_adjoint_traffic():
     """{"fwd": bytes, "bwd": bytes} per launch at 8192 envs x 256 steps, if the adjoint
     sources hash to the recorded value."""
@@ -590,7 +603,9 @@ def hetero(args):
     launch_us = best["ms_per_rollout"] * 1e3 / (T // CHUNK) / per_chunk
     out["roofline"] = {"bound": "alu", "kernel": "k_persistent<float>" if best["mode"] == "persistent" else "k_step (per class)",
                        "achieved": best["tflops"], "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
-                       "frac": best["tflops"] * 1e12 / PEAK_FP32_VECTOR, "traffic": None,
+                       "frac": best["tflops"] * 1e12 / PEAK_FP32_VECTOR,
+                       "traffic": (recorded_hetero_traffic().get(best["K"]) if best["mode"] == "persistent" else None),
+                       "traffic_unit": "B/launch",
                        "launches_per_chunk": per_chunk, "us_per_launch_with_gaps": launch_us,
                        "flops_per_env_step": flops / n}
     if not args.no_cpu_baseline:

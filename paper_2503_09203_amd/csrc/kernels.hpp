@@ -214,6 +214,7 @@ struct PersistArgs {
     DevMisc* misc;
     int32_t rd, wr, advance;
     int32_t n_heavy;       // tiles [0, n_heavy) go first to the first wave on each SIMD
+    int32_t any_shaped;    // some class has dead zones or reverse gains: the kernel with both bodies
     uint32_t* simd_rank;   // [kSimdKeys] arrival table, or null
     float* tile_partials;  // [n_tiles][kStats] or null
     double* stats;         // [16][kStats]

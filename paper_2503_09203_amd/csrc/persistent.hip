@@ -8,6 +8,9 @@
 // thruster count is uniform per wave and the `switch` over m selects a fully unrolled step
 // body without divergence. The counter is double-buffered like the step counter: block 0
 // clears the slot the next launch will use, so no end-of-launch handshake is needed.
+// A batch with no shaped-thrust class runs an instantiation without the shaped body:
+// holding both, the kernel needs more than the 256 registers that two waves per SIMD
+// allow, and spills 50 of them to scratch memory.
 #include <hip/hip_runtime.h>
 
 #include "env_loop.hpp"
@@ -52,17 +55,17 @@ __device__ __forceinline__ ClassT<T> class_to_sgpr(const ClassT<T>& L) {
     return C;
 }
 
-template <typename T, int M>
+template <typename T, int M, bool kShapedBody>
 __device__ __forceinline__ void run_tile(const StepArgs& A, const ClassT<T>& L, bool shaped, int64_t env, int64_t t0,
                                          int K, float st[kStats]) {
     const ClassT<T> C = class_to_sgpr<T, M>(L);
-    if (shaped)
+    if (kShapedBody && shaped)
         env_steps<T, M, false, true>(A, C, env, t0, K, st);
     else
         env_steps<T, M, false, false>(A, C, env, t0, K, st);
 }
 
-template <typename T>
+template <typename T, bool kShapedBody>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) k_persistent(PersistArgs P) {
     __shared__ ClassT<T> lds_cls[16];
     __shared__ SegDesc lds_seg[16];
@@ -127,14 +130,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
 #pragma unroll
         for (int j = 0; j < kStats; ++j) st[j] = 0.0f;
         switch (sd.m) {
-            case 1: run_tile<T, 1>(A, C, shaped, env, t0, P.K, st); break;
-            case 2: run_tile<T, 2>(A, C, shaped, env, t0, P.K, st); break;
-            case 3: run_tile<T, 3>(A, C, shaped, env, t0, P.K, st); break;
-            case 4: run_tile<T, 4>(A, C, shaped, env, t0, P.K, st); break;
-            case 5: run_tile<T, 5>(A, C, shaped, env, t0, P.K, st); break;
-            case 6: run_tile<T, 6>(A, C, shaped, env, t0, P.K, st); break;
-            case 7: run_tile<T, 7>(A, C, shaped, env, t0, P.K, st); break;
-            default: run_tile<T, 8>(A, C, shaped, env, t0, P.K, st); break;
+            case 1: run_tile<T, 1, kShapedBody>(A, C, shaped, env, t0, P.K, st); break;
+            case 2: run_tile<T, 2, kShapedBody>(A, C, shaped, env, t0, P.K, st); break;
+            case 3: run_tile<T, 3, kShapedBody>(A, C, shaped, env, t0, P.K, st); break;
+            case 4: run_tile<T, 4, kShapedBody>(A, C, shaped, env, t0, P.K, st); break;
+            case 5: run_tile<T, 5, kShapedBody>(A, C, shaped, env, t0, P.K, st); break;
+            case 6: run_tile<T, 6, kShapedBody>(A, C, shaped, env, t0, P.K, st); break;
+            case 7: run_tile<T, 7, kShapedBody>(A, C, shaped, env, t0, P.K, st); break;
+            default: run_tile<T, 8, kShapedBody>(A, C, shaped, env, t0, P.K, st); break;
         }
         if (P.tile_partials) {
 #pragma unroll
@@ -170,7 +173,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
 
 template <typename T>
 hipError_t launch_persistent(const PersistArgs& P, int grid, int block, hipStream_t s) {
-    hipLaunchKernelGGL(k_persistent<T>, dim3(grid), dim3(block), 0, s, P);
+    if (P.any_shaped)
+        hipLaunchKernelGGL((k_persistent<T, true>), dim3(grid), dim3(block), 0, s, P);
+    else
+        hipLaunchKernelGGL((k_persistent<T, false>), dim3(grid), dim3(block), 0, s, P);
     return hipGetLastError();
 }
 

@@ -620,6 +620,7 @@ mgx_status enqueue_step(mgx_batch* b, const void* actions, int64_t n_rows, int64
         pa.advance = K;
         pa.tile_partials = stats ? b->d_tile_partials : nullptr;
         pa.stats = b->d_stats;
+        for (int c = 0; c < b->n_classes; ++c) pa.any_shaped |= b->h_class_f[c].shaped != 0 ? 1 : 0;
         const int waves_per_block = block / kWave;
         int grid = b->n_cu * b->grid_per_cu;
         const int needed = (b->n_tiles + waves_per_block - 1) / waves_per_block;

@@ -59,3 +59,12 @@ def test_recorded_traffic_of_every_step_body_follows_the_sources():
         line = [l for l in open(path) if l.startswith("traffic:")]
         assert len(line) == 1, wl
         assert (bench.kernel_sources_sha256() in line[0]) == bool(t), wl
+
+
+def test_recorded_hetero_traffic_follows_the_sources():
+    t = bench.recorded_hetero_traffic()
+    if t:
+        assert set(t) == {32} and all(v > 0 for v in t.values())
+    line = [l for l in open(os.path.join(ROOT, "profiles", "k_persistent_hetero70512x1024.md")) if l.startswith("traffic:")]
+    assert len(line) == 1
+    assert (bench.kernel_sources_sha256(bench.HETERO_SOURCES) in line[0]) == bool(t)
